@@ -1,0 +1,287 @@
+"""Second-order formulation (Sec. 2, eq. WE): the oracle's nodal leapfrog scheme.
+
+TEST INFRASTRUCTURE ONLY (see the oracle package docstring).
+
+Continuous system (eq. WE):  (1/c^2) y_tt - lap y = Re(f e^{-iwt}),
+dy/dn + (1/c) y_t = Re(gS e^{-iwt}) on absorbing faces, dy/dn = 0 on Neumann faces,
+y = 0 on the sound-soft set D (homogeneous Dirichlet, eq. WE_DBC with g_D = 0).
+
+Space (reading of the paper's mass-lumped P1 FE on a structured grid): nodes x_I = I h,
+I in {0..n}^d.  Lumped mass w_I = h^d prod_k (1/2 if I_k is 0 or n_k), M = diag(w / c^2).
+Stiffness (S u)_I = sum over the axis edges e = (I, J) of a_e (u_I - u_J), with
+a_e = h^{d-2} prod over the other axes k' of (1/2 if the edge lies in a boundary plane
+x_k' = 0 or 1).  Absorbing faces add the boundary mass B_I = (1/c_I) sum over absorbing
+faces containing I of the lumped face weight h^{d-1} prod (1/2 on the face's own edges).
+Load F^n = w Re(f e^{-iwt_n}) + sum_abs (face weight) Re(gS e^{-iwt_n}).
+
+Time (leapfrog, damping centred), t_n = n dt:
+    (M + dt/2 B) u^{n+1} = 2 M u^n - (M - dt/2 B) u^{n-1} - dt^2 (S u^n - F^n),  u = 0 on D
+    start  u^1 = u^0 + dt (1 - beta) v^0 - dt^2/2 M^{-1} (S u^0 - F^0)   (ghost u^{-1} = u^1 - 2 dt v^0)
+    end    v^N = (u^{N+1} - u^{N-1}) / (2 dt),  Phi(u^0, v^0) = (u^N, v^N)
+with beta = dt B / (2 M).
+
+Energy metric (eq. cost_functional_J):  M_E = blockdiag(S, M) on the free nodes.
+Riesz map (eq. CMCG_PRECONDITIONIER): blockdiag(S^{-1}, M^{-1}); when D is empty S is
+singular (constants) and its pseudo-inverse on zero-sum vectors is used.
+Output (eq. fundamental-frequency-solution, discrete): U = (2/N) sum_{n<N} u^n e^{i w t_n}.
+
+Arrays: node fields of shape (nz+1, ny+1, nx+1) (3D) or (ny+1, nx+1) (2D), x fastest.
+State vector: [u (all nodes), v (all nodes)], sound-soft entries zero.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import cmcg as _cmcg
+
+ABSORBING = 0
+
+
+def _half(m: int) -> np.ndarray:
+    """1/2 at both ends of an axis of m+1 nodes, 1 inside."""
+    a = np.ones(m + 1)
+    a[0] = a[-1] = 0.5
+    return a
+
+
+class F2:
+    """The discrete second-order scheme for one problem (2D or 3D)."""
+
+    def __init__(self, prob, N: Optional[int] = None):
+        assert prob.formulation == 2 and prob.dim in (2, 3)
+        self.prob = prob
+        self.d = d = prob.dim
+        self.n = [int(m) for m in prob.n[:d]]          # x, y[, z]
+        self.h = h = float(prob.h)
+        self.shape = tuple(m + 1 for m in reversed(self.n))
+        self.c = prob.c_array().reshape(self.shape)
+        self.omega = float(prob.omega)
+        self.T = 2.0 * math.pi / self.omega
+        if N is None:
+            N = int(math.ceil(self.T * float(self.c.max()) / (prob.courant * h)))
+        assert N >= 2
+        self.N = N
+        self.dt = self.T / N
+        self.bc = list(prob.face_bc)[: 2 * d]
+        self.free = (np.ones(self.shape) if prob.sound_soft is None
+                     else 1.0 - np.asarray(prob.sound_soft, dtype=np.float64).reshape(self.shape))
+        # per-axis half factors broadcast to the node array (axis k -> numpy axis d-1-k)
+        self.halfs = []
+        for k in range(d):
+            sh = [1] * d
+            sh[d - 1 - k] = self.n[k] + 1
+            self.halfs.append(_half(self.n[k]).reshape(sh))
+        w = np.full(self.shape, h ** d)
+        for k in range(d):
+            w = w * self.halfs[k]
+        self.w = w
+        self.M = w / (self.c * self.c)
+        # boundary mass and face weights
+        B = np.zeros(self.shape)
+        self.face_w = []
+        for k in range(d):
+            fw = np.full(self.shape, h ** (d - 1))
+            for kk in range(d):
+                if kk != k:
+                    fw = fw * self.halfs[kk]
+            for side in (0, 1):
+                sel = [slice(None)] * d
+                sel[d - 1 - k] = 0 if side == 0 else self.n[k]
+                self.face_w.append((tuple(sel), fw[tuple(sel)]))
+                if self.bc[2 * k + side] == ABSORBING:
+                    B[tuple(sel)] += fw[tuple(sel)] / self.c[tuple(sel)]
+        self.B = B
+        self.beta = 0.5 * self.dt * B / self.M
+        self.f = (np.zeros(self.shape, complex) if prob.f is None
+                  else np.asarray(prob.f, dtype=complex).reshape(self.shape))
+        self.g = None if prob.gS is None else [np.asarray(a, dtype=complex) for a in prob.gS]
+        self.nn = int(np.prod(self.shape))
+        self.size = 2 * self.nn
+        self._S_lu = None
+
+    # ---------------------------------------------------------------- operators
+    def S(self, u: np.ndarray) -> np.ndarray:
+        """Stiffness apply, summed edge by edge."""
+        d, h = self.d, self.h
+        out = np.zeros(self.shape)
+        for k in range(d):
+            ax = d - 1 - k
+            a = np.full([1] * d, h ** (d - 2))
+            for kk in range(d):
+                if kk != k:
+                    a = a * self.halfs[kk]
+            lo = [slice(None)] * d
+            hi = [slice(None)] * d
+            lo[ax] = slice(0, -1)
+            hi[ax] = slice(1, None)
+            lo, hi = tuple(lo), tuple(hi)
+            ae = np.broadcast_to(a, self.shape)[lo]
+            flux = ae * (u[hi] - u[lo])
+            out[lo] -= flux
+            out[hi] += flux
+        return out
+
+    def load(self, t: float) -> np.ndarray:
+        e = np.exp(-1j * self.omega * t)
+        F = self.w * (self.f * e).real
+        if self.g is not None:
+            for idx, (sel, fw) in enumerate(self.face_w):
+                if self.bc[idx] == ABSORBING:
+                    F[sel] += fw * (self.g[idx].reshape(fw.shape) * e).real
+        return F
+
+    # ---------------------------------------------------------------- time stepping
+    def _accel(self, u, F):
+        """dt^2 M^{-1} (S u - F) (F may be None)."""
+        r = self.S(u)
+        if F is not None:
+            r = r - F
+        return self.dt ** 2 * r / self.M
+
+    def period(self, z: np.ndarray, forced: bool, U_acc: Optional[np.ndarray] = None):
+        """Phi(z) (forced) or E z (homogeneous).  If U_acc is given, u^n e^{i w t_n} for
+        n < N is accumulated into it (the filter sum)."""
+        dt, beta, R = self.dt, self.beta, self.free
+        u0 = R * z[: self.nn].reshape(self.shape)
+        v0 = R * z[self.nn:].reshape(self.shape)
+        F = (lambda n: self.load(n * dt)) if forced else (lambda n: None)
+        um = u0
+        u = R * (u0 + dt * (1.0 - beta) * v0 - 0.5 * self._accel(u0, F(0)))
+        if U_acc is not None:
+            U_acc += um
+        for n in range(1, self.N + 1):
+            if U_acc is not None and n < self.N:
+                U_acc += u * np.exp(1j * self.omega * n * dt)
+            up = R * ((2.0 * u - (1.0 - beta) * um - self._accel(u, F(n))) / (1.0 + beta))
+            if n == self.N:
+                vN = (up - um) / (2.0 * dt)
+                return np.concatenate([u.ravel(), vN.ravel()])
+            um, u = u, up
+
+    def period_T(self, y: np.ndarray) -> np.ndarray:
+        """E^T y, with E = (end map) (step map)^{N-1} (start map) on the states
+        (u^0, v^0) -> (u^1, u^0) -> ... -> (u^N, u^{N-1}) -> (u^N, v^N); each transpose is
+        written out from its map and they are applied in reverse order."""
+        dt, beta, R = self.dt, self.beta, self.free
+        x = R * y[: self.nn].reshape(self.shape)
+        yv = R * y[self.nn:].reshape(self.shape)
+
+        def KT(q):
+            """Transpose of K a = (2 a - dt^2 M^{-1} S a) / (1 + beta), masked."""
+            s = R * q / (1.0 + beta)
+            return R * (2.0 * s - self.dt ** 2 * self.S(s / self.M))
+
+        L = -(1.0 - beta) / (1.0 + beta)
+        # end map (a, b) -> (a, (K a + L b - b) / (2 dt)):  transpose
+        a = x + KT(yv) / (2.0 * dt)
+        b = R * (L - 1.0) * yv / (2.0 * dt)
+        # step map (a, b) -> (K a + L b, a):  transpose (x, y) -> (K^T x + y, L x)
+        for _ in range(self.N - 1):
+            a, b = KT(a) + b, R * L * a
+        # start map (u0, v0) -> (A u0 + B v0, u0), A = I - dt^2/2 M^{-1} S, B = dt (1 - beta)
+        u0 = R * (a - 0.5 * self.dt ** 2 * self.S(R * a / self.M)) + b
+        v0 = R * dt * (1.0 - beta) * a
+        return np.concatenate([u0.ravel(), v0.ravel()])
+
+    # ---------------------------------------------------------------- metric, Riesz
+    def ME(self, w: np.ndarray) -> np.ndarray:
+        R = self.free
+        u = R * w[: self.nn].reshape(self.shape)
+        v = R * w[self.nn:].reshape(self.shape)
+        return np.concatenate([(R * self.S(u)).ravel(), (R * self.M * v).ravel()])
+
+    def stiffness_matrix(self) -> sp.csr_matrix:
+        """S as a sparse matrix, built edge by edge (independent of `S`)."""
+        d, h = self.d, self.h
+        idx = np.arange(self.nn).reshape(self.shape)
+        rows, cols, vals = [], [], []
+        for k in range(d):
+            ax = d - 1 - k
+            a = np.full([1] * d, h ** (d - 2))
+            for kk in range(d):
+                if kk != k:
+                    a = a * self.halfs[kk]
+            lo = [slice(None)] * d
+            hi = [slice(None)] * d
+            lo[ax] = slice(0, -1)
+            hi[ax] = slice(1, None)
+            I = idx[tuple(lo)].ravel()
+            J = idx[tuple(hi)].ravel()
+            ae = np.broadcast_to(a, self.shape)[tuple(lo)].ravel()
+            rows += [I, J, I, J]
+            cols += [I, J, J, I]
+            vals += [ae, ae, -ae, -ae]
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(self.nn, self.nn))
+
+    def _riesz_factor(self):
+        if self._S_lu is None:
+            S = self.stiffness_matrix()
+            free = np.flatnonzero(self.free.ravel() > 0.5)
+            self._pure_neumann = bool(self.free.min() > 0.5)
+            keep = free[1:] if self._pure_neumann else free
+            self._keep = keep
+            self._S_lu = spla.splu(S[keep][:, keep].tocsc())
+        return self._S_lu
+
+    def riesz(self, rhat: np.ndarray) -> np.ndarray:
+        """blockdiag(S^{-1}, M^{-1}) on the free nodes; with no sound-soft node, S^+ on
+        zero-sum vectors (solve with the first node pinned, then remove the mean)."""
+        lu = self._riesz_factor()
+        ru = rhat[: self.nn]
+        xu = np.zeros(self.nn)
+        xu[self._keep] = lu.solve(ru[self._keep])
+        if self._pure_neumann:
+            xu -= xu.mean()
+        xv = (self.free * rhat[self.nn:].reshape(self.shape) / self.M).ravel()
+        return np.concatenate([xu, xv])
+
+    def energy(self, u_next: np.ndarray, u: np.ndarray) -> float:
+        """E^{n+1/2} = 1/2 delta^T M delta + 1/2 (u^{n+1})^T S u^n, delta = (u^{n+1}-u^n)/dt."""
+        dl = (u_next - u) / self.dt
+        return 0.5 * float(np.sum(dl * self.M * dl)) + 0.5 * float(np.sum(u_next * self.S(u)))
+
+    # ---------------------------------------------------------------- CMCG and output
+    def solve(self, tol: float, max_iter: int = 10000, z0=None, record=None):
+        return _cmcg.cmcg(lambda x: self.period(x, True), lambda x: self.period(x, False),
+                          self.period_T, self.ME, self.riesz, self.size, tol, max_iter,
+                          z0=z0, record=record)
+
+    def filter(self, z: np.ndarray) -> np.ndarray:
+        """U = (2/N) sum_{n<N} u^n e^{i w t_n} over one forced period from z."""
+        U = np.zeros(self.shape, complex)
+        self.period(z, True, U_acc=U)
+        return 2.0 * U / self.N
+
+    def step6_output(self, z: np.ndarray) -> np.ndarray:
+        """The paper's Step 6 output u = v_0 + (i / omega) v_1."""
+        return (z[: self.nn] + 1j * z[self.nn:] / self.omega).reshape(self.shape)
+
+    def functional(self, z):
+        return _cmcg.functional(lambda x: self.period(x, True), self.ME, z)
+
+    # ---------------------------------------------------------------- direct solve
+    def direct(self):
+        """Direct sparse solve of [S - wt^2 M - i wh B] U = Fhat on the free nodes with
+        wt = (2/dt) sin(w dt / 2), wh = sin(w dt) / dt, Fhat = w f + sum_abs (face weight) gS.
+        Returns (U, z_periodic) with z = (Re U, wh Im U)."""
+        dt = self.dt
+        wt2 = (2.0 / dt * math.sin(0.5 * self.omega * dt)) ** 2
+        wh = math.sin(self.omega * dt) / dt
+        S = self.stiffness_matrix()
+        A = (S - wt2 * sp.diags(self.M.ravel()) - 1j * wh * sp.diags(self.B.ravel())).tocsr()
+        Fh = self.w * self.f
+        if self.g is not None:
+            for idx, (sel, fw) in enumerate(self.face_w):
+                if self.bc[idx] == ABSORBING:
+                    Fh[sel] += fw * self.g[idx].reshape(fw.shape)
+        free = np.flatnonzero(self.free.ravel() > 0.5)
+        U = np.zeros(self.nn, complex)
+        U[free] = spla.spsolve(A[free][:, free].tocsc(), Fh.ravel()[free])
+        z = np.concatenate([U.real, wh * U.imag])
+        return U.reshape(self.shape), z
