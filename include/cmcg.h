@@ -1,0 +1,165 @@
+/*
+ * cmcg.h - C ABI of the MI355X (gfx950) controllability-method solver for the Helmholtz
+ * equation: the periodic solution of the time-harmonically forced wave equation is found by
+ * conjugate gradients on its initial state (Grote, Nataf, Tang, Tournier, "Parallel
+ * Controllability Methods for the Helmholtz Equation", the CMCG Algorithm of Sec. 2.3).
+ *
+ * Every call returns a cmcg_status (0 = CMCG_OK); nothing unwinds across the ABI.  A handle
+ * must not be used by two threads at once; different handles are independent.  All device
+ * work of a handle runs on the HIP stream given in cmcg_options (NULL = a stream the handle
+ * creates).  The handle owns all device memory it allocates until cmcg_destroy.
+ *
+ * Problem (eq. HE):  -lap u - k^2 u = f in the box [0, n_x h] x [0, n_y h] (x [0, n_z h]),
+ * h = 1 / n_x, k = omega / c(x);  du/dn - i k u = gS on absorbing faces, du/dn = 0 on
+ * Neumann faces, u = 0 on sound-soft nodes.  Time domain (eq. WE / eq. mixWE): the forced
+ * wave equation with source Re(f e^{-i omega t}) and boundary data Re(gS e^{-i omega t});
+ * one period T = 2 pi / omega is N = ceil(T c_max / (courant h)) leapfrog steps, dt = T / N.
+ *
+ * Formulations:
+ *  1 (F1, dim 2): first-order velocity/flux system (Sec. 3.1, eq. mixWE) on a staggered grid:
+ *    v and c at the n_x x n_y cell centres, flux on interior faces, absorbing condition
+ *    p.n + v/c = gS on boundary faces.  Energy metric of eq. mix_cost_functional_J.
+ *  2 (F2, dim 3): second-order system (Sec. 2, eq. WE) on the (n+1)^3 nodes, mass-lumped
+ *    7-point stencil, energy metric of eq. cost_functional_J, Riesz map of
+ *    eq. CMCG_PRECONDITIONIER solved on the device each iteration.
+ *
+ * Array layouts (host arrays unless stated):
+ *  - F1 cell fields (c, f, u): n_y rows of n_x values, x fastest.
+ *  - F2 node fields (c, f, sound_soft, u): (n_z+1) planes of (n_y+1) rows of (n_x+1) values.
+ *  - gS: the faces -x, +x, -y, +y[, -z, +z] concatenated.  F1: n_y values for each x face,
+ *    n_x for each y face.  F2: each face's nodes in array order of the two remaining axes
+ *    (slower axis first): (n_z+1)(n_y+1) for x faces, (n_z+1)(n_x+1) for y faces,
+ *    (n_y+1)(n_x+1) for z faces.
+ *  - Packed state vectors (cmcg_apply, cmcg_get_state, cmcg_filter), FP64 DEVICE arrays:
+ *    F1: [Px (n_y rows of n_x-1), Py (n_y-1 rows of n_x), v (n_y rows of n_x)];
+ *    F2: [u (all nodes), v (all nodes)], sound-soft entries zero.
+ */
+#ifndef CMCG_H
+#define CMCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cmcg_handle cmcg_handle;
+
+typedef enum {
+  CMCG_OK = 0,
+  CMCG_ENOTCONV = 1,      /* warning: max_iter reached; the result is the last iterate   */
+  CMCG_EINVAL = -1,       /* invalid argument (sizes, NaN or non-positive c or omega...)  */
+  CMCG_ECFL = -2,         /* courant * sqrt(dim) >= 1: leapfrog would be unstable          */
+  CMCG_ENOMEM = -3,       /* device allocation failed                                      */
+  CMCG_EDEVICE = -4,      /* a HIP call failed; see cmcg_last_error()                      */
+  CMCG_EBREAKDOWN = -5,   /* CG breakdown: <qhat, d> <= 0 or a non-finite scalar           */
+  CMCG_EUNSUPPORTED = -6  /* a valid combination this library does not implement           */
+} cmcg_status;
+
+enum { CMCG_ABSORBING = 0, CMCG_NEUMANN = 1 };
+enum { CMCG_FP64 = 0, CMCG_FP32_MIXED = 1 };
+
+typedef struct {
+  int32_t dim;                 /* 2 (F1) or 3 (F2)                                           */
+  int32_t formulation;         /* 1 = first-order staggered, 2 = second-order nodal           */
+  int64_t n[3];                /* cells per axis; n[2] ignored in 2D; h = 1 / n[0]             */
+  double omega;                /* angular frequency > 0                                        */
+  const double *c;             /* wave speed > 0 (cell or node field); NULL -> c_const         */
+  double c_const;
+  const double *f_re, *f_im;   /* source amplitude (same layout as c); either may be NULL      */
+  const double *gS_re, *gS_im; /* absorbing-boundary data, concatenated faces; may be NULL     */
+  const uint8_t *sound_soft;   /* F2: 1 = homogeneous Dirichlet node; NULL = none               */
+  int32_t face_bc[6];          /* -x,+x,-y,+y,-z,+z: CMCG_ABSORBING or CMCG_NEUMANN            */
+  double courant;              /* sigma in (0, 1/sqrt(dim)); 0 -> 0.5                          */
+} cmcg_problem;
+
+typedef struct {
+  int32_t precision;           /* CMCG_FP64, or CMCG_FP32_MIXED: FP32 fields and stencil
+                                  arithmetic, FP64 iterate, residual, scalars and sums         */
+  double tol;                  /* stop when sqrt(<r,r>_E / <r0,r0>_E) <= tol (Step 5.8)        */
+  int32_t max_iter;            /* CG iteration cap (> 0)                                       */
+  int32_t device;              /* HIP device ordinal                                           */
+  void *hip_stream;            /* hipStream_t to run on, or NULL                                */
+  int32_t steps_per_launch;    /* leapfrog steps fused per kernel launch (temporal blocking);
+                                  0 = library default                                          */
+  int32_t riesz_max_iter;      /* F2: cap on the Riesz (elliptic) PCG iterations; 0 = default  */
+  double riesz_tol;            /* F2: relative tolerance of the Riesz solve; 0 = default       */
+} cmcg_options;
+
+typedef struct {
+  int32_t iterations;          /* CG iterations done                                           */
+  int32_t steps_per_period;    /* N                                                            */
+  double dt;
+  double rel_residual;         /* last sqrt(<r,r>_E / <r0,r0>_E)                               */
+  double seconds;              /* device time of the last cmcg_solve (HIP events), create excluded */
+  double seconds_fwd, seconds_adj, seconds_riesz, seconds_other;  /* phase split of iterations */
+  double grid_updates;         /* grid-point updates (cell- or node-steps) of the last solve   */
+  int64_t riesz_iterations;    /* F2: total inner PCG iterations                               */
+} cmcg_report;
+
+/* Create a solver for `problem`: validates it, sets T, N and dt, allocates the device state and
+ * copies the inputs host -> device.  The caller may free its arrays afterwards.  On error *out
+ * is NULL. */
+cmcg_status cmcg_create(const cmcg_problem *problem, const cmcg_options *opts, cmcg_handle **out);
+
+/* Full CMCG solve from z = 0 (Steps 1-6) followed by the fundamental-frequency filter
+ * (eq. fundamental-frequency-solution for F2, eq. TH_FILTERED_MIXED_SOLUTION for F1).
+ * u_re, u_im: caller-allocated, host or device, same layout as c (either may be NULL to skip
+ * the copy).  May be called repeatedly.  Returns CMCG_ENOTCONV when max_iter is reached. */
+cmcg_status cmcg_solve(cmcg_handle *h, double *u_re, double *u_im, cmcg_report *rep);
+
+/* NULL-safe. */
+void cmcg_destroy(cmcg_handle *h);
+
+const char *cmcg_status_string(cmcg_status s);
+/* Message of the last failure on this thread ("" if none). */
+const char *cmcg_last_error(void);
+
+/* ---- stage-level calls (same kernels as cmcg_solve; used by tests and benchmarks) ---- */
+
+typedef struct {
+  int32_t steps_per_period;
+  double dt, T, h;
+  int64_t state_len;           /* length of a packed state vector                             */
+  int64_t field_len;           /* length of the output field u                                */
+  int64_t device_bytes;        /* device memory held by the handle                            */
+} cmcg_info;
+
+cmcg_status cmcg_get_info(const cmcg_handle *h, cmcg_info *info);
+
+enum {
+  CMCG_OP_FORWARD = 0,         /* E z: homogeneous leapfrog from t = 0                         */
+  CMCG_OP_FORCED = 1,          /* Phi(z) = E z + s: forced leapfrog from t = 0                  */
+  CMCG_OP_ADJOINT = 2,         /* E* y = M_E^{-1} E^T M_E y: the backward (adjoint) period, the
+                                  exact transpose of the discrete forward period in the energy
+                                  inner product (eq. AWE / eq. mixJ_deriative_2, discrete)      */
+  CMCG_OP_RIESZ = 3            /* F2: P y = blockdiag(S^{-1}, M^{-1}) y (eq. CMCG_PRECONDITIONIER);
+                                  F1: M_E^{-1} y                                               */
+};
+
+/* out = op(in) over `steps` leapfrog steps (0 = one full period N; F1 only for steps != 0).
+ * in, out: packed FP64 device vectors of length state_len; the work runs in the handle's
+ * precision (FP32-mixed rounds `in` to FP32).  in and out may alias. */
+cmcg_status cmcg_apply(cmcg_handle *h, int32_t op, int32_t steps, const double *in, double *out);
+
+/* Filter output from an explicit initial state z (packed FP64 device vector): one forced period
+ * from z with the accumulation of eq. fundamental-frequency-solution / eq.
+ * TH_FILTERED_MIXED_SOLUTION.  u_re, u_im: host or device, layout of c. */
+cmcg_status cmcg_filter(cmcg_handle *h, const double *z, double *u_re, double *u_im);
+
+/* The solve split in three: cmcg_begin (z = 0, Steps 1-4), cmcg_iterate (up to `iters` CG
+ * iterations of Step 5; stops early at tol), cmcg_finish (filter + copy out).  cmcg_solve is
+ * begin + iterate(max_iter) + finish.  *converged is set to 1 once tol is met. */
+cmcg_status cmcg_begin(cmcg_handle *h);
+cmcg_status cmcg_iterate(cmcg_handle *h, int32_t iters, int32_t *converged, cmcg_report *rep);
+cmcg_status cmcg_finish(cmcg_handle *h, double *u_re, double *u_im, cmcg_report *rep);
+
+/* Copy the current CG iterate z (which = 0), residual r (1) or direction d (2) into a packed
+ * FP64 device vector. */
+cmcg_status cmcg_get_state(cmcg_handle *h, int32_t which, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMCG_H */

@@ -1,0 +1,276 @@
+"""Python binding of libcmcg (include/cmcg.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module converts NumPy inputs to the C
+structs, passes torch device pointers and the current torch stream, and converts outputs back.
+If the built library is missing, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmcg.so")
+
+# torch is loaded first so that libcmcg binds (by SONAME) to the HIP runtime torch already
+# mapped: one HIP/HSA runtime per process, shared device memory and streams.
+import torch  # noqa: E402,F401
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1903_12522_amd.build` "
+                      "or __graft_entry__.build() first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, ENOTCONV, EINVAL, ECFL, ENOMEM, EDEVICE, EBREAKDOWN, EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5, -6
+FP64, FP32_MIXED = 0, 1
+OP_FORWARD, OP_FORCED, OP_ADJOINT, OP_RIESZ = 0, 1, 2, 3
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("formulation", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("omega", ctypes.c_double),
+                ("c", _dp), ("c_const", ctypes.c_double),
+                ("f_re", _dp), ("f_im", _dp), ("gS_re", _dp), ("gS_im", _dp),
+                ("sound_soft", ctypes.POINTER(ctypes.c_uint8)),
+                ("face_bc", ctypes.c_int32 * 6), ("courant", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("hip_stream", ctypes.c_void_p), ("steps_per_launch", ctypes.c_int32),
+                ("riesz_max_iter", ctypes.c_int32), ("riesz_tol", ctypes.c_double)]
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("steps_per_period", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("seconds_fwd", ctypes.c_double),
+                ("seconds_adj", ctypes.c_double), ("seconds_riesz", ctypes.c_double),
+                ("seconds_other", ctypes.c_double), ("grid_updates", ctypes.c_double),
+                ("riesz_iterations", ctypes.c_int64)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("steps_per_period", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("T", ctypes.c_double), ("h", ctypes.c_double), ("state_len", ctypes.c_int64),
+                ("field_len", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+_H = ctypes.c_void_p
+_sig = {
+    "cmcg_create": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
+                                   ctypes.POINTER(_H)]),
+    "cmcg_solve": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Report)]),
+    "cmcg_destroy": (None, [_H]),
+    "cmcg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "cmcg_last_error": (ctypes.c_char_p, []),
+    "cmcg_get_info": (ctypes.c_int, [_H, ctypes.POINTER(_Info)]),
+    "cmcg_apply": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
+    "cmcg_filter": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cmcg_begin": (ctypes.c_int, [_H]),
+    "cmcg_iterate": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(_Report)]),
+    "cmcg_finish": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Report)]),
+    "cmcg_get_state": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_void_p]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_sig.keys())
+
+
+class CMCGError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.cmcg_status_string(status).decode()
+        detail = _lib.cmcg_last_error().decode()
+        super().__init__(f"{where}: {msg} (status {status}){': ' + detail if detail else ''}")
+
+
+def _check(st: int, where: str, allow_notconv: bool = False) -> int:
+    if st == OK or (allow_notconv and st == ENOTCONV):
+        return st
+    raise CMCGError(st, where)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+def _report_dict(r: _Report) -> dict:
+    return {k: getattr(r, k) for k, _ in _Report._fields_}
+
+
+def _concat_faces(parts, dtype) -> np.ndarray:
+    return np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=dtype).ravel() for p in parts]))
+
+
+class Solver:
+    """One CMCG problem on the GPU.  `problem` is a cmcg_inputs.Problem."""
+
+    def __init__(self, problem, precision: str = "fp64", tol: float = 1e-6, max_iter: int = 1000,
+                 device: int = 0, steps_per_launch: int = 0, stream=None,
+                 riesz_tol: float = 0.0, riesz_max_iter: int = 0):
+        import torch  # device memory and streams
+        self._torch = torch
+        self.problem = problem
+        p = _Problem()
+        p.dim = problem.dim
+        p.formulation = problem.formulation
+        for k in range(3):
+            p.n[k] = int(problem.n[k]) if k < len(problem.n) else 1
+        p.omega = float(problem.omega)
+        keep = []
+
+        def arr(x, dtype=np.float64):
+            a = np.ascontiguousarray(np.asarray(x, dtype=dtype).ravel())
+            keep.append(a)
+            return a
+
+        if problem.c is not None:
+            p.c = _ptr(arr(problem.c))
+        p.c_const = float(problem.c_const)
+        if problem.f is not None:
+            f = np.asarray(problem.f)
+            p.f_re = _ptr(arr(f.real))
+            if np.iscomplexobj(f) and np.any(f.imag != 0):
+                p.f_im = _ptr(arr(f.imag))
+        if problem.gS is not None:
+            g = _concat_faces(problem.gS, np.complex128)
+            p.gS_re = _ptr(arr(g.real))
+            if np.any(g.imag != 0):
+                p.gS_im = _ptr(arr(g.imag))
+        if problem.sound_soft is not None:
+            m = arr(problem.sound_soft, np.uint8)
+            p.sound_soft = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        bc = list(problem.face_bc) + [1] * 6
+        for k in range(6):
+            p.face_bc[k] = int(bc[k])
+        p.courant = float(problem.courant)
+        o = _Options()
+        o.precision = FP64 if precision == "fp64" else FP32_MIXED
+        o.tol = float(tol)
+        o.max_iter = int(max_iter)
+        o.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        o.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+        o.steps_per_launch = int(steps_per_launch)
+        o.riesz_tol = float(riesz_tol)
+        o.riesz_max_iter = int(riesz_max_iter)
+        h = _H()
+        _check(_lib.cmcg_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)), "cmcg_create")
+        self._h = h
+        self.precision = precision
+        info = _Info()
+        _check(_lib.cmcg_get_info(h, ctypes.byref(info)), "cmcg_get_info")
+        self.info = {k: getattr(info, k) for k, _ in _Info._fields_}
+        self.field_shape = problem.field_shape()
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cmcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------ solve
+    def solve(self, device_output: bool = False) -> Tuple[object, dict]:
+        """Full CMCG solve; returns (u, report).  u is a complex NumPy array of the field shape,
+        or a pair of torch FP64 device tensors (re, im) if device_output."""
+        rep = _Report()
+        ure, uim, keep = self._out_buffers(device_output)
+        st = _check(_lib.cmcg_solve(self._h, ure, uim, ctypes.byref(rep)), "cmcg_solve",
+                    allow_notconv=True)
+        d = _report_dict(rep)
+        d["converged"] = st == OK
+        return self._out_value(keep, device_output), d
+
+    def begin(self):
+        _check(_lib.cmcg_begin(self._h), "cmcg_begin")
+
+    def iterate(self, iters: int) -> Tuple[bool, dict]:
+        conv = ctypes.c_int32(0)
+        rep = _Report()
+        _check(_lib.cmcg_iterate(self._h, int(iters), ctypes.byref(conv), ctypes.byref(rep)),
+               "cmcg_iterate")
+        return bool(conv.value), _report_dict(rep)
+
+    def finish(self, device_output: bool = False):
+        rep = _Report()
+        ure, uim, keep = self._out_buffers(device_output)
+        _check(_lib.cmcg_finish(self._h, ure, uim, ctypes.byref(rep)), "cmcg_finish")
+        return self._out_value(keep, device_output), _report_dict(rep)
+
+    # ------------------------------------------------------------------ stage calls
+    def apply(self, op: int, z, steps: int = 0):
+        """op(z) on a packed FP64 state; z may be a NumPy array or a torch device tensor.
+        Returns the same kind."""
+        torch = self._torch
+        as_np = isinstance(z, np.ndarray)
+        zin = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64)).cuda() if as_np else z
+        assert zin.dtype == torch.float64 and zin.is_cuda and zin.numel() == self.info["state_len"]
+        zin = zin.contiguous()
+        out = torch.empty_like(zin)
+        _check(_lib.cmcg_apply(self._h, int(op), int(steps), ctypes.c_void_p(zin.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr())), "cmcg_apply")
+        return out.cpu().numpy() if as_np else out
+
+    def filter(self, z) -> np.ndarray:
+        torch = self._torch
+        zin = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64)).cuda() \
+            if isinstance(z, np.ndarray) else z.contiguous()
+        ure, uim, keep = self._out_buffers(False)
+        _check(_lib.cmcg_filter(self._h, ctypes.c_void_p(zin.data_ptr()), ure, uim), "cmcg_filter")
+        return self._out_value(keep, False)
+
+    def state(self, which: int = 0) -> np.ndarray:
+        torch = self._torch
+        out = torch.empty(self.info["state_len"], dtype=torch.float64, device="cuda")
+        _check(_lib.cmcg_get_state(self._h, int(which), ctypes.c_void_p(out.data_ptr())),
+               "cmcg_get_state")
+        return out.cpu().numpy()
+
+    # ------------------------------------------------------------------ helpers
+    def _out_buffers(self, device_output: bool):
+        if device_output:
+            torch = self._torch
+            re = torch.empty(self.field_shape, dtype=torch.float64, device="cuda")
+            im = torch.empty_like(re)
+            return ctypes.c_void_p(re.data_ptr()), ctypes.c_void_p(im.data_ptr()), (re, im)
+        re = np.empty(self.field_shape, dtype=np.float64)
+        im = np.empty_like(re)
+        return re.ctypes.data_as(ctypes.c_void_p), im.ctypes.data_as(ctypes.c_void_p), (re, im)
+
+    @staticmethod
+    def _out_value(keep, device_output: bool):
+        if device_output:
+            return keep
+        return keep[0] + 1j * keep[1]
+
+
+def status_string(st: int) -> str:
+    return _lib.cmcg_status_string(st).decode()

@@ -1,0 +1,99 @@
+"""CPU-side checks of the C ABI: the built library loads, exports every function that
+include/cmcg.h declares, and rejects invalid problems in host validation (no GPU touched:
+these return before any HIP call)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmcg.h")
+LIB = os.path.join(ROOT, "paper_1903_12522_amd", "libcmcg.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmcg_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libcmcg.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "cmcg_create" in names and "cmcg_solve" in names and "cmcg_destroy" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_1903_12522_amd import cmcg
+    assert set(cmcg.EXPORTED) == set(_declared())
+
+
+def _problem(cm, **kw):
+    p = cm._Problem()
+    p.dim, p.formulation = kw.get("dim", 2), kw.get("formulation", 1)
+    for k, v in enumerate(kw.get("n", (16, 16, 1))):
+        p.n[k] = v
+    p.omega = kw.get("omega", 2 * math.pi)
+    p.c_const = kw.get("c_const", 1.0)
+    p.courant = kw.get("courant", 0.5)
+    for k in range(6):
+        p.face_bc[k] = kw.get("bc", 0)
+    return p
+
+
+def _create(cm, p, **ok):
+    o = cm._Options()
+    o.precision = ok.get("precision", 0)
+    o.tol = ok.get("tol", 1e-6)
+    o.max_iter = ok.get("max_iter", 10)
+    h = cm._H()
+    st = cm._lib.cmcg_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw,opt,expect", [
+    (dict(courant=0.72), {}, -2),                       # sigma sqrt(2) >= 1: unstable leapfrog
+    (dict(dim=3, formulation=2, n=(8, 8, 8), courant=0.58), {}, -2),
+    (dict(omega=0.0), {}, -1),
+    (dict(omega=float("nan")), {}, -1),
+    (dict(c_const=-1.0), {}, -1),
+    (dict(n=(1, 16, 1)), {}, -1),
+    (dict(bc=7), {}, -1),
+    (dict(), dict(precision=5), -1),
+    (dict(), dict(max_iter=0), -1),
+    (dict(dim=3, formulation=1, n=(8, 8, 8)), {}, -6),   # first-order 3D is not provided
+])
+def test_invalid_inputs_rejected_before_device(kw, opt, expect):
+    from paper_1903_12522_amd import cmcg as cm
+    st, h = _create(cm, _problem(cm, **kw), **opt)
+    assert st == expect
+    assert not h.value
+    assert cm._lib.cmcg_last_error().decode() != ""
+
+
+def test_nan_wave_speed_rejected():
+    from paper_1903_12522_amd import cmcg as cm
+    p = _problem(cm)
+    c = np.ones(16 * 16)
+    c[37] = np.nan
+    p.c = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st, h = _create(cm, p)
+    assert st == -1 and not h.value
+
+
+def test_status_strings():
+    from paper_1903_12522_amd import cmcg as cm
+    for s in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert cm.status_string(s)
+    cm._lib.cmcg_destroy(None)      # NULL-safe
