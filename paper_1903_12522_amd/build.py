@@ -14,6 +14,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every multiply-add the kernels want is written as fma(); nothing else is contracted, so
+    # a cell's arithmetic does not depend on how a kernel variant was unrolled
+    "-ffp-contract=off",
     "-Wno-unused-result",
 ]
 

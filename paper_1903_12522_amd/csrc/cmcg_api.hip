@@ -500,7 +500,7 @@ cmcg_status cmcg_create(const cmcg_problem *P, const cmcg_options *O, cmcg_handl
   H->max_iter = O->max_iter;
   H->device = O->device;
   int kb = O->steps_per_launch > 0 ? O->steps_per_launch : 4;
-  if (kb != 1 && kb != 2 && kb != 4 && kb != 8) return set_error("steps_per_launch must be 1, 2, 4 or 8"), CMCG_EINVAL;
+  if (kb < 1 || kb > kMaxBlockSteps) return set_error("steps_per_launch must be in 1..8"), CMCG_EINVAL;
   H->kblock = kb;
   CMCG_HIP(hipSetDevice(H->device));
   if (O->hip_stream) {

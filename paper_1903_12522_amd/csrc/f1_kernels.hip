@@ -14,27 +14,25 @@
 //   v <- v - dt/2 c^2 D p;   p <- p - dt G (v / (1+gamma)),  v <- a v;   v <- v - dt/2 c^2 D p
 // with a = (1-gamma)/(1+gamma); its half kicks of v merge the same way.
 //
-// Kernel design: a block owns a 64 x TY output tile and stages the tile plus a halo of
-// KMAX+1 cells of every field in LDS; it runs up to KMAX leapfrog steps there (temporal
-// blocking: one HBM read and one write of the state per KMAX steps) and writes back only the
-// tile, whose values are exact because each step widens the dependency cone by one cell.
-// Rows are read and written with 64 consecutive lanes on consecutive x (coalesced).
+// Kernel design (register streaming with temporal blocking).  Each 64-lane wavefront owns a
+// strip of 64 consecutive columns (one column per lane, so every row access is one coalesced
+// 256/512-byte segment) and marches upward through a band of rows.  The K leapfrog steps of a
+// launch are K pipeline levels held in registers: at row iteration j, level k advances row
+// j - k from level k-1, so one HBM read and one HBM write of the state serve K steps.  Left and
+// right neighbours come from the adjacent lanes (cross-lane shuffles), the row below from the
+// previous iteration's registers; each level narrows the valid lanes by one on each side, so a
+// wave writes 64 - 2(K+1) columns, and each band starts K+2 rows early to fill the pipeline.
+// There is no LDS and no barrier.  The period's opening half kick is folded into level 0.
 #include "cmcg_internal.h"
 
 namespace cmcg {
 namespace {
 
-constexpr int kTX = 64;
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;   // 4 wavefronts per workgroup, each an independent strip
 
-__device__ __forceinline__ int absorbing_faces(const F1Geom &g, int i, int j) {
-  return (i == 0 ? g.abs_face[0] : 0) + (i == g.nx - 1 ? g.abs_face[1] : 0) +
-         (j == 0 ? g.abs_face[2] : 0) + (j == g.ny - 1 ? g.abs_face[3] : 0);
-}
-
-// XCD-aware tile order: hardware dispatches consecutive workgroups round-robin over the 8
-// XCDs; remap so that each XCD walks a contiguous band of tiles (neighbouring tiles share halo
-// rows in that XCD's L2).
+// XCD-aware workgroup order: consecutive workgroup ids are dispatched round-robin over the 8
+// XCDs; remap so each XCD walks a contiguous band of (column group, row band) tiles, whose
+// overlapping halo rows and columns then meet in that XCD's L2.
 __device__ __forceinline__ void tile_of_block(int &bx, int &by) {
   const int nbx = gridDim.x, nby = gridDim.y;
   const int nb = nbx * nby;
@@ -45,242 +43,215 @@ __device__ __forceinline__ void tile_of_block(int &bx, int &by) {
   by = t / nbx;
 }
 
-template <typename T, int KMAX, int TY>
-__global__ __launch_bounds__(kThreads) void f1_forward_kernel(F1Geom g, F1Ptrs<T> p, F1Launch L) {
-  constexpr int H = KMAX + 1;
-  constexpr int LX = kTX + 2 * H;
-  constexpr int LY = TY + 2 * H;
-  __shared__ T sPx[LY][LX];
-  __shared__ T sPy[LY][LX];
-  __shared__ T sv[LY][LX];
-  __shared__ T scc[LY][LX];
+template <typename T>
+__device__ __forceinline__ T lane_from_left(T x) { return __shfl_up(x, 1, 64); }
+template <typename T>
+__device__ __forceinline__ T lane_from_right(T x) { return __shfl_down(x, 1, 64); }
+
+template <typename T, int K, bool ADJ>
+__global__ __launch_bounds__(kThreads) void f1_stream_kernel(F1Geom g, F1Ptrs<T> p, F1Launch L,
+                                                             int band) {
+  constexpr int H = K + 1;             // lanes lost on each side: K levels + the opening kick
+  constexpr int OW = 64 - 2 * H;       // columns written per wavefront
+  const int lane = threadIdx.x & 63;
   int bx, by;
   tile_of_block(bx, by);
-  const int i0 = bx * kTX - H;
-  const int j0 = by * TY - H;
-  const int tid = threadIdx.x;
-  const T dt = (T)g.dt;
-  const T inv_h = (T)(1.0 / g.h);
-  const T half_inv_h = (T)(0.5 / g.h);
-  const size_t fs = p.fs;
+  const int strip = bx * (kThreads / 64) + (threadIdx.x >> 6);
+  if (strip * OW >= g.nx) return;      // wave-uniform
+  const int i = strip * OW - H + lane;
+  const int nx = g.nx, ny = g.ny;
+  const size_t pitch = (size_t)g.pitch, fs = p.fs;
+  const int s0 = by * band;
+  const int s1 = min(s0 + band, ny);
+  const T dt = (T)g.dt, hk = T(0.5) * (T)g.dt;
+  const T inv_h = (T)(1.0 / g.h), half_inv_h = (T)(0.5 / g.h);
+  const bool colIn = (i >= 0) && (i < nx);
+  const bool pxCol = (i >= 0) && (i <= nx - 2);
+  const int mx = (i == 0 ? g.abs_face[0] : 0) + (i == nx - 1 ? g.abs_face[1] : 0);
+  const bool laneOut = colIn && lane >= H && lane < 64 - H;
 
-  for (int idx = tid; idx < LX * LY; idx += kThreads) {
-    const int ly = idx / LX, lx = idx - (idx / LX) * LX;
-    const int i = i0 + lx, j = j0 + ly;
-    const bool in = (i >= 0) && (i < g.nx) && (j >= 0) && (j < g.ny);
-    const size_t o = (size_t)j * g.pitch + i;
-    sPx[ly][lx] = in ? p.in[o] : T(0);
-    sPy[ly][lx] = in ? p.in[o + fs] : T(0);
-    sv[ly][lx] = in ? p.in[o + 2 * fs] : T(0);
-    scc[ly][lx] = in ? p.cc[o] : T(0);
+  // per-level emissions of the previous (p) and current (c) row iteration:
+  // level k emits v^k(r), Px^k(r) and Py^k(r-1) with r = j - k; CC is c^2 of row r.
+  T Vp[K + 1], PXp[K + 1], PYp[K + 1], CCp[K + 1];
+  T Vc[K + 1], PXc[K + 1], PYc[K + 1], CCc[K + 1];
+  T HOLD[K + 1];   // level 0: raw Py of the current row; adjoint level k: Py^k(r) one row ahead
+#pragma unroll
+  for (int k = 0; k <= K; ++k) {
+    Vp[k] = PXp[k] = PYp[k] = CCp[k] = T(0);
+    Vc[k] = PXc[k] = PYc[k] = CCc[k] = T(0);
+    HOLD[k] = T(0);
   }
-  __syncthreads();
+  const int jstart = s0 - K - 2, jend = s1 + K;
+  if (colIn && jstart - 1 >= 0 && jstart - 1 < ny) HOLD[0] = p.in[(size_t)(jstart - 1) * pitch + i + fs];
 
-  if (L.accumulate) {
-    // filter sum: (Ure, Uim) += v^n (cos, sin)(omega t_n) on the tile
-    for (int idx = tid; idx < kTX * TY; idx += kThreads) {
-      const int ly = H + idx / kTX, lx = H + idx % kTX;
-      const int i = i0 + lx, j = j0 + ly;
-      if (i < g.nx && j < g.ny) {
-        const size_t o = (size_t)j * g.pitch + i;
-        const double v = (double)sv[ly][lx];
-        p.ure[o] += v * L.fcos;
-        p.uim[o] += v * L.fsin;
-      }
+  for (int j = jstart; j <= jend; ++j) {
+    // ---- level 0: load row j
+    const bool in0 = colIn && j >= 0 && j < ny;
+    const size_t o0 = (size_t)(in0 ? j : 0) * pitch + (colIn ? i : 0);
+    T v0 = in0 ? p.in[o0 + 2 * fs] : T(0);
+    T px0 = in0 ? p.in[o0] : T(0);
+    const T py0 = in0 ? p.in[o0 + fs] : T(0);
+    const T c0 = in0 ? p.cc[o0] : T(0);
+    if (L.accumulate && laneOut && j >= s0 && j < s1) {
+      const double vv = (double)v0;
+      p.ure[o0] += vv * L.fcos;
+      p.uim[o0] += vv * L.fsin;
     }
-  }
-
-  if (L.first) {
-    // opening half kick  p <- p + dt/2 G v
-    const T k = T(0.5) * dt;
-    for (int idx = tid; idx < LX * LY; idx += kThreads) {
-      const int ly = idx / LX, lx = idx - (idx / LX) * LX;
-      const int i = i0 + lx, j = j0 + ly;
-      if (i < 0 || j < 0 || j >= g.ny || i >= g.nx) continue;
-      if (i <= g.nx - 2 && lx <= LX - 2) sPx[ly][lx] += k * ((sv[ly][lx + 1] - sv[ly][lx]) * inv_h);
-      if (j <= g.ny - 2 && ly <= LY - 2) sPy[ly][lx] += k * ((sv[ly + 1][lx] - sv[ly][lx]) * inv_h);
-    }
-    __syncthreads();
-  }
-
-  for (int s = 0; s < L.nsteps; ++s) {
-    const T cs = (T)L.cs[s], sn = (T)L.sn[s];
-    // velocity update  (1+gamma) v' = (1-gamma) v + dt c^2 (D p + F)
-    for (int idx = tid; idx < LX * LY; idx += kThreads) {
-      const int ly = idx / LX, lx = idx - (idx / LX) * LX;
-      const int i = i0 + lx, j = j0 + ly;
-      if (lx < 1 || ly < 1 || i < 0 || j < 0 || i >= g.nx || j >= g.ny) continue;
-      T div = (sPx[ly][lx] - sPx[ly][lx - 1] + sPy[ly][lx] - sPy[ly - 1][lx]) * inv_h;
-      if (L.forced) {
-        const size_t o = (size_t)j * g.pitch + i;
-        div += p.fre[o] * cs;
-        if (p.fim) div += p.fim[o] * sn;
-      }
-      const T c2 = scc[ly][lx];
-      const int m = absorbing_faces(g, i, j);
-      T v = sv[ly][lx];
-      if (m == 0) {
-        v = v + dt * c2 * div;
+    T pyprev = HOLD[0];   // raw Py(j-1)
+    HOLD[0] = py0;
+    if (L.first) {
+      if (!ADJ) {
+        // opening half kick  p <- p + dt/2 G v  (Px of row j, Py of row j-1)
+        const T vr = lane_from_right(v0);
+        if (in0 && pxCol) px0 = fma(hk, (vr - v0) * inv_h, px0);
+        if (colIn && j - 1 >= 0 && j - 1 <= ny - 2) pyprev = fma(hk, (v0 - Vp[0]) * inv_h, pyprev);
       } else {
-        const T gam = dt * (T)m * sqrt(c2) * half_inv_h;
-        v = ((T(1) - gam) * v + dt * c2 * div) / (T(1) + gam);
+        // opening half kick  v <- v - dt/2 c^2 D p  (row j)
+        const T pl = lane_from_left(px0);
+        if (in0) v0 = fma(-hk * c0, ((px0 - pl) + (py0 - pyprev)) * inv_h, v0);
       }
-      sv[ly][lx] = v;
     }
-    __syncthreads();
-    // flux kick  p <- p + kick G v'
-    const T k = (L.last && s == L.nsteps - 1) ? T(0.5) * dt : dt;
-    for (int idx = tid; idx < LX * LY; idx += kThreads) {
-      const int ly = idx / LX, lx = idx - (idx / LX) * LX;
-      const int i = i0 + lx, j = j0 + ly;
-      if (i < 0 || j < 0 || j >= g.ny || i >= g.nx) continue;
-      if (i <= g.nx - 2 && lx <= LX - 2) sPx[ly][lx] += k * ((sv[ly][lx + 1] - sv[ly][lx]) * inv_h);
-      if (j <= g.ny - 2 && ly <= LY - 2) sPy[ly][lx] += k * ((sv[ly + 1][lx] - sv[ly][lx]) * inv_h);
-    }
-    __syncthreads();
-  }
+    Vc[0] = v0;
+    PXc[0] = px0;
+    PYc[0] = pyprev;
+    CCc[0] = c0;
 
-  for (int idx = tid; idx < kTX * TY; idx += kThreads) {
-    const int ly = H + idx / kTX, lx = H + idx % kTX;
-    const int i = i0 + lx, j = j0 + ly;
-    if (i >= g.nx || j >= g.ny) continue;
-    const size_t o = (size_t)j * g.pitch + i;
-    T a = sPx[ly][lx], b = sPy[ly][lx], c = sv[ly][lx];
-    if (p.sub) {
-      a -= p.sub[o];
-      b -= p.sub[o + fs];
-      c -= p.sub[o + 2 * fs];
+    // ---- levels 1..K
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+      const int r = j - k;
+      const bool rIn = (r >= 0) && (r < ny);
+      const bool cin = rIn && colIn;
+      const T kick = (L.last && k == K) ? hk : dt;
+      if (!ADJ) {
+        const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
+        const T c2 = CCp[k - 1];
+        const T pl = lane_from_left(px);
+        T div = ((px - pl) + (pyr - pyrm1)) * inv_h;
+        if (L.forced && cin) {
+          const size_t o = (size_t)r * pitch + i;
+          div = fma(p.fre[o], (T)L.cs[k - 1], div);
+          if (p.fim) div = fma(p.fim[o], (T)L.sn[k - 1], div);
+        }
+        const int m = mx + (r == 0 ? g.abs_face[2] : 0) + (r == ny - 1 ? g.abs_face[3] : 0);
+        T vn = T(0);
+        if (cin) {
+          if (m == 0) {
+            vn = fma(dt * c2, div, v);
+          } else {
+            const T gam = dt * (T)m * sqrt(c2) * half_inv_h;
+            vn = fma(dt * c2, div, (T(1) - gam) * v) / (T(1) + gam);
+          }
+        }
+        const T vr = lane_from_right(vn);
+        const T pxn = (cin && pxCol) ? fma(kick, (vr - vn) * inv_h, px) : px;
+        const bool pyv = colIn && (r - 1 >= 0) && (r - 1 <= ny - 2);
+        const T pyn = pyv ? fma(kick, (vn - Vp[k]) * inv_h, pyrm1) : pyrm1;
+        Vc[k] = vn;
+        PXc[k] = pxn;
+        PYc[k] = pyn;
+        CCc[k] = c2;
+      } else {
+        // inputs: v^{k-1}(r+1) (current), v^{k-1}(r), Px^{k-1}(r) (previous), Py^{k-1}(r)
+        const T vA = Vc[k - 1], vB = Vp[k - 1], pxB = PXp[k - 1], pyB = PYc[k - 1];
+        const T c2A = CCc[k - 1], c2B = CCp[k - 1];
+        const int rA = r + 1;
+        const int mA = (colIn && rA >= 0 && rA < ny)
+                           ? mx + (rA == 0 ? g.abs_face[2] : 0) + (rA == ny - 1 ? g.abs_face[3] : 0)
+                           : 0;
+        const int mB = cin ? mx + (r == 0 ? g.abs_face[2] : 0) + (r == ny - 1 ? g.abs_face[3] : 0) : 0;
+        const T gA = mA ? dt * (T)mA * sqrt(c2A) * half_inv_h : T(0);
+        const T gB = mB ? dt * (T)mB * sqrt(c2B) * half_inv_h : T(0);
+        const T wA = mA ? vA / (T(1) + gA) : vA;
+        const T wB = mB ? vB / (T(1) + gB) : vB;
+        const T wBr = lane_from_right(wB);
+        // p <- p - dt G w
+        const T pxn = (cin && pxCol) ? fma(-dt, (wBr - wB) * inv_h, pxB) : pxB;
+        const bool pyv = colIn && r >= 0 && r <= ny - 2;
+        const T pyn = pyv ? fma(-dt, (wA - wB) * inv_h, pyB) : pyB;   // Py^k(r)
+        // v <- a v - kick c^2 D p
+        const T pl = lane_from_left(pxn);
+        T vn = T(0);
+        if (cin) {
+          const T a = mB ? (T(1) - gB) / (T(1) + gB) : T(1);
+          vn = fma(-kick * c2B, ((pxn - pl) + (pyn - HOLD[k])) * inv_h, a * vB);
+        }
+        Vc[k] = vn;
+        PXc[k] = pxn;
+        PYc[k] = HOLD[k];
+        HOLD[k] = pyn;
+        CCc[k] = c2B;
+      }
     }
-    p.out[o] = a;
-    p.out[o + fs] = b;
-    p.out[o + 2 * fs] = c;
+
+    // ---- write level K: v, Px of row j-K and Py of row j-K-1
+    if (laneOut) {
+      const int ro = j - K;
+      if (ro >= s0 && ro < s1) {
+        const size_t o = (size_t)ro * pitch + i;
+        T a = PXc[K], c = Vc[K];
+        if (p.sub) {
+          a -= p.sub[o];
+          c -= p.sub[o + 2 * fs];
+        }
+        p.out[o] = a;
+        p.out[o + 2 * fs] = c;
+      }
+      if (ro - 1 >= s0 && ro - 1 < s1) {
+        const size_t o = (size_t)(ro - 1) * pitch + i;
+        T b = PYc[K];
+        if (p.sub) b -= p.sub[o + fs];
+        p.out[o + fs] = b;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+      Vp[k] = Vc[k];
+      PXp[k] = PXc[k];
+      PYp[k] = PYc[k];
+      CCp[k] = CCc[k];
+    }
   }
 }
 
-template <typename T, int KMAX, int TY>
-__global__ __launch_bounds__(kThreads) void f1_adjoint_kernel(F1Geom g, F1Ptrs<T> p, F1Launch L) {
-  constexpr int H = KMAX + 1;
-  constexpr int LX = kTX + 2 * H;
-  constexpr int LY = TY + 2 * H;
-  __shared__ T sPx[LY][LX];
-  __shared__ T sPy[LY][LX];
-  __shared__ T sv[LY][LX];
-  __shared__ T scc[LY][LX];
-  int bx, by;
-  tile_of_block(bx, by);
-  const int i0 = bx * kTX - H;
-  const int j0 = by * TY - H;
-  const int tid = threadIdx.x;
-  const T dt = (T)g.dt;
-  const T inv_h = (T)(1.0 / g.h);
-  const T half_inv_h = (T)(0.5 / g.h);
-  const size_t fs = p.fs;
-
-  for (int idx = tid; idx < LX * LY; idx += kThreads) {
-    const int ly = idx / LX, lx = idx - (idx / LX) * LX;
-    const int i = i0 + lx, j = j0 + ly;
-    const bool in = (i >= 0) && (i < g.nx) && (j >= 0) && (j < g.ny);
-    const size_t o = (size_t)j * g.pitch + i;
-    sPx[ly][lx] = in ? p.in[o] : T(0);
-    sPy[ly][lx] = in ? p.in[o + fs] : T(0);
-    sv[ly][lx] = in ? p.in[o + 2 * fs] : T(0);
-    scc[ly][lx] = in ? p.cc[o] : T(0);
-  }
-  __syncthreads();
-
-  if (L.first) {
-    // opening half kick  v <- v - dt/2 c^2 D p
-    const T k = T(0.5) * dt;
-    for (int idx = tid; idx < LX * LY; idx += kThreads) {
-      const int ly = idx / LX, lx = idx - (idx / LX) * LX;
-      const int i = i0 + lx, j = j0 + ly;
-      if (lx < 1 || ly < 1 || i < 0 || j < 0 || i >= g.nx || j >= g.ny) continue;
-      const T div = (sPx[ly][lx] - sPx[ly][lx - 1] + sPy[ly][lx] - sPy[ly - 1][lx]) * inv_h;
-      sv[ly][lx] -= k * scc[ly][lx] * div;
-    }
-    __syncthreads();
-  }
-
-  for (int s = 0; s < L.nsteps; ++s) {
-    // flux update  p <- p - dt G (v / (1+gamma))
-    for (int idx = tid; idx < LX * LY; idx += kThreads) {
-      const int ly = idx / LX, lx = idx - (idx / LX) * LX;
-      const int i = i0 + lx, j = j0 + ly;
-      if (i < 0 || j < 0 || j >= g.ny || i >= g.nx) continue;
-      const int m0 = absorbing_faces(g, i, j);
-      const T w0 = m0 ? sv[ly][lx] / (T(1) + dt * (T)m0 * sqrt(scc[ly][lx]) * half_inv_h) : sv[ly][lx];
-      if (i <= g.nx - 2 && lx <= LX - 2) {
-        const int m1 = absorbing_faces(g, i + 1, j);
-        const T w1 = m1 ? sv[ly][lx + 1] / (T(1) + dt * (T)m1 * sqrt(scc[ly][lx + 1]) * half_inv_h)
-                        : sv[ly][lx + 1];
-        sPx[ly][lx] -= dt * ((w1 - w0) * inv_h);
-      }
-      if (j <= g.ny - 2 && ly <= LY - 2) {
-        const int m1 = absorbing_faces(g, i, j + 1);
-        const T w1 = m1 ? sv[ly + 1][lx] / (T(1) + dt * (T)m1 * sqrt(scc[ly + 1][lx]) * half_inv_h)
-                        : sv[ly + 1][lx];
-        sPy[ly][lx] -= dt * ((w1 - w0) * inv_h);
-      }
-    }
-    __syncthreads();
-    // velocity update  v <- a v - kick c^2 D p
-    const T k = (L.last && s == L.nsteps - 1) ? T(0.5) * dt : dt;
-    for (int idx = tid; idx < LX * LY; idx += kThreads) {
-      const int ly = idx / LX, lx = idx - (idx / LX) * LX;
-      const int i = i0 + lx, j = j0 + ly;
-      if (lx < 1 || ly < 1 || i < 0 || j < 0 || i >= g.nx || j >= g.ny) continue;
-      const T div = (sPx[ly][lx] - sPx[ly][lx - 1] + sPy[ly][lx] - sPy[ly - 1][lx]) * inv_h;
-      const T c2 = scc[ly][lx];
-      const int m = absorbing_faces(g, i, j);
-      T v = sv[ly][lx];
-      if (m) {
-        const T gam = dt * (T)m * sqrt(c2) * half_inv_h;
-        v = (T(1) - gam) / (T(1) + gam) * v;
-      }
-      sv[ly][lx] = v - k * c2 * div;
-    }
-    __syncthreads();
-  }
-
-  for (int idx = tid; idx < kTX * TY; idx += kThreads) {
-    const int ly = H + idx / kTX, lx = H + idx % kTX;
-    const int i = i0 + lx, j = j0 + ly;
-    if (i >= g.nx || j >= g.ny) continue;
-    const size_t o = (size_t)j * g.pitch + i;
-    T a = sPx[ly][lx], b = sPy[ly][lx], c = sv[ly][lx];
-    if (p.sub) {
-      a -= p.sub[o];
-      b -= p.sub[o + fs];
-      c -= p.sub[o + 2 * fs];
-    }
-    p.out[o] = a;
-    p.out[o + fs] = b;
-    p.out[o + 2 * fs] = c;
-  }
+// Rows per band: enough wavefronts to fill 256 CUs several times over, long enough bands to
+// keep the pipeline fill (2K+3 rows) small.
+inline int band_rows(int nx, int ny, int K) {
+  const int ow = 64 - 2 * (K + 1);
+  const long strips = (nx + ow - 1) / ow;
+  int band = 256;
+  while (band > 16 && strips * ((ny + band - 1) / band) < 8192) band /= 2;
+  return band;
 }
 
-template <typename T, int KMAX, int TY, bool ADJ>
+template <typename T, int K, bool ADJ>
 hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hipStream_t s) {
-  dim3 grid((g.nx + kTX - 1) / kTX, (g.ny + TY - 1) / TY);
-  if (ADJ)
-    hipLaunchKernelGGL((f1_adjoint_kernel<T, KMAX, TY>), grid, dim3(kThreads), 0, s, g, p, L);
-  else
-    hipLaunchKernelGGL((f1_forward_kernel<T, KMAX, TY>), grid, dim3(kThreads), 0, s, g, p, L);
+  constexpr int OW = 64 - 2 * (K + 1);
+  const int strips = (g.nx + OW - 1) / OW;
+  const int band = band_rows(g.nx, g.ny, K);
+  dim3 grid((strips + 3) / 4, (g.ny + band - 1) / band);
+  hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ>), grid, dim3(kThreads), 0, s, g, p, L, band);
   return hipGetLastError();
 }
 
 template <typename T, bool ADJ>
 hipError_t launch_dispatch(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, int kmax,
                            hipStream_t s) {
-  switch (kmax) {
-    case 1: return launch_one<T, 1, 16, ADJ>(g, p, L, s);
-    case 2: return launch_one<T, 2, 16, ADJ>(g, p, L, s);
-    case 4: return launch_one<T, 4, 32, ADJ>(g, p, L, s);
-    case 8: return launch_one<T, 8, 32, ADJ>(g, p, L, s);
+  (void)kmax;
+  switch (L.nsteps) {
+    case 1: return launch_one<T, 1, ADJ>(g, p, L, s);
+    case 2: return launch_one<T, 2, ADJ>(g, p, L, s);
+    case 3: return launch_one<T, 3, ADJ>(g, p, L, s);
+    case 4: return launch_one<T, 4, ADJ>(g, p, L, s);
+    case 5: return launch_one<T, 5, ADJ>(g, p, L, s);
+    case 6: return launch_one<T, 6, ADJ>(g, p, L, s);
+    case 7: return launch_one<T, 7, ADJ>(g, p, L, s);
+    case 8: return launch_one<T, 8, ADJ>(g, p, L, s);
     default: return hipErrorInvalidValue;
   }
 }
 
+// ---------------------------------------------------------------------------------------
 // ---------------------------------------------------------------------------------------
 // CG vector kernels
 // ---------------------------------------------------------------------------------------
