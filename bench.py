@@ -1,0 +1,183 @@
+"""Benchmark of the CMCG hot path on one MI355X.
+
+Workload: the 4096^2 first-order random-medium problem (c a seeded Gaussian random field in
+[1, 2], omega = 2 pi 100, 8 seeded Gaussian sources, absorbing sides; N = 164 leapfrog steps per
+period).  A timed *step* is one CMCG iteration in FP32-mixed precision: a homogeneous forward
+period, the adjoint (backward) period, the energy inner products and the CG update, i.e.
+2 N x 4096^2 grid-point updates.  `value` is grid-point updates per second (GLUP/s) over the
+timed steps, inputs resident in HBM.
+
+Also reported: time-to-solution at relative residual 1e-6 in FP32-mixed and FP64 (full solves
+from z = 0 including the filter), their ratio and the FP32-mixed error against FP64, the
+roofline of the dominant kernel from the library's HIP events, and the CPU oracle timed on a
+bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-tts] [--no-cpu]
+       python bench.py --calibrate-copy   (one 1 GiB device copy, for counter calibration)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "leapfrog GLUP/s + CMCG time-to-solution at rel. residual 1e-6, FP32-mixed vs FP64"
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def calibrate_copy():
+    import torch
+    n = 1 << 27                      # 2^27 doubles = 1 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n * 8}))
+
+
+def cpu_baseline(prob, steps: int = 6):
+    """The oracle as it stands, on the full grid: `steps` forward leapfrog steps plus `steps`
+    transposed steps (the two halves of a CG iteration), timed on one host core."""
+    from oracle.f1 import F1
+    import numpy as np
+    o = F1(prob)
+    rng = np.random.default_rng(0)
+    z = rng.standard_normal(o.size)
+    t0 = time.perf_counter()
+    o.period(z, False, steps=steps)
+    o.period_T(z, steps=steps)
+    dt = time.perf_counter() - t0
+    cells = prob.n[0] * prob.n[1]
+    return {"value": round(2 * steps * cells / dt / 1e9, 4), "unit": "GLUP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} forward + {steps} transposed leapfrog steps of the NumPy FP64 oracle "
+                      f"on the full {prob.n[0]}x{prob.n[1]} grid ({dt:.1f} s; NumPy element-wise "
+                      f"kernels run on one thread)",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps-per-launch", type=int, default=0)
+    ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--n", type=int, default=4096)
+    args = ap.parse_args()
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return 0
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU slab decomposition is a design, not part of this build",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import cmcg_inputs as ci
+    from paper_1903_12522_amd import cmcg
+
+    torch.cuda.set_device(0)
+    log("building the 4096^2 random-medium workload")
+    prob = ci.random_medium_2d(n=args.n)
+    cells = prob.n[0] * prob.n[1]
+    spl = args.steps_per_launch
+
+    # ---------------------------------------------------------------- timed CG iterations
+    with cmcg.Solver(prob, "fp32", tol=0.0, max_iter=1 << 30, steps_per_launch=spl) as s:
+        N = s.info["steps_per_period"]
+        s.begin()
+        log(f"N = {N} steps per period; {args.warmup} warm-up iterations")
+        _, rep0 = s.iterate(args.warmup) if args.warmup > 0 else (None, None)
+        if rep0 is None:
+            _, rep0 = s.iterate(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s.iterate(1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, rep1 = s.iterate(0)
+        kb = spl if spl > 0 else 4
+        dev_bytes = s.info["device_bytes"]
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    glups = args.steps * 2 * N * cells / elapsed / 1e9
+    log(f"{args.steps} iterations in {elapsed:.3f} s: {ms_per_step:.2f} ms/iteration, {glups:.1f} GLUP/s")
+
+    # roofline of the dominant kernel: phase times from the library's HIP events on its stream
+    launches = math.ceil(N / kb)
+    fwd = (rep1["seconds_fwd"] - rep0["seconds_fwd"]) / args.steps / launches
+    adj = (rep1["seconds_adj"] - rep0["seconds_adj"]) / args.steps / launches
+    bytes_per_update = 28            # FP32: read Px, Py, v, c^2; write Px, Py, v
+    alg_bytes = bytes_per_update * cells * kb       # per launch: kb leapfrog steps of every cell
+    dom, dom_t, other_t = ("adjoint", adj, fwd) if adj >= fwd else ("forward", fwd, adj)
+    achieved = alg_bytes / dom_t / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 3), "traffic": None,
+                "kernel": f"f1_stream_kernel<float, {kb}, {'true' if dom == 'adjoint' else 'false'}>",
+                "avg_launch_us": round(dom_t * 1e6, 2),
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "other_direction_avg_launch_us": round(other_t * 1e6, 2)}
+
+    out = {"metric": METRIC, "value": round(glups, 2), "unit": "GLUP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"first-order random medium {prob.n[0]}x{prob.n[1]}, "
+                                  f"omega=2pi*100, 8 sources, FP32-mixed CG iteration",
+                      "cells": cells, "steps_per_period": N, "steps_per_launch": kb,
+                      "grid_updates_per_step": 2 * N * cells, "device_bytes": dev_bytes},
+           "roofline": roofline}
+
+    # ---------------------------------------------------------------- time to solution
+    if not args.no_tts:
+        res = {}
+        U = {}
+        for prec in ("fp32", "fp64"):
+            with cmcg.Solver(prob, prec, tol=1e-6, max_iter=5000, steps_per_launch=spl) as s:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                u, rep = s.solve(device_output=True)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                U[prec] = torch.complex(u[0], u[1])
+            res[prec] = {"seconds": round(rep["seconds"], 3), "wall_seconds": round(wall, 3),
+                         "iterations": rep["iterations"], "converged": rep["converged"],
+                         "rel_residual": rep["rel_residual"],
+                         "glups": round(rep["grid_updates"] / rep["seconds"] / 1e9, 2)}
+            log(f"TTS {prec}: {rep['seconds']:.3f} s, {rep['iterations']} iterations")
+        err = float(torch.linalg.vector_norm(U["fp32"] - U["fp64"]) / torch.linalg.vector_norm(U["fp64"]))
+        out["time_to_solution"] = {
+            "tol": 1e-6, "fp32_mixed": res["fp32"], "fp64": res["fp64"],
+            "fp64_over_fp32_mixed": round(res["fp64"]["seconds"] / res["fp32"]["seconds"], 3),
+            "fp32_mixed_rel_l2_vs_fp64": err}
+        del U
+
+    # ---------------------------------------------------------------- CPU oracle baseline
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -84,6 +84,10 @@ typedef struct {
                                   0 = library default                                          */
   int32_t riesz_max_iter;      /* F2: cap on the Riesz (elliptic) PCG iterations; 0 = default  */
   double riesz_tol;            /* F2: relative tolerance of the Riesz solve; 0 = default       */
+  double fp64_refresh;         /* FP32-mixed: recompute the true gradient with FP64 periods
+                                  whenever <r,r>_E has fallen by fp64_refresh^2 since the last
+                                  refresh, and before declaring convergence (reliable updates);
+                                  0 = default 0.1, < 0 = never                                  */
 } cmcg_options;
 
 typedef struct {
@@ -95,6 +99,7 @@ typedef struct {
   double seconds_fwd, seconds_adj, seconds_riesz, seconds_other;  /* phase split of iterations */
   double grid_updates;         /* grid-point updates (cell- or node-steps) of the last solve   */
   int64_t riesz_iterations;    /* F2: total inner PCG iterations                               */
+  int32_t fp64_refreshes;      /* FP32-mixed: number of FP64 true-gradient refreshes           */
 } cmcg_report;
 
 /* Create a solver for `problem`: validates it, sets T, N and dt, allocates the device state and

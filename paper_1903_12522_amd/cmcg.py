@@ -44,7 +44,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("hip_stream", ctypes.c_void_p), ("steps_per_launch", ctypes.c_int32),
-                ("riesz_max_iter", ctypes.c_int32), ("riesz_tol", ctypes.c_double)]
+                ("riesz_max_iter", ctypes.c_int32), ("riesz_tol", ctypes.c_double),
+                ("fp64_refresh", ctypes.c_double)]
 
 
 class _Report(ctypes.Structure):
@@ -53,7 +54,7 @@ class _Report(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("seconds_fwd", ctypes.c_double),
                 ("seconds_adj", ctypes.c_double), ("seconds_riesz", ctypes.c_double),
                 ("seconds_other", ctypes.c_double), ("grid_updates", ctypes.c_double),
-                ("riesz_iterations", ctypes.c_int64)]
+                ("riesz_iterations", ctypes.c_int64), ("fp64_refreshes", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -121,7 +122,7 @@ class Solver:
 
     def __init__(self, problem, precision: str = "fp64", tol: float = 1e-6, max_iter: int = 1000,
                  device: int = 0, steps_per_launch: int = 0, stream=None,
-                 riesz_tol: float = 0.0, riesz_max_iter: int = 0):
+                 riesz_tol: float = 0.0, riesz_max_iter: int = 0, fp64_refresh: float = 0.0):
         import torch  # device memory and streams
         self._torch = torch
         self.problem = problem
@@ -170,6 +171,7 @@ class Solver:
         o.steps_per_launch = int(steps_per_launch)
         o.riesz_tol = float(riesz_tol)
         o.riesz_max_iter = int(riesz_max_iter)
+        o.fp64_refresh = float(fp64_refresh)
         h = _H()
         _check(_lib.cmcg_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)), "cmcg_create")
         self._h = h

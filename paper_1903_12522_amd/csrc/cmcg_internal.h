@@ -56,7 +56,8 @@ enum FinalMode : int {
   kFinStart = 0,   // delta0 = delta = sum; rel = 1
   kFinAlpha = 1,   // qd = sum; alpha = delta / qd; breakdown if qd <= 0 or non-finite
   kFinBeta = 2,    // beta = sum / delta; delta = sum; rel = sqrt(sum / delta0)
-  kFinStore = 3    // scalars[slot] = sum
+  kFinStore = 3,   // scalars[slot] = sum
+  kFinRefresh = 4  // true residual replaced the recursive one: beta = sum / delta_before, delta = sum
 };
 
 // Launches a one-block kernel that sums `n` partials in order and applies `mode`.

@@ -346,6 +346,16 @@ __global__ __launch_bounds__(kRedThreads) void finalize_kernel(const double *par
       break;
     case kFinBeta: {
       const double d = sc[kDelta];
+      sc[kTmp] = d;
+      sc[kBeta] = d > 0.0 ? sum / d : 0.0;
+      sc[kDelta] = sum;
+      sc[kRel] = sc[kDelta0] > 0.0 ? sqrt(fmax(sum, 0.0) / sc[kDelta0]) : 0.0;
+      if (!isfinite(sum)) sc[kBreak] = 1.0;
+      break;
+    }
+    case kFinRefresh: {
+      // the recursive residual was replaced by the true one: beta and delta from it
+      const double d = sc[kTmp];
       sc[kBeta] = d > 0.0 ? sum / d : 0.0;
       sc[kDelta] = sum;
       sc[kRel] = sc[kDelta0] > 0.0 ? sqrt(fmax(sum, 0.0) / sc[kDelta0]) : 0.0;

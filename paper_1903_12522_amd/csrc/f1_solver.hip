@@ -1,0 +1,465 @@
+// First-order (staggered, 2D) solver runtime: memory plan, period loops, and the CG driver of the
+// CMCG Algorithm (Sec. 2.3, Steps 1-6, with the first-order gradient of eq. mixJ_deriative_2).
+//
+// Precision policy.  FP64 mode: every period in FP64.  FP32-mixed mode: the CG iterations' forward
+// and backward periods run in FP32 (state, coefficients and stencil arithmetic), while the iterate
+// z, the residual r, every inner product and every CG scalar stay FP64.  Because one period is a
+// long product of step matrices, an FP32 period has a rounding floor of about 1e-6 |d| that is not
+// small against (E - I) d for nearly periodic directions; CG on the FP32 operator alone stalls far
+// above 1e-6.  The mixed mode therefore uses reliable updates (residual replacement): whenever the
+// recursive residual has fallen by the refresh factor since the last refresh (and before declaring
+// convergence), the true gradient at the FP64 iterate is recomputed with one FP64 forward and one
+// FP64 backward period and replaces r; the search direction is kept.  The initial gradient and the
+// output filter period are FP64 as well.
+#include "solver.h"
+
+namespace cmcg {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// c^2 per cell and the forcing amplitude Fhat = f + (1/h) sum_abs gS of every cell (the boundary
+// data enters the velocity equation through the boundary flux p.n = gS - v/c).
+template <typename T>
+__global__ void f1_setup_kernel(F1Geom g, const double *c, double c_const, const double *fre,
+                                const double *fim, const double *gre, const double *gim, T *cc,
+                                T *Fre, T *Fim, size_t fs) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const int nx = g.nx, ny = g.ny;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
+    const int j = (int)(o / g.pitch), i = (int)(o % g.pitch);
+    if (i >= nx) {
+      cc[o] = T(1);
+      Fre[o] = T(0);
+      if (Fim) Fim[o] = T(0);
+      continue;
+    }
+    const size_t k = (size_t)j * nx + i;
+    const double cv = c ? c[k] : c_const;
+    cc[o] = (T)(cv * cv);
+    double ar = fre ? fre[k] : 0.0, ai = fim ? fim[k] : 0.0;
+    const double ih = 1.0 / g.h;
+    if (gre || gim) {
+      // faces: -x (ny values), +x (ny), -y (nx), +y (nx)
+      const size_t off[4] = {0, (size_t)ny, (size_t)2 * ny, (size_t)2 * ny + nx};
+      const bool on[4] = {i == 0, i == nx - 1, j == 0, j == ny - 1};
+      const int along[4] = {j, j, i, i};
+      for (int f = 0; f < 4; ++f) {
+        if (!on[f] || !g.abs_face[f]) continue;
+        if (gre) ar += gre[off[f] + along[f]] * ih;
+        if (gim) ai += gim[off[f] + along[f]] * ih;
+      }
+    }
+    Fre[o] = (T)ar;
+    if (Fim) Fim[o] = (T)ai;
+  }
+}
+
+// u = i V / omega with V = (2/N) (Ure + i Uim)  (eq. TH_FILTERED_MIXED_SOLUTION, discrete)
+__global__ void f1_output_kernel(const double *ure, const double *uim, double scale, double *out_re,
+                                 double *out_im, size_t fs) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
+    out_re[o] = -scale * uim[o];
+    out_im[o] = scale * ure[o];
+  }
+}
+
+// Riesz map of the first-order formulation, M_E^{-1} y (the control space is L^2)
+template <typename T>
+__global__ void f1_riesz_kernel(F1Geom g, T *y, const T *cc, size_t fs) {
+  const double ih2 = 1.0 / (g.h * g.h);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
+    y[o] = (T)((double)y[o] * ih2);
+    y[o + fs] = (T)((double)y[o + fs] * ih2);
+    y[o + 2 * fs] = (T)((double)y[o + 2 * fs] * ih2 * (double)cc[o]);
+  }
+}
+
+// One precision's working set: two ping-pong states, the period output w and the backward
+// output q, and the coefficient and forcing fields.
+struct F1Set {
+  int prec = CMCG_FP64;
+  void *S0 = nullptr, *S1 = nullptr, *W = nullptr, *Q = nullptr;
+  void *cc = nullptr, *Fre = nullptr, *Fim = nullptr;
+};
+
+template <typename T>
+T *tp(void *p) { return static_cast<T *>(p); }
+template <typename T>
+const T *tpc(const void *p) { return static_cast<const T *>(p); }
+
+class F1Solver final : public Solver {
+ public:
+  F1Geom g{};
+  size_t fs = 0, vecN = 0;
+  SolverConfig cfg;
+  hipStream_t s = nullptr;
+  DeviceArena arena;
+  PhaseEvents ev;
+  F1Set lo, hi;          // lo: precision of the CG periods; hi: FP64 (the same set in FP64 mode)
+  bool mixed = false;
+  void *D = nullptr;     // search direction, lo precision
+  double *Z = nullptr, *R = nullptr, *Ure = nullptr, *Uim = nullptr;
+  double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
+  bool started = false;
+  int iter = 0, refreshes = 0, last_refresh = 0;
+  double rel = 1.0, delta_at_refresh = 0.0;
+  double t_fwd = 0, t_adj = 0, t_other = 0, t_total = 0, updates = 0;
+
+  ~F1Solver() override {
+    if (s) (void)hipStreamSynchronize(s);
+    if (h_scalars) (void)hipHostFree(h_scalars);
+  }
+
+  size_t device_bytes() const override { return arena.bytes(); }
+
+  // ------------------------------------------------------------------ create
+  cmcg_status create(const cmcg_problem *P) {
+    const int nx = (int)P->n[0], ny = (int)P->n[1];
+    s = cfg.stream;
+    g.nx = nx;
+    g.ny = ny;
+    g.pitch = (nx + 63) / 64 * 64;
+    g.h = cfg.h;
+    g.dt = cfg.dt;
+    for (int f = 0; f < 4; ++f) g.abs_face[f] = P->face_bc[f] == CMCG_ABSORBING ? 1 : 0;
+    fs = (size_t)ny * g.pitch;
+    vecN = 3 * fs;
+    mixed = cfg.prec == CMCG_FP32_MIXED;
+    CMCG_TRY(ev.init(8));
+    CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
+    std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
+    const bool has_im = P->f_im || P->gS_im;
+    CMCG_TRY(alloc_set(hi, CMCG_FP64, has_im));
+    if (mixed) {
+      CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, has_im));
+    } else {
+      lo = hi;
+    }
+    CMCG_TRY(arena.alloc(vecN * (mixed ? sizeof(float) : sizeof(double)), &D, s));
+    CMCG_TRY(arena.alloc_n(vecN, &Z, s));
+    CMCG_TRY(arena.alloc_n(vecN, &R, s));
+    CMCG_TRY(arena.alloc_n(fs, &Ure, s));
+    CMCG_TRY(arena.alloc_n(fs, &Uim, s));
+    CMCG_TRY(arena.alloc_n(kRedBlocks, &partials, s));
+    CMCG_TRY(arena.alloc_n(kNumScalars, &scalars, s));
+    // host inputs -> temporary device copies -> setup kernels for each set
+    const size_t ncell = (size_t)nx * ny, nface = 2 * (size_t)ny + 2 * (size_t)nx;
+    DeviceArena tmp;
+    const double *src[5] = {P->c, P->f_re, P->f_im, P->gS_re, P->gS_im};
+    const size_t len[5] = {ncell, ncell, ncell, nface, nface};
+    double *dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 5; ++k) {
+      if (!src[k]) continue;
+      CMCG_TRY(tmp.alloc_n(len[k], &dev[k], s));
+      CMCG_HIP(hipMemcpyAsync(dev[k], src[k], len[k] * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    hipLaunchKernelGGL((f1_setup_kernel<double>), dim3(grid_for(fs)), dim3(256), 0, s, g, dev[0],
+                       P->c_const, dev[1], dev[2], dev[3], dev[4], tp<double>(hi.cc),
+                       tp<double>(hi.Fre), tp<double>(hi.Fim), fs);
+    CMCG_HIP(hipGetLastError());
+    if (mixed) {
+      hipLaunchKernelGGL((f1_setup_kernel<float>), dim3(grid_for(fs)), dim3(256), 0, s, g, dev[0],
+                         P->c_const, dev[1], dev[2], dev[3], dev[4], tp<float>(lo.cc),
+                         tp<float>(lo.Fre), tp<float>(lo.Fim), fs);
+      CMCG_HIP(hipGetLastError());
+    }
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status alloc_set(F1Set &b, int prec, bool has_im) {
+    const size_t esz = prec == CMCG_FP64 ? sizeof(double) : sizeof(float);
+    b.prec = prec;
+    CMCG_TRY(arena.alloc(vecN * esz, &b.S0, s));
+    CMCG_TRY(arena.alloc(vecN * esz, &b.S1, s));
+    CMCG_TRY(arena.alloc(vecN * esz, &b.W, s));
+    CMCG_TRY(arena.alloc(vecN * esz, &b.Q, s));
+    CMCG_TRY(arena.alloc(fs * esz, &b.cc, s));
+    CMCG_TRY(arena.alloc(fs * esz, &b.Fre, s));
+    if (has_im) CMCG_TRY(arena.alloc(fs * esz, &b.Fim, s));
+    return CMCG_OK;
+  }
+
+  // ------------------------------------------------------------------ periods
+  template <typename T>
+  cmcg_status period_t(const F1Set &b, bool adjoint, bool forced, const T *in, T *out, const T *sub,
+                       int steps, bool filter) {
+    const int K = filter ? 1 : cfg.kblock;
+    int n0 = 0, l = 0;
+    T *S[2] = {tp<T>(b.S0), tp<T>(b.S1)};
+    while (n0 < steps) {
+      const int ns = std::min(K, steps - n0);
+      const bool lastl = (n0 + ns == steps);
+      F1Launch L{};
+      L.nsteps = ns;
+      L.first = (n0 == 0);
+      L.last = lastl;
+      L.forced = forced ? 1 : 0;
+      L.accumulate = filter ? 1 : 0;
+      for (int k = 0; k < ns; ++k) {
+        const double t = (n0 + k + 0.5) * cfg.dt;      // source at t_{n+1/2}
+        L.cs[k] = std::cos(cfg.omega * t);
+        L.sn[k] = std::sin(cfg.omega * t);
+      }
+      L.fcos = std::cos(cfg.omega * n0 * cfg.dt);       // filter weight at t_n
+      L.fsin = std::sin(cfg.omega * n0 * cfg.dt);
+      F1Ptrs<T> p{};
+      p.in = (l == 0) ? in : S[(l - 1) & 1];
+      p.out = lastl ? out : S[l & 1];
+      p.sub = lastl ? sub : nullptr;
+      p.cc = tp<T>(b.cc);
+      p.fre = tp<T>(b.Fre);
+      p.fim = tp<T>(b.Fim);
+      p.ure = Ure;
+      p.uim = Uim;
+      p.fs = fs;
+      CMCG_HIP(adjoint ? f1_adjoint_launch<T>(g, p, L, K, s) : f1_forward_launch<T>(g, p, L, K, s));
+      n0 += ns;
+      ++l;
+    }
+    updates += (double)steps * g.nx * g.ny;
+    return CMCG_OK;
+  }
+
+  cmcg_status period(const F1Set &b, bool adjoint, bool forced, const void *in, void *out,
+                     const void *sub, int steps, bool filter) {
+    if (b.prec == CMCG_FP64)
+      return period_t<double>(b, adjoint, forced, tpc<double>(in), tp<double>(out),
+                              tpc<double>(sub), steps, filter);
+    return period_t<float>(b, adjoint, forced, tpc<float>(in), tp<float>(out), tpc<float>(sub),
+                           steps, filter);
+  }
+
+  cmcg_status dot_to(const F1Set &b, const void *x, const void *y, int mode) {
+    // <x, y>_E with x, y in the precision of set b
+    if (b.prec == CMCG_FP64)
+      CMCG_HIP(f1_dot<double, double>(g, tpc<double>(x), tpc<double>(y), b.cc, 1, fs, partials, s));
+    else
+      CMCG_HIP(f1_dot<float, float>(g, tpc<float>(x), tpc<float>(y), b.cc, 0, fs, partials, s));
+    CMCG_HIP(finalize(partials, kRedBlocks, scalars, mode, 0, s));
+    return CMCG_OK;
+  }
+
+  cmcg_status read_scalars() {
+    CMCG_HIP(hipMemcpyAsync(h_scalars, scalars, kNumScalars * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  // r = E*(Phi(z) - z) - (Phi(z) - z) at the FP64 iterate, with FP64 periods (Steps 2-3)
+  cmcg_status true_gradient(int mode) {
+    CMCG_TRY(period(hi, false, true, Z, hi.W, Z, cfg.N, false));
+    CMCG_TRY(period(hi, true, false, hi.W, hi.Q, hi.W, cfg.N, false));
+    CMCG_HIP(hipMemcpyAsync(R, hi.Q, vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CMCG_HIP(f1_dot<double, double>(g, R, R, hi.cc, 1, fs, partials, s));
+    CMCG_HIP(finalize(partials, kRedBlocks, scalars, mode, 0, s));
+    return CMCG_OK;
+  }
+
+  // ------------------------------------------------------------------ CG driver
+  cmcg_status begin() override {
+    t_fwd = t_adj = t_other = t_total = 0.0;
+    updates = 0;
+    iter = refreshes = last_refresh = 0;
+    CMCG_HIP(hipEventRecord(ev[0], s));
+    // Steps 1-4: z = 0, gradient, r = d = gradient (the Riesz map M_E^{-1} is built into E*)
+    CMCG_HIP(hipMemsetAsync(Z, 0, vecN * sizeof(double), s));
+    CMCG_TRY(true_gradient(kFinStart));
+    if (mixed) CMCG_HIP(convert<float, double>(tp<float>(D), R, vecN, s));
+    else CMCG_HIP(hipMemcpyAsync(D, R, vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CMCG_HIP(hipEventRecord(ev[1], s));
+    CMCG_TRY(read_scalars());
+    t_other += PhaseEvents::seconds(ev[0], ev[1]);
+    rel = 1.0;
+    delta_at_refresh = h_scalars[kDelta];
+    started = true;
+    if (h_scalars[kBreak] != 0.0) return set_error("non-finite initial gradient"), CMCG_EBREAKDOWN;
+    return CMCG_OK;
+  }
+
+  cmcg_status iterate(int iters, int *converged) override {
+    if (!started) return set_error("cmcg_begin first"), CMCG_EINVAL;
+    *converged = (rel <= cfg.tol || h_scalars[kDelta0] == 0.0) ? 1 : 0;
+    for (int it = 0; it < iters && !*converged; ++it) {
+      CMCG_HIP(hipEventRecord(ev[2], s));
+      // Step 5.1: w = E d - d (forward), q = E* w - w (backward)
+      CMCG_TRY(period(lo, false, false, D, lo.W, D, cfg.N, false));
+      CMCG_HIP(hipEventRecord(ev[3], s));
+      CMCG_TRY(period(lo, true, false, lo.W, lo.Q, lo.W, cfg.N, false));
+      CMCG_HIP(hipEventRecord(ev[4], s));
+      // Step 5.3: alpha = delta / <q, d>_E
+      CMCG_TRY(dot_to(lo, lo.Q, D, kFinAlpha));
+      // Steps 5.4-5.5 and delta' = <r, r>_E; beta = delta' / delta
+      if (mixed)
+        CMCG_HIP(f1_cg_update<float>(g, Z, R, tpc<float>(D), tpc<float>(lo.Q), lo.cc, fs, scalars,
+                                     partials, s));
+      else
+        CMCG_HIP(f1_cg_update<double>(g, Z, R, tpc<double>(D), tpc<double>(lo.Q), lo.cc, fs,
+                                      scalars, partials, s));
+      CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinBeta, 0, s));
+      CMCG_HIP(hipEventRecord(ev[5], s));
+      CMCG_TRY(read_scalars());
+      t_fwd += PhaseEvents::seconds(ev[2], ev[3]);
+      t_adj += PhaseEvents::seconds(ev[3], ev[4]);
+      t_other += PhaseEvents::seconds(ev[4], ev[5]);
+      ++iter;
+      if (h_scalars[kBreak] != 0.0)
+        return set_error("CG breakdown: <qhat, d> <= 0 or non-finite scalar"), CMCG_EBREAKDOWN;
+      rel = h_scalars[kRel];
+      if (mixed && cfg.refresh > 0.0 &&
+          (rel <= cfg.tol || h_scalars[kDelta] <= cfg.refresh * cfg.refresh * delta_at_refresh)) {
+        // reliable update: replace the recursive residual by the true FP64 gradient
+        CMCG_HIP(hipEventRecord(ev[6], s));
+        CMCG_TRY(true_gradient(kFinRefresh));
+        CMCG_HIP(hipEventRecord(ev[7], s));
+        CMCG_TRY(read_scalars());
+        t_other += PhaseEvents::seconds(ev[6], ev[7]);
+        rel = h_scalars[kRel];
+        delta_at_refresh = h_scalars[kDelta];
+        ++refreshes;
+        last_refresh = iter;
+      }
+      // Step 5.8
+      if (rel <= cfg.tol) {
+        *converged = 1;
+        break;
+      }
+      // Step 5.7: d = r + beta d
+      if (mixed) CMCG_HIP(direction_update<float>(tp<float>(D), R, scalars, vecN, s));
+      else CMCG_HIP(direction_update<double>(tp<double>(D), R, scalars, vecN, s));
+    }
+    return CMCG_OK;
+  }
+
+  cmcg_status filter_from_hi(const double *z, double *u_re, double *u_im) {
+    CMCG_HIP(hipMemsetAsync(Ure, 0, fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Uim, 0, fs * sizeof(double), s));
+    CMCG_TRY(period(hi, false, true, z, hi.Q, nullptr, cfg.N, true));
+    double *ore = tp<double>(hi.W), *oim = tp<double>(hi.W) + fs;
+    hipLaunchKernelGGL(f1_output_kernel, dim3(grid_for(fs)), dim3(256), 0, s, Ure, Uim,
+                       2.0 / (cfg.N * cfg.omega), ore, oim, fs);
+    CMCG_HIP(hipGetLastError());
+    CMCG_HIP(hipEventRecord(ev[6], s));
+    const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
+    if (u_re) CMCG_HIP(hipMemcpy2DAsync(u_re, row, ore, pitchb, row, g.ny, hipMemcpyDefault, s));
+    if (u_im) CMCG_HIP(hipMemcpy2DAsync(u_im, row, oim, pitchb, row, g.ny, hipMemcpyDefault, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status finish(double *u_re, double *u_im) override {
+    if (!started) return set_error("cmcg_begin first"), CMCG_EINVAL;
+    // Step 6 through the fundamental-frequency filter: one forced FP64 period from z
+    return filter_from_hi(Z, u_re, u_im);
+  }
+
+  cmcg_status solve(double *u_re, double *u_im) override {
+    CMCG_TRY(begin());
+    int conv = 0;
+    CMCG_TRY(iterate(cfg.max_iter, &conv));
+    CMCG_HIP(hipEventRecord(ev[7], s));
+    CMCG_TRY(finish(u_re, u_im));
+    t_other += PhaseEvents::seconds(ev[7], ev[6]);
+    t_total = PhaseEvents::seconds(ev[0], ev[6]);
+    return conv ? CMCG_OK : CMCG_ENOTCONV;
+  }
+
+  // ------------------------------------------------------------------ stage calls
+  cmcg_status apply(int op, int steps, const double *in, double *out) override {
+    const int ns = steps > 0 ? steps : cfg.N;
+    void *W = lo.W, *Q = lo.Q;
+    if (lo.prec == CMCG_FP64) CMCG_HIP(f1_unpack<double>(g, in, tp<double>(W), fs, s));
+    else CMCG_HIP(f1_unpack<float>(g, in, tp<float>(W), fs, s));
+    if (op == CMCG_OP_FORWARD || op == CMCG_OP_FORCED) {
+      CMCG_TRY(period(lo, false, op == CMCG_OP_FORCED, W, Q, nullptr, ns, false));
+    } else if (op == CMCG_OP_ADJOINT) {
+      CMCG_TRY(period(lo, true, false, W, Q, nullptr, ns, false));
+    } else {
+      if (lo.prec == CMCG_FP64)
+        hipLaunchKernelGGL((f1_riesz_kernel<double>), dim3(grid_for(fs)), dim3(256), 0, s, g,
+                           tp<double>(W), tp<double>(lo.cc), fs);
+      else
+        hipLaunchKernelGGL((f1_riesz_kernel<float>), dim3(grid_for(fs)), dim3(256), 0, s, g,
+                           tp<float>(W), tp<float>(lo.cc), fs);
+      CMCG_HIP(hipGetLastError());
+      Q = W;
+    }
+    if (lo.prec == CMCG_FP64) CMCG_HIP(f1_pack<double>(g, tp<double>(Q), out, fs, s));
+    else CMCG_HIP(f1_pack<float>(g, tp<float>(Q), out, fs, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status filter(const double *z, double *u_re, double *u_im) override {
+    // the period reads its input only in its first launch and never writes hi.W
+    CMCG_HIP(f1_unpack<double>(g, z, tp<double>(hi.W), fs, s));
+    CMCG_HIP(hipMemsetAsync(Ure, 0, fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Uim, 0, fs * sizeof(double), s));
+    CMCG_TRY(period(hi, false, true, hi.W, hi.Q, nullptr, cfg.N, true));
+    double *ore = tp<double>(hi.S1), *oim = tp<double>(hi.S1) + fs;
+    hipLaunchKernelGGL(f1_output_kernel, dim3(grid_for(fs)), dim3(256), 0, s, Ure, Uim,
+                       2.0 / (cfg.N * cfg.omega), ore, oim, fs);
+    CMCG_HIP(hipGetLastError());
+    const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
+    if (u_re) CMCG_HIP(hipMemcpy2DAsync(u_re, row, ore, pitchb, row, g.ny, hipMemcpyDefault, s));
+    if (u_im) CMCG_HIP(hipMemcpy2DAsync(u_im, row, oim, pitchb, row, g.ny, hipMemcpyDefault, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status get_state(int which, double *out) override {
+    if (which == 0) CMCG_HIP(f1_pack<double>(g, Z, out, fs, s));
+    else if (which == 1) CMCG_HIP(f1_pack<double>(g, R, out, fs, s));
+    else if (mixed) CMCG_HIP(f1_pack<float>(g, tp<float>(D), out, fs, s));
+    else CMCG_HIP(f1_pack<double>(g, tp<double>(D), out, fs, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  void report(cmcg_report *r) const override {
+    r->iterations = iter;
+    r->steps_per_period = cfg.N;
+    r->dt = cfg.dt;
+    r->rel_residual = rel;
+    r->seconds = t_total;
+    r->seconds_fwd = t_fwd;
+    r->seconds_adj = t_adj;
+    r->seconds_riesz = 0.0;
+    r->seconds_other = t_other;
+    r->grid_updates = updates;
+    r->riesz_iterations = 0;
+    r->fp64_refreshes = refreshes;
+  }
+
+  void info(cmcg_info *i) const override {
+    const int64_t nx = g.nx, ny = g.ny;
+    i->steps_per_period = cfg.N;
+    i->dt = cfg.dt;
+    i->T = cfg.T;
+    i->h = cfg.h;
+    i->state_len = ny * (nx - 1) + (ny - 1) * nx + nx * ny;
+    i->field_len = nx * ny;
+    i->device_bytes = (int64_t)arena.bytes();
+  }
+};
+
+}  // namespace
+
+cmcg_status make_f1_solver(const cmcg_problem *P, const SolverConfig &cfg, Solver **out) {
+  *out = nullptr;
+  F1Solver *S = new F1Solver();
+  S->cfg = cfg;
+  cmcg_status st = S->create(P);
+  if (st != CMCG_OK) {
+    delete S;
+    return st;
+  }
+  *out = S;
+  return CMCG_OK;
+}
+
+}  // namespace cmcg

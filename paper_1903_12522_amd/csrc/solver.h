@@ -1,0 +1,110 @@
+// Formulation-independent solver interface behind the C ABI, and small runtime utilities.
+#pragma once
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "cmcg_internal.h"
+
+namespace cmcg {
+
+// Options resolved from cmcg_options / cmcg_problem at create time.
+struct SolverConfig {
+  int prec = CMCG_FP64;
+  double tol = 1e-6;
+  int max_iter = 1000;
+  int kblock = 4;          // leapfrog steps per launch
+  double refresh = 0.1;    // FP32-mixed: FP64 residual refresh factor (<= 0: never)
+  double riesz_tol = 0.0;
+  int riesz_max_iter = 0;
+  hipStream_t stream = nullptr;
+  double h = 0, omega = 0, T = 0, dt = 0;
+  int N = 0;
+};
+
+// Device allocations owned by one solver (freed in the destructor).
+class DeviceArena {
+ public:
+  ~DeviceArena() { release(); }
+  cmcg_status alloc(size_t bytes, void **p, hipStream_t s) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipMalloc(" + std::to_string(bytes) + " B): " + hipGetErrorString(e));
+      return CMCG_ENOMEM;
+    }
+    ptrs_.push_back(*p);
+    bytes_ += bytes;
+    CMCG_HIP(hipMemsetAsync(*p, 0, bytes, s));
+    return CMCG_OK;
+  }
+  template <typename T>
+  cmcg_status alloc_n(size_t n, T **p, hipStream_t s) {
+    return alloc(n * sizeof(T), reinterpret_cast<void **>(p), s);
+  }
+  void release() {
+    for (void *p : ptrs_) (void)hipFree(p);
+    ptrs_.clear();
+    bytes_ = 0;
+  }
+  size_t bytes() const { return bytes_; }
+
+ private:
+  std::vector<void *> ptrs_;
+  size_t bytes_ = 0;
+};
+
+// Phase timer: pairs of HIP events recorded on the solver's stream.
+class PhaseEvents {
+ public:
+  ~PhaseEvents() {
+    for (auto e : ev_)
+      if (e) (void)hipEventDestroy(e);
+  }
+  cmcg_status init(int n) {
+    ev_.assign(n, nullptr);
+    for (auto &e : ev_) CMCG_HIP(hipEventCreate(&e));
+    return CMCG_OK;
+  }
+  hipEvent_t operator[](int k) const { return ev_[k]; }
+  static double seconds(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0.0;
+    }
+    return 1e-3 * ms;
+  }
+
+ private:
+  std::vector<hipEvent_t> ev_;
+};
+
+class Solver {
+ public:
+  virtual ~Solver() {}
+  virtual cmcg_status begin() = 0;
+  virtual cmcg_status iterate(int iters, int *converged) = 0;
+  virtual cmcg_status finish(double *u_re, double *u_im) = 0;
+  // begin + iterate(max_iter) + finish, timed end to end on the device
+  virtual cmcg_status solve(double *u_re, double *u_im) = 0;
+  virtual cmcg_status apply(int op, int steps, const double *in, double *out) = 0;
+  virtual cmcg_status filter(const double *z, double *u_re, double *u_im) = 0;
+  virtual cmcg_status get_state(int which, double *out) = 0;
+  virtual void report(cmcg_report *r) const = 0;
+  virtual void info(cmcg_info *i) const = 0;
+  virtual size_t device_bytes() const = 0;
+};
+
+cmcg_status make_f1_solver(const cmcg_problem *P, const SolverConfig &cfg, Solver **out);
+cmcg_status make_f2_solver(const cmcg_problem *P, const SolverConfig &cfg, Solver **out);
+
+inline int grid_for(size_t n, int threads = 256) {
+  size_t b = (n + threads - 1) / threads;
+  return (int)std::max<size_t>(1, std::min<size_t>(b, 8192));
+}
+
+}  // namespace cmcg

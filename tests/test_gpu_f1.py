@@ -215,3 +215,18 @@ def test_full_size_period_sampled(cm, c2, prec, tol):
         if ci0 < nx - 1:
             sp = np.max(np.abs(Pxs)) + 1e-300
             assert abs(Pxo[cj0, ci0] - Pxs[cj0 - j0, ci0 - i0]) <= tol * sp
+
+
+def test_fp32_mixed_reliable_updates_match_fp64(cm):
+    """FP32 periods alone stall above 1e-6 on a heterogeneous medium; with FP64 residual
+    refreshes the FP32-mixed solve converges in about the FP64 iteration count and lands within
+    1e-4 (relative L2) of the FP64 solution."""
+    prob = ci.random_medium_2d(n=512, freq=12.5, n_src=4, seed=99)
+    with cm.Solver(prob, "fp64", tol=1e-6, max_iter=3000) as s:
+        U64, r64 = s.solve()
+    with cm.Solver(prob, "fp32", tol=1e-6, max_iter=3000) as s:
+        U32, r32 = s.solve()
+    assert r64["converged"] and r32["converged"]
+    assert r32["fp64_refreshes"] >= 1
+    assert r32["iterations"] <= 1.15 * r64["iterations"] + 5
+    assert _rel(U32, U64) < 1e-4
