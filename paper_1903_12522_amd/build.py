@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcmcg.so")
-SOURCES = ["cmcg_api.hip", "f1_kernels.hip", "f1_solver.hip", "f2_solver.hip"]
+SOURCES = ["cmcg_api.hip", "f1_kernels.hip", "f1_solver.hip", "f2_kernels.hip", "riesz_mg.hip",
+           "f2_solver.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,115 @@
+// Second-order (nodal, 3D) device layout, kernel launchers and the Riesz (elliptic) solver.
+#pragma once
+
+#include "cmcg_internal.h"
+
+namespace cmcg {
+
+// Node fields: (nz+1) planes of (ny+1) rows of `px` values (x fastest, rows padded to 64).
+struct F2Geom {
+  int nx = 0, ny = 0, nz = 0;        // cells per axis (nodes are n+1)
+  int px = 0;                        // row pitch in elements
+  size_t plane = 0, fs = 0;          // plane stride, field stride
+  double h = 0, dt = 0;
+  int abs_face[6] = {0, 0, 0, 0, 0, 0};
+  double lam_const = 0;              // (c dt / h)^2 when c is constant (lam array absent)
+  const uint8_t *mask = nullptr;     // sound-soft nodes (device layout), or null
+  int mlo[3] = {0, 0, 0}, mhi[3] = {-1, -1, -1};   // bounding box of the sound-soft nodes
+  int kchunk = 64;                   // planes per thread column
+  __host__ __device__ size_t idx(int i, int j, int k) const {
+    return (size_t)k * plane + (size_t)j * px + i;
+  }
+};
+
+enum F2Mode : int {
+  kF2FwdStart = 0,
+  kF2FwdStep = 1,
+  kF2FwdEnd = 2,
+  kF2Metric = 3,
+  kF2AdjInit = 4,
+  kF2AdjStepFirst = 5,
+  kF2AdjStep = 6,
+  kF2AdjEnd = 7
+};
+
+template <typename T>
+struct F2Args {
+  const T *st = nullptr;     // stencilled field
+  const T *aux = nullptr;    // second input (v^0, u^{n-1}, w_v, y_u, b_0 or a_{m-1})
+  const T *sub = nullptr;    // epilogue subtrahend (two fields) or null
+  const T *lam = nullptr;    // (c dt / h)^2 per node, or null (constant)
+  const T *fre = nullptr, *fim = nullptr;   // dt^2 c^2 G per node
+  T *out = nullptr, *out2 = nullptr;
+  double *ure = nullptr, *uim = nullptr;    // filter accumulators
+  int forced = 0;
+  double fcos = 1, fsin = 0;                // source phase cos/sin(omega t_n)
+  double wcos = 1, wsin = 0;                // filter weight cos/sin(omega t_n)
+};
+
+template <typename T>
+hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s);
+template <typename TA, typename TB>
+hipError_t dot_plain(const TA *a, const TB *b, size_t n, double *partials, hipStream_t s);
+template <typename T>
+hipError_t f2_cg_update(const F2Geom &g, double *z, double *ru, double *rh, const T *d,
+                        const double *qu, const T *qh, const T *lam, const double *sc,
+                        double *partials, hipStream_t s);
+template <typename T>
+hipError_t f2_delta(const F2Geom &g, const double *ru, const double *rh, const T *lam,
+                    double *partials, hipStream_t s);
+template <typename T>
+hipError_t f2_direction(const F2Geom &g, T *d, const double *ru, const double *rh, const T *lam,
+                        const double *sc, int first, hipStream_t s);
+template <typename T>
+hipError_t f2_mass_inverse(const F2Geom &g, const T *qh_v, double *q_v, const T *lam, hipStream_t s);
+template <typename T>
+hipError_t f2_setup(const F2Geom &g, const double *c, double c_const, const double *fre,
+                    const double *fim, const double *gre, const double *gim, T *lam, T *Fre, T *Fim,
+                    hipStream_t s);
+template <typename T>
+hipError_t f2_unpack(const F2Geom &g, const double *packed, T *dev, int nfields, hipStream_t s);
+template <typename T>
+hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Riesz map of eq. CMCG_PRECONDITIONIER: solve S x = b on the free nodes (S = diag(h eta) L,
+// the mass-lumped stiffness), by conjugate gradients preconditioned with one geometric multigrid
+// V-cycle (damped Jacobi smoothing, trilinear prolongation, its transpose as restriction,
+// rediscretised coarse operators, sound-soft mask injected to coarse nodes).  With no sound-soft
+// node S is singular (constants): right-hand side and iterates are kept zero-sum.
+// ---------------------------------------------------------------------------------------
+struct MGLevel {
+  F2Geom g;                         // geometry (mask pointer into `maskbuf`)
+  double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+  uint8_t *maskbuf = nullptr;
+  size_t nfree = 0;                 // number of free (non-sound-soft) real nodes
+};
+
+class DeviceArena;
+
+class RieszMG {
+ public:
+  ~RieszMG();
+  cmcg_status build(const F2Geom &fine, DeviceArena &arena, hipStream_t s);
+  // x = S^{-1} b (x: FP64 fine-level field; b: fine-level field in FP64, or FP32 if b_is_float;
+  // x may not alias b).  *iters receives the number of PCG iterations.
+  cmcg_status solve(const void *b, int b_is_float, double *x, double tol, int max_iter, int *iters);
+  // x = B b: one V-cycle (the preconditioner), exposed for tests
+  cmcg_status vcycle(const double *b, double *x);
+  bool pure_neumann() const { return neumann_; }
+
+ private:
+  cmcg_status vcycle_level(int l);
+  cmcg_status smooth(int l, int sweeps);
+  cmcg_status project(double *v, int l);
+  cmcg_status dot(const double *a, const double *b, size_t n, double *out);
+  std::vector<MGLevel> lv_;
+  double *pr_ = nullptr, *pz_ = nullptr, *pp_ = nullptr, *pq_ = nullptr;   // fine PCG vectors
+  double *partials_ = nullptr, *scal_ = nullptr, *h_scal_ = nullptr;
+  hipStream_t s_ = nullptr;
+  bool neumann_ = false;
+  int pre_ = 2, post_ = 2, coarse_sweeps_ = 64;
+  double omega_ = 0.8;
+};
+
+}  // namespace cmcg

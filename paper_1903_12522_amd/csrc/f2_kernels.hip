@@ -1,0 +1,507 @@
+// Second-order (nodal, 3D) leapfrog on gfx950: start map, steps and end map of one period, the
+// literal transpose of each (the backward period), the energy metric, and the CG vector kernels.
+//
+// Scheme (Sec. 2, eq. WE; mass-lumped nodal discretisation of a structured box, leapfrog with an
+// integer number of steps per period).  Nodes I in {0..n}^3, eta_I = prod over axes of (1/2 if I
+// is on that axis' boundary), lumped mass M = h^3 eta / c^2, stiffness S = diag(h eta) L where L
+// is the 7-point operator 6 u_I - sum of the six neighbours with mirrored neighbours across the
+// box faces (u_{-1} = u_1, u_{n+1} = u_{n-1}).  Hence
+//     dt^2 M^{-1} S u = lambda L u,          dt^2 S M^{-1} s = eta L(lambda s / eta),
+// lambda = (c dt / h)^2.  Absorbing faces add beta = sqrt(lambda) m (m = number of absorbing faces
+// at the node), the load enters as F = dt^2 c^2 Re(G e^{-i w t}), G = f + (2/h) sum_abs gS, and
+// sound-soft nodes are held at zero (R = 1 - mask).
+//   start:  u^1 = R(u^0 + dt (1-beta) v^0 - (lambda L u^0 - F^0)/2)
+//   step:   u^{n+1} = R(2 u^n - (1-beta) u^{n-1} - lambda L u^n + F^n) / (1+beta)
+//   end:    v^N = (u^{N+1} - u^{N-1}) / (2 dt),  Phi(u^0, v^0) = (u^N, v^N)
+// The transposed period runs the same three-level recurrence backward on a = adjoint state:
+//   a_{m+1} = K^T a_m + Lb a_{m-1},  K^T a = R(2 s - eta L(lambda s / eta)),  s = R a / (1+beta),
+//   Lb = -(1-beta)/(1+beta)
+// with the transposed end map as its start and the transposed start map as its end.
+//
+// Kernel design: one thread per (i, j) column marches through a run of planes k, keeping the
+// planes k-1, k, k+1 of the stencilled field in registers; x/y neighbours are loaded from the
+// rows that adjacent lanes and wavefronts load anyway (L1/L2 hits), so HBM sees each field once.
+#include "f2_internal.h"
+
+namespace cmcg {
+namespace {
+
+__device__ __forceinline__ int mirror(int i, int n) { return i < 0 ? 1 : (i > n ? n - 1 : i); }
+
+__device__ __forceinline__ double eta_of(const F2Geom &g, int i, int j, int k) {
+  double e = 1.0;
+  if (i == 0 || i == g.nx) e *= 0.5;
+  if (j == 0 || j == g.ny) e *= 0.5;
+  if (k == 0 || k == g.nz) e *= 0.5;
+  return e;
+}
+
+__device__ __forceinline__ int abs_faces(const F2Geom &g, int i, int j, int k) {
+  return (i == 0 ? g.abs_face[0] : 0) + (i == g.nx ? g.abs_face[1] : 0) +
+         (j == 0 ? g.abs_face[2] : 0) + (j == g.ny ? g.abs_face[3] : 0) +
+         (k == 0 ? g.abs_face[4] : 0) + (k == g.nz ? g.abs_face[5] : 0);
+}
+
+__device__ __forceinline__ bool masked(const F2Geom &g, int i, int j, int k) {
+  if (!g.mask) return false;
+  if (i < g.mlo[0] || i > g.mhi[0] || j < g.mlo[1] || j > g.mhi[1] || k < g.mlo[2] || k > g.mhi[2])
+    return false;
+  return g.mask[g.idx(i, j, k)] != 0;
+}
+
+template <typename T>
+__device__ __forceinline__ T lam_at(const F2Geom &g, const T *lam, size_t o) {
+  return lam ? lam[o] : (T)g.lam_const;
+}
+
+// value of the stencilled field at a node, per mode
+template <typename T, int MODE>
+__device__ __forceinline__ T sval(const F2Geom &g, const T *f, const T *lam, int i, int j, int k) {
+  const size_t o = g.idx(i, j, k);
+  const T a = f[o];
+  if (MODE == kF2AdjInit || MODE == kF2AdjStep || MODE == kF2AdjStepFirst) {
+    // g = lambda s / eta,  s = R a / (1 + beta)
+    if (masked(g, i, j, k)) return T(0);
+    const T l = lam_at(g, lam, o);
+    const int m = abs_faces(g, i, j, k);
+    const T beta = m ? (T)m * sqrt(l) : T(0);
+    return l * a / ((T(1) + beta) * (T)eta_of(g, i, j, k));
+  } else if (MODE == kF2AdjEnd) {
+    // g' = lambda R a / eta
+    if (masked(g, i, j, k)) return T(0);
+    return lam_at(g, lam, o) * a / (T)eta_of(g, i, j, k);
+  } else if (MODE == kF2Metric) {
+    return masked(g, i, j, k) ? T(0) : a;
+  }
+  return a;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i > g.nx || j > g.ny) return;
+  const int k0 = blockIdx.z * g.kchunk;
+  const int k1 = min(k0 + g.kchunk, g.nz + 1);
+  const int im = mirror(i - 1, g.nx), ip = mirror(i + 1, g.nx);
+  const int jm = mirror(j - 1, g.ny), jp = mirror(j + 1, g.ny);
+  const T dt = (T)g.dt;
+  T zm = sval<T, MODE>(g, p.st, p.lam, i, j, mirror(k0 - 1, g.nz));
+  T zc = sval<T, MODE>(g, p.st, p.lam, i, j, k0);
+  for (int k = k0; k < k1; ++k) {
+    const T zp = sval<T, MODE>(g, p.st, p.lam, i, j, mirror(k + 1, g.nz));
+    const T lap = T(6) * zc - (zm + zp + sval<T, MODE>(g, p.st, p.lam, im, j, k) +
+                               sval<T, MODE>(g, p.st, p.lam, ip, j, k) +
+                               sval<T, MODE>(g, p.st, p.lam, i, jm, k) +
+                               sval<T, MODE>(g, p.st, p.lam, i, jp, k));
+    const size_t o = g.idx(i, j, k);
+    const bool R = !masked(g, i, j, k);
+    const T l = lam_at(g, p.lam, o);
+    const int m = abs_faces(g, i, j, k);
+    const T beta = m ? (T)m * sqrt(l) : T(0);
+    T F = T(0);
+    if (p.forced) {
+      F = p.fre[o] * (T)p.fcos;
+      if (p.fim) F = fma(p.fim[o], (T)p.fsin, F);
+    }
+    if (MODE == kF2FwdStart) {
+      // u^1 = R(u^0 + dt (1-beta) v^0 - (lambda L u^0 - F^0) / 2)
+      const T u0 = zc, v0 = p.aux[o];
+      if (p.ure) {
+        p.ure[o] += (double)u0 * p.wcos;
+        p.uim[o] += (double)u0 * p.wsin;
+      }
+      p.out[o] = R ? u0 + dt * (T(1) - beta) * v0 - T(0.5) * (l * lap - F) : T(0);
+    } else if (MODE == kF2FwdStep) {
+      const T u = zc, um = p.aux[o];
+      if (p.ure) {
+        p.ure[o] += (double)u * p.wcos;
+        p.uim[o] += (double)u * p.wsin;
+      }
+      p.out[o] = R ? (T(2) * u - (T(1) - beta) * um - (l * lap - F)) / (T(1) + beta) : T(0);
+    } else if (MODE == kF2FwdEnd) {
+      // out = (u^N, (u^{N+1} - u^{N-1}) / (2 dt)) - sub
+      const T u = zc, um = p.aux[o];
+      const T up = R ? (T(2) * u - (T(1) - beta) * um - (l * lap - F)) / (T(1) + beta) : T(0);
+      T ou = u, ov = (up - um) / (T(2) * dt);
+      if (p.sub) {
+        ou -= p.sub[o];
+        ov -= p.sub[o + g.fs];
+      }
+      p.out[o] = ou;
+      p.out[o + g.fs] = ov;
+    } else if (MODE == kF2Metric) {
+      // y = M_E w = (S w_u, M w_v) on the free nodes
+      const T eta = (T)eta_of(g, i, j, k);
+      const T h = (T)g.h;
+      const T c2 = l * (T)(g.h * g.h / (g.dt * g.dt));
+      p.out[o] = R ? h * eta * lap : T(0);
+      p.out[o + g.fs] = (R && c2 > T(0)) ? h * h * h * eta / c2 * p.aux[o] : T(0);
+    } else if (MODE == kF2AdjInit) {
+      // transposed end map on y = (x, yv):  a_0 = R x + K^T(yv) / (2 dt),
+      //                                     b_0 = R (Lb - 1) yv / (2 dt)
+      const T yv = p.st[o];
+      const T eta = (T)eta_of(g, i, j, k);
+      const T s = R ? yv / (T(1) + beta) : T(0);
+      const T KT = R ? T(2) * s - eta * lap : T(0);
+      const T Lb = -(T(1) - beta) / (T(1) + beta);
+      const T x = R ? p.aux[o] : T(0);
+      p.out[o] = x + KT / (T(2) * dt);
+      p.out2[o] = R ? (Lb - T(1)) * yv / (T(2) * dt) : T(0);
+    } else if (MODE == kF2AdjStep || MODE == kF2AdjStepFirst) {
+      // a_{m+1} = K^T a_m + (b_0 on the first step, else Lb a_{m-1})
+      const T a = p.st[o];
+      const T eta = (T)eta_of(g, i, j, k);
+      const T s = R ? a / (T(1) + beta) : T(0);
+      const T KT = R ? T(2) * s - eta * lap : T(0);
+      T b;
+      if (MODE == kF2AdjStepFirst) {
+        b = p.aux[o];
+      } else {
+        const T Lb = -(T(1) - beta) / (T(1) + beta);
+        b = R ? Lb * p.aux[o] : T(0);
+      }
+      p.out[o] = KT + b;
+    } else if (MODE == kF2AdjEnd) {
+      // transposed start map: u0 = R(a - eta L(lambda R a / eta) / 2) + b, v0 = R dt (1-beta) a,
+      // b = Lb a_prev; out = (u0, v0) - sub
+      const T a = p.st[o];
+      const T eta = (T)eta_of(g, i, j, k);
+      const T Lb = -(T(1) - beta) / (T(1) + beta);
+      const T b = R ? Lb * p.aux[o] : T(0);
+      T ou = (R ? a - T(0.5) * eta * lap : T(0)) + b;
+      T ov = R ? dt * (T(1) - beta) * a : T(0);
+      if (p.sub) {
+        ou -= p.sub[o];
+        ov -= p.sub[o + g.fs];
+      }
+      p.out[o] = ou;
+      p.out[o + g.fs] = ov;
+    }
+    zm = zc;
+    zc = zp;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// vector kernels (plain dot products: dual x primal)
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ double block_sum(double x) {
+  __shared__ double part[kRedThreads / 64];
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) part[wv] = x;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kRedThreads / 64; ++k) t += part[k];
+  __syncthreads();
+  return t;
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kRedThreads) void dot_kernel(const TA *a, const TB *b, size_t n,
+                                                          double *partials) {
+  double acc = 0.0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+    acc += (double)a[k] * (double)b[k];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// M^{-1} on the velocity block, per node: c^2 / (h^3 eta) on free nodes, 0 on sound-soft nodes
+// and padding (lambda = 0 there)
+template <typename T>
+__device__ __forceinline__ double minv_at(const F2Geom &g, const T *lam, size_t o, int i, int j,
+                                          int k) {
+  if (masked(g, i, j, k)) return 0.0;
+  const double l = lam ? (double)lam[o] : g.lam_const;
+  return l * (g.h * g.h / (g.dt * g.dt)) / (g.h * g.h * g.h * eta_of(g, i, j, k));
+}
+
+#define F2_NODES(g)                                                                          \
+  const size_t stride_ = (size_t)gridDim.x * blockDim.x;                                     \
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < (g).fs; o += stride_) { \
+    const int i = (int)(o % (g).px);                                                         \
+    const int j = (int)((o / (g).px) % ((g).ny + 1));                                        \
+    const int k = (int)(o / (g).plane);                                                      \
+    if (i > (g).nx) continue;
+
+// Steps 5.4-5.5 with primal and dual residuals (the velocity block of the primal residual is
+// r_v = M^{-1} rh_v and is not stored):  z -= alpha d, r_u -= alpha q_u, rh -= alpha qh;
+// partial delta' = <rh, r> = rh_u . r_u + rh_v . M^{-1} rh_v
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void f2_cg_update_kernel(F2Geom g, double *z, double *ru,
+                                                                   double *rh, const T *d,
+                                                                   const double *qu, const T *qh,
+                                                                   const T *lam, const double *sc,
+                                                                   double *partials) {
+  const double alpha = sc[kAlpha];
+  const size_t fs = g.fs;
+  double acc = 0.0;
+  F2_NODES(g)
+  z[o] -= alpha * (double)d[o];
+  z[o + fs] -= alpha * (double)d[o + fs];
+  const double rn = ru[o] - alpha * qu[o];
+  ru[o] = rn;
+  const double rhu = rh[o] - alpha * (double)qh[o];
+  const double rhv = rh[o + fs] - alpha * (double)qh[o + fs];
+  rh[o] = rhu;
+  rh[o + fs] = rhv;
+  acc += rhu * rn + rhv * rhv * minv_at(g, lam, o, i, j, k);
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// delta = <rh, r> with r_v = M^{-1} rh_v
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void f2_delta_kernel(F2Geom g, const double *ru,
+                                                               const double *rh, const T *lam,
+                                                               double *partials) {
+  const size_t fs = g.fs;
+  double acc = 0.0;
+  F2_NODES(g)
+  acc += rh[o] * ru[o] + rh[o + fs] * rh[o + fs] * minv_at(g, lam, o, i, j, k);
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// Step 5.7: d = r + beta d  (d_u = r_u + beta d_u, d_v = M^{-1} rh_v + beta d_v); beta from sc,
+// or 0 when `first` (d = r)
+template <typename T>
+__global__ void f2_direction_kernel(F2Geom g, T *d, const double *ru, const double *rh,
+                                    const T *lam, const double *sc, int first) {
+  const size_t fs = g.fs;
+  const double beta = first ? 0.0 : sc[kBeta];
+  F2_NODES(g)
+  d[o] = (T)(ru[o] + beta * (double)d[o]);
+  d[o + fs] = (T)(minv_at(g, lam, o, i, j, k) * rh[o + fs] + beta * (double)d[o + fs]);
+  }
+}
+
+// q_v = M^{-1} qh_v on the free nodes (the velocity block of the Riesz map)
+template <typename T>
+__global__ void f2_mass_inverse_kernel(F2Geom g, const T *qh_v, double *q_v, const T *lam) {
+  const size_t n = g.fs;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const double hh = g.h * g.h / (g.dt * g.dt);
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
+    const int i = (int)(o % g.px);
+    const int j = (int)((o / g.px) % (g.ny + 1));
+    const int k = (int)(o / g.plane);
+    if (i > g.nx || masked(g, i, j, k)) {
+      q_v[o] = 0.0;
+      continue;
+    }
+    const double l = lam ? (double)lam[o] : g.lam_const;
+    const double c2 = l * hh;
+    q_v[o] = (double)qh_v[o] * c2 / (g.h * g.h * g.h * eta_of(g, i, j, k));
+  }
+}
+
+template <typename T>
+__global__ void f2_setup_kernel(F2Geom g, const double *c, double c_const, const double *fre,
+                                const double *fim, const double *gre, const double *gim,
+                                T *lam, T *Fre, T *Fim) {
+  const size_t n = g.fs;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
+    const int i = (int)(o % g.px);
+    const int j = (int)((o / g.px) % (ny + 1));
+    const int k = (int)(o / g.plane);
+    if (i > nx) {
+      if (lam) lam[o] = T(0);
+      if (Fre) Fre[o] = T(0);
+      if (Fim) Fim[o] = T(0);
+      continue;
+    }
+    const size_t u = ((size_t)k * (ny + 1) + j) * (nx + 1) + i;   // packed user index
+    const double cv = c ? c[u] : c_const;
+    const double l = (cv * g.dt / g.h) * (cv * g.dt / g.h);
+    if (lam) lam[o] = (T)l;
+    if (Fre) {
+      double ar = fre ? fre[u] : 0.0, ai = fim ? fim[u] : 0.0;
+      if (gre || gim) {
+        // faces -x, +x, -y, +y, -z, +z; nodes in order of the remaining axes, slower first
+        const size_t sx = (size_t)(nz + 1) * (ny + 1), sy = (size_t)(nz + 1) * (nx + 1);
+        const size_t off[6] = {0, sx, 2 * sx, 2 * sx + sy, 2 * sx + 2 * sy,
+                               2 * sx + 2 * sy + (size_t)(ny + 1) * (nx + 1)};
+        const bool on[6] = {i == 0, i == nx, j == 0, j == ny, k == 0, k == nz};
+        const size_t along[6] = {(size_t)k * (ny + 1) + j, (size_t)k * (ny + 1) + j,
+                                 (size_t)k * (nx + 1) + i, (size_t)k * (nx + 1) + i,
+                                 (size_t)j * (nx + 1) + i, (size_t)j * (nx + 1) + i};
+        for (int f = 0; f < 6; ++f) {
+          if (!on[f] || !g.abs_face[f]) continue;
+          if (gre) ar += 2.0 / g.h * gre[off[f] + along[f]];
+          if (gim) ai += 2.0 / g.h * gim[off[f] + along[f]];
+        }
+      }
+      const double s = g.dt * g.dt * cv * cv;
+      Fre[o] = (T)(s * ar);
+      if (Fim) Fim[o] = (T)(s * ai);
+    }
+  }
+}
+
+// packed user node array (FP64) <-> device layout (T), two fields
+template <typename T>
+__global__ void f2_unpack_kernel(F2Geom g, const double *packed, T *dev, int nfields) {
+  const size_t n = g.fs;
+  const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
+    const int i = (int)(o % g.px);
+    const int j = (int)((o / g.px) % (g.ny + 1));
+    const int k = (int)(o / g.plane);
+    for (int f = 0; f < nfields; ++f) {
+      T v = T(0);
+      if (i <= g.nx && !masked(g, i, j, k)) {
+        const size_t u = ((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i;
+        v = (T)packed[f * nn + u];
+      }
+      dev[o + f * n] = v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void f2_pack_kernel(F2Geom g, const T *dev, double *packed, int nfields) {
+  const size_t n = g.fs;
+  const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
+    const int i = (int)(o % g.px);
+    if (i > g.nx) continue;
+    const int j = (int)((o / g.px) % (g.ny + 1));
+    const int k = (int)(o / g.plane);
+    const size_t u = ((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i;
+    for (int f = 0; f < nfields; ++f) packed[f * nn + u] = (double)dev[o + f * n];
+  }
+}
+
+inline int gridn(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s) {
+  dim3 grid((g.nx + 1 + 63) / 64, (g.ny + 1 + 3) / 4, (g.nz + 1 + g.kchunk - 1) / g.kchunk);
+  dim3 block(256);
+  switch (mode) {
+#define CASE(M) \
+  case M: hipLaunchKernelGGL((f2_march_kernel<T, M>), grid, block, 0, s, g, p); break;
+    CASE(kF2FwdStart)
+    CASE(kF2FwdStep)
+    CASE(kF2FwdEnd)
+    CASE(kF2Metric)
+    CASE(kF2AdjInit)
+    CASE(kF2AdjStepFirst)
+    CASE(kF2AdjStep)
+    CASE(kF2AdjEnd)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename TA, typename TB>
+hipError_t dot_plain(const TA *a, const TB *b, size_t n, double *partials, hipStream_t s) {
+  hipLaunchKernelGGL((dot_kernel<TA, TB>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, a, b, n,
+                     partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t f2_cg_update(const F2Geom &g, double *z, double *ru, double *rh, const T *d,
+                        const double *qu, const T *qh, const T *lam, const double *sc,
+                        double *partials, hipStream_t s) {
+  hipLaunchKernelGGL((f2_cg_update_kernel<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, z, ru,
+                     rh, d, qu, qh, lam, sc, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t f2_delta(const F2Geom &g, const double *ru, const double *rh, const T *lam,
+                    double *partials, hipStream_t s) {
+  hipLaunchKernelGGL((f2_delta_kernel<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, ru, rh,
+                     lam, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t f2_direction(const F2Geom &g, T *d, const double *ru, const double *rh, const T *lam,
+                        const double *sc, int first, hipStream_t s) {
+  hipLaunchKernelGGL((f2_direction_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, d, ru, rh,
+                     lam, sc, first);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t f2_mass_inverse(const F2Geom &g, const T *qh_v, double *q_v, const T *lam,
+                           hipStream_t s) {
+  hipLaunchKernelGGL((f2_mass_inverse_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, qh_v, q_v,
+                     lam);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t f2_setup(const F2Geom &g, const double *c, double c_const, const double *fre,
+                    const double *fim, const double *gre, const double *gim, T *lam, T *Fre, T *Fim,
+                    hipStream_t s) {
+  hipLaunchKernelGGL((f2_setup_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, c, c_const, fre,
+                     fim, gre, gim, lam, Fre, Fim);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t f2_unpack(const F2Geom &g, const double *packed, T *dev, int nfields, hipStream_t s) {
+  hipLaunchKernelGGL((f2_unpack_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, packed, dev,
+                     nfields);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, hipStream_t s) {
+  hipLaunchKernelGGL((f2_pack_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, dev, packed,
+                     nfields);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                   \
+  template hipError_t f2_march<T>(int, const F2Geom &, const F2Args<T> &, hipStream_t);          \
+  template hipError_t f2_cg_update<T>(const F2Geom &, double *, double *, double *, const T *,   \
+                                      const double *, const T *, const T *, const double *,      \
+                                      double *, hipStream_t);                                    \
+  template hipError_t f2_delta<T>(const F2Geom &, const double *, const double *, const T *,     \
+                                  double *, hipStream_t);                                        \
+  template hipError_t f2_direction<T>(const F2Geom &, T *, const double *, const double *,       \
+                                      const T *, const double *, int, hipStream_t);              \
+  template hipError_t f2_mass_inverse<T>(const F2Geom &, const T *, double *, const T *,         \
+                                         hipStream_t);                                            \
+  template hipError_t f2_setup<T>(const F2Geom &, const double *, double, const double *,        \
+                                  const double *, const double *, const double *, T *, T *, T *, \
+                                  hipStream_t);                                                   \
+  template hipError_t f2_unpack<T>(const F2Geom &, const double *, T *, int, hipStream_t);       \
+  template hipError_t f2_pack<T>(const F2Geom &, const T *, double *, int, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+template hipError_t dot_plain<double, double>(const double *, const double *, size_t, double *, hipStream_t);
+template hipError_t dot_plain<float, float>(const float *, const float *, size_t, double *, hipStream_t);
+template hipError_t dot_plain<double, float>(const double *, const float *, size_t, double *, hipStream_t);
+template hipError_t dot_plain<float, double>(const float *, const double *, size_t, double *, hipStream_t);
+
+}  // namespace cmcg

@@ -1,12 +1,569 @@
-// Second-order (nodal, 3D) solver: not built yet.
+// Second-order (nodal, 3D) solver runtime: memory plan, the forward / backward period sequences,
+// the energy metric, the Riesz map, and the CG driver of the CMCG Algorithm (Sec. 2.3, Steps 1-6).
+//
+// One CG iteration (Step 5):  w = E d - d;  y = M_E w;  qh = E^T y - y  (the literal transpose
+// of the discrete period, discretise-then-optimise);  q = P qh with P = blockdiag(S^{-1}, M^{-1})
+// (Riesz representer, eq. CMCG_PRECONDITIONIER; with no sound-soft node S^{-1} acts on zero-sum
+// vectors);  alpha = delta / <qh, d>;  z -= alpha d, r -= alpha q, rh -= alpha qh;
+// delta' = <rh, r>;  beta = delta' / delta;  d = r + beta d.  r_v = M^{-1} rh_v is not stored.
+// Precision policy as in the first-order solver: FP32-mixed runs the CG periods in FP32 and
+// refreshes the true gradient with FP64 periods (reliable updates); z, residuals, the Riesz solve
+// and every reduction are FP64.
+#include "f2_internal.h"
 #include "solver.h"
 
 namespace cmcg {
+namespace {
 
-cmcg_status make_f2_solver(const cmcg_problem *, const SolverConfig &, Solver **out) {
+template <typename T>
+T *tp(void *p) { return static_cast<T *>(p); }
+template <typename T>
+const T *tpc(const void *p) { return static_cast<const T *>(p); }
+
+__global__ void mask_unpack_kernel(F2Geom g, const uint8_t *packed, uint8_t *dev) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < g.fs; o += stride) {
+    const int i = (int)(o % g.px);
+    const int j = (int)((o / g.px) % (g.ny + 1));
+    const int k = (int)(o / g.plane);
+    dev[o] = (i <= g.nx) ? packed[((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i] : 0;
+  }
+}
+
+// filter output u = (2/N) (Ure + i Uim), copied into a contiguous node array
+__global__ void f2_output_kernel(F2Geom g, const double *ure, const double *uim, double scale,
+                                 double *ore, double *oim) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < g.fs; o += stride) {
+    const int i = (int)(o % g.px);
+    if (i > g.nx) continue;
+    const int j = (int)((o / g.px) % (g.ny + 1));
+    const int k = (int)(o / g.plane);
+    const size_t u = ((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i;
+    ore[u] = scale * ure[o];
+    oim[u] = scale * uim[o];
+  }
+}
+
+int gridn(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+struct F2Set {
+  int prec = CMCG_FP64;
+  void *A = nullptr, *B = nullptr, *C = nullptr;   // three-level state buffers (one field each)
+  void *W = nullptr, *Y = nullptr;                 // two-field: period output / metric output
+  void *lam = nullptr, *Fre = nullptr, *Fim = nullptr;
+};
+
+class F2Solver final : public Solver {
+ public:
+  F2Geom g;
+  SolverConfig cfg;
+  hipStream_t s = nullptr;
+  DeviceArena arena;
+  PhaseEvents ev;
+  F2Set lo, hi;
+  bool mixed = false;
+  uint8_t *mask = nullptr;
+  void *D = nullptr;                 // direction (lo, two fields)
+  double *Z = nullptr;               // iterate (two fields)
+  double *RU = nullptr;              // primal residual, u block
+  double *RH = nullptr;              // dual residual (two fields)
+  double *QU = nullptr;              // Riesz output, u block
+  double *Ure = nullptr, *Uim = nullptr;
+  double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
+  RieszMG mg;
+  bool started = false;
+  int iter = 0, refreshes = 0;
+  long long riesz_iters = 0;
+  double rel = 1.0, delta_at_refresh = 0.0;
+  double riesz_tol = 1e-10;
+  int riesz_max = 500;
+  double t_fwd = 0, t_adj = 0, t_riesz = 0, t_other = 0, t_total = 0, updates = 0;
+
+  ~F2Solver() override {
+    if (s) (void)hipStreamSynchronize(s);
+    if (h_scalars) (void)hipHostFree(h_scalars);
+  }
+  size_t device_bytes() const override { return arena.bytes(); }
+
+  cmcg_status alloc_set(F2Set &b, int prec, bool var_c, bool forced, bool has_im) {
+    const size_t esz = prec == CMCG_FP64 ? sizeof(double) : sizeof(float);
+    b.prec = prec;
+    CMCG_TRY(arena.alloc(g.fs * esz, &b.A, s));
+    CMCG_TRY(arena.alloc(g.fs * esz, &b.B, s));
+    CMCG_TRY(arena.alloc(g.fs * esz, &b.C, s));
+    CMCG_TRY(arena.alloc(2 * g.fs * esz, &b.W, s));
+    CMCG_TRY(arena.alloc(2 * g.fs * esz, &b.Y, s));
+    if (var_c) CMCG_TRY(arena.alloc(g.fs * esz, &b.lam, s));
+    if (forced) CMCG_TRY(arena.alloc(g.fs * esz, &b.Fre, s));
+    if (forced && has_im) CMCG_TRY(arena.alloc(g.fs * esz, &b.Fim, s));
+    return CMCG_OK;
+  }
+
+  cmcg_status create(const cmcg_problem *P) {
+    s = cfg.stream;
+    g.nx = (int)P->n[0];
+    g.ny = (int)P->n[1];
+    g.nz = (int)P->n[2];
+    g.px = (g.nx + 1 + 63) / 64 * 64;
+    g.plane = (size_t)g.px * (g.ny + 1);
+    g.fs = g.plane * (g.nz + 1);
+    g.h = cfg.h;
+    g.dt = cfg.dt;
+    for (int f = 0; f < 6; ++f) g.abs_face[f] = P->face_bc[f] == CMCG_ABSORBING ? 1 : 0;
+    g.lam_const = (P->c_const * cfg.dt / cfg.h) * (P->c_const * cfg.dt / cfg.h);
+    g.kchunk = 64;
+    mixed = cfg.prec == CMCG_FP32_MIXED;
+    riesz_tol = cfg.riesz_tol > 0 ? cfg.riesz_tol : 1e-10;
+    riesz_max = cfg.riesz_max_iter > 0 ? cfg.riesz_max_iter : 500;
+    CMCG_TRY(ev.init(10));
+    CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
+    std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
+    const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    // sound-soft mask and its bounding box
+    if (P->sound_soft) {
+      // bounding box of the sound-soft nodes (kernels skip the mask outside it)
+      int lo3[3] = {1 << 30, 1 << 30, 1 << 30}, hi3[3] = {-1, -1, -1};
+      for (int k = 0; k <= g.nz; ++k)
+        for (int j = 0; j <= g.ny; ++j) {
+          const uint8_t *row = P->sound_soft + ((size_t)k * (g.ny + 1) + j) * (g.nx + 1);
+          for (int i = 0; i <= g.nx; ++i)
+            if (row[i]) {
+              lo3[0] = std::min(lo3[0], i), hi3[0] = std::max(hi3[0], i);
+              lo3[1] = std::min(lo3[1], j), hi3[1] = std::max(hi3[1], j);
+              lo3[2] = std::min(lo3[2], k), hi3[2] = std::max(hi3[2], k);
+            }
+        }
+      if (hi3[0] >= 0) {
+        DeviceArena tmp;
+        uint8_t *dm = nullptr;
+        CMCG_TRY(tmp.alloc_n(nn, &dm, s));
+        CMCG_HIP(hipMemcpyAsync(dm, P->sound_soft, nn, hipMemcpyHostToDevice, s));
+        CMCG_TRY(arena.alloc_n(g.fs, &mask, s));
+        hipLaunchKernelGGL(mask_unpack_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, dm, mask);
+        CMCG_HIP(hipGetLastError());
+        CMCG_HIP(hipStreamSynchronize(s));
+        g.mask = mask;
+        for (int a = 0; a < 3; ++a) {
+          g.mlo[a] = lo3[a];
+          g.mhi[a] = hi3[a];
+        }
+      }
+    }
+    const bool var_c = P->c != nullptr;
+    const bool forced = P->f_re || P->f_im || P->gS_re || P->gS_im;
+    const bool has_im = P->f_im || P->gS_im;
+    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im));
+    if (mixed) CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, var_c, forced, has_im));
+    else lo = hi;
+    CMCG_TRY(arena.alloc(2 * g.fs * (mixed ? sizeof(float) : sizeof(double)), &D, s));
+    CMCG_TRY(arena.alloc_n(2 * g.fs, &Z, s));
+    CMCG_TRY(arena.alloc_n(g.fs, &RU, s));
+    CMCG_TRY(arena.alloc_n(2 * g.fs, &RH, s));
+    CMCG_TRY(arena.alloc_n(g.fs, &QU, s));
+    CMCG_TRY(arena.alloc_n(g.fs, &Ure, s));
+    CMCG_TRY(arena.alloc_n(g.fs, &Uim, s));
+    CMCG_TRY(arena.alloc_n(kRedBlocks, &partials, s));
+    CMCG_TRY(arena.alloc_n(kNumScalars, &scalars, s));
+    // coefficients and load
+    {
+      const size_t sx = (size_t)(g.nz + 1) * (g.ny + 1), sy = (size_t)(g.nz + 1) * (g.nx + 1),
+                   sz = (size_t)(g.ny + 1) * (g.nx + 1);
+      const size_t nface = 2 * (sx + sy + sz);
+      DeviceArena tmp;
+      const double *src[5] = {P->c, P->f_re, P->f_im, P->gS_re, P->gS_im};
+      const size_t len[5] = {nn, nn, nn, nface, nface};
+      double *dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+      for (int k = 0; k < 5; ++k) {
+        if (!src[k]) continue;
+        CMCG_TRY(tmp.alloc_n(len[k], &dev[k], s));
+        CMCG_HIP(hipMemcpyAsync(dev[k], src[k], len[k] * sizeof(double), hipMemcpyHostToDevice, s));
+      }
+      CMCG_HIP(f2_setup<double>(g, dev[0], P->c_const, dev[1], dev[2], dev[3], dev[4],
+                                tp<double>(hi.lam), tp<double>(hi.Fre), tp<double>(hi.Fim), s));
+      if (mixed)
+        CMCG_HIP(f2_setup<float>(g, dev[0], P->c_const, dev[1], dev[2], dev[3], dev[4],
+                                 tp<float>(lo.lam), tp<float>(lo.Fre), tp<float>(lo.Fim), s));
+      CMCG_HIP(hipStreamSynchronize(s));
+    }
+    CMCG_TRY(mg.build(g, arena, s));
+    return CMCG_OK;
+  }
+
+  // ------------------------------------------------------------------ periods
+  template <typename T>
+  cmcg_status fwd_t(const F2Set &b, bool forced, const T *zin, T *out, const T *sub, bool filter) {
+    const int N = cfg.N;
+    F2Args<T> p;
+    p.lam = tpc<T>(b.lam);
+    p.fre = tpc<T>(b.Fre);
+    p.fim = tpc<T>(b.Fim);
+    p.forced = (forced && b.Fre) ? 1 : 0;
+    if (filter) {
+      p.ure = Ure;
+      p.uim = Uim;
+    }
+    T *buf[3] = {tp<T>(b.A), tp<T>(b.B), tp<T>(b.C)};
+    // start map: u^1 from (u^0, v^0)
+    p.st = zin;
+    p.aux = zin + g.fs;
+    p.out = buf[0];
+    p.fcos = 1.0;
+    p.fsin = 0.0;
+    p.wcos = 1.0;
+    p.wsin = 0.0;
+    CMCG_HIP(f2_march<T>(kF2FwdStart, g, p, s));
+    const T *prev = zin;
+    int cur = 0;
+    for (int n = 1; n < N; ++n) {
+      const double t = n * cfg.dt;
+      p.fcos = std::cos(cfg.omega * t);
+      p.fsin = std::sin(cfg.omega * t);
+      p.wcos = p.fcos;
+      p.wsin = p.fsin;
+      const int nxt = (cur + 1) % 3;
+      p.st = buf[cur];
+      p.aux = prev;
+      p.out = buf[nxt];
+      CMCG_HIP(f2_march<T>(kF2FwdStep, g, p, s));
+      prev = buf[cur];
+      cur = nxt;
+    }
+    // end map: (u^N, v^N) with v^N = (u^{N+1} - u^{N-1}) / (2 dt)
+    p.ure = p.uim = nullptr;
+    p.fcos = std::cos(cfg.omega * N * cfg.dt);
+    p.fsin = std::sin(cfg.omega * N * cfg.dt);
+    p.st = buf[cur];
+    p.aux = prev;
+    p.out = out;
+    p.sub = sub;
+    CMCG_HIP(f2_march<T>(kF2FwdEnd, g, p, s));
+    updates += (double)(N + 1) * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    return CMCG_OK;
+  }
+
+  template <typename T>
+  cmcg_status metric_t(const F2Set &b, const T *w, T *y) {
+    F2Args<T> p;
+    p.lam = tpc<T>(b.lam);
+    p.st = w;
+    p.aux = w + g.fs;
+    p.out = y;
+    CMCG_HIP(f2_march<T>(kF2Metric, g, p, s));
+    return CMCG_OK;
+  }
+
+  // out = E^T y (- sub)
+  template <typename T>
+  cmcg_status adj_t(const F2Set &b, const T *y, T *out, const T *sub) {
+    const int N = cfg.N;
+    F2Args<T> p;
+    p.lam = tpc<T>(b.lam);
+    T *buf[3] = {tp<T>(b.A), tp<T>(b.B), tp<T>(b.C)};
+    // transposed end map: a_0 (A), b_0 (B)
+    p.st = y + g.fs;
+    p.aux = y;
+    p.out = buf[0];
+    p.out2 = buf[1];
+    CMCG_HIP(f2_march<T>(kF2AdjInit, g, p, s));
+    p.out2 = nullptr;
+    // first transposed step: a_1 = K^T a_0 + b_0 -> C
+    p.st = buf[0];
+    p.aux = buf[1];
+    p.out = buf[2];
+    CMCG_HIP(f2_march<T>(kF2AdjStepFirst, g, p, s));
+    int prev = 0, cur = 2;
+    for (int m = 1; m < N - 1; ++m) {
+      const int nxt = 3 - prev - cur;
+      p.st = buf[cur];
+      p.aux = buf[prev];
+      p.out = buf[nxt];
+      CMCG_HIP(f2_march<T>(kF2AdjStep, g, p, s));
+      prev = cur;
+      cur = nxt;
+    }
+    // transposed start map
+    p.st = buf[cur];
+    p.aux = buf[prev];
+    p.out = out;
+    p.sub = sub;
+    CMCG_HIP(f2_march<T>(kF2AdjEnd, g, p, s));
+    updates += (double)(N + 1) * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    return CMCG_OK;
+  }
+
+  cmcg_status fwd(const F2Set &b, bool forced, const void *zin, void *out, const void *sub,
+                  bool filter) {
+    if (b.prec == CMCG_FP64)
+      return fwd_t<double>(b, forced, tpc<double>(zin), tp<double>(out), tpc<double>(sub), filter);
+    return fwd_t<float>(b, forced, tpc<float>(zin), tp<float>(out), tpc<float>(sub), filter);
+  }
+  cmcg_status metric(const F2Set &b, const void *w, void *y) {
+    if (b.prec == CMCG_FP64) return metric_t<double>(b, tpc<double>(w), tp<double>(y));
+    return metric_t<float>(b, tpc<float>(w), tp<float>(y));
+  }
+  cmcg_status adj(const F2Set &b, const void *y, void *out, const void *sub) {
+    if (b.prec == CMCG_FP64) return adj_t<double>(b, tpc<double>(y), tp<double>(out), tpc<double>(sub));
+    return adj_t<float>(b, tpc<float>(y), tp<float>(out), tpc<float>(sub));
+  }
+
+  // qh = (E^T - I) M_E (E z - z [+ s])  into set b's W (the metric output Y is the subtrahend)
+  cmcg_status gradient_dual(const F2Set &b, bool forced, const void *zin) {
+    CMCG_TRY(fwd(b, forced, zin, b.W, zin, false));
+    CMCG_TRY(metric(b, b.W, b.Y));
+    CMCG_TRY(adj(b, b.Y, b.W, b.Y));
+    return CMCG_OK;
+  }
+
+  cmcg_status riesz_u(const void *qh_u, int is_float, double *out) {
+    int it = 0;
+    CMCG_HIP(hipEventRecord(ev[8], s));
+    CMCG_TRY(mg.solve(qh_u, is_float, out, riesz_tol, riesz_max, &it));
+    CMCG_HIP(hipEventRecord(ev[9], s));
+    CMCG_HIP(hipEventSynchronize(ev[9]));
+    t_riesz += PhaseEvents::seconds(ev[8], ev[9]);
+    riesz_iters += it;
+    return CMCG_OK;
+  }
+
+  cmcg_status read_scalars() {
+    CMCG_HIP(hipMemcpyAsync(h_scalars, scalars, kNumScalars * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  // true gradient at the FP64 iterate: RH = qh (dual), RU = S^{-1} qh_u; delta via `mode`
+  cmcg_status true_gradient(int mode) {
+    CMCG_TRY(gradient_dual(hi, true, Z));
+    CMCG_HIP(hipMemcpyAsync(RH, hi.W, 2 * g.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    CMCG_TRY(riesz_u(RH, 0, RU));
+    CMCG_HIP(f2_delta<double>(g, RU, RH, tpc<double>(hi.lam), partials, s));
+    CMCG_HIP(finalize(partials, kRedBlocks, scalars, mode, 0, s));
+    return CMCG_OK;
+  }
+
+  cmcg_status direction(int first) {
+    if (mixed) CMCG_HIP(f2_direction<float>(g, tp<float>(D), RU, RH, tpc<float>(lo.lam), scalars, first, s));
+    else CMCG_HIP(f2_direction<double>(g, tp<double>(D), RU, RH, tpc<double>(lo.lam), scalars, first, s));
+    return CMCG_OK;
+  }
+
+  // ------------------------------------------------------------------ CG driver
+  cmcg_status begin() override {
+    t_fwd = t_adj = t_riesz = t_other = t_total = 0.0;
+    updates = 0;
+    iter = refreshes = 0;
+    riesz_iters = 0;
+    CMCG_HIP(hipEventRecord(ev[0], s));
+    CMCG_HIP(hipMemsetAsync(Z, 0, 2 * g.fs * sizeof(double), s));
+    CMCG_TRY(true_gradient(kFinStart));
+    CMCG_TRY(direction(1));
+    CMCG_HIP(hipEventRecord(ev[1], s));
+    CMCG_TRY(read_scalars());
+    t_other += PhaseEvents::seconds(ev[0], ev[1]);
+    rel = 1.0;
+    delta_at_refresh = h_scalars[kDelta];
+    started = true;
+    if (h_scalars[kBreak] != 0.0) return set_error("non-finite initial gradient"), CMCG_EBREAKDOWN;
+    return CMCG_OK;
+  }
+
+  cmcg_status iterate(int iters, int *converged) override {
+    if (!started) return set_error("cmcg_begin first"), CMCG_EINVAL;
+    *converged = (rel <= cfg.tol || h_scalars[kDelta0] == 0.0) ? 1 : 0;
+    for (int it = 0; it < iters && !*converged; ++it) {
+      CMCG_HIP(hipEventRecord(ev[2], s));
+      // Step 5.1: w = E d - d, y = M_E w, qh = E^T y - y
+      CMCG_TRY(fwd(lo, false, D, lo.W, D, false));
+      CMCG_TRY(metric(lo, lo.W, lo.Y));
+      CMCG_HIP(hipEventRecord(ev[3], s));
+      CMCG_TRY(adj(lo, lo.Y, lo.W, lo.Y));
+      CMCG_HIP(hipEventRecord(ev[4], s));
+      // Step 5.2: q_u = S^{-1} qh_u (q_v = M^{-1} qh_v is applied on the fly)
+      CMCG_TRY(riesz_u(lo.W, mixed ? 1 : 0, QU));
+      CMCG_HIP(hipEventRecord(ev[5], s));
+      // Steps 5.3-5.6
+      if (mixed) {
+        CMCG_HIP(dot_plain<float, float>(tpc<float>(lo.W), tpc<float>(D), 2 * g.fs, partials, s));
+        CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinAlpha, 0, s));
+        CMCG_HIP(f2_cg_update<float>(g, Z, RU, RH, tpc<float>(D), QU, tpc<float>(lo.W),
+                                     tpc<float>(lo.lam), scalars, partials, s));
+      } else {
+        CMCG_HIP(dot_plain<double, double>(tpc<double>(lo.W), tpc<double>(D), 2 * g.fs, partials, s));
+        CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinAlpha, 0, s));
+        CMCG_HIP(f2_cg_update<double>(g, Z, RU, RH, tpc<double>(D), QU, tpc<double>(lo.W),
+                                      tpc<double>(lo.lam), scalars, partials, s));
+      }
+      CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinBeta, 0, s));
+      CMCG_HIP(hipEventRecord(ev[6], s));
+      CMCG_TRY(read_scalars());
+      t_fwd += PhaseEvents::seconds(ev[2], ev[3]);
+      t_adj += PhaseEvents::seconds(ev[3], ev[4]);
+      t_other += PhaseEvents::seconds(ev[5], ev[6]);
+      ++iter;
+      if (h_scalars[kBreak] != 0.0)
+        return set_error("CG breakdown: <qhat, d> <= 0 or non-finite scalar"), CMCG_EBREAKDOWN;
+      rel = h_scalars[kRel];
+      if (mixed && cfg.refresh > 0.0 &&
+          (rel <= cfg.tol || h_scalars[kDelta] <= cfg.refresh * cfg.refresh * delta_at_refresh)) {
+        CMCG_HIP(hipEventRecord(ev[6], s));
+        CMCG_TRY(true_gradient(kFinRefresh));
+        CMCG_HIP(hipEventRecord(ev[7], s));
+        CMCG_TRY(read_scalars());
+        t_other += PhaseEvents::seconds(ev[6], ev[7]);
+        rel = h_scalars[kRel];
+        delta_at_refresh = h_scalars[kDelta];
+        ++refreshes;
+      }
+      if (rel <= cfg.tol) {
+        *converged = 1;
+        break;
+      }
+      CMCG_TRY(direction(0));
+    }
+    return CMCG_OK;
+  }
+
+  cmcg_status output(const double *z, double *u_re, double *u_im, bool record) {
+    CMCG_HIP(hipMemsetAsync(Ure, 0, g.fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Uim, 0, g.fs * sizeof(double), s));
+    CMCG_TRY(fwd(hi, true, z, hi.W, nullptr, true));
+    // contiguous node output staged in hi.Y (two fields of fs >= nn values)
+    double *ore = tp<double>(hi.Y), *oim = tp<double>(hi.Y) + g.fs;
+    hipLaunchKernelGGL(f2_output_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, Ure, Uim,
+                       2.0 / cfg.N, ore, oim);
+    CMCG_HIP(hipGetLastError());
+    if (record) CMCG_HIP(hipEventRecord(ev[7], s));
+    const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    if (u_re) CMCG_HIP(hipMemcpyAsync(u_re, ore, nn * sizeof(double), hipMemcpyDefault, s));
+    if (u_im) CMCG_HIP(hipMemcpyAsync(u_im, oim, nn * sizeof(double), hipMemcpyDefault, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status finish(double *u_re, double *u_im) override {
+    if (!started) return set_error("cmcg_begin first"), CMCG_EINVAL;
+    return output(Z, u_re, u_im, true);
+  }
+
+  cmcg_status solve(double *u_re, double *u_im) override {
+    CMCG_TRY(begin());
+    int conv = 0;
+    CMCG_TRY(iterate(cfg.max_iter, &conv));
+    CMCG_HIP(hipEventRecord(ev[6], s));
+    CMCG_TRY(finish(u_re, u_im));
+    t_other += PhaseEvents::seconds(ev[6], ev[7]);
+    t_total = PhaseEvents::seconds(ev[0], ev[7]);
+    return conv ? CMCG_OK : CMCG_ENOTCONV;
+  }
+
+  // ------------------------------------------------------------------ stage calls
+  cmcg_status apply(int op, int steps, const double *in, double *out) override {
+    if (steps != 0) return set_error("second-order periods take steps = 0"), CMCG_EINVAL;
+    // stage the packed input into set lo's Y, run, pack lo's W
+    if (lo.prec == CMCG_FP64) CMCG_HIP(f2_unpack<double>(g, in, tp<double>(lo.Y), 2, s));
+    else CMCG_HIP(f2_unpack<float>(g, in, tp<float>(lo.Y), 2, s));
+    if (op == CMCG_OP_FORWARD || op == CMCG_OP_FORCED) {
+      CMCG_TRY(fwd(lo, op == CMCG_OP_FORCED, lo.Y, lo.W, nullptr, false));
+    } else if (op == CMCG_OP_ADJOINT) {
+      // the literal transpose E^T (not weighted by M_E: M_E is singular without sound-soft nodes)
+      CMCG_TRY(adj(lo, lo.Y, lo.W, nullptr));
+    } else {
+      // P y = (S^{-1} y_u, M^{-1} y_v), FP64
+      CMCG_HIP(f2_unpack<double>(g, in, tp<double>(hi.Y), 2, s));
+      CMCG_TRY(riesz_u(hi.Y, 0, QU));
+      CMCG_HIP(f2_mass_inverse<double>(g, tp<double>(hi.Y) + g.fs, tp<double>(hi.W) + g.fs,
+                                       tpc<double>(hi.lam), s));
+      CMCG_HIP(hipMemcpyAsync(hi.W, QU, g.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+      CMCG_HIP(f2_pack<double>(g, tp<double>(hi.W), out, 2, s));
+      CMCG_HIP(hipStreamSynchronize(s));
+      return CMCG_OK;
+    }
+    if (lo.prec == CMCG_FP64) CMCG_HIP(f2_pack<double>(g, tp<double>(lo.W), out, 2, s));
+    else CMCG_HIP(f2_pack<float>(g, tp<float>(lo.W), out, 2, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status filter(const double *z, double *u_re, double *u_im) override {
+    // stage z in hi.W (the forced period writes only A/B/C and its output, here hi.Y is free)
+    CMCG_HIP(f2_unpack<double>(g, z, tp<double>(hi.W), 2, s));
+    CMCG_HIP(hipMemsetAsync(Ure, 0, g.fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Uim, 0, g.fs * sizeof(double), s));
+    CMCG_TRY(fwd(hi, true, hi.W, hi.Y, nullptr, true));
+    double *ore = tp<double>(hi.W), *oim = tp<double>(hi.W) + g.fs;
+    hipLaunchKernelGGL(f2_output_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, Ure, Uim,
+                       2.0 / cfg.N, ore, oim);
+    CMCG_HIP(hipGetLastError());
+    const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    if (u_re) CMCG_HIP(hipMemcpyAsync(u_re, ore, nn * sizeof(double), hipMemcpyDefault, s));
+    if (u_im) CMCG_HIP(hipMemcpyAsync(u_im, oim, nn * sizeof(double), hipMemcpyDefault, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status get_state(int which, double *out) override {
+    if (which == 0) {
+      CMCG_HIP(f2_pack<double>(g, Z, out, 2, s));
+    } else if (which == 1) {
+      // primal residual (r_u, M^{-1} rh_v)
+      CMCG_HIP(hipMemcpyAsync(hi.W, RU, g.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+      CMCG_HIP(f2_mass_inverse<double>(g, RH + g.fs, tp<double>(hi.W) + g.fs, tpc<double>(hi.lam), s));
+      CMCG_HIP(f2_pack<double>(g, tp<double>(hi.W), out, 2, s));
+    } else if (mixed) {
+      CMCG_HIP(f2_pack<float>(g, tp<float>(D), out, 2, s));
+    } else {
+      CMCG_HIP(f2_pack<double>(g, tp<double>(D), out, 2, s));
+    }
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  void report(cmcg_report *r) const override {
+    r->iterations = iter;
+    r->steps_per_period = cfg.N;
+    r->dt = cfg.dt;
+    r->rel_residual = rel;
+    r->seconds = t_total;
+    r->seconds_fwd = t_fwd;
+    r->seconds_adj = t_adj;
+    r->seconds_riesz = t_riesz;
+    r->seconds_other = t_other;
+    r->grid_updates = updates;
+    r->riesz_iterations = riesz_iters;
+    r->fp64_refreshes = refreshes;
+  }
+
+  void info(cmcg_info *i) const override {
+    const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    i->steps_per_period = cfg.N;
+    i->dt = cfg.dt;
+    i->T = cfg.T;
+    i->h = cfg.h;
+    i->state_len = 2 * nn;
+    i->field_len = nn;
+    i->device_bytes = (int64_t)arena.bytes();
+  }
+};
+
+}  // namespace
+
+cmcg_status make_f2_solver(const cmcg_problem *P, const SolverConfig &cfg, Solver **out) {
   *out = nullptr;
-  set_error("second-order formulation not built yet");
-  return CMCG_EUNSUPPORTED;
+  if (P->n[2] < 2) return set_error("second-order solver needs n[2] >= 2"), CMCG_EINVAL;
+  F2Solver *S = new F2Solver();
+  S->cfg = cfg;
+  cmcg_status st = S->create(P);
+  if (st != CMCG_OK) {
+    delete S;
+    return st;
+  }
+  *out = S;
+  return CMCG_OK;
 }
 
 }  // namespace cmcg

@@ -1,0 +1,352 @@
+// Riesz representer of eq. CMCG_PRECONDITIONIER on the device: the elliptic solve S x = b with the
+// mass-lumped nodal stiffness S = diag(h eta) L (L: 7-point operator with mirrored neighbours at
+// the box faces), homogeneous Dirichlet on sound-soft nodes.  Conjugate gradients in FP64,
+// preconditioned by a symmetric geometric multigrid V-cycle:
+//   * levels: cells halved per axis while every axis stays even and >= 2 cells; the coarse
+//     operator is the same discretisation with spacing 2h; a coarse node is sound-soft when the
+//     fine node at its position is;
+//   * smoother: damped Jacobi (the diagonal of S is 6 h eta), the same number of sweeps before and
+//     after the coarse correction, so the cycle is a symmetric operator;
+//   * transfers: trilinear prolongation P and restriction P^T, both restricted to free nodes;
+//   * coarsest level: a fixed number of Jacobi sweeps from zero (a fixed symmetric polynomial).
+// With no sound-soft node S is singular (constant vectors); right-hand side, preconditioned
+// residuals and the solution are kept zero-sum (plain sum over nodes).
+#include "f2_internal.h"
+#include "solver.h"
+
+namespace cmcg {
+namespace {
+
+__device__ __forceinline__ int mir(int i, int n) { return i < 0 ? 1 : (i > n ? n - 1 : i); }
+
+__device__ __forceinline__ double eta3(const F2Geom &g, int i, int j, int k) {
+  double e = 1.0;
+  if (i == 0 || i == g.nx) e *= 0.5;
+  if (j == 0 || j == g.ny) e *= 0.5;
+  if (k == 0 || k == g.nz) e *= 0.5;
+  return e;
+}
+
+__device__ __forceinline__ bool msk(const F2Geom &g, int i, int j, int k) {
+  if (!g.mask) return false;
+  if (i < g.mlo[0] || i > g.mhi[0] || j < g.mlo[1] || j > g.mhi[1] || k < g.mlo[2] || k > g.mhi[2])
+    return false;
+  return g.mask[g.idx(i, j, k)] != 0;
+}
+
+__device__ __forceinline__ double lap7(const F2Geom &g, const double *x, int i, int j, int k) {
+  const double c = x[g.idx(i, j, k)];
+  return 6.0 * c - (x[g.idx(mir(i - 1, g.nx), j, k)] + x[g.idx(mir(i + 1, g.nx), j, k)] +
+                    x[g.idx(i, mir(j - 1, g.ny), k)] + x[g.idx(i, mir(j + 1, g.ny), k)] +
+                    x[g.idx(i, j, mir(k - 1, g.nz))] + x[g.idx(i, j, mir(k + 1, g.nz))]);
+}
+
+#define NODE_LOOP(g)                                                                       \
+  const size_t stride_ = (size_t)gridDim.x * blockDim.x;                                   \
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < (g).fs; o += stride_) { \
+    const int i = (int)(o % (g).px);                                                       \
+    const int j = (int)((o / (g).px) % ((g).ny + 1));                                      \
+    const int k = (int)(o / (g).plane);                                                    \
+    if (i > (g).nx) continue;
+
+// y = R S x
+__global__ void s_apply_kernel(F2Geom g, const double *x, double *y) {
+  NODE_LOOP(g)
+  y[o] = msk(g, i, j, k) ? 0.0 : g.h * eta3(g, i, j, k) * lap7(g, x, i, j, k);
+  }
+}
+
+// r = R (b - S x)
+__global__ void residual_kernel(F2Geom g, const double *x, const double *b, double *r) {
+  NODE_LOOP(g)
+  r[o] = msk(g, i, j, k) ? 0.0 : b[o] - g.h * eta3(g, i, j, k) * lap7(g, x, i, j, k);
+  }
+}
+
+// damped Jacobi: xo = R (x + omega (b - S x) / (6 h eta))
+__global__ void jacobi_kernel(F2Geom g, const double *x, const double *b, double *xo, double omega,
+                              int from_zero) {
+  NODE_LOOP(g)
+  if (msk(g, i, j, k)) {
+    xo[o] = 0.0;
+    continue;
+  }
+  const double he = g.h * eta3(g, i, j, k);
+  if (from_zero) {
+    xo[o] = omega * b[o] / (6.0 * he);
+  } else {
+    xo[o] = x[o] + omega * (b[o] - he * lap7(g, x, i, j, k)) / (6.0 * he);
+  }
+  }
+}
+
+// bc = R_c P^T rf  (full weighting over the 27 fine neighbours of the coarse node's position)
+__global__ void restrict_kernel(F2Geom gf, F2Geom gc, const double *rf, double *bc) {
+  NODE_LOOP(gc)
+  if (msk(gc, i, j, k)) {
+    bc[o] = 0.0;
+    continue;
+  }
+  double acc = 0.0;
+  for (int dk = -1; dk <= 1; ++dk) {
+    const int fk = 2 * k + dk;
+    if (fk < 0 || fk > gf.nz) continue;
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int fj = 2 * j + dj;
+      if (fj < 0 || fj > gf.ny) continue;
+      for (int di = -1; di <= 1; ++di) {
+        const int fi = 2 * i + di;
+        if (fi < 0 || fi > gf.nx) continue;
+        const double w = (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0);
+        acc += w * rf[gf.idx(fi, fj, fk)];
+      }
+    }
+  }
+  bc[o] = acc;
+  }
+}
+
+// xf += R_f P xc  (trilinear interpolation)
+__global__ void prolong_add_kernel(F2Geom gf, F2Geom gc, const double *xc, double *xf) {
+  NODE_LOOP(gf)
+  if (msk(gf, i, j, k)) {
+    xf[o] = 0.0;
+    continue;
+  }
+  const int ci0 = i >> 1, ci1 = (i + 1) >> 1;
+  const int cj0 = j >> 1, cj1 = (j + 1) >> 1;
+  const int ck0 = k >> 1, ck1 = (k + 1) >> 1;
+  const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
+  double acc = 0.0;
+  const int is[2] = {ci0, ci1}, js[2] = {cj0, cj1}, ks[2] = {ck0, ck1};
+  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+  for (int c = 0; c < nk; ++c)
+    for (int b = 0; b < nj; ++b)
+      for (int a = 0; a < ni; ++a) acc += wi * wj * wk * xc[gc.idx(is[a], js[b], ks[c])];
+  xf[o] += acc;
+  }
+}
+
+// coarse mask: node I sound-soft iff the fine node 2I is
+__global__ void coarse_mask_kernel(F2Geom gf, F2Geom gc, const uint8_t *mf, uint8_t *mc) {
+  NODE_LOOP(gc)
+  mc[o] = mf[gf.idx(2 * i, 2 * j, 2 * k)];
+  }
+}
+
+// v -= s[slot] / count on real nodes (mean removal)
+__global__ void sub_mean_kernel(F2Geom g, double *v, const double *sc, int slot, double count) {
+  const double m = sc[slot] / count;
+  NODE_LOOP(g)
+  v[o] -= m;
+  }
+}
+
+__global__ void axpy2_kernel(double *x, double *r, const double *p, const double *q, double alpha,
+                             size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    x[k] += alpha * p[k];
+    r[k] -= alpha * q[k];
+  }
+}
+
+__global__ void xpay_kernel(double *p, const double *z, double beta, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+    p[k] = z[k] + beta * p[k];
+}
+
+__global__ void ones_kernel(double *v, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) v[k] = 1.0;
+}
+
+int gridn(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+}  // namespace
+
+RieszMG::~RieszMG() {
+  if (h_scal_) (void)hipHostFree(h_scal_);
+}
+
+cmcg_status RieszMG::build(const F2Geom &fine, DeviceArena &arena, hipStream_t s) {
+  s_ = s;
+  lv_.clear();
+  neumann_ = fine.mask == nullptr;
+  MGLevel L0;
+  L0.g = fine;
+  lv_.push_back(L0);
+  while (true) {
+    const F2Geom &g = lv_.back().g;
+    if (lv_.size() >= 12 || g.nx % 2 || g.ny % 2 || g.nz % 2 || g.nx < 4 || g.ny < 4 || g.nz < 4)
+      break;
+    MGLevel L;
+    L.g = g;
+    L.g.nx = g.nx / 2;
+    L.g.ny = g.ny / 2;
+    L.g.nz = g.nz / 2;
+    L.g.px = (L.g.nx + 1 + 63) / 64 * 64;
+    L.g.plane = (size_t)L.g.px * (L.g.ny + 1);
+    L.g.fs = L.g.plane * (L.g.nz + 1);
+    L.g.h = 2.0 * g.h;
+    for (int a = 0; a < 3; ++a) {
+      L.g.mlo[a] = g.mlo[a] / 2;
+      L.g.mhi[a] = (g.mhi[a] + 1) / 2;
+    }
+    L.g.mask = nullptr;
+    lv_.push_back(L);
+  }
+  for (size_t l = 0; l < lv_.size(); ++l) {
+    MGLevel &L = lv_[l];
+    if (l > 0) {
+      CMCG_TRY(arena.alloc_n(L.g.fs, &L.x, s));
+      CMCG_TRY(arena.alloc_n(L.g.fs, &L.b, s));
+    }
+    if (l > 0) CMCG_TRY(arena.alloc_n(L.g.fs, &L.r, s));
+    CMCG_TRY(arena.alloc_n(L.g.fs, &L.t, s));
+    if (l > 0 && fine.mask) {
+      CMCG_TRY(arena.alloc_n(L.g.fs, &L.maskbuf, s));
+      hipLaunchKernelGGL(coarse_mask_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s, lv_[l - 1].g,
+                         L.g, lv_[l - 1].g.mask, L.maskbuf);
+      CMCG_HIP(hipGetLastError());
+      L.g.mask = L.maskbuf;
+    }
+    L.nfree = (size_t)(L.g.nx + 1) * (L.g.ny + 1) * (L.g.nz + 1);
+  }
+  const size_t n = fine.fs;
+  CMCG_TRY(arena.alloc_n(n, &pr_, s));
+  CMCG_TRY(arena.alloc_n(n, &pz_, s));
+  CMCG_TRY(arena.alloc_n(n, &pp_, s));
+  CMCG_TRY(arena.alloc_n(n, &pq_, s));
+  lv_[0].r = pq_;   // S p is consumed before each V-cycle, so its buffer serves as the residual
+  CMCG_TRY(arena.alloc_n(kRedBlocks, &partials_, s));
+  CMCG_TRY(arena.alloc_n(kNumScalars, &scal_, s));
+  if (!h_scal_) CMCG_HIP(hipHostMalloc((void **)&h_scal_, kNumScalars * sizeof(double)));
+  CMCG_HIP(hipStreamSynchronize(s));
+  return CMCG_OK;
+}
+
+cmcg_status RieszMG::dot(const double *a, const double *b, size_t n, double *out) {
+  CMCG_HIP(dot_plain<double, double>(a, b, n, partials_, s_));
+  CMCG_HIP(finalize(partials_, kRedBlocks, scal_, kFinStore, 0, s_));
+  CMCG_HIP(hipMemcpyAsync(h_scal_, scal_, sizeof(double), hipMemcpyDeviceToHost, s_));
+  CMCG_HIP(hipStreamSynchronize(s_));
+  *out = h_scal_[0];
+  return CMCG_OK;
+}
+
+cmcg_status RieszMG::project(double *v, int l) {
+  // v <- v - (sum v) / count on real nodes (pure Neumann only); padding stays 0 in the sum
+  const F2Geom &g = lv_[l].g;
+  hipLaunchKernelGGL(ones_kernel, dim3(gridn(g.fs)), dim3(256), 0, s_, lv_[l].t, g.fs);
+  CMCG_HIP(hipGetLastError());
+  // padding of t must not count: the plain sum of v over all entries is its sum over real
+  // nodes because v is zero on padding
+  CMCG_HIP(dot_plain<double, double>(v, lv_[l].t, g.fs, partials_, s_));
+  CMCG_HIP(finalize(partials_, kRedBlocks, scal_, kFinStore, 1, s_));
+  hipLaunchKernelGGL(sub_mean_kernel, dim3(gridn(g.fs)), dim3(256), 0, s_, g, v, scal_, 1,
+                     (double)lv_[l].nfree);
+  CMCG_HIP(hipGetLastError());
+  return CMCG_OK;
+}
+
+cmcg_status RieszMG::smooth(int l, int sweeps) {
+  // `sweeps` damped Jacobi sweeps from x = 0, ping-pong between x and t, result left in x
+  MGLevel &L = lv_[l];
+  double *cur = L.x, *other = L.t;
+  for (int k = 0; k < sweeps; ++k) {
+    hipLaunchKernelGGL(jacobi_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s_, L.g, cur, L.b, other,
+                       omega_, k == 0 ? 1 : 0);
+    CMCG_HIP(hipGetLastError());
+    std::swap(cur, other);
+  }
+  if (cur != L.x)
+    CMCG_HIP(hipMemcpyAsync(L.x, cur, L.g.fs * sizeof(double), hipMemcpyDeviceToDevice, s_));
+  return CMCG_OK;
+}
+
+cmcg_status RieszMG::vcycle_level(int l) {
+  MGLevel &L = lv_[l];
+  const int last = (int)lv_.size() - 1;
+  if (l == last) {
+    CMCG_TRY(smooth(l, coarse_sweeps_));
+    return CMCG_OK;
+  }
+  CMCG_TRY(smooth(l, pre_));
+  hipLaunchKernelGGL(residual_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s_, L.g, L.x, L.b, L.r);
+  CMCG_HIP(hipGetLastError());
+  MGLevel &C = lv_[l + 1];
+  hipLaunchKernelGGL(restrict_kernel, dim3(gridn(C.g.fs)), dim3(256), 0, s_, L.g, C.g, L.r, C.b);
+  CMCG_HIP(hipGetLastError());
+  CMCG_TRY(vcycle_level(l + 1));
+  hipLaunchKernelGGL(prolong_add_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s_, L.g, C.g, C.x, L.x);
+  CMCG_HIP(hipGetLastError());
+  // post-smoothing continues from the corrected x: x <- x + omega D^{-1}(b - S x), `post` times
+  double *cur = L.x, *other = L.t;
+  for (int k = 0; k < post_; ++k) {
+    hipLaunchKernelGGL(jacobi_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s_, L.g, cur, L.b, other,
+                       omega_, 0);
+    CMCG_HIP(hipGetLastError());
+    std::swap(cur, other);
+  }
+  if (cur != L.x)
+    CMCG_HIP(hipMemcpyAsync(L.x, cur, L.g.fs * sizeof(double), hipMemcpyDeviceToDevice, s_));
+  return CMCG_OK;
+}
+
+cmcg_status RieszMG::vcycle(const double *b, double *x) {
+  MGLevel &L = lv_[0];
+  L.b = const_cast<double *>(b);
+  L.x = x;
+  CMCG_TRY(vcycle_level(0));
+  if (neumann_) CMCG_TRY(project(x, 0));
+  return CMCG_OK;
+}
+
+cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol, int max_iter,
+                           int *iters) {
+  const F2Geom &g = lv_[0].g;
+  const size_t n = g.fs;
+  *iters = 0;
+  CMCG_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s_));
+  if (b_is_float)
+    CMCG_HIP(convert<double, float>(pr_, static_cast<const float *>(b), n, s_));
+  else
+    CMCG_HIP(hipMemcpyAsync(pr_, b, n * sizeof(double), hipMemcpyDeviceToDevice, s_));
+  if (neumann_) CMCG_TRY(project(pr_, 0));
+  double bb = 0.0;
+  CMCG_TRY(dot(pr_, pr_, n, &bb));
+  if (bb == 0.0) return CMCG_OK;
+  CMCG_TRY(vcycle(pr_, pz_));
+  CMCG_HIP(hipMemcpyAsync(pp_, pz_, n * sizeof(double), hipMemcpyDeviceToDevice, s_));
+  double rz = 0.0;
+  CMCG_TRY(dot(pr_, pz_, n, &rz));
+  for (int it = 1; it <= max_iter; ++it) {
+    hipLaunchKernelGGL(s_apply_kernel, dim3(gridn(n)), dim3(256), 0, s_, g, pp_, pq_);
+    CMCG_HIP(hipGetLastError());
+    double pq = 0.0;
+    CMCG_TRY(dot(pp_, pq_, n, &pq));
+    if (!(pq > 0.0)) return set_error("Riesz PCG breakdown"), CMCG_EBREAKDOWN;
+    const double alpha = rz / pq;
+    hipLaunchKernelGGL(axpy2_kernel, dim3(gridn(n)), dim3(256), 0, s_, x, pr_, pp_, pq_, alpha, n);
+    CMCG_HIP(hipGetLastError());
+    *iters = it;
+    double rr = 0.0;
+    CMCG_TRY(dot(pr_, pr_, n, &rr));
+    if (rr <= tol * tol * bb) break;
+    CMCG_TRY(vcycle(pr_, pz_));
+    double rz2 = 0.0;
+    CMCG_TRY(dot(pr_, pz_, n, &rz2));
+    hipLaunchKernelGGL(xpay_kernel, dim3(gridn(n)), dim3(256), 0, s_, pp_, pz_, rz2 / rz, n);
+    CMCG_HIP(hipGetLastError());
+    rz = rz2;
+  }
+  if (neumann_) CMCG_TRY(project(x, 0));
+  return CMCG_OK;
+}
+
+}  // namespace cmcg

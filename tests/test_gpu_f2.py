@@ -1,0 +1,149 @@
+"""GPU parity for the second-order (F2, nodal 3D) path against the FP64 CPU oracle: periods, the
+literal transpose, the Riesz map, the filter and full CMCG solves, element by element."""
+import math
+
+import numpy as np
+import pytest
+
+import cmcg_inputs as ci
+from cmcg_inputs import Problem
+from oracle.f2 import F2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    from paper_1903_12522_amd import cmcg
+    return cmcg
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _mixed3d(n=(13, 11, 9), seed=3, masked=True):
+    """Ragged box (rows of 14 nodes, several x tiles only at larger sizes), random c, a
+    sound-soft block, complex source, boundary data on absorbing faces, one Neumann face pair."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(m + 1 for m in reversed(n))
+    c = 1.0 + rng.uniform(size=shape)
+    f = np.zeros(shape, complex)
+    f[2:5, 3:6, 4:8] = rng.standard_normal((3, 3, 4)) + 1j * rng.standard_normal((3, 3, 4))
+    mask = None
+    if masked:
+        mask = np.zeros(shape, np.uint8)
+        mask[4:6, 5:8, 6:9] = 1
+    bc = (0, 0, 1, 0, 0, 1)
+    gS = []
+    for axis in range(3):
+        others = [a for a in range(3) if a != axis]
+        fshape = tuple(n[a] + 1 for a in reversed(others))
+        for side in range(2):
+            gS.append(rng.standard_normal(fshape) + 1j * rng.standard_normal(fshape))
+    return Problem(dim=3, formulation=2, n=n, omega=2 * math.pi * 1.7, c=c, f=f, gS=gS,
+                   sound_soft=mask, face_bc=bc, courant=0.5, name="mixed3d")
+
+
+@pytest.mark.parametrize("masked", [True, False])
+def test_periods_match_oracle_fp64(cm, masked):
+    prob = _mixed3d(masked=masked)
+    o = F2(prob)
+    rng = np.random.default_rng(5)
+    z = rng.standard_normal(o.size)
+    z[: o.nn] *= o.free.ravel()
+    z[o.nn:] *= o.free.ravel()
+    with cm.Solver(prob, "fp64") as s:
+        assert s.info["steps_per_period"] == o.N
+        assert _rel(s.apply(cm.OP_FORWARD, z), o.period(z, False)) < 1e-13
+        assert _rel(s.apply(cm.OP_FORCED, z), o.period(z, True)) < 1e-13
+        assert _rel(s.apply(cm.OP_ADJOINT, z), o.period_T(z)) < 1e-13
+        y = rng.standard_normal(o.size) * np.concatenate([o.free.ravel()] * 2)
+        if not masked:
+            y[: o.nn] -= y[: o.nn].mean()
+        else:
+            pass
+        assert _rel(s.apply(cm.OP_RIESZ, y), o.riesz(y)) < 1e-8
+
+
+def test_periods_fp32_within_rounding(cm):
+    prob = _mixed3d(n=(70, 9, 8), seed=4)
+    o = F2(prob)
+    z = np.random.default_rng(6).standard_normal(o.size)
+    z *= np.concatenate([o.free.ravel()] * 2)
+    with cm.Solver(prob, "fp32") as s:
+        assert _rel(s.apply(cm.OP_FORWARD, z), o.period(z, False)) < 5e-5
+        assert _rel(s.apply(cm.OP_ADJOINT, z), o.period_T(z)) < 5e-5
+
+
+def test_filter_matches_oracle(cm):
+    prob = _mixed3d(seed=7)
+    o = F2(prob)
+    z = np.random.default_rng(8).standard_normal(o.size) * np.concatenate([o.free.ravel()] * 2)
+    with cm.Solver(prob, "fp64") as s:
+        assert _rel(s.filter(z), o.filter(z)) < 1e-13
+
+
+def test_adjoint_identity_on_gpu(cm):
+    prob = ci.inclusions_3d(n=32, freq=3.0, n_incl=8, seed=3, width=0.06)
+    o = F2(prob)
+    rng = np.random.default_rng(9)
+    z, y = rng.standard_normal(o.size), rng.standard_normal(o.size)
+    with cm.Solver(prob, "fp64") as s:
+        Ez = s.apply(cm.OP_FORWARD, z)
+        ETy = s.apply(cm.OP_ADJOINT, y)
+    assert abs(Ez @ y - z @ ETy) <= 1e-13 * np.linalg.norm(Ez) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("kind", ["inclusions", "sphere"])
+def test_cmcg_fp64_matches_oracle(cm, kind):
+    if kind == "inclusions":
+        prob = ci.inclusions_3d(n=12, freq=1.5, n_incl=6, seed=9, width=0.12, r_range=(0.1, 0.25))
+    else:
+        prob = ci.sound_soft_sphere_3d(n=12, freq=1.2, radius=0.2)
+    o = F2(prob)
+    zo, hist, it = o.solve(tol=1e-11, max_iter=3000)
+    Uo = o.filter(zo)
+    with cm.Solver(prob, "fp64", tol=1e-11, max_iter=3000, riesz_tol=1e-13) as s:
+        U, rep = s.solve()
+    assert rep["converged"]
+    assert abs(rep["iterations"] - it) <= 2
+    assert _rel(U, Uo) < 1e-9
+    Ud, _ = o.direct()
+    assert _rel(U, Ud) < 1e-8
+
+
+def test_cg_iterates_track_oracle(cm):
+    prob = ci.inclusions_3d(n=10, freq=1.5, n_incl=4, seed=2, width=0.15, r_range=(0.1, 0.3))
+    o = F2(prob)
+    rec = []
+    o.solve(tol=0.0, max_iter=5, record=rec)
+    with cm.Solver(prob, "fp64", tol=0.0, max_iter=5, riesz_tol=1e-13) as s:
+        s.begin()
+        for l in range(1, 6):
+            s.iterate(1)
+            zg = s.state(0)
+            # the constant shift (lambda) is not fixed by CG: compare modulo constants in u
+            du = zg[: o.nn] - rec[l][: o.nn]
+            du -= du.mean()
+            assert np.linalg.norm(du) <= 1e-9 * np.linalg.norm(rec[l][: o.nn])
+            assert _rel(zg[o.nn:], rec[l][o.nn:]) < 1e-9
+
+
+def test_fp32_mixed_matches_fp64(cm):
+    prob = ci.inclusions_3d(n=32, freq=3.0, n_incl=10, seed=4, width=0.05)
+    with cm.Solver(prob, "fp64", tol=1e-6, max_iter=2000) as s:
+        U64, r64 = s.solve()
+    with cm.Solver(prob, "fp32", tol=1e-6, max_iter=2000) as s:
+        U32, r32 = s.solve()
+    assert r64["converged"] and r32["converged"]
+    assert _rel(U32, U64) < 1e-4
+    assert r32["iterations"] <= 1.2 * r64["iterations"] + 5
+
+
+def test_sound_soft_field_vanishes_on_obstacle(cm):
+    prob = ci.sound_soft_sphere_3d(n=24, freq=2.0, radius=0.2)
+    with cm.Solver(prob, "fp64", tol=1e-8, max_iter=2000) as s:
+        U, rep = s.solve()
+    assert rep["converged"]
+    assert np.max(np.abs(U[prob.sound_soft.astype(bool)])) == 0.0
