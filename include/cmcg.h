@@ -163,6 +163,41 @@ cmcg_status cmcg_finish(cmcg_handle *h, double *u_re, double *u_im, cmcg_report 
  * FP64 device vector. */
 cmcg_status cmcg_get_state(cmcg_handle *h, int32_t which, double *out);
 
+/* ---- continuous-batching server (first-order 2D solves) ----
+ * Solves of different grid sizes and frequencies share the GPU: submitted requests wait in
+ * arrival order until their device footprint fits the HBM budget and a slot is free; admitted
+ * requests keep their CG state resident.  Each cmcg_server_step advances every running solve by
+ * one launch of leapfrog steps, with ONE batched kernel launch per (precision, direction, steps)
+ * group covering all those solves' tiles, then runs the CG updates of the solves whose period
+ * ended.  A solve's result does not depend on what it was batched with.  Not thread-safe. */
+typedef struct cmcg_server cmcg_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes;    /* admission budget for the resident solves' device memory     */
+  int32_t max_slots;           /* cap on concurrently resident solves (0 = 16)                 */
+  int32_t steps_per_launch;    /* leapfrog steps per launch (0 = library default)              */
+  int32_t device;
+  void *hip_stream;            /* stream for all server work, or NULL                          */
+} cmcg_server_options;
+
+enum { CMCG_REQ_QUEUED = 0, CMCG_REQ_RUNNING = 1, CMCG_REQ_DONE = 2, CMCG_REQ_FAILED = -1 };
+
+cmcg_status cmcg_server_create(const cmcg_server_options *opts, cmcg_server **out);
+/* Copies the problem's host arrays; the request starts queued.  opts->precision, tol and
+ * max_iter apply to this solve; its stream is the server's.  *id identifies it in poll. */
+cmcg_status cmcg_server_submit(cmcg_server *s, const cmcg_problem *p, const cmcg_options *opts,
+                               int64_t *id);
+/* One tick: admit what fits, advance running solves, finish converged ones.  Optional counts. */
+cmcg_status cmcg_server_step(cmcg_server *s, int32_t *active, int32_t *queued);
+/* *state = CMCG_REQ_*; when DONE, copies the filtered solution (host arrays, layout of c) and
+ * the report, and returns the solve's status (CMCG_OK or CMCG_ENOTCONV). */
+cmcg_status cmcg_server_poll(cmcg_server *s, int64_t id, int32_t *state, double *u_re,
+                             double *u_im, cmcg_report *rep);
+/* Device bytes held by resident solves, and the running / queued counts. */
+cmcg_status cmcg_server_stats(const cmcg_server *s, int64_t *used_bytes, int32_t *active,
+                              int32_t *queued);
+void cmcg_server_destroy(cmcg_server *s);   /* NULL-safe */
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,6 +63,12 @@ class _Info(ctypes.Structure):
                 ("field_len", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("hip_stream", ctypes.c_void_p)]
+
+
 _H = ctypes.c_void_p
 _sig = {
     "cmcg_create": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
@@ -80,6 +86,18 @@ _sig = {
                                     ctypes.POINTER(_Report)]),
     "cmcg_finish": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Report)]),
     "cmcg_get_state": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_void_p]),
+    "cmcg_server_create": (ctypes.c_int, [ctypes.POINTER(_ServerOptions), ctypes.POINTER(_H)]),
+    "cmcg_server_submit": (ctypes.c_int, [_H, ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "cmcg_server_step": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "cmcg_server_poll": (ctypes.c_int, [_H, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(_Report)]),
+    "cmcg_server_stats": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "cmcg_server_destroy": (None, [_H]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -126,52 +144,13 @@ class Solver:
         import torch  # device memory and streams
         self._torch = torch
         self.problem = problem
-        p = _Problem()
-        p.dim = problem.dim
-        p.formulation = problem.formulation
-        for k in range(3):
-            p.n[k] = int(problem.n[k]) if k < len(problem.n) else 1
-        p.omega = float(problem.omega)
-        keep = []
-
-        def arr(x, dtype=np.float64):
-            a = np.ascontiguousarray(np.asarray(x, dtype=dtype).ravel())
-            keep.append(a)
-            return a
-
-        if problem.c is not None:
-            p.c = _ptr(arr(problem.c))
-        p.c_const = float(problem.c_const)
-        if problem.f is not None:
-            f = np.asarray(problem.f)
-            p.f_re = _ptr(arr(f.real))
-            if np.iscomplexobj(f) and np.any(f.imag != 0):
-                p.f_im = _ptr(arr(f.imag))
-        if problem.gS is not None:
-            g = _concat_faces(problem.gS, np.complex128)
-            p.gS_re = _ptr(arr(g.real))
-            if np.any(g.imag != 0):
-                p.gS_im = _ptr(arr(g.imag))
-        if problem.sound_soft is not None:
-            m = arr(problem.sound_soft, np.uint8)
-            p.sound_soft = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-        bc = list(problem.face_bc) + [1] * 6
-        for k in range(6):
-            p.face_bc[k] = int(bc[k])
-        p.courant = float(problem.courant)
-        o = _Options()
-        o.precision = FP64 if precision == "fp64" else FP32_MIXED
-        o.tol = float(tol)
-        o.max_iter = int(max_iter)
-        o.device = int(device)
+        p, self._keep = marshal_problem(problem)
+        o = make_options(precision, tol, max_iter, device, steps_per_launch, riesz_tol,
+                         riesz_max_iter, fp64_refresh)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
         o.hip_stream = ctypes.c_void_p(stream.cuda_stream)
-        o.steps_per_launch = int(steps_per_launch)
-        o.riesz_tol = float(riesz_tol)
-        o.riesz_max_iter = int(riesz_max_iter)
-        o.fp64_refresh = float(fp64_refresh)
         h = _H()
         _check(_lib.cmcg_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)), "cmcg_create")
         self._h = h
@@ -276,3 +255,132 @@ class Solver:
 
 def status_string(st: int) -> str:
     return _lib.cmcg_status_string(st).decode()
+
+
+def marshal_problem(problem):
+    """cmcg_inputs.Problem -> (_Problem struct, list of arrays the struct points into)."""
+    p = _Problem()
+    p.dim = problem.dim
+    p.formulation = problem.formulation
+    for k in range(3):
+        p.n[k] = int(problem.n[k]) if k < len(problem.n) else 1
+    p.omega = float(problem.omega)
+    keep = []
+
+    def arr(x, dtype=np.float64):
+        a = np.ascontiguousarray(np.asarray(x, dtype=dtype).ravel())
+        keep.append(a)
+        return a
+
+    if problem.c is not None:
+        p.c = _ptr(arr(problem.c))
+    p.c_const = float(problem.c_const)
+    if problem.f is not None:
+        f = np.asarray(problem.f)
+        p.f_re = _ptr(arr(f.real))
+        if np.iscomplexobj(f) and np.any(f.imag != 0):
+            p.f_im = _ptr(arr(f.imag))
+    if problem.gS is not None:
+        g = _concat_faces(problem.gS, np.complex128)
+        p.gS_re = _ptr(arr(g.real))
+        if np.any(g.imag != 0):
+            p.gS_im = _ptr(arr(g.imag))
+    if problem.sound_soft is not None:
+        m = arr(problem.sound_soft, np.uint8)
+        p.sound_soft = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    bc = list(problem.face_bc) + [1] * 6
+    for k in range(6):
+        p.face_bc[k] = int(bc[k])
+    p.courant = float(problem.courant)
+    return p, keep
+
+
+def make_options(precision="fp64", tol=1e-6, max_iter=1000, device=0, steps_per_launch=0,
+                 riesz_tol=0.0, riesz_max_iter=0, fp64_refresh=0.0) -> _Options:
+    o = _Options()
+    o.precision = FP64 if precision == "fp64" else FP32_MIXED
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.device = int(device)
+    o.steps_per_launch = int(steps_per_launch)
+    o.riesz_tol = float(riesz_tol)
+    o.riesz_max_iter = int(riesz_max_iter)
+    o.fp64_refresh = float(fp64_refresh)
+    return o
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, -1
+
+
+class Server:
+    """Continuous-batching server for first-order 2D solves (cmcg_server_* in include/cmcg.h)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 16, steps_per_launch: int = 0,
+                 device: int = 0, stream=None):
+        import torch
+        o = _ServerOptions()
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.max_slots = int(max_slots)
+        o.steps_per_launch = int(steps_per_launch)
+        o.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        o.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+        h = _H()
+        _check(_lib.cmcg_server_create(ctypes.byref(o), ctypes.byref(h)), "cmcg_server_create")
+        self._h = h
+        self._shapes = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cmcg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, problem, precision: str = "fp32", tol: float = 1e-6,
+               max_iter: int = 1000) -> int:
+        p, keep = marshal_problem(problem)
+        o = make_options(precision, tol, max_iter)
+        rid = ctypes.c_int64(0)
+        _check(_lib.cmcg_server_submit(self._h, ctypes.byref(p), ctypes.byref(o),
+                                       ctypes.byref(rid)), "cmcg_server_submit")
+        self._shapes[rid.value] = problem.field_shape()
+        return rid.value
+
+    def step(self):
+        a, q = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib.cmcg_server_step(self._h, ctypes.byref(a), ctypes.byref(q)), "cmcg_server_step")
+        return a.value, q.value
+
+    def poll(self, rid: int):
+        """Returns (state, u or None, report or None, status)."""
+        state = ctypes.c_int32(0)
+        shape = self._shapes[rid]
+        re = np.empty(shape)
+        im = np.empty(shape)
+        rep = _Report()
+        st = _lib.cmcg_server_poll(self._h, int(rid), ctypes.byref(state),
+                                   re.ctypes.data_as(ctypes.c_void_p),
+                                   im.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rep))
+        if state.value == REQ_DONE:
+            return state.value, re + 1j * im, _report_dict(rep), st
+        return state.value, None, None, st
+
+    def stats(self):
+        used = ctypes.c_int64(0)
+        a, q = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib.cmcg_server_stats(self._h, ctypes.byref(used), ctypes.byref(a),
+                                      ctypes.byref(q)), "cmcg_server_stats")
+        return used.value, a.value, q.value

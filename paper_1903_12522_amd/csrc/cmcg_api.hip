@@ -15,7 +15,9 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-cmcg_status validate(const cmcg_problem *P, const cmcg_options *O) {
+}  // namespace
+
+cmcg_status validate_problem(const cmcg_problem *P, const cmcg_options *O) {
   if (!P || !O) return set_error("null problem or options"), CMCG_EINVAL;
   if (P->dim != 2 && P->dim != 3) return set_error("dim must be 2 or 3"), CMCG_EINVAL;
   if (P->formulation != 1 && P->formulation != 2)
@@ -45,7 +47,39 @@ cmcg_status validate(const cmcg_problem *P, const cmcg_options *O) {
   return CMCG_OK;
 }
 
-}  // namespace
+cmcg_status make_config(const cmcg_problem *P, const cmcg_options *O, hipStream_t stream,
+                        SolverConfig *cfg) {
+  CMCG_TRY(validate_problem(P, O));
+  const int64_t npts = P->formulation == 1
+                           ? P->n[0] * P->n[1]
+                           : (P->n[0] + 1) * (P->n[1] + 1) * (P->dim == 3 ? P->n[2] + 1 : 1);
+  double cmax = P->c_const;
+  if (P->c) {
+    cmax = 0.0;
+    for (int64_t k = 0; k < npts; ++k) {
+      const double c = P->c[k];
+      if (!(c > 0.0) || !std::isfinite(c)) return set_error("c must be finite and > 0"), CMCG_EINVAL;
+      cmax = std::max(cmax, c);
+    }
+  }
+  cfg->prec = O->precision;
+  cfg->tol = O->tol;
+  cfg->max_iter = O->max_iter;
+  cfg->kblock = O->steps_per_launch > 0 ? O->steps_per_launch : 4;
+  cfg->refresh = O->fp64_refresh == 0.0 ? 0.1 : O->fp64_refresh;
+  cfg->riesz_tol = O->riesz_tol;
+  cfg->riesz_max_iter = O->riesz_max_iter;
+  cfg->stream = stream;
+  cfg->h = 1.0 / (double)P->n[0];
+  cfg->omega = P->omega;
+  cfg->T = 2.0 * kPi / P->omega;
+  const double sigma = P->courant == 0.0 ? 0.5 : P->courant;
+  // integer number of leapfrog steps per period, c_max dt / h <= sigma
+  cfg->N = std::max(3, (int)std::ceil(cfg->T * cmax / (sigma * cfg->h)));
+  cfg->dt = cfg->T / cfg->N;
+  return CMCG_OK;
+}
+
 }  // namespace cmcg
 
 using namespace cmcg;
@@ -89,20 +123,8 @@ cmcg_status cmcg_create(const cmcg_problem *P, const cmcg_options *O, cmcg_handl
   if (!out) return set_error("out is NULL"), CMCG_EINVAL;
   *out = nullptr;
   g_last_error.clear();
-  CMCG_TRY(validate(P, O));
-  const int dim = P->dim;
-  const int64_t npts = P->formulation == 1
-                           ? P->n[0] * P->n[1]
-                           : (P->n[0] + 1) * (P->n[1] + 1) * (dim == 3 ? P->n[2] + 1 : 1);
-  double cmax = P->c_const;
-  if (P->c) {
-    cmax = 0.0;
-    for (int64_t k = 0; k < npts; ++k) {
-      const double c = P->c[k];
-      if (!(c > 0.0) || !std::isfinite(c)) return set_error("c must be finite and > 0"), CMCG_EINVAL;
-      cmax = std::max(cmax, c);
-    }
-  }
+  SolverConfig cfg;
+  CMCG_TRY(make_config(P, O, nullptr, &cfg));
   int ndev = 0;
   const hipError_t de = hipGetDeviceCount(&ndev);
   if (de != hipSuccess || ndev == 0) {
@@ -119,22 +141,7 @@ cmcg_status cmcg_create(const cmcg_problem *P, const cmcg_options *O, cmcg_handl
     CMCG_HIP(hipStreamCreateWithFlags(&H->stream, hipStreamNonBlocking));
     H->own_stream = true;
   }
-  SolverConfig cfg;
-  cfg.prec = O->precision;
-  cfg.tol = O->tol;
-  cfg.max_iter = O->max_iter;
-  cfg.kblock = O->steps_per_launch > 0 ? O->steps_per_launch : 4;
-  cfg.refresh = O->fp64_refresh == 0.0 ? 0.1 : O->fp64_refresh;
-  cfg.riesz_tol = O->riesz_tol;
-  cfg.riesz_max_iter = O->riesz_max_iter;
   cfg.stream = H->stream;
-  cfg.h = 1.0 / (double)P->n[0];
-  cfg.omega = P->omega;
-  cfg.T = 2.0 * kPi / P->omega;
-  const double sigma = P->courant == 0.0 ? 0.5 : P->courant;
-  // integer number of leapfrog steps per period, c_max dt / h <= sigma
-  cfg.N = std::max(3, (int)std::ceil(cfg.T * cmax / (sigma * cfg.h)));
-  cfg.dt = cfg.T / cfg.N;
   Solver *S = nullptr;
   cmcg_status st = P->formulation == 1 ? make_f1_solver(P, cfg, &S) : make_f2_solver(P, cfg, &S);
   if (st != CMCG_OK) {
@@ -206,6 +213,92 @@ cmcg_status cmcg_get_state(cmcg_handle *H, int32_t which, double *out) {
   if (!H || !out || which < 0 || which > 2) return set_error("bad argument"), CMCG_EINVAL;
   CMCG_HIP(hipSetDevice(H->device));
   return H->solver->get_state(which, out);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// continuous-batching server
+// ---------------------------------------------------------------------------------------
+struct cmcg_server {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Server *impl = nullptr;
+};
+
+extern "C" {
+
+void cmcg_server_destroy(cmcg_server *S) {
+  if (!S) return;
+  (void)hipSetDevice(S->device);
+  delete S->impl;
+  if (S->own_stream && S->stream) (void)hipStreamDestroy(S->stream);
+  delete S;
+}
+
+cmcg_status cmcg_server_create(const cmcg_server_options *o, cmcg_server **out) {
+  if (!o || !out) return set_error("null argument"), CMCG_EINVAL;
+  *out = nullptr;
+  if (o->hbm_budget_bytes <= 0 || o->max_slots < 0 || o->steps_per_launch < 0 ||
+      o->steps_per_launch > kMaxBlockSteps)
+    return set_error("bad server options"), CMCG_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return set_error("no HIP device"), CMCG_EDEVICE;
+  }
+  if (o->device < 0 || o->device >= ndev) return set_error("device ordinal out of range"), CMCG_EINVAL;
+  std::unique_ptr<cmcg_server> S(new cmcg_server());
+  S->device = o->device;
+  CMCG_HIP(hipSetDevice(S->device));
+  if (o->hip_stream) {
+    S->stream = static_cast<hipStream_t>(o->hip_stream);
+  } else {
+    CMCG_HIP(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+    S->own_stream = true;
+  }
+  cmcg_status st = make_f1_server(o, S->stream, &S->impl);
+  if (st != CMCG_OK) {
+    cmcg_server_destroy(S.release());
+    return st;
+  }
+  *out = S.release();
+  return CMCG_OK;
+}
+
+cmcg_status cmcg_server_submit(cmcg_server *S, const cmcg_problem *p, const cmcg_options *o,
+                               int64_t *id) {
+  if (!S) return set_error("null server"), CMCG_EINVAL;
+  return S->impl->submit(p, o, id);
+}
+
+cmcg_status cmcg_server_step(cmcg_server *S, int32_t *active, int32_t *queued) {
+  if (!S) return set_error("null server"), CMCG_EINVAL;
+  int a = 0, q = 0;
+  cmcg_status st = S->impl->step(&a, &q);
+  if (active) *active = a;
+  if (queued) *queued = q;
+  return st;
+}
+
+cmcg_status cmcg_server_poll(cmcg_server *S, int64_t id, int32_t *state, double *u_re,
+                             double *u_im, cmcg_report *rep) {
+  if (!S || !state) return set_error("null argument"), CMCG_EINVAL;
+  int st = 0;
+  cmcg_status r = S->impl->poll(id, &st, u_re, u_im, rep);
+  *state = st;
+  return r;
+}
+
+cmcg_status cmcg_server_stats(const cmcg_server *S, int64_t *used_bytes, int32_t *active,
+                              int32_t *queued) {
+  if (!S || !used_bytes || !active || !queued) return set_error("null argument"), CMCG_EINVAL;
+  int a = 0, q = 0;
+  S->impl->stats(used_bytes, &a, &q);
+  *active = a;
+  *queued = q;
+  return CMCG_OK;
 }
 
 }  // extern "C"

@@ -99,6 +99,21 @@ struct F1Ptrs {
   size_t fs;           // field stride in elements (ny * pitch)
 };
 
+// One solve's share of a batched (multi-solve) launch.
+template <typename T>
+struct F1SlotLaunch {
+  F1Geom g;
+  F1Ptrs<T> p;
+  F1Launch L;
+  int band, nbx, block0, nblocks;
+};
+
+// Launch geometry of the streaming kernel for an nx x ny grid at K steps per launch.
+void f1_launch_shape(int nx, int ny, int K, int *nbx, int *nby, int *band);
+template <typename T>
+hipError_t f1_multi_launch(int K, bool adjoint, const F1SlotLaunch<T> *slots, int nslots,
+                           int blocks, hipStream_t s);
+
 template <typename T>
 hipError_t f1_forward_launch(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, int kmax,
                              hipStream_t s);

@@ -49,13 +49,11 @@ template <typename T>
 __device__ __forceinline__ T lane_from_right(T x) { return __shfl_down(x, 1, 64); }
 
 template <typename T, int K, bool ADJ>
-__global__ __launch_bounds__(kThreads) void f1_stream_kernel(F1Geom g, F1Ptrs<T> p, F1Launch L,
-                                                             int band) {
+__device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> &p,
+                                               const F1Launch &L, int band, int bx, int by) {
   constexpr int H = K + 1;             // lanes lost on each side: K levels + the opening kick
   constexpr int OW = 64 - 2 * H;       // columns written per wavefront
   const int lane = threadIdx.x & 63;
-  int bx, by;
-  tile_of_block(bx, by);
   const int strip = bx * (kThreads / 64) + (threadIdx.x >> 6);
   if (strip * OW >= g.nx) return;      // wave-uniform
   const int i = strip * OW - H + lane;
@@ -214,6 +212,30 @@ __global__ __launch_bounds__(kThreads) void f1_stream_kernel(F1Geom g, F1Ptrs<T>
   }
 }
 
+template <typename T, int K, bool ADJ>
+__global__ __launch_bounds__(kThreads) void f1_stream_kernel(F1Geom g, F1Ptrs<T> p, F1Launch L,
+                                                             int band) {
+  int bx, by;
+  tile_of_block(bx, by);
+  f1_stream_body<T, K, ADJ>(g, p, L, band, bx, by);
+}
+
+// Several independent solves in one launch (continuous batching): workgroup b belongs to the
+// last slot whose first workgroup is <= b and runs that solve's tile exactly as a single-solve
+// launch would, so every solve's arithmetic is the same alone or batched.
+template <typename T, int K, bool ADJ>
+__global__ __launch_bounds__(kThreads) void f1_multi_kernel(const F1SlotLaunch<T> *slots,
+                                                            int nslots) {
+  int s = 0;
+  for (int k = 1; k < nslots; ++k)
+    if (slots[k].block0 <= (int)blockIdx.x) s = k;
+  const F1Geom g = slots[s].g;
+  const F1Ptrs<T> p = slots[s].p;
+  const F1Launch L = slots[s].L;
+  const int t = (int)blockIdx.x - slots[s].block0;
+  f1_stream_body<T, K, ADJ>(g, p, L, slots[s].band, t % slots[s].nbx, t / slots[s].nbx);
+}
+
 // Rows per band: enough wavefronts to fill 256 CUs several times over, long enough bands to
 // keep the pipeline fill (2K+3 rows) small.
 inline int band_rows(int nx, int ny, int K) {
@@ -231,6 +253,13 @@ hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hi
   const int band = band_rows(g.nx, g.ny, K);
   dim3 grid((strips + 3) / 4, (g.ny + band - 1) / band);
   hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ>), grid, dim3(kThreads), 0, s, g, p, L, band);
+  return hipGetLastError();
+}
+
+template <typename T, int K, bool ADJ>
+hipError_t launch_multi_k(const F1SlotLaunch<T> *slots, int nslots, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((f1_multi_kernel<T, K, ADJ>), dim3(blocks), dim3(kThreads), 0, s, slots,
+                     nslots);
   return hipGetLastError();
 }
 
@@ -443,6 +472,28 @@ hipError_t f1_adjoint_launch(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch
   return launch_dispatch<T, true>(g, p, L, kmax, s);
 }
 
+void f1_launch_shape(int nx, int ny, int K, int *nbx, int *nby, int *band) {
+  const int ow = 64 - 2 * (K + 1);
+  const int strips = (nx + ow - 1) / ow;
+  *band = band_rows(nx, ny, K);
+  *nbx = (strips + 3) / 4;
+  *nby = (ny + *band - 1) / *band;
+}
+
+template <typename T>
+hipError_t f1_multi_launch(int K, bool adjoint, const F1SlotLaunch<T> *slots, int nslots,
+                           int blocks, hipStream_t s) {
+#define MK(k)                                                                        \
+  case k:                                                                            \
+    return adjoint ? launch_multi_k<T, k, true>(slots, nslots, blocks, s)            \
+                   : launch_multi_k<T, k, false>(slots, nslots, blocks, s);
+  switch (K) {
+    MK(1) MK(2) MK(3) MK(4) MK(5) MK(6) MK(7) MK(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef MK
+}
+
 template <typename TA, typename TB>
 hipError_t f1_dot(const F1Geom &g, const TA *a, const TB *b, const void *cc, int cc_is_double,
                   size_t fs, double *partials, hipStream_t s) {
@@ -488,6 +539,8 @@ hipError_t f1_pack(const F1Geom &g, const T *dev, double *packed, size_t fs, hip
 }
 
 // explicit instantiations
+template hipError_t f1_multi_launch<float>(int, bool, const F1SlotLaunch<float> *, int, int, hipStream_t);
+template hipError_t f1_multi_launch<double>(int, bool, const F1SlotLaunch<double> *, int, int, hipStream_t);
 template hipError_t f1_forward_launch<float>(const F1Geom &, const F1Ptrs<float> &, const F1Launch &, int, hipStream_t);
 template hipError_t f1_forward_launch<double>(const F1Geom &, const F1Ptrs<double> &, const F1Launch &, int, hipStream_t);
 template hipError_t f1_adjoint_launch<float>(const F1Geom &, const F1Ptrs<float> &, const F1Launch &, int, hipStream_t);

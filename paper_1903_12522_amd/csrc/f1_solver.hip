@@ -11,6 +11,10 @@
 // convergence), the true gradient at the FP64 iterate is recomputed with one FP64 forward and one
 // FP64 backward period and replaces r; the search direction is kept.  The initial gradient and the
 // output filter period are FP64 as well.
+#include <deque>
+#include <map>
+#include <cstring>
+
 #include "solver.h"
 
 namespace cmcg {
@@ -184,41 +188,54 @@ class F1Solver final : public Solver {
   }
 
   // ------------------------------------------------------------------ periods
+  // Parameters of the launch that advances a period from step n0 (all earlier launches of the
+  // period had exactly K steps; the state ping-pongs between S0 and S1; the first launch reads
+  // `in`, the last writes `out` - `sub`).  Returns the number of steps of this launch.
+  template <typename T>
+  int build_launch(const F1Set &b, bool forced, const T *in, T *out, const T *sub, int steps,
+                   int n0, int K, bool filter, F1Ptrs<T> *pp, F1Launch *LL) const {
+    T *S[2] = {tp<T>(b.S0), tp<T>(b.S1)};
+    const int l = n0 / K;
+    const int ns = std::min(K, steps - n0);
+    const bool lastl = (n0 + ns == steps);
+    F1Launch L{};
+    L.nsteps = ns;
+    L.first = (n0 == 0);
+    L.last = lastl;
+    L.forced = forced ? 1 : 0;
+    L.accumulate = filter ? 1 : 0;
+    for (int k = 0; k < ns; ++k) {
+      const double t = (n0 + k + 0.5) * cfg.dt;      // source at t_{n+1/2}
+      L.cs[k] = std::cos(cfg.omega * t);
+      L.sn[k] = std::sin(cfg.omega * t);
+    }
+    L.fcos = std::cos(cfg.omega * n0 * cfg.dt);       // filter weight at t_n
+    L.fsin = std::sin(cfg.omega * n0 * cfg.dt);
+    F1Ptrs<T> p{};
+    p.in = (l == 0) ? in : S[(l - 1) & 1];
+    p.out = lastl ? out : S[l & 1];
+    p.sub = lastl ? sub : nullptr;
+    p.cc = tp<T>(b.cc);
+    p.fre = tp<T>(b.Fre);
+    p.fim = tp<T>(b.Fim);
+    p.ure = Ure;
+    p.uim = Uim;
+    p.fs = fs;
+    *pp = p;
+    *LL = L;
+    return ns;
+  }
+
   template <typename T>
   cmcg_status period_t(const F1Set &b, bool adjoint, bool forced, const T *in, T *out, const T *sub,
                        int steps, bool filter) {
     const int K = filter ? 1 : cfg.kblock;
-    int n0 = 0, l = 0;
-    T *S[2] = {tp<T>(b.S0), tp<T>(b.S1)};
-    while (n0 < steps) {
-      const int ns = std::min(K, steps - n0);
-      const bool lastl = (n0 + ns == steps);
-      F1Launch L{};
-      L.nsteps = ns;
-      L.first = (n0 == 0);
-      L.last = lastl;
-      L.forced = forced ? 1 : 0;
-      L.accumulate = filter ? 1 : 0;
-      for (int k = 0; k < ns; ++k) {
-        const double t = (n0 + k + 0.5) * cfg.dt;      // source at t_{n+1/2}
-        L.cs[k] = std::cos(cfg.omega * t);
-        L.sn[k] = std::sin(cfg.omega * t);
-      }
-      L.fcos = std::cos(cfg.omega * n0 * cfg.dt);       // filter weight at t_n
-      L.fsin = std::sin(cfg.omega * n0 * cfg.dt);
-      F1Ptrs<T> p{};
-      p.in = (l == 0) ? in : S[(l - 1) & 1];
-      p.out = lastl ? out : S[l & 1];
-      p.sub = lastl ? sub : nullptr;
-      p.cc = tp<T>(b.cc);
-      p.fre = tp<T>(b.Fre);
-      p.fim = tp<T>(b.Fim);
-      p.ure = Ure;
-      p.uim = Uim;
-      p.fs = fs;
+    for (int n0 = 0; n0 < steps;) {
+      F1Ptrs<T> p;
+      F1Launch L;
+      const int ns = build_launch<T>(b, forced, in, out, sub, steps, n0, K, filter, &p, &L);
       CMCG_HIP(adjoint ? f1_adjoint_launch<T>(g, p, L, K, s) : f1_forward_launch<T>(g, p, L, K, s));
       n0 += ns;
-      ++l;
     }
     updates += (double)steps * g.nx * g.ny;
     return CMCG_OK;
@@ -454,6 +471,416 @@ cmcg_status make_f1_solver(const cmcg_problem *P, const SolverConfig &cfg, Solve
   F1Solver *S = new F1Solver();
   S->cfg = cfg;
   cmcg_status st = S->create(P);
+  if (st != CMCG_OK) {
+    delete S;
+    return st;
+  }
+  *out = S;
+  return CMCG_OK;
+}
+
+
+// =========================================================================================
+// Continuous-batching server for first-order solves.
+//
+// Requests are admitted in arrival order while the sum of their device footprints stays within
+// the HBM budget and the slot cap; each admitted solve keeps its whole CG state resident in its
+// own buffers.  One server tick advances every running solve by one launch's worth of leapfrog
+// steps: the launches of all solves that are in a period are grouped by (precision, direction,
+// steps) and each group is ONE kernel launch over the union of the solves' tiles
+// (f1_multi_kernel).  Solves whose period ended in this tick then run their CG reductions and
+// update (per-solve, deterministic), and the host reads their scalars after a single stream
+// synchronisation per tick.  A solve's arithmetic does not depend on what else is batched with it.
+// =========================================================================================
+namespace {
+
+enum ServePhase { kPhGradFwd, kPhGradAdj, kPhFwd, kPhAdj, kPhFilter, kPhDone };
+
+size_t f1_footprint(int nx, int ny, int prec, bool has_im) {
+  const size_t pitch = (size_t)(nx + 63) / 64 * 64, fs = (size_t)ny * pitch, vecN = 3 * fs;
+  auto r8 = [](size_t b) { return b == 0 ? 8 : b; };
+  size_t total = 0;
+  auto set = [&](size_t esz) {
+    total += 4 * r8(vecN * esz) + 2 * r8(fs * esz) + (has_im ? r8(fs * esz) : 0);
+  };
+  set(8);
+  if (prec == CMCG_FP32_MIXED) set(4);
+  total += r8(vecN * (prec == CMCG_FP32_MIXED ? 4 : 8));
+  total += 2 * r8(vecN * 8) + 2 * r8(fs * 8);
+  total += r8(kRedBlocks * 8) + r8(kNumScalars * 8);
+  return total;
+}
+
+struct ServeRequest {
+  int64_t id = 0;
+  int state = 0;                 // 0 queued, 1 running, 2 done, -1 failed
+  cmcg_problem P{};
+  cmcg_options O{};
+  std::vector<double> c, fre, fim, gre, gim;
+  size_t footprint = 0;
+  F1Solver *S = nullptr;
+  int phase = kPhGradFwd, n0 = 0, grad_mode = kFinStart, pending = 0;
+  bool converged = false;
+  cmcg_status status = CMCG_OK;
+  std::vector<double> ure, uim;
+  cmcg_report rep{};
+};
+
+template <typename T>
+struct GroupKey {
+  bool adj;
+  int ns;
+};
+
+class F1Server final : public Server {
+ public:
+  int64_t budget = 0;
+  int max_slots = 16, kblock = 4, device = 0;
+  hipStream_t s = nullptr;
+  std::map<int64_t, ServeRequest *> reqs;
+  std::deque<int64_t> queue;
+  std::vector<int64_t> active;
+  size_t used = 0;
+  int64_t next_id = 1;
+  // descriptor staging for the batched launches of one tick
+  void *h_desc = nullptr, *d_desc = nullptr;
+  size_t desc_cap = 0;
+
+  ~F1Server() override {
+    if (s) (void)hipStreamSynchronize(s);
+    for (auto &kv : reqs) {
+      delete kv.second->S;
+      delete kv.second;
+    }
+    if (h_desc) (void)hipHostFree(h_desc);
+    if (d_desc) (void)hipFree(d_desc);
+  }
+
+  cmcg_status init() {
+    desc_cap = 1 << 20;
+    CMCG_HIP(hipHostMalloc(&h_desc, desc_cap));
+    CMCG_HIP(hipMalloc(&d_desc, desc_cap));
+    return CMCG_OK;
+  }
+
+  cmcg_status submit(const cmcg_problem *P, const cmcg_options *O, int64_t *id) override {
+    if (!P || !O || !id) return set_error("null argument"), CMCG_EINVAL;
+    CMCG_TRY(validate_problem(P, O));
+    if (P->formulation != 1 || P->dim != 2)
+      return set_error("the server batches first-order 2D solves"), CMCG_EUNSUPPORTED;
+    auto *R = new ServeRequest();
+    R->id = next_id++;
+    R->P = *P;
+    R->O = *O;
+    const size_t ncell = (size_t)P->n[0] * P->n[1], nface = 2 * (size_t)(P->n[0] + P->n[1]);
+    auto keep = [](const double *src, size_t n, std::vector<double> &dst) -> const double * {
+      if (!src) return nullptr;
+      dst.assign(src, src + n);
+      return dst.data();
+    };
+    R->P.c = keep(P->c, ncell, R->c);
+    R->P.f_re = keep(P->f_re, ncell, R->fre);
+    R->P.f_im = keep(P->f_im, ncell, R->fim);
+    R->P.gS_re = keep(P->gS_re, nface, R->gre);
+    R->P.gS_im = keep(P->gS_im, nface, R->gim);
+    R->P.sound_soft = nullptr;
+    R->O.hip_stream = nullptr;
+    R->O.steps_per_launch = O->steps_per_launch > 0 ? O->steps_per_launch : kblock;
+    R->footprint = f1_footprint((int)P->n[0], (int)P->n[1], O->precision,
+                                P->f_im != nullptr || P->gS_im != nullptr);
+    if ((int64_t)R->footprint > budget) {
+      delete R;
+      return set_error("request larger than the server's HBM budget"), CMCG_ENOMEM;
+    }
+    reqs[R->id] = R;
+    queue.push_back(R->id);
+    *id = R->id;
+    return CMCG_OK;
+  }
+
+  cmcg_status admit() {
+    while (!queue.empty()) {
+      ServeRequest *R = reqs[queue.front()];
+      if ((int)active.size() >= max_slots || (int64_t)(used + R->footprint) > budget) break;
+      queue.pop_front();
+      SolverConfig cfg;
+      cmcg_status st = make_config(&R->P, &R->O, s, &cfg);
+      Solver *base = nullptr;
+      if (st == CMCG_OK) st = make_f1_solver(&R->P, cfg, &base);
+      if (st != CMCG_OK) {
+        R->state = -1;
+        R->status = st;
+        continue;
+      }
+      R->S = static_cast<F1Solver *>(base);
+      R->state = 1;
+      R->phase = kPhGradFwd;
+      R->grad_mode = kFinStart;
+      R->n0 = 0;
+      F1Solver *S = R->S;
+      S->iter = S->refreshes = 0;
+      S->updates = 0;
+      S->rel = 1.0;
+      CMCG_HIP(hipMemsetAsync(S->Z, 0, S->vecN * sizeof(double), s));
+      used += S->arena.bytes();
+      active.push_back(R->id);
+    }
+    return CMCG_OK;
+  }
+
+  // the period job of a running solve
+  void job(ServeRequest *R, const F1Set **b, bool *adj, bool *forced, const void **in, void **out,
+           const void **sub, bool *filter) {
+    F1Solver *S = R->S;
+    *filter = false;
+    switch (R->phase) {
+      case kPhGradFwd: *b = &S->hi; *adj = false; *forced = true; *in = S->Z; *out = S->hi.W; *sub = S->Z; break;
+      case kPhGradAdj: *b = &S->hi; *adj = true; *forced = false; *in = S->hi.W; *out = S->hi.Q; *sub = S->hi.W; break;
+      case kPhFwd: *b = &S->lo; *adj = false; *forced = false; *in = S->D; *out = S->lo.W; *sub = S->D; break;
+      case kPhAdj: *b = &S->lo; *adj = true; *forced = false; *in = S->lo.W; *out = S->lo.Q; *sub = S->lo.W; break;
+      default: *b = &S->hi; *adj = false; *forced = true; *in = S->Z; *out = S->hi.Q; *sub = nullptr; *filter = true; break;
+    }
+  }
+
+  template <typename T>
+  cmcg_status launch_groups(std::vector<ServeRequest *> &slots, const std::vector<int> &sel,
+                            size_t &off) {
+    // group by (direction, steps); each group is one batched launch
+    std::map<std::pair<int, int>, std::vector<F1SlotLaunch<T>>> groups;
+    for (int idx : sel) {
+      ServeRequest *R = slots[idx];
+      F1Solver *S = R->S;
+      const F1Set *b;
+      bool adj, forced, filter;
+      const void *in, *sub;
+      void *out;
+      job(R, &b, &adj, &forced, &in, &out, &sub, &filter);
+      const int K = filter ? 1 : S->cfg.kblock;
+      F1SlotLaunch<T> d{};
+      d.g = S->g;
+      const int ns = S->build_launch<T>(*b, forced, static_cast<const T *>(in), static_cast<T *>(out),
+                                        static_cast<const T *>(sub), S->cfg.N, R->n0, K, filter,
+                                        &d.p, &d.L);
+      int nby;
+      f1_launch_shape(S->g.nx, S->g.ny, ns, &d.nbx, &nby, &d.band);
+      d.nblocks = d.nbx * nby;
+      groups[{adj ? 1 : 0, ns}].push_back(d);
+      R->n0 += ns;
+      S->updates += (double)ns * S->g.nx * S->g.ny;
+    }
+    for (auto &kv : groups) {
+      auto &v = kv.second;
+      int blocks = 0;
+      for (auto &d : v) {
+        d.block0 = blocks;
+        blocks += d.nblocks;
+      }
+      const size_t bytes = v.size() * sizeof(F1SlotLaunch<T>);
+      if (off + bytes > desc_cap) return set_error("server descriptor buffer full"), CMCG_ENOMEM;
+      std::memcpy(static_cast<char *>(h_desc) + off, v.data(), bytes);
+      auto *dd = reinterpret_cast<F1SlotLaunch<T> *>(static_cast<char *>(d_desc) + off);
+      CMCG_HIP(hipMemcpyAsync(dd, static_cast<char *>(h_desc) + off, bytes, hipMemcpyHostToDevice, s));
+      CMCG_HIP(f1_multi_launch<T>(kv.first.second, kv.first.first != 0, dd, (int)v.size(), blocks, s));
+      off = (off + bytes + 255) / 256 * 256;
+    }
+    return CMCG_OK;
+  }
+
+  // reductions and CG update after a period ended (issued on the stream, read after the sync)
+  cmcg_status post_period(ServeRequest *R) {
+    F1Solver *S = R->S;
+    if (R->phase == kPhGradFwd) {
+      R->phase = kPhGradAdj;
+      R->n0 = 0;
+    } else if (R->phase == kPhFwd) {
+      R->phase = kPhAdj;
+      R->n0 = 0;
+    } else if (R->phase == kPhGradAdj) {
+      CMCG_HIP(hipMemcpyAsync(S->R, S->hi.Q, S->vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
+      CMCG_HIP(f1_dot<double, double>(S->g, S->R, S->R, S->hi.cc, 1, S->fs, S->partials, s));
+      CMCG_HIP(finalize(S->partials, kRedBlocks, S->scalars, R->grad_mode, 0, s));
+      CMCG_HIP(hipMemcpyAsync(S->h_scalars, S->scalars, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+      R->pending = 1;
+    } else if (R->phase == kPhAdj) {
+      CMCG_TRY(S->dot_to(S->lo, S->lo.Q, S->D, kFinAlpha));
+      if (S->mixed)
+        CMCG_HIP(f1_cg_update<float>(S->g, S->Z, S->R, tpc<float>(S->D), tpc<float>(S->lo.Q), S->lo.cc,
+                                     S->fs, S->scalars, S->partials, s));
+      else
+        CMCG_HIP(f1_cg_update<double>(S->g, S->Z, S->R, tpc<double>(S->D), tpc<double>(S->lo.Q),
+                                      S->lo.cc, S->fs, S->scalars, S->partials, s));
+      CMCG_HIP(finalize(S->partials, kRedBlocks, S->scalars, kFinBeta, 0, s));
+      CMCG_HIP(hipMemcpyAsync(S->h_scalars, S->scalars, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
+      R->pending = 2;
+    } else if (R->phase == kPhFilter) {
+      double *ore = tp<double>(S->hi.W), *oim = tp<double>(S->hi.W) + S->fs;
+      hipLaunchKernelGGL(f1_output_kernel, dim3(grid_for(S->fs)), dim3(256), 0, s, S->Ure, S->Uim,
+                         2.0 / (S->cfg.N * S->cfg.omega), ore, oim, S->fs);
+      CMCG_HIP(hipGetLastError());
+      const size_t nxy = (size_t)S->g.nx * S->g.ny;
+      R->ure.resize(nxy);
+      R->uim.resize(nxy);
+      const size_t row = (size_t)S->g.nx * sizeof(double), pitchb = (size_t)S->g.pitch * sizeof(double);
+      CMCG_HIP(hipMemcpy2DAsync(R->ure.data(), row, ore, pitchb, row, S->g.ny, hipMemcpyDeviceToHost, s));
+      CMCG_HIP(hipMemcpy2DAsync(R->uim.data(), row, oim, pitchb, row, S->g.ny, hipMemcpyDeviceToHost, s));
+      R->pending = 3;
+    }
+    return CMCG_OK;
+  }
+
+  cmcg_status enter_filter(ServeRequest *R) {
+    F1Solver *S = R->S;
+    CMCG_HIP(hipMemsetAsync(S->Ure, 0, S->fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(S->Uim, 0, S->fs * sizeof(double), s));
+    R->phase = kPhFilter;
+    R->n0 = 0;
+    return CMCG_OK;
+  }
+
+  cmcg_status direction(ServeRequest *R) {
+    F1Solver *S = R->S;
+    if (S->mixed) CMCG_HIP(direction_update<float>(tp<float>(S->D), S->R, S->scalars, S->vecN, s));
+    else CMCG_HIP(direction_update<double>(tp<double>(S->D), S->R, S->scalars, S->vecN, s));
+    R->phase = kPhFwd;
+    R->n0 = 0;
+    return CMCG_OK;
+  }
+
+  // host decisions after the tick's synchronisation (CG Steps 5.6-5.8, refresh, completion)
+  cmcg_status decide(ServeRequest *R) {
+    F1Solver *S = R->S;
+    const double *h = S->h_scalars;
+    const int pend = R->pending;
+    R->pending = 0;
+    if (pend == 1) {
+      if (h[kBreak] != 0.0) return fail(R, CMCG_EBREAKDOWN);
+      S->rel = h[kRel];
+      S->delta_at_refresh = h[kDelta];
+      if (R->grad_mode == kFinStart) {
+        if (S->mixed) CMCG_HIP(convert<float, double>(tp<float>(S->D), S->R, S->vecN, s));
+        else CMCG_HIP(hipMemcpyAsync(S->D, S->R, S->vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (h[kDelta0] == 0.0) {
+          R->converged = true;
+          return enter_filter(R);
+        }
+        R->phase = kPhFwd;
+        R->n0 = 0;
+        return CMCG_OK;
+      }
+      ++S->refreshes;
+      if (S->rel <= S->cfg.tol) {
+        R->converged = true;
+        return enter_filter(R);
+      }
+      return direction(R);
+    }
+    if (pend == 2) {
+      ++S->iter;
+      if (h[kBreak] != 0.0) return fail(R, CMCG_EBREAKDOWN);
+      S->rel = h[kRel];
+      if (S->mixed && S->cfg.refresh > 0.0 &&
+          (S->rel <= S->cfg.tol || h[kDelta] <= S->cfg.refresh * S->cfg.refresh * S->delta_at_refresh)) {
+        R->grad_mode = kFinRefresh;
+        R->phase = kPhGradFwd;
+        R->n0 = 0;
+        return CMCG_OK;
+      }
+      if (S->rel <= S->cfg.tol) {
+        R->converged = true;
+        return enter_filter(R);
+      }
+      if (S->iter >= S->cfg.max_iter) return enter_filter(R);
+      return direction(R);
+    }
+    if (pend == 3) {
+      S->report(&R->rep);
+      R->status = R->converged ? CMCG_OK : CMCG_ENOTCONV;
+      R->state = 2;
+      R->phase = kPhDone;
+      release(R);
+    }
+    return CMCG_OK;
+  }
+
+  cmcg_status fail(ServeRequest *R, cmcg_status st) {
+    R->status = st;
+    R->state = -1;
+    R->phase = kPhDone;
+    release(R);
+    return CMCG_OK;
+  }
+
+  void release(ServeRequest *R) {
+    if (!R->S) return;
+    (void)hipStreamSynchronize(s);
+    used -= R->S->arena.bytes();
+    delete R->S;
+    R->S = nullptr;
+    active.erase(std::remove(active.begin(), active.end(), R->id), active.end());
+  }
+
+  cmcg_status step(int *n_active, int *n_queued) override {
+    CMCG_HIP(hipSetDevice(device));
+    CMCG_TRY(admit());
+    std::vector<ServeRequest *> slots;
+    std::vector<int> sel32, sel64;
+    for (int64_t id : active) {
+      ServeRequest *R = reqs[id];
+      if (R->phase == kPhDone) continue;
+      slots.push_back(R);
+      const F1Set *b;
+      bool adj, forced, filter;
+      const void *in, *sub;
+      void *out;
+      job(R, &b, &adj, &forced, &in, &out, &sub, &filter);
+      (b->prec == CMCG_FP64 ? sel64 : sel32).push_back((int)slots.size() - 1);
+    }
+    size_t off = 0;
+    CMCG_TRY(launch_groups<float>(slots, sel32, off));
+    CMCG_TRY(launch_groups<double>(slots, sel64, off));
+    for (ServeRequest *R : slots)
+      if (R->n0 >= R->S->cfg.N) CMCG_TRY(post_period(R));
+    CMCG_HIP(hipStreamSynchronize(s));
+    for (ServeRequest *R : slots)
+      if (R->pending) CMCG_TRY(decide(R));
+    if (n_active) *n_active = (int)active.size();
+    if (n_queued) *n_queued = (int)queue.size();
+    return CMCG_OK;
+  }
+
+  cmcg_status poll(int64_t id, int *state, double *u_re, double *u_im, cmcg_report *rep) override {
+    auto it = reqs.find(id);
+    if (it == reqs.end()) return set_error("unknown request id"), CMCG_EINVAL;
+    ServeRequest *R = it->second;
+    *state = R->state;
+    if (R->state == 2) {
+      if (u_re) std::memcpy(u_re, R->ure.data(), R->ure.size() * sizeof(double));
+      if (u_im) std::memcpy(u_im, R->uim.data(), R->uim.size() * sizeof(double));
+      if (rep) *rep = R->rep;
+      return R->status;
+    }
+    if (R->state == -1) return R->status;
+    return CMCG_OK;
+  }
+
+  void stats(int64_t *used_bytes, int *n_active, int *n_queued) const override {
+    *used_bytes = (int64_t)used;
+    *n_active = (int)active.size();
+    *n_queued = (int)queue.size();
+  }
+};
+
+}  // namespace
+
+cmcg_status make_f1_server(const cmcg_server_options *o, hipStream_t s, Server **out) {
+  *out = nullptr;
+  auto *S = new F1Server();
+  S->budget = o->hbm_budget_bytes;
+  S->max_slots = o->max_slots > 0 ? o->max_slots : 16;
+  S->kblock = o->steps_per_launch > 0 ? o->steps_per_launch : 4;
+  S->device = o->device;
+  S->s = s;
+  cmcg_status st = S->init();
   if (st != CMCG_OK) {
     delete S;
     return st;

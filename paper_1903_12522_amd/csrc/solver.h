@@ -99,8 +99,26 @@ class Solver {
   virtual size_t device_bytes() const = 0;
 };
 
+// Validates a problem and its options (host-side checks only) and resolves the solver
+// configuration: T = 2 pi / omega, N = ceil(T c_max / (courant h)) (>= 3), dt = T / N.
+cmcg_status validate_problem(const cmcg_problem *P, const cmcg_options *O);
+cmcg_status make_config(const cmcg_problem *P, const cmcg_options *O, hipStream_t stream,
+                        SolverConfig *cfg);
+
 cmcg_status make_f1_solver(const cmcg_problem *P, const SolverConfig &cfg, Solver **out);
 cmcg_status make_f2_solver(const cmcg_problem *P, const SolverConfig &cfg, Solver **out);
+
+// Continuous-batching request server (first-order solves).
+class Server {
+ public:
+  virtual ~Server() {}
+  virtual cmcg_status submit(const cmcg_problem *P, const cmcg_options *O, int64_t *id) = 0;
+  virtual cmcg_status step(int *n_active, int *n_queued) = 0;
+  virtual cmcg_status poll(int64_t id, int *state, double *u_re, double *u_im,
+                           cmcg_report *rep) = 0;
+  virtual void stats(int64_t *used_bytes, int *n_active, int *n_queued) const = 0;
+};
+cmcg_status make_f1_server(const cmcg_server_options *o, hipStream_t s, Server **out);
 
 inline int grid_for(size_t n, int threads = 256) {
   size_t b = (n + threads - 1) / threads;
