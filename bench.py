@@ -115,7 +115,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, rep1 = s.iterate(0)
-        kb = spl if spl > 0 else 4
+        kb = spl if spl > 0 else 6
         dev_bytes = s.info["device_bytes"]
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps

@@ -23,6 +23,8 @@
 // previous iteration's registers; each level narrows the valid lanes by one on each side, so a
 // wave writes 64 - 2(K+1) columns, and each band starts K+2 rows early to fill the pipeline.
 // There is no LDS and no barrier.  The period's opening half kick is folded into level 0.
+#include <cstdlib>
+
 #include "cmcg_internal.h"
 
 namespace cmcg {
@@ -43,33 +45,54 @@ __device__ __forceinline__ void tile_of_block(int &bx, int &by) {
   by = t / nbx;
 }
 
-template <typename T>
-__device__ __forceinline__ T lane_from_left(T x) { return __shfl_up(x, 1, 64); }
-template <typename T>
-__device__ __forceinline__ T lane_from_right(T x) { return __shfl_down(x, 1, 64); }
+// Cross-lane neighbours through DPP wavefront shifts (an operand modifier of a VALU move, no LDS
+// round trip): wave_shr:1 hands every lane the value of the lane below it, wave_shl:1 the value of
+// the lane above it.  Lanes at the wave's ends receive 0; they are halo lanes that are never
+// written back.
+__device__ __forceinline__ int dpp_shr1(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_shl1(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float lane_from_left(float x) { return __int_as_float(dpp_shr1(__float_as_int(x))); }
+__device__ __forceinline__ float lane_from_right(float x) { return __int_as_float(dpp_shl1(__float_as_int(x))); }
+__device__ __forceinline__ double lane_from_left(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)dpp_shr1((int)(unsigned)(b & 0xffffffffull));
+  const unsigned hi = (unsigned)dpp_shr1((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_from_right(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)dpp_shl1((int)(unsigned)(b & 0xffffffffull));
+  const unsigned hi = (unsigned)dpp_shl1((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
-template <typename T, int K, bool ADJ>
+// The coefficient field holds kap = dt c^2 / h per cell and the forcing field h Fhat, so that
+//   dt c^2 (D p + F) = kap (dsum + h F),   dsum = (Px - Px_left) + (Py - Py_below),
+//   p-kick  kick G v = (kick / h) (v_right - v),   gamma = m sqrt(kap dt / h) / 2.
+// EDGE = false is the compile-time fast path of wavefronts whose 64 columns are all interior
+// (1 <= i <= nx-2): no column masks and no absorbing faces except on the first and last row,
+// which are wave-uniform branches.
+template <typename T, int K, bool ADJ, bool EDGE>
 __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> &p,
-                                               const F1Launch &L, int band, int bx, int by) {
-  constexpr int H = K + 1;             // lanes lost on each side: K levels + the opening kick
-  constexpr int OW = 64 - 2 * H;       // columns written per wavefront
-  const int lane = threadIdx.x & 63;
-  const int strip = bx * (kThreads / 64) + (threadIdx.x >> 6);
-  if (strip * OW >= g.nx) return;      // wave-uniform
-  const int i = strip * OW - H + lane;
+                                               const F1Launch &L, const int i, const int lane,
+                                               const int s0, const int s1) {
+  constexpr int H = K + 1;
   const int nx = g.nx, ny = g.ny;
   const size_t pitch = (size_t)g.pitch, fs = p.fs;
-  const int s0 = by * band;
-  const int s1 = min(s0 + band, ny);
-  const T dt = (T)g.dt, hk = T(0.5) * (T)g.dt;
-  const T inv_h = (T)(1.0 / g.h), half_inv_h = (T)(0.5 / g.h);
-  const bool colIn = (i >= 0) && (i < nx);
-  const bool pxCol = (i >= 0) && (i <= nx - 2);
-  const int mx = (i == 0 ? g.abs_face[0] : 0) + (i == nx - 1 ? g.abs_face[1] : 0);
+  const T dth = (T)(g.dt / g.h);                // dt / h
+  const T hdth = T(0.5) * dth;
+  const bool colIn = EDGE ? ((i >= 0) && (i < nx)) : true;
+  const bool pxCol = EDGE ? ((i >= 0) && (i <= nx - 2)) : true;
+  const int mx = EDGE ? ((i == 0 ? g.abs_face[0] : 0) + (i == nx - 1 ? g.abs_face[1] : 0)) : 0;
+  const int af2 = g.abs_face[2], af3 = g.abs_face[3];
   const bool laneOut = colIn && lane >= H && lane < 64 - H;
 
   // per-level emissions of the previous (p) and current (c) row iteration:
-  // level k emits v^k(r), Px^k(r) and Py^k(r-1) with r = j - k; CC is c^2 of row r.
+  // level k emits v^k(r), Px^k(r) and Py^k(r-1) with r = j - k; CC is kap of row r.
   T Vp[K + 1], PXp[K + 1], PYp[K + 1], CCp[K + 1];
   T Vc[K + 1], PXc[K + 1], PYc[K + 1], CCc[K + 1];
   T HOLD[K + 1];   // level 0: raw Py of the current row; adjoint level k: Py^k(r) one row ahead
@@ -84,12 +107,16 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
 
   for (int j = jstart; j <= jend; ++j) {
     // ---- level 0: load row j
-    const bool in0 = colIn && j >= 0 && j < ny;
-    const size_t o0 = (size_t)(in0 ? j : 0) * pitch + (colIn ? i : 0);
-    T v0 = in0 ? p.in[o0 + 2 * fs] : T(0);
-    T px0 = in0 ? p.in[o0] : T(0);
-    const T py0 = in0 ? p.in[o0 + fs] : T(0);
-    const T c0 = in0 ? p.cc[o0] : T(0);
+    const bool rowIn = (j >= 0) && (j < ny);
+    const bool in0 = rowIn && colIn;
+    const size_t o0 = (size_t)(rowIn ? j : 0) * pitch + (colIn ? i : 0);
+    T v0 = T(0), px0 = T(0), py0 = T(0), c0 = T(0);
+    if (in0) {
+      v0 = p.in[o0 + 2 * fs];
+      px0 = p.in[o0];
+      py0 = p.in[o0 + fs];
+      c0 = p.cc[o0];
+    }
     if (L.accumulate && laneOut && j >= s0 && j < s1) {
       const double vv = (double)v0;
       p.ure[o0] += vv * L.fcos;
@@ -101,12 +128,12 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
       if (!ADJ) {
         // opening half kick  p <- p + dt/2 G v  (Px of row j, Py of row j-1)
         const T vr = lane_from_right(v0);
-        if (in0 && pxCol) px0 = fma(hk, (vr - v0) * inv_h, px0);
-        if (colIn && j - 1 >= 0 && j - 1 <= ny - 2) pyprev = fma(hk, (v0 - Vp[0]) * inv_h, pyprev);
+        if (in0 && pxCol) px0 = fma(hdth, vr - v0, px0);
+        if (colIn && j - 1 >= 0 && j - 1 <= ny - 2) pyprev = fma(hdth, v0 - Vp[0], pyprev);
       } else {
         // opening half kick  v <- v - dt/2 c^2 D p  (row j)
         const T pl = lane_from_left(px0);
-        if (in0) v0 = fma(-hk * c0, ((px0 - pl) + (py0 - pyprev)) * inv_h, v0);
+        if (in0) v0 = fma(T(-0.5) * c0, (px0 - pl) + (py0 - pyprev), v0);
       }
     }
     Vc[0] = v0;
@@ -120,65 +147,71 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
       const int r = j - k;
       const bool rIn = (r >= 0) && (r < ny);
       const bool cin = rIn && colIn;
-      const T kick = (L.last && k == K) ? hk : dt;
+      const bool lastk = L.last && k == K;
       if (!ADJ) {
         const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
-        const T c2 = CCp[k - 1];
+        const T kap = CCp[k - 1];
+        const T kick_h = lastk ? hdth : dth;
         const T pl = lane_from_left(px);
-        T div = ((px - pl) + (pyr - pyrm1)) * inv_h;
+        T dsum = (px - pl) + (pyr - pyrm1);
         if (L.forced && cin) {
           const size_t o = (size_t)r * pitch + i;
-          div = fma(p.fre[o], (T)L.cs[k - 1], div);
-          if (p.fim) div = fma(p.fim[o], (T)L.sn[k - 1], div);
+          dsum = fma(p.fre[o], (T)L.cs[k - 1], dsum);
+          if (p.fim) dsum = fma(p.fim[o], (T)L.sn[k - 1], dsum);
         }
-        const int m = mx + (r == 0 ? g.abs_face[2] : 0) + (r == ny - 1 ? g.abs_face[3] : 0);
         T vn = T(0);
-        if (cin) {
+        const bool rowB = (r == 0) || (r == ny - 1);
+        if (!EDGE && !rowB) {
+          if (rIn) vn = fma(kap, dsum, v);
+        } else if (cin) {
+          const int m = mx + (r == 0 ? af2 : 0) + (r == ny - 1 ? af3 : 0);
           if (m == 0) {
-            vn = fma(dt * c2, div, v);
+            vn = fma(kap, dsum, v);
           } else {
-            const T gam = dt * (T)m * sqrt(c2) * half_inv_h;
-            vn = fma(dt * c2, div, (T(1) - gam) * v) / (T(1) + gam);
+            const T gam = T(0.5) * (T)m * sqrt(kap * dth);
+            vn = fma(kap, dsum, (T(1) - gam) * v) / (T(1) + gam);
           }
         }
         const T vr = lane_from_right(vn);
-        const T pxn = (cin && pxCol) ? fma(kick, (vr - vn) * inv_h, px) : px;
+        const T pxn = (cin && pxCol) ? fma(kick_h, vr - vn, px) : px;
         const bool pyv = colIn && (r - 1 >= 0) && (r - 1 <= ny - 2);
-        const T pyn = pyv ? fma(kick, (vn - Vp[k]) * inv_h, pyrm1) : pyrm1;
+        const T pyn = pyv ? fma(kick_h, vn - Vp[k], pyrm1) : pyrm1;
         Vc[k] = vn;
         PXc[k] = pxn;
         PYc[k] = pyn;
-        CCc[k] = c2;
+        CCc[k] = kap;
       } else {
         // inputs: v^{k-1}(r+1) (current), v^{k-1}(r), Px^{k-1}(r) (previous), Py^{k-1}(r)
         const T vA = Vc[k - 1], vB = Vp[k - 1], pxB = PXp[k - 1], pyB = PYc[k - 1];
-        const T c2A = CCc[k - 1], c2B = CCp[k - 1];
+        const T kA = CCc[k - 1], kB = CCp[k - 1];
         const int rA = r + 1;
-        const int mA = (colIn && rA >= 0 && rA < ny)
-                           ? mx + (rA == 0 ? g.abs_face[2] : 0) + (rA == ny - 1 ? g.abs_face[3] : 0)
-                           : 0;
-        const int mB = cin ? mx + (r == 0 ? g.abs_face[2] : 0) + (r == ny - 1 ? g.abs_face[3] : 0) : 0;
-        const T gA = mA ? dt * (T)mA * sqrt(c2A) * half_inv_h : T(0);
-        const T gB = mB ? dt * (T)mB * sqrt(c2B) * half_inv_h : T(0);
-        const T wA = mA ? vA / (T(1) + gA) : vA;
-        const T wB = mB ? vB / (T(1) + gB) : vB;
+        T wA = vA, wB = vB, aB = T(1);
+        const bool rowB = (r == 0) || (r == ny - 1) || (rA == 0) || (rA == ny - 1);
+        if (EDGE || rowB) {
+          const int mA = (colIn && rA >= 0 && rA < ny)
+                             ? mx + (rA == 0 ? af2 : 0) + (rA == ny - 1 ? af3 : 0) : 0;
+          const int mB = cin ? mx + (r == 0 ? af2 : 0) + (r == ny - 1 ? af3 : 0) : 0;
+          if (mA) wA = vA / (T(1) + T(0.5) * (T)mA * sqrt(kA * dth));
+          if (mB) {
+            const T gB = T(0.5) * (T)mB * sqrt(kB * dth);
+            wB = vB / (T(1) + gB);
+            aB = (T(1) - gB) / (T(1) + gB);
+          }
+        }
         const T wBr = lane_from_right(wB);
         // p <- p - dt G w
-        const T pxn = (cin && pxCol) ? fma(-dt, (wBr - wB) * inv_h, pxB) : pxB;
+        const T pxn = (cin && pxCol) ? fma(-dth, wBr - wB, pxB) : pxB;
         const bool pyv = colIn && r >= 0 && r <= ny - 2;
-        const T pyn = pyv ? fma(-dt, (wA - wB) * inv_h, pyB) : pyB;   // Py^k(r)
-        // v <- a v - kick c^2 D p
+        const T pyn = pyv ? fma(-dth, wA - wB, pyB) : pyB;   // Py^k(r)
+        // v <- a v - kick c^2 D p = a v - (kick / dt) kap dsum
         const T pl = lane_from_left(pxn);
         T vn = T(0);
-        if (cin) {
-          const T a = mB ? (T(1) - gB) / (T(1) + gB) : T(1);
-          vn = fma(-kick * c2B, ((pxn - pl) + (pyn - HOLD[k])) * inv_h, a * vB);
-        }
+        if (cin) vn = fma(lastk ? T(-0.5) * kB : -kB, (pxn - pl) + (pyn - HOLD[k]), aB * vB);
         Vc[k] = vn;
         PXc[k] = pxn;
         PYc[k] = HOLD[k];
         HOLD[k] = pyn;
-        CCc[k] = c2B;
+        CCc[k] = kB;
       }
     }
 
@@ -212,12 +245,124 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
   }
 }
 
+// The common case, fully specialised: a wavefront whose 64 columns are interior, a band whose
+// rows (with its pipeline margin) are interior, and a launch with no opening kick, no source and
+// no filter.  No masks and no per-row branches remain; the arithmetic per cell is identical to
+// the general body's, so results do not depend on which variant ran.
+template <typename T, int K, bool ADJ>
+__device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> &p,
+                                               const F1Launch &L, const int i, const int lane,
+                                               const int s0, const int s1) {
+  constexpr int H = K + 1;
+  const size_t pitch = (size_t)g.pitch, fs = p.fs;
+  const T dth = (T)(g.dt / g.h);
+  const T hdth = T(0.5) * dth;
+  const bool laneOut = lane >= H && lane < 64 - H;
+  T Vp[K + 1], PXp[K + 1], PYp[K + 1], CCp[K + 1];
+  T Vc[K + 1], PXc[K + 1], PYc[K + 1], CCc[K + 1];
+  T HOLD[K + 1];
+#pragma unroll
+  for (int k = 0; k <= K; ++k) {
+    Vp[k] = PXp[k] = PYp[k] = CCp[k] = T(0);
+    Vc[k] = PXc[k] = PYc[k] = CCc[k] = T(0);
+    HOLD[k] = T(0);
+  }
+  const int jstart = s0 - K - 2, jend = s1 + K;
+  const T *pin = p.in + (size_t)jstart * pitch + i;
+  const T *pcc = p.cc + (size_t)jstart * pitch + i;
+  HOLD[0] = pin[fs - pitch];
+  for (int j = jstart; j <= jend; ++j, pin += pitch, pcc += pitch) {
+    Vc[0] = pin[2 * fs];
+    PXc[0] = pin[0];
+    PYc[0] = HOLD[0];          // Py(j-1)
+    HOLD[0] = pin[fs];
+    CCc[0] = pcc[0];
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+      const bool lastk = L.last && k == K;
+      if (!ADJ) {
+        const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
+        const T kap = CCp[k - 1];
+        const T kick_h = lastk ? hdth : dth;
+        const T pl = lane_from_left(px);
+        const T vn = fma(kap, (px - pl) + (pyr - pyrm1), v);
+        const T vr = lane_from_right(vn);
+        Vc[k] = vn;
+        PXc[k] = fma(kick_h, vr - vn, px);
+        PYc[k] = fma(kick_h, vn - Vp[k], pyrm1);
+        CCc[k] = kap;
+      } else {
+        const T vA = Vc[k - 1], vB = Vp[k - 1], pxB = PXp[k - 1], pyB = PYc[k - 1];
+        const T kB = CCp[k - 1];
+        const T wBr = lane_from_right(vB);
+        const T pxn = fma(-dth, wBr - vB, pxB);
+        const T pyn = fma(-dth, vA - vB, pyB);
+        const T pl = lane_from_left(pxn);
+        Vc[k] = fma(lastk ? T(-0.5) * kB : -kB, (pxn - pl) + (pyn - HOLD[k]), vB);
+        PXc[k] = pxn;
+        PYc[k] = HOLD[k];
+        HOLD[k] = pyn;
+        CCc[k] = kB;
+      }
+    }
+    if (laneOut) {
+      const int ro = j - K;
+      if (ro >= s0 && ro < s1) {
+        const size_t o = (size_t)ro * pitch + i;
+        T a = PXc[K], c = Vc[K];
+        if (p.sub) {
+          a -= p.sub[o];
+          c -= p.sub[o + 2 * fs];
+        }
+        p.out[o] = a;
+        p.out[o + 2 * fs] = c;
+      }
+      if (ro - 1 >= s0 && ro - 1 < s1) {
+        const size_t o = (size_t)(ro - 1) * pitch + i;
+        T b = PYc[K];
+        if (p.sub) b -= p.sub[o + fs];
+        p.out[o + fs] = b;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+      Vp[k] = Vc[k];
+      PXp[k] = PXc[k];
+      PYp[k] = PYc[k];
+      CCp[k] = CCc[k];
+    }
+  }
+}
+
+// Tile (bx, by) of a launch: wavefront w of the workgroup owns column strip 4 bx + w of the
+// band of rows by.  Interior wavefronts (all 64 columns in 1..nx-2) take the unmasked variant.
+template <typename T, int K, bool ADJ>
+__device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> &p,
+                                               const F1Launch &L, int band, int bx, int by) {
+  constexpr int H = K + 1;             // lanes lost on each side: K levels + the opening kick
+  constexpr int OW = 64 - 2 * H;       // columns written per wavefront
+  const int lane = threadIdx.x & 63;
+  const int strip = bx * (kThreads / 64) + (threadIdx.x >> 6);
+  if (strip * OW >= g.nx) return;      // wave-uniform
+  const int i0 = strip * OW - H;
+  const int s0 = by * band;
+  const int s1 = min(s0 + band, g.ny);
+  const bool inner_cols = i0 >= 1 && i0 + 63 <= g.nx - 2;
+  const bool inner_rows = s0 >= 2 * K + 3 && s1 + K <= g.ny - 2;
+  if (inner_cols && inner_rows && !L.first && !L.forced && !L.accumulate)
+    f1_stream_fast<T, K, ADJ>(g, p, L, i0 + lane, lane, s0, s1);
+  else if (inner_cols)
+    f1_stream_body<T, K, ADJ, false>(g, p, L, i0 + lane, lane, s0, s1);
+  else
+    f1_stream_body<T, K, ADJ, true>(g, p, L, i0 + lane, lane, s0, s1);
+}
+
 template <typename T, int K, bool ADJ>
 __global__ __launch_bounds__(kThreads) void f1_stream_kernel(F1Geom g, F1Ptrs<T> p, F1Launch L,
                                                              int band) {
   int bx, by;
   tile_of_block(bx, by);
-  f1_stream_body<T, K, ADJ>(g, p, L, band, bx, by);
+  f1_stream_tile<T, K, ADJ>(g, p, L, band, bx, by);
 }
 
 // Several independent solves in one launch (continuous batching): workgroup b belongs to the
@@ -233,12 +378,18 @@ __global__ __launch_bounds__(kThreads) void f1_multi_kernel(const F1SlotLaunch<T
   const F1Ptrs<T> p = slots[s].p;
   const F1Launch L = slots[s].L;
   const int t = (int)blockIdx.x - slots[s].block0;
-  f1_stream_body<T, K, ADJ>(g, p, L, slots[s].band, t % slots[s].nbx, t / slots[s].nbx);
+  f1_stream_tile<T, K, ADJ>(g, p, L, slots[s].band, t % slots[s].nbx, t / slots[s].nbx);
 }
 
 // Rows per band: enough wavefronts to fill 256 CUs several times over, long enough bands to
 // keep the pipeline fill (2K+3 rows) small.
+// CMCG_F1_BAND (environment, read once) overrides the band height for launch-shape sweeps.
 inline int band_rows(int nx, int ny, int K) {
+  static const int forced = [] {
+    const char *e = std::getenv("CMCG_F1_BAND");
+    return e ? std::atoi(e) : 0;
+  }();
+  if (forced > 0) return forced;
   const int ow = 64 - 2 * (K + 1);
   const long strips = (nx + ow - 1) / ow;
   int band = 256;
@@ -314,14 +465,14 @@ __global__ __launch_bounds__(kRedThreads) void f1_dot_kernel(F1Geom g, const TA 
                                                              const TC *cc, size_t fs,
                                                              double *partials) {
   // <a, b>_E = h^2 (sum over faces a b + sum over cells a b / c^2)
+  // cell weight h^2 / c^2 = h dt / kap
   double acc_p = 0.0, acc_v = 0.0;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
     acc_p += (double)a[o] * (double)b[o] + (double)a[o + fs] * (double)b[o + fs];
     acc_v += (double)a[o + 2 * fs] * (double)b[o + 2 * fs] / (double)cc[o];
   }
-  const double h2 = g.h * g.h;
-  const double t = block_sum(h2 * acc_p + h2 * acc_v);
+  const double t = block_sum(g.h * g.h * acc_p + g.h * g.dt * acc_v);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
@@ -346,8 +497,7 @@ __global__ __launch_bounds__(kRedThreads) void f1_cg_update_kernel(F1Geom g, dou
       else acc_v += rn * rn / (double)cc[o];
     }
   }
-  const double h2 = g.h * g.h;
-  const double t = block_sum(h2 * acc_p + h2 * acc_v);
+  const double t = block_sum(g.h * g.h * acc_p + g.h * g.dt * acc_v);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 

@@ -22,8 +22,8 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// c^2 per cell and the forcing amplitude Fhat = f + (1/h) sum_abs gS of every cell (the boundary
-// data enters the velocity equation through the boundary flux p.n = gS - v/c).
+// kap = dt c^2 / h per cell and h Fhat, Fhat = f + (1/h) sum_abs gS the forcing amplitude of every
+// cell (the boundary data enters the velocity equation through the boundary flux p.n = gS - v/c).
 template <typename T>
 __global__ void f1_setup_kernel(F1Geom g, const double *c, double c_const, const double *fre,
                                 const double *fim, const double *gre, const double *gim, T *cc,
@@ -40,7 +40,7 @@ __global__ void f1_setup_kernel(F1Geom g, const double *c, double c_const, const
     }
     const size_t k = (size_t)j * nx + i;
     const double cv = c ? c[k] : c_const;
-    cc[o] = (T)(cv * cv);
+    cc[o] = (T)(g.dt * cv * cv / g.h);        // kap = dt c^2 / h
     double ar = fre ? fre[k] : 0.0, ai = fim ? fim[k] : 0.0;
     const double ih = 1.0 / g.h;
     if (gre || gim) {
@@ -54,8 +54,8 @@ __global__ void f1_setup_kernel(F1Geom g, const double *c, double c_const, const
         if (gim) ai += gim[off[f] + along[f]] * ih;
       }
     }
-    Fre[o] = (T)ar;
-    if (Fim) Fim[o] = (T)ai;
+    Fre[o] = (T)(g.h * ar);                   // h Fhat
+    if (Fim) Fim[o] = (T)(g.h * ai);
   }
 }
 
@@ -69,15 +69,16 @@ __global__ void f1_output_kernel(const double *ure, const double *uim, double sc
   }
 }
 
-// Riesz map of the first-order formulation, M_E^{-1} y (the control space is L^2)
+// Riesz map of the first-order formulation, M_E^{-1} y (the control space is L^2): faces 1/h^2,
+// cells c^2 / h^2 = kap / (h dt)
 template <typename T>
 __global__ void f1_riesz_kernel(F1Geom g, T *y, const T *cc, size_t fs) {
-  const double ih2 = 1.0 / (g.h * g.h);
+  const double ih2 = 1.0 / (g.h * g.h), ihdt = 1.0 / (g.h * g.dt);
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
     y[o] = (T)((double)y[o] * ih2);
     y[o + fs] = (T)((double)y[o + fs] * ih2);
-    y[o + 2 * fs] = (T)((double)y[o + 2 * fs] * ih2 * (double)cc[o]);
+    y[o + 2 * fs] = (T)((double)y[o + 2 * fs] * ihdt * (double)cc[o]);
   }
 }
 
