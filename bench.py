@@ -46,6 +46,79 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes": n * 8}))
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter record (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain-copy calibration), or None when the record is for another
+    version of the kernel source."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_1903_12522_amd", "csrc", "f1_kernels.hip")
+    try:
+        rec = json.load(open(rec_path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    e = rec.get("kernels", {}).get(kernel)
+    if not e or rec.get("f1_kernels_sha256") != sha:
+        return None
+    return int(e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"])
+
+
+def single_source_tts():
+    """Time to solution of the 128^2 single-source first-order problem (FP64, tol 1e-8)."""
+    import torch
+    import cmcg_inputs as ci
+    from paper_1903_12522_amd import cmcg
+    prob = ci.single_source_2d()
+    with cmcg.Solver(prob, "fp64", tol=1e-8, max_iter=5000) as s:
+        s.solve()                                   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep = s.solve(device_output=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    return {"workload": "first-order 128x128, c=1, omega=8pi, tol 1e-8, FP64",
+            "seconds": round(rep["seconds"], 4), "wall_seconds": round(wall, 4),
+            "iterations": rep["iterations"], "steps_per_period": rep["steps_per_period"],
+            "converged": rep["converged"]}
+
+
+def nodal_3d(which: str, precision: str, max_iter: int):
+    import torch
+    import cmcg_inputs as ci
+    from paper_1903_12522_amd import cmcg
+    prob = ci.inclusions_3d() if which == "inclusions" else ci.sound_soft_sphere_3d()
+    torch.cuda.empty_cache()
+    with cmcg.Solver(prob, precision, tol=1e-6, max_iter=max_iter) as s:
+        t0 = time.perf_counter()
+        _, rep = s.solve(device_output=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gb = s.info["device_bytes"] / 1e9
+    nodes = (prob.n[0] + 1) * (prob.n[1] + 1) * (prob.n[2] + 1)
+    return {"workload": f"second-order {which} {prob.n[0]}^3, {precision}", "nodes": nodes,
+            "seconds": round(rep["seconds"], 3), "wall_seconds": round(wall, 3),
+            "iterations": rep["iterations"], "converged": rep["converged"],
+            "rel_residual": rep["rel_residual"], "steps_per_period": rep["steps_per_period"],
+            "seconds_fwd": round(rep["seconds_fwd"], 3), "seconds_adj": round(rep["seconds_adj"], 3),
+            "seconds_riesz": round(rep["seconds_riesz"], 3),
+            "riesz_iterations": rep["riesz_iterations"],
+            "glups_periods": round(rep["grid_updates"] / max(rep["seconds_fwd"] + rep["seconds_adj"], 1e-9) / 1e9, 1),
+            "device_GB": round(gb, 1)}
+
+
+def serving_run(count: int):
+    import cmcg_inputs as ci
+    from paper_1903_12522_amd import cmcg, serving
+    reqs = ci.serving_requests(count=count)
+    with cmcg.Server(64 << 30, max_slots=32) as srv:
+        recs, summ = serving.run(srv, reqs, precision="fp32", tol=1e-6, max_iter=2000,
+                                 on_event=lambda m: log("serving: " + m))
+    summ["workload"] = (f"{count} requests, Poisson 20/s, sides 256-2048, 4-64 wavelengths, "
+                        "FP32-mixed, tol 1e-6, HBM budget 64 GiB, 32 slots")
+    return summ
+
+
 def cpu_baseline(prob, steps: int = 6):
     """The oracle as it stands, on the full grid: `steps` forward leapfrog steps plus `steps`
     transposed steps (the two halves of a CG iteration), timed on one host core."""
@@ -77,6 +150,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--nodal", default="", help="comma list of inclusions,sphere: 3D solves")
+    ap.add_argument("--nodal-max-iter", type=int, default=3000)
+    ap.add_argument("--serving", type=int, default=0, help="replay this many serving requests")
     args = ap.parse_args()
 
     if args.calibrate_copy:
@@ -119,7 +195,9 @@ def main():
         dev_bytes = s.info["device_bytes"]
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
-    glups = args.steps * 2 * N * cells / elapsed / 1e9
+    # every leapfrog update done in the timed region (FP64 residual refreshes included)
+    updates = rep1["grid_updates"] - rep0["grid_updates"]
+    glups = updates / elapsed / 1e9
     log(f"{args.steps} iterations in {elapsed:.3f} s: {ms_per_step:.2f} ms/iteration, {glups:.1f} GLUP/s")
 
     # roofline of the dominant kernel: phase times from the library's HIP events on its stream
@@ -130,9 +208,11 @@ def main():
     alg_bytes = bytes_per_update * cells * kb       # per launch: kb leapfrog steps of every cell
     dom, dom_t, other_t = ("adjoint", adj, fwd) if adj >= fwd else ("forward", fwd, adj)
     achieved = alg_bytes / dom_t / 1e9
+    kname = f"f1_stream_kernel<float, {kb}, {'true' if dom == 'adjoint' else 'false'}>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 3), "traffic": None,
-                "kernel": f"f1_stream_kernel<float, {kb}, {'true' if dom == 'adjoint' else 'false'}>",
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 3),
+                "traffic": measured_traffic(kname),
+                "kernel": kname,
                 "avg_launch_us": round(dom_t * 1e6, 2),
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "other_direction_avg_launch_us": round(other_t * 1e6, 2)}
@@ -170,6 +250,12 @@ def main():
             "fp64_over_fp32_mixed": round(res["fp64"]["seconds"] / res["fp32"]["seconds"], 3),
             "fp32_mixed_rel_l2_vs_fp64": err}
         del U
+
+    out["single_source_128"] = single_source_tts()
+    for which in [w for w in args.nodal.split(",") if w]:
+        out[f"nodal_{which}"] = {p: nodal_3d(which, p, args.nodal_max_iter) for p in ("fp32", "fp64")}
+    if args.serving > 0:
+        out["serving"] = serving_run(args.serving)
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu:
