@@ -270,6 +270,20 @@ def channel_plane_wave_f2(n: Sequence[int], k: float, dirichlet_at_zero: bool = 
                    name="f2_channel" + ("_dirichlet" if dirichlet_at_zero else ""))
 
 
+def channel_bounded_neumann_f2(n: Sequence[int], k: float) -> Problem:
+    """Channel version of the bounded-domain example u(x) = 16 x^2 (x - 1)^2 on the F2 nodal
+    grid: c = 1, omega = k, every face Neumann (no absorption, no sound-soft nodes), real source
+    f = -u'' - k^2 u = -16 (12 x^2 - 12 x + 2) - 16 k^2 x^2 (x - 1)^2 sampled at the nodes."""
+    dim = len(n)
+    h = 1.0 / n[0]
+    shp = tuple(m + 1 for m in reversed(n))
+    x = np.broadcast_to(np.arange(n[0] + 1) * h, shp)
+    f = -16.0 * (12 * x * x - 12 * x + 2) - 16.0 * k * k * x * x * (x - 1) ** 2
+    return Problem(dim=dim, formulation=2, n=tuple(n), omega=k, c=None, c_const=1.0,
+                   f=f.astype(np.complex128), gS=None, sound_soft=None,
+                   face_bc=(NEUMANN,) * (2 * dim), courant=0.5, name="f2_bounded_neumann")
+
+
 @dataclasses.dataclass
 class Request:
     arrival_s: float

@@ -147,3 +147,30 @@ def test_sound_soft_field_vanishes_on_obstacle(cm):
         U, rep = s.solve()
     assert rep["converged"]
     assert np.max(np.abs(U[prob.sound_soft.astype(bool)])) == 0.0
+
+
+@pytest.mark.parametrize("example", ["convergence_rates", "bounded_domain_filter"])
+def test_paper_1d_examples_as_3d_channels(cm, example):
+    """The paper's worked examples of Sec. 3.4 (u = -exp(i k x), k = 5 pi / 4, Dirichlet at 0,
+    lifted to homogeneous data) and Sec. 3.5 (u = 16 x^2 (x - 1)^2, all faces Neumann, k = pi / 4)
+    as 3D channels: the FP64 GPU solve equals the oracle's and the closed form to the
+    discretisation error."""
+    nx = 32
+    if example == "convergence_rates":
+        k = 5 * math.pi / 4
+        prob = ci.channel_plane_wave_f2((nx, 2, 2), k, dirichlet_at_zero=True)
+    else:
+        k = math.pi / 4
+        prob = ci.channel_bounded_neumann_f2((nx, 2, 2), k)
+    o = F2(prob)
+    Ud, _ = o.direct()
+    with cm.Solver(prob, "fp64", tol=1e-11, max_iter=5000, riesz_tol=1e-13) as s:
+        U, rep = s.solve()
+    assert rep["converged"]
+    assert _rel(U, Ud) < 1e-8
+    x = np.arange(nx + 1) / nx
+    if example == "convergence_rates":
+        uh = -U - np.exp(-1j * k * x)
+        assert np.max(np.abs(uh + np.exp(1j * k * x))) < 0.01
+    else:
+        assert np.max(np.abs(U - 16 * x ** 2 * (x - 1) ** 2)) < 0.07
