@@ -119,7 +119,7 @@ def serving_run(count: int):
     return summ
 
 
-def cpu_baseline(prob, steps: int = 6):
+def cpu_baseline(prob, steps: int = 20):
     """The oracle as it stands, on the full grid: `steps` forward leapfrog steps plus `steps`
     transposed steps (the two halves of a CG iteration), timed on one host core."""
     from oracle.f1 import F1
