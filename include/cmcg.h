@@ -88,7 +88,15 @@ typedef struct {
                                   whenever <r,r>_E has fallen by fp64_refresh^2 since the last
                                   refresh, and before declaring convergence (reliable updates);
                                   0 = default 0.1, < 0 = never                                  */
+  int32_t riesz_mode;          /* F2 Riesz map q_u = P_u qh_u (eq. CMCG_PRECONDITIONIER):
+                                  CMCG_RIESZ_SOLVE: S^{-1} by multigrid-preconditioned CG to
+                                  riesz_tol (the exact map); CMCG_RIESZ_VCYCLE: one fixed
+                                  symmetric multigrid V-cycle B ~ S^{-1} (an SPD stand-in: CG
+                                  converges to the same minimiser, the stopping norm is the B
+                                  one); 0 = default: SOLVE for FP64, VCYCLE for FP32-mixed      */
 } cmcg_options;
+
+enum { CMCG_RIESZ_DEFAULT = 0, CMCG_RIESZ_SOLVE = 1, CMCG_RIESZ_VCYCLE = 2 };
 
 typedef struct {
   int32_t iterations;          /* CG iterations done                                           */

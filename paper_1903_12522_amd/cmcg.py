@@ -45,7 +45,7 @@ class _Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("hip_stream", ctypes.c_void_p), ("steps_per_launch", ctypes.c_int32),
                 ("riesz_max_iter", ctypes.c_int32), ("riesz_tol", ctypes.c_double),
-                ("fp64_refresh", ctypes.c_double)]
+                ("fp64_refresh", ctypes.c_double), ("riesz_mode", ctypes.c_int32)]
 
 
 class _Report(ctypes.Structure):
@@ -140,13 +140,14 @@ class Solver:
 
     def __init__(self, problem, precision: str = "fp64", tol: float = 1e-6, max_iter: int = 1000,
                  device: int = 0, steps_per_launch: int = 0, stream=None,
-                 riesz_tol: float = 0.0, riesz_max_iter: int = 0, fp64_refresh: float = 0.0):
+                 riesz_tol: float = 0.0, riesz_max_iter: int = 0, fp64_refresh: float = 0.0,
+                 riesz_mode="default"):
         import torch  # device memory and streams
         self._torch = torch
         self.problem = problem
         p, self._keep = marshal_problem(problem)
         o = make_options(precision, tol, max_iter, device, steps_per_launch, riesz_tol,
-                         riesz_max_iter, fp64_refresh)
+                         riesz_max_iter, fp64_refresh, riesz_mode)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
@@ -295,8 +296,13 @@ def marshal_problem(problem):
     return p, keep
 
 
+RIESZ_DEFAULT, RIESZ_SOLVE, RIESZ_VCYCLE = 0, 1, 2
+_RIESZ = {"default": RIESZ_DEFAULT, "solve": RIESZ_SOLVE, "vcycle": RIESZ_VCYCLE}
+
+
 def make_options(precision="fp64", tol=1e-6, max_iter=1000, device=0, steps_per_launch=0,
-                 riesz_tol=0.0, riesz_max_iter=0, fp64_refresh=0.0) -> _Options:
+                 riesz_tol=0.0, riesz_max_iter=0, fp64_refresh=0.0,
+                 riesz_mode="default") -> _Options:
     o = _Options()
     o.precision = FP64 if precision == "fp64" else FP32_MIXED
     o.tol = float(tol)
@@ -306,6 +312,7 @@ def make_options(precision="fp64", tol=1e-6, max_iter=1000, device=0, steps_per_
     o.riesz_tol = float(riesz_tol)
     o.riesz_max_iter = int(riesz_max_iter)
     o.fp64_refresh = float(fp64_refresh)
+    o.riesz_mode = _RIESZ[riesz_mode] if isinstance(riesz_mode, str) else int(riesz_mode)
     return o
 
 

@@ -39,6 +39,9 @@ cmcg_status validate_problem(const cmcg_problem *P, const cmcg_options *O) {
     return set_error("precision must be CMCG_FP64 or CMCG_FP32_MIXED"), CMCG_EINVAL;
   if (!(O->tol >= 0.0) || O->max_iter <= 0)
     return set_error("tol >= 0 and max_iter > 0 required"), CMCG_EINVAL;
+  if (O->riesz_mode != CMCG_RIESZ_DEFAULT && O->riesz_mode != CMCG_RIESZ_SOLVE &&
+      O->riesz_mode != CMCG_RIESZ_VCYCLE)
+    return set_error("riesz_mode must be CMCG_RIESZ_DEFAULT, _SOLVE or _VCYCLE"), CMCG_EINVAL;
   if (O->steps_per_launch < 0 || O->steps_per_launch > kMaxBlockSteps)
     return set_error("steps_per_launch must be in 0..8"), CMCG_EINVAL;
   if (!((P->dim == 2 && P->formulation == 1) || (P->dim == 3 && P->formulation == 2)))
@@ -70,6 +73,9 @@ cmcg_status make_config(const cmcg_problem *P, const cmcg_options *O, hipStream_
   cfg->refresh = O->fp64_refresh == 0.0 ? 0.1 : O->fp64_refresh;
   cfg->riesz_tol = O->riesz_tol;
   cfg->riesz_max_iter = O->riesz_max_iter;
+  cfg->riesz_mode = O->riesz_mode != CMCG_RIESZ_DEFAULT
+                        ? O->riesz_mode
+                        : (O->precision == CMCG_FP64 ? CMCG_RIESZ_SOLVE : CMCG_RIESZ_VCYCLE);
   cfg->stream = stream;
   cfg->h = 1.0 / (double)P->n[0];
   cfg->omega = P->omega;

@@ -26,6 +26,7 @@
 #include <cstdlib>
 
 #include "cmcg_internal.h"
+#include "dpp.h"
 
 namespace cmcg {
 namespace {
@@ -43,31 +44,6 @@ __device__ __forceinline__ void tile_of_block(int &bx, int &by) {
   if (nb % 8 == 0) t = (b % 8) * (nb / 8) + b / 8;
   bx = t % nbx;
   by = t / nbx;
-}
-
-// Cross-lane neighbours through DPP wavefront shifts (an operand modifier of a VALU move, no LDS
-// round trip): wave_shr:1 hands every lane the value of the lane below it, wave_shl:1 the value of
-// the lane above it.  Lanes at the wave's ends receive 0; they are halo lanes that are never
-// written back.
-__device__ __forceinline__ int dpp_shr1(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, false);
-}
-__device__ __forceinline__ int dpp_shl1(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false);
-}
-__device__ __forceinline__ float lane_from_left(float x) { return __int_as_float(dpp_shr1(__float_as_int(x))); }
-__device__ __forceinline__ float lane_from_right(float x) { return __int_as_float(dpp_shl1(__float_as_int(x))); }
-__device__ __forceinline__ double lane_from_left(double x) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const unsigned lo = (unsigned)dpp_shr1((int)(unsigned)(b & 0xffffffffull));
-  const unsigned hi = (unsigned)dpp_shr1((int)(unsigned)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-__device__ __forceinline__ double lane_from_right(double x) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const unsigned lo = (unsigned)dpp_shl1((int)(unsigned)(b & 0xffffffffull));
-  const unsigned hi = (unsigned)dpp_shl1((int)(unsigned)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // The coefficient field holds kap = dt c^2 / h per cell and the forcing field h Fhat, so that

@@ -21,15 +21,33 @@ struct F2Geom {
   }
 };
 
+// Node loop over the real nodes of a field: one wavefront per (j, k) row, lanes over i; rows are
+// dealt to the wavefronts of the grid in a fixed order (reductions stay deterministic).  Padding
+// columns i > nx are never visited.  Close with F2_ROWS_END.
+#define F2_ROWS(g)                                                                          \
+  const int lane_ = threadIdx.x & 63;                                                       \
+  const int wpb_ = blockDim.x >> 6;                                                         \
+  const int nrows_ = ((g).ny + 1) * ((g).nz + 1);                                           \
+  for (int r_ = blockIdx.x * wpb_ + (threadIdx.x >> 6); r_ < nrows_; r_ += gridDim.x * wpb_) { \
+    const int j = r_ % ((g).ny + 1), k = r_ / ((g).ny + 1);                                 \
+    const size_t row_ = (size_t)r_ * (g).px;                                                \
+    for (int i = lane_; i <= (g).nx; i += 64) {                                             \
+      const size_t o = row_ + i;
+#define F2_ROWS_END \
+  }                 \
+  }
+
+// Sweeps of the period kernel.  The backward period runs in the scaled adjoint variable
+// g = psi a, psi = lambda R / ((1 + beta) eta): in it the transposed step is the forward step,
+// so only its first sweep (transposed end map) and last sweep (transposed start map) differ.
 enum F2Mode : int {
-  kF2FwdStart = 0,
-  kF2FwdStep = 1,
-  kF2FwdEnd = 2,
-  kF2Metric = 3,
-  kF2AdjInit = 4,
-  kF2AdjStepFirst = 5,
-  kF2AdjStep = 6,
-  kF2AdjEnd = 7
+  kF2FwdStart = 0,      // start map u^1 from (u^0, v^0)
+  kF2FwdStep = 1,       // u^{n+1} from (u^n, u^{n-1}); also every interior backward step
+  kF2FwdEnd = 2,        // end map (u^N, v^N) - sub
+  kF2Metric = 3,        // y = M_E w
+  kF2AdjInit = 4,       // transposed end map in g: g_0 and psi b_0 from (g_y = psi y_v, y_u)
+  kF2AdjStepFirst = 5,  // g_1 = K g_0 + psi b_0
+  kF2AdjEnd = 6         // transposed start map from (g_M, g_{M-1}) back to (u_0, v_0) - sub
 };
 
 template <typename T>
@@ -48,6 +66,9 @@ struct F2Args {
 
 template <typename T>
 hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s);
+// out = psi in, psi = lambda R / ((1 + beta) eta) (entry into the scaled adjoint variable)
+template <typename T>
+hipError_t f2_psi_scale(const F2Geom &g, const T *in, const T *lam, T *out, hipStream_t s);
 template <typename TA, typename TB>
 hipError_t dot_plain(const TA *a, const TB *b, size_t n, double *partials, hipStream_t s);
 template <typename T>
@@ -94,8 +115,12 @@ class RieszMG {
   // x = S^{-1} b (x: FP64 fine-level field; b: fine-level field in FP64, or FP32 if b_is_float;
   // x may not alias b).  *iters receives the number of PCG iterations.
   cmcg_status solve(const void *b, int b_is_float, double *x, double tol, int max_iter, int *iters);
-  // x = B b: one V-cycle (the preconditioner), exposed for tests
+  // x = B b: one V-cycle (the preconditioner; b is overwritten only through the projection
+  // of a pure-Neumann problem's right-hand side, which the caller has already applied)
   cmcg_status vcycle(const double *b, double *x);
+  // x = Pi B Pi b for an FP64 or FP32 right-hand side (Pi: zero-sum projection when S is
+  // singular): the fixed symmetric V-cycle used in place of S^{-1}
+  cmcg_status apply_vcycle(const void *b, int b_is_float, double *x);
   bool pure_neumann() const { return neumann_; }
 
  private:

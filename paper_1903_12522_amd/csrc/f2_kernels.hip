@@ -18,10 +18,21 @@
 //   Lb = -(1-beta)/(1+beta)
 // with the transposed end map as its start and the transposed start map as its end.
 //
+// The backward period is run in the scaled variable g = psi a, psi = lambda R / ((1+beta) eta).
+// Because eta L = S / h is symmetric, psi K^T a = K g, and the recurrence becomes
+//   g_{m+1} = K g_m + Lb g_{m-1},   K g = R (2 g - lambda L g) / (1 + beta),
+// the forward homogeneous step itself; the transposed end map enters g (g_y = psi y_v stencilled
+// plainly) and the transposed start map leaves it (a = (1 + beta) eta g / lambda, stencilling
+// (1 + beta) g = lambda R a / eta).  Only the first and last sweeps carry per-node transforms.
+//
 // Kernel design: one thread per (i, j) column marches through a run of planes k, keeping the
-// planes k-1, k, k+1 of the stencilled field in registers; x/y neighbours are loaded from the
-// rows that adjacent lanes and wavefronts load anyway (L1/L2 hits), so HBM sees each field once.
+// planes k-1, k, k+1 of the stencilled field in registers.  The x neighbours come from the
+// adjacent lanes through DPP shifts (the two end lanes of a wavefront load theirs), the y
+// neighbours from the rows that the neighbouring wavefronts load anyway (L1/L2 hits), so HBM sees
+// each field once per sweep.  Interior nodes (no absorbing face, beta = 0) take a division-free
+// update.
 #include "f2_internal.h"
+#include "dpp.h"
 
 namespace cmcg {
 namespace {
@@ -54,133 +65,154 @@ __device__ __forceinline__ T lam_at(const F2Geom &g, const T *lam, size_t o) {
   return lam ? lam[o] : (T)g.lam_const;
 }
 
-// value of the stencilled field at a node, per mode
+// value of the stencilled field at a node, per sweep
 template <typename T, int MODE>
 __device__ __forceinline__ T sval(const F2Geom &g, const T *f, const T *lam, int i, int j, int k) {
   const size_t o = g.idx(i, j, k);
   const T a = f[o];
-  if (MODE == kF2AdjInit || MODE == kF2AdjStep || MODE == kF2AdjStepFirst) {
-    // g = lambda s / eta,  s = R a / (1 + beta)
-    if (masked(g, i, j, k)) return T(0);
-    const T l = lam_at(g, lam, o);
+  if (MODE == kF2Metric) return masked(g, i, j, k) ? T(0) : a;
+  if (MODE == kF2AdjEnd) {
+    // (1 + beta) g  (g vanishes on sound-soft nodes)
     const int m = abs_faces(g, i, j, k);
-    const T beta = m ? (T)m * sqrt(l) : T(0);
-    return l * a / ((T(1) + beta) * (T)eta_of(g, i, j, k));
-  } else if (MODE == kF2AdjEnd) {
-    // g' = lambda R a / eta
-    if (masked(g, i, j, k)) return T(0);
-    return lam_at(g, lam, o) * a / (T)eta_of(g, i, j, k);
-  } else if (MODE == kF2Metric) {
-    return masked(g, i, j, k) ? T(0) : a;
+    if (m == 0) return a;
+    return (T(1) + (T)m * sqrt(lam_at(g, lam, o))) * a;
   }
   return a;
 }
 
+// The grid is (x tiles of 64 nodes, y tiles of 4 rows, z chunks); each wavefront owns one row.
+// Lanes past the last node shadow it so that every lane takes part in the DPP shifts; they
+// never store.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 64 + lane;
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i > g.nx || j > g.ny) return;
+  if (j > g.ny) return;                      // a whole wavefront
+  const bool live = i <= g.nx;
+  const int ic = live ? i : g.nx;
+  const bool last = ic == g.nx;              // right neighbour is the mirrored left one
+  const int iml = mirror(ic - 1, g.nx), ipl = mirror(ic + 1, g.nx);
+  const int jm = mirror(j - 1, g.ny), jp = mirror(j + 1, g.ny);
   const int k0 = blockIdx.z * g.kchunk;
   const int k1 = min(k0 + g.kchunk, g.nz + 1);
-  const int im = mirror(i - 1, g.nx), ip = mirror(i + 1, g.nx);
-  const int jm = mirror(j - 1, g.ny), jp = mirror(j + 1, g.ny);
   const T dt = (T)g.dt;
-  T zm = sval<T, MODE>(g, p.st, p.lam, i, j, mirror(k0 - 1, g.nz));
-  T zc = sval<T, MODE>(g, p.st, p.lam, i, j, k0);
+  T zm = sval<T, MODE>(g, p.st, p.lam, ic, j, mirror(k0 - 1, g.nz));
+  T zc = sval<T, MODE>(g, p.st, p.lam, ic, j, k0);
   for (int k = k0; k < k1; ++k) {
-    const T zp = sval<T, MODE>(g, p.st, p.lam, i, j, mirror(k + 1, g.nz));
-    const T lap = T(6) * zc - (zm + zp + sval<T, MODE>(g, p.st, p.lam, im, j, k) +
-                               sval<T, MODE>(g, p.st, p.lam, ip, j, k) +
-                               sval<T, MODE>(g, p.st, p.lam, i, jm, k) +
-                               sval<T, MODE>(g, p.st, p.lam, i, jp, k));
-    const size_t o = g.idx(i, j, k);
-    const bool R = !masked(g, i, j, k);
-    const T l = lam_at(g, p.lam, o);
-    const int m = abs_faces(g, i, j, k);
-    const T beta = m ? (T)m * sqrt(l) : T(0);
-    T F = T(0);
-    if (p.forced) {
-      F = p.fre[o] * (T)p.fcos;
-      if (p.fim) F = fma(p.fim[o], (T)p.fsin, F);
-    }
-    if (MODE == kF2FwdStart) {
-      // u^1 = R(u^0 + dt (1-beta) v^0 - (lambda L u^0 - F^0) / 2)
-      const T u0 = zc, v0 = p.aux[o];
-      if (p.ure) {
-        p.ure[o] += (double)u0 * p.wcos;
-        p.uim[o] += (double)u0 * p.wsin;
+    const T zp = sval<T, MODE>(g, p.st, p.lam, ic, j, mirror(k + 1, g.nz));
+    T xl = lane_from_left(zc);
+    T xr = lane_from_right(zc);
+    if (lane == 0) xl = sval<T, MODE>(g, p.st, p.lam, iml, j, k);
+    if (lane == 63) xr = sval<T, MODE>(g, p.st, p.lam, ipl, j, k);
+    if (last) xr = xl;
+    const T ym = sval<T, MODE>(g, p.st, p.lam, ic, jm, k);
+    const T yp = sval<T, MODE>(g, p.st, p.lam, ic, jp, k);
+    const T lap = T(6) * zc - (zm + zp + xl + xr + ym + yp);
+    if (live) {
+      const size_t o = g.idx(ic, j, k);
+      const bool R = !masked(g, ic, j, k);
+      const T l = lam_at(g, p.lam, o);
+      const int m = abs_faces(g, ic, j, k);
+      const T beta = m ? (T)m * sqrt(l) : T(0);
+      T F = T(0);
+      if (MODE == kF2FwdStart || MODE == kF2FwdStep || MODE == kF2FwdEnd) {
+        if (p.forced) {
+          F = p.fre[o] * (T)p.fcos;
+          if (p.fim) F = fma(p.fim[o], (T)p.fsin, F);
+        }
       }
-      p.out[o] = R ? u0 + dt * (T(1) - beta) * v0 - T(0.5) * (l * lap - F) : T(0);
-    } else if (MODE == kF2FwdStep) {
-      const T u = zc, um = p.aux[o];
-      if (p.ure) {
-        p.ure[o] += (double)u * p.wcos;
-        p.uim[o] += (double)u * p.wsin;
+      if (MODE == kF2FwdStart) {
+        // u^1 = R(u^0 + dt (1-beta) v^0 - (lambda L u^0 - F^0) / 2)
+        const T u0 = zc, v0 = p.aux[o];
+        if (p.ure) {
+          p.ure[o] += (double)u0 * p.wcos;
+          p.uim[o] += (double)u0 * p.wsin;
+        }
+        p.out[o] = R ? u0 + dt * (T(1) - beta) * v0 - T(0.5) * (l * lap - F) : T(0);
+      } else if (MODE == kF2FwdStep) {
+        const T u = zc, um = p.aux[o];
+        if (p.ure) {
+          p.ure[o] += (double)u * p.wcos;
+          p.uim[o] += (double)u * p.wsin;
+        }
+        T un;
+        if (m == 0) un = fma(-l, lap, T(2) * u - um) + F;
+        else un = (T(2) * u - (T(1) - beta) * um - (l * lap - F)) / (T(1) + beta);
+        p.out[o] = R ? un : T(0);
+      } else if (MODE == kF2FwdEnd) {
+        // out = (u^N, (u^{N+1} - u^{N-1}) / (2 dt)) - sub
+        const T u = zc, um = p.aux[o];
+        T up;
+        if (m == 0) up = fma(-l, lap, T(2) * u - um) + F;
+        else up = (T(2) * u - (T(1) - beta) * um - (l * lap - F)) / (T(1) + beta);
+        if (!R) up = T(0);
+        T ou = u, ov = (up - um) / (T(2) * dt);
+        if (p.sub) {
+          ou -= p.sub[o];
+          ov -= p.sub[o + g.fs];
+        }
+        p.out[o] = ou;
+        p.out[o + g.fs] = ov;
+      } else if (MODE == kF2Metric) {
+        // y = M_E w = (S w_u, M w_v) on the free nodes
+        const T eta = (T)eta_of(g, ic, j, k);
+        const T h = (T)g.h;
+        const T c2 = l * (T)(g.h * g.h / (g.dt * g.dt));
+        p.out[o] = R ? h * eta * lap : T(0);
+        p.out[o + g.fs] = (R && c2 > T(0)) ? h * h * h * eta / c2 * p.aux[o] : T(0);
+      } else if (MODE == kF2AdjInit) {
+        // st = g_y = psi y_v, aux = y_u:  g_0 = psi y_u + K g_y / (2 dt),
+        //                                 psi b_0 = (Lb - 1) g_y / (2 dt) = -g_y / ((1+beta) dt)
+        const T eta = (T)eta_of(g, ic, j, k);
+        const T psi = R ? l / ((T(1) + beta) * eta) : T(0);
+        const T Kg = R ? (T(2) * zc - l * lap) / (T(1) + beta) : T(0);
+        p.out[o] = psi * p.aux[o] + Kg / (T(2) * dt);
+        p.out2[o] = R ? -zc / ((T(1) + beta) * dt) : T(0);
+      } else if (MODE == kF2AdjStepFirst) {
+        // g_1 = K g_0 + psi b_0
+        T gn;
+        if (m == 0) gn = fma(-l, lap, T(2) * zc);
+        else gn = (T(2) * zc - l * lap) / (T(1) + beta);
+        p.out[o] = R ? gn + p.aux[o] : T(0);
+      } else if (MODE == kF2AdjEnd) {
+        // st = g_M (stencilled as (1+beta) g), aux = g_{M-1}; a = (1+beta) eta g / lambda:
+        //   u_0 = R(a - eta L((1+beta) g) / 2) + Lb a_{M-1},  Lb a_{M-1} = -(1-beta) eta g_{M-1} / lambda
+        //   v_0 = R dt (1-beta) a
+        const T eta = (T)eta_of(g, ic, j, k);
+        const T a = eta * zc / l;
+        T ou = R ? a - T(0.5) * eta * lap - (T(1) - beta) * eta * p.aux[o] / l : T(0);
+        T ov = R ? dt * (T(1) - beta) * a : T(0);
+        if (p.sub) {
+          ou -= p.sub[o];
+          ov -= p.sub[o + g.fs];
+        }
+        p.out[o] = ou;
+        p.out[o + g.fs] = ov;
       }
-      p.out[o] = R ? (T(2) * u - (T(1) - beta) * um - (l * lap - F)) / (T(1) + beta) : T(0);
-    } else if (MODE == kF2FwdEnd) {
-      // out = (u^N, (u^{N+1} - u^{N-1}) / (2 dt)) - sub
-      const T u = zc, um = p.aux[o];
-      const T up = R ? (T(2) * u - (T(1) - beta) * um - (l * lap - F)) / (T(1) + beta) : T(0);
-      T ou = u, ov = (up - um) / (T(2) * dt);
-      if (p.sub) {
-        ou -= p.sub[o];
-        ov -= p.sub[o + g.fs];
-      }
-      p.out[o] = ou;
-      p.out[o + g.fs] = ov;
-    } else if (MODE == kF2Metric) {
-      // y = M_E w = (S w_u, M w_v) on the free nodes
-      const T eta = (T)eta_of(g, i, j, k);
-      const T h = (T)g.h;
-      const T c2 = l * (T)(g.h * g.h / (g.dt * g.dt));
-      p.out[o] = R ? h * eta * lap : T(0);
-      p.out[o + g.fs] = (R && c2 > T(0)) ? h * h * h * eta / c2 * p.aux[o] : T(0);
-    } else if (MODE == kF2AdjInit) {
-      // transposed end map on y = (x, yv):  a_0 = R x + K^T(yv) / (2 dt),
-      //                                     b_0 = R (Lb - 1) yv / (2 dt)
-      const T yv = p.st[o];
-      const T eta = (T)eta_of(g, i, j, k);
-      const T s = R ? yv / (T(1) + beta) : T(0);
-      const T KT = R ? T(2) * s - eta * lap : T(0);
-      const T Lb = -(T(1) - beta) / (T(1) + beta);
-      const T x = R ? p.aux[o] : T(0);
-      p.out[o] = x + KT / (T(2) * dt);
-      p.out2[o] = R ? (Lb - T(1)) * yv / (T(2) * dt) : T(0);
-    } else if (MODE == kF2AdjStep || MODE == kF2AdjStepFirst) {
-      // a_{m+1} = K^T a_m + (b_0 on the first step, else Lb a_{m-1})
-      const T a = p.st[o];
-      const T eta = (T)eta_of(g, i, j, k);
-      const T s = R ? a / (T(1) + beta) : T(0);
-      const T KT = R ? T(2) * s - eta * lap : T(0);
-      T b;
-      if (MODE == kF2AdjStepFirst) {
-        b = p.aux[o];
-      } else {
-        const T Lb = -(T(1) - beta) / (T(1) + beta);
-        b = R ? Lb * p.aux[o] : T(0);
-      }
-      p.out[o] = KT + b;
-    } else if (MODE == kF2AdjEnd) {
-      // transposed start map: u0 = R(a - eta L(lambda R a / eta) / 2) + b, v0 = R dt (1-beta) a,
-      // b = Lb a_prev; out = (u0, v0) - sub
-      const T a = p.st[o];
-      const T eta = (T)eta_of(g, i, j, k);
-      const T Lb = -(T(1) - beta) / (T(1) + beta);
-      const T b = R ? Lb * p.aux[o] : T(0);
-      T ou = (R ? a - T(0.5) * eta * lap : T(0)) + b;
-      T ov = R ? dt * (T(1) - beta) * a : T(0);
-      if (p.sub) {
-        ou -= p.sub[o];
-        ov -= p.sub[o + g.fs];
-      }
-      p.out[o] = ou;
-      p.out[o + g.fs] = ov;
     }
     zm = zc;
     zc = zp;
   }
+}
+
+// out = psi in, psi = lambda R / ((1 + beta) eta)
+template <typename T>
+__global__ void f2_psi_scale_kernel(F2Geom g, const T *in, const T *lam, T *out) {
+  F2_ROWS(g)
+  if (masked(g, i, j, k)) {
+    out[o] = T(0);
+    continue;
+  }
+  const T l = lam_at(g, lam, o);
+  const int m = abs_faces(g, i, j, k);
+  if (m == 0 && i > 0 && i < g.nx && j > 0 && j < g.ny && k > 0 && k < g.nz) {
+    out[o] = l * in[o];
+  } else {
+    const T beta = m ? (T)m * sqrt(l) : T(0);
+    out[o] = l * in[o] / ((T(1) + beta) * (T)eta_of(g, i, j, k));
+  }
+  F2_ROWS_END
 }
 
 // ---------------------------------------------------------------------------------------
@@ -217,7 +249,6 @@ __global__ __launch_bounds__(kRedThreads) void dot_kernel(const TA *a, const TB 
 }
 
 // M^{-1} on the velocity block, per node: c^2 / (h^3 eta) on free nodes, 0 on sound-soft nodes
-// and padding (lambda = 0 there)
 template <typename T>
 __device__ __forceinline__ double minv_at(const F2Geom &g, const T *lam, size_t o, int i, int j,
                                           int k) {
@@ -225,14 +256,6 @@ __device__ __forceinline__ double minv_at(const F2Geom &g, const T *lam, size_t 
   const double l = lam ? (double)lam[o] : g.lam_const;
   return l * (g.h * g.h / (g.dt * g.dt)) / (g.h * g.h * g.h * eta_of(g, i, j, k));
 }
-
-#define F2_NODES(g)                                                                          \
-  const size_t stride_ = (size_t)gridDim.x * blockDim.x;                                     \
-  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < (g).fs; o += stride_) { \
-    const int i = (int)(o % (g).px);                                                         \
-    const int j = (int)((o / (g).px) % ((g).ny + 1));                                        \
-    const int k = (int)(o / (g).plane);                                                      \
-    if (i > (g).nx) continue;
 
 // Steps 5.4-5.5 with primal and dual residuals (the velocity block of the primal residual is
 // r_v = M^{-1} rh_v and is not stored):  z -= alpha d, r_u -= alpha q_u, rh -= alpha qh;
@@ -246,7 +269,7 @@ __global__ __launch_bounds__(kRedThreads) void f2_cg_update_kernel(F2Geom g, dou
   const double alpha = sc[kAlpha];
   const size_t fs = g.fs;
   double acc = 0.0;
-  F2_NODES(g)
+  F2_ROWS(g)
   z[o] -= alpha * (double)d[o];
   z[o + fs] -= alpha * (double)d[o + fs];
   const double rn = ru[o] - alpha * qu[o];
@@ -256,7 +279,7 @@ __global__ __launch_bounds__(kRedThreads) void f2_cg_update_kernel(F2Geom g, dou
   rh[o] = rhu;
   rh[o + fs] = rhv;
   acc += rhu * rn + rhv * rhv * minv_at(g, lam, o, i, j, k);
-  }
+  F2_ROWS_END
   const double t = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
@@ -268,9 +291,9 @@ __global__ __launch_bounds__(kRedThreads) void f2_delta_kernel(F2Geom g, const d
                                                                double *partials) {
   const size_t fs = g.fs;
   double acc = 0.0;
-  F2_NODES(g)
+  F2_ROWS(g)
   acc += rh[o] * ru[o] + rh[o + fs] * rh[o + fs] * minv_at(g, lam, o, i, j, k);
-  }
+  F2_ROWS_END
   const double t = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
@@ -282,116 +305,79 @@ __global__ void f2_direction_kernel(F2Geom g, T *d, const double *ru, const doub
                                     const T *lam, const double *sc, int first) {
   const size_t fs = g.fs;
   const double beta = first ? 0.0 : sc[kBeta];
-  F2_NODES(g)
+  F2_ROWS(g)
   d[o] = (T)(ru[o] + beta * (double)d[o]);
   d[o + fs] = (T)(minv_at(g, lam, o, i, j, k) * rh[o + fs] + beta * (double)d[o + fs]);
-  }
+  F2_ROWS_END
 }
 
 // q_v = M^{-1} qh_v on the free nodes (the velocity block of the Riesz map)
 template <typename T>
 __global__ void f2_mass_inverse_kernel(F2Geom g, const T *qh_v, double *q_v, const T *lam) {
-  const size_t n = g.fs;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const double hh = g.h * g.h / (g.dt * g.dt);
-  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
-    const int i = (int)(o % g.px);
-    const int j = (int)((o / g.px) % (g.ny + 1));
-    const int k = (int)(o / g.plane);
-    if (i > g.nx || masked(g, i, j, k)) {
-      q_v[o] = 0.0;
-      continue;
-    }
-    const double l = lam ? (double)lam[o] : g.lam_const;
-    const double c2 = l * hh;
-    q_v[o] = (double)qh_v[o] * c2 / (g.h * g.h * g.h * eta_of(g, i, j, k));
-  }
+  F2_ROWS(g)
+  q_v[o] = (double)qh_v[o] * minv_at(g, lam, o, i, j, k);
+  F2_ROWS_END
 }
 
 template <typename T>
 __global__ void f2_setup_kernel(F2Geom g, const double *c, double c_const, const double *fre,
                                 const double *fim, const double *gre, const double *gim,
                                 T *lam, T *Fre, T *Fim) {
-  const size_t n = g.fs;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
-    const int i = (int)(o % g.px);
-    const int j = (int)((o / g.px) % (ny + 1));
-    const int k = (int)(o / g.plane);
-    if (i > nx) {
-      if (lam) lam[o] = T(0);
-      if (Fre) Fre[o] = T(0);
-      if (Fim) Fim[o] = T(0);
-      continue;
-    }
-    const size_t u = ((size_t)k * (ny + 1) + j) * (nx + 1) + i;   // packed user index
-    const double cv = c ? c[u] : c_const;
-    const double l = (cv * g.dt / g.h) * (cv * g.dt / g.h);
-    if (lam) lam[o] = (T)l;
-    if (Fre) {
-      double ar = fre ? fre[u] : 0.0, ai = fim ? fim[u] : 0.0;
-      if (gre || gim) {
-        // faces -x, +x, -y, +y, -z, +z; nodes in order of the remaining axes, slower first
-        const size_t sx = (size_t)(nz + 1) * (ny + 1), sy = (size_t)(nz + 1) * (nx + 1);
-        const size_t off[6] = {0, sx, 2 * sx, 2 * sx + sy, 2 * sx + 2 * sy,
-                               2 * sx + 2 * sy + (size_t)(ny + 1) * (nx + 1)};
-        const bool on[6] = {i == 0, i == nx, j == 0, j == ny, k == 0, k == nz};
-        const size_t along[6] = {(size_t)k * (ny + 1) + j, (size_t)k * (ny + 1) + j,
-                                 (size_t)k * (nx + 1) + i, (size_t)k * (nx + 1) + i,
-                                 (size_t)j * (nx + 1) + i, (size_t)j * (nx + 1) + i};
-        for (int f = 0; f < 6; ++f) {
-          if (!on[f] || !g.abs_face[f]) continue;
-          if (gre) ar += 2.0 / g.h * gre[off[f] + along[f]];
-          if (gim) ai += 2.0 / g.h * gim[off[f] + along[f]];
-        }
+  F2_ROWS(g)
+  const size_t u = ((size_t)k * (ny + 1) + j) * (nx + 1) + i;   // packed user index
+  const double cv = c ? c[u] : c_const;
+  const double l = (cv * g.dt / g.h) * (cv * g.dt / g.h);
+  if (lam) lam[o] = (T)l;
+  if (Fre) {
+    double ar = fre ? fre[u] : 0.0, ai = fim ? fim[u] : 0.0;
+    if (gre || gim) {
+      // faces -x, +x, -y, +y, -z, +z; nodes in order of the remaining axes, slower first
+      const size_t sx = (size_t)(nz + 1) * (ny + 1), sy = (size_t)(nz + 1) * (nx + 1);
+      const size_t off[6] = {0, sx, 2 * sx, 2 * sx + sy, 2 * sx + 2 * sy,
+                             2 * sx + 2 * sy + (size_t)(ny + 1) * (nx + 1)};
+      const bool on[6] = {i == 0, i == nx, j == 0, j == ny, k == 0, k == nz};
+      const size_t along[6] = {(size_t)k * (ny + 1) + j, (size_t)k * (ny + 1) + j,
+                               (size_t)k * (nx + 1) + i, (size_t)k * (nx + 1) + i,
+                               (size_t)j * (nx + 1) + i, (size_t)j * (nx + 1) + i};
+      for (int f = 0; f < 6; ++f) {
+        if (!on[f] || !g.abs_face[f]) continue;
+        if (gre) ar += 2.0 / g.h * gre[off[f] + along[f]];
+        if (gim) ai += 2.0 / g.h * gim[off[f] + along[f]];
       }
-      const double s = g.dt * g.dt * cv * cv;
-      Fre[o] = (T)(s * ar);
-      if (Fim) Fim[o] = (T)(s * ai);
     }
+    const double s = g.dt * g.dt * cv * cv;
+    Fre[o] = (T)(s * ar);
+    if (Fim) Fim[o] = (T)(s * ai);
   }
+  F2_ROWS_END
 }
 
-// packed user node array (FP64) <-> device layout (T), two fields
+// packed user node array (FP64) <-> device layout (T); sound-soft entries enter as 0
 template <typename T>
 __global__ void f2_unpack_kernel(F2Geom g, const double *packed, T *dev, int nfields) {
-  const size_t n = g.fs;
   const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
-    const int i = (int)(o % g.px);
-    const int j = (int)((o / g.px) % (g.ny + 1));
-    const int k = (int)(o / g.plane);
-    for (int f = 0; f < nfields; ++f) {
-      T v = T(0);
-      if (i <= g.nx && !masked(g, i, j, k)) {
-        const size_t u = ((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i;
-        v = (T)packed[f * nn + u];
-      }
-      dev[o + f * n] = v;
-    }
-  }
+  F2_ROWS(g)
+  const size_t u = ((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i;
+  const bool m = masked(g, i, j, k);
+  for (int f = 0; f < nfields; ++f) dev[o + f * g.fs] = m ? T(0) : (T)packed[f * nn + u];
+  F2_ROWS_END
 }
 
 template <typename T>
 __global__ void f2_pack_kernel(F2Geom g, const T *dev, double *packed, int nfields) {
-  const size_t n = g.fs;
   const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
-    const int i = (int)(o % g.px);
-    if (i > g.nx) continue;
-    const int j = (int)((o / g.px) % (g.ny + 1));
-    const int k = (int)(o / g.plane);
-    const size_t u = ((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i;
-    for (int f = 0; f < nfields; ++f) packed[f * nn + u] = (double)dev[o + f * n];
-  }
+  F2_ROWS(g)
+  const size_t u = ((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i;
+  for (int f = 0; f < nfields; ++f) packed[f * nn + u] = (double)dev[o + f * g.fs];
+  F2_ROWS_END
 }
 
-inline int gridn(size_t n) {
-  size_t b = (n + 255) / 256;
-  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+// blocks for a row loop: four rows per 256-thread block
+inline int rows_grid(const F2Geom &g) {
+  const long rows = (long)(g.ny + 1) * (g.nz + 1);
+  const long b = (rows + 3) / 4;
+  return (int)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
 }  // namespace
@@ -409,11 +395,16 @@ hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s
     CASE(kF2Metric)
     CASE(kF2AdjInit)
     CASE(kF2AdjStepFirst)
-    CASE(kF2AdjStep)
     CASE(kF2AdjEnd)
 #undef CASE
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t f2_psi_scale(const F2Geom &g, const T *in, const T *lam, T *out, hipStream_t s) {
+  hipLaunchKernelGGL((f2_psi_scale_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, in, lam, out);
   return hipGetLastError();
 }
 
@@ -444,7 +435,7 @@ hipError_t f2_delta(const F2Geom &g, const double *ru, const double *rh, const T
 template <typename T>
 hipError_t f2_direction(const F2Geom &g, T *d, const double *ru, const double *rh, const T *lam,
                         const double *sc, int first, hipStream_t s) {
-  hipLaunchKernelGGL((f2_direction_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, d, ru, rh,
+  hipLaunchKernelGGL((f2_direction_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, d, ru, rh,
                      lam, sc, first);
   return hipGetLastError();
 }
@@ -452,8 +443,8 @@ hipError_t f2_direction(const F2Geom &g, T *d, const double *ru, const double *r
 template <typename T>
 hipError_t f2_mass_inverse(const F2Geom &g, const T *qh_v, double *q_v, const T *lam,
                            hipStream_t s) {
-  hipLaunchKernelGGL((f2_mass_inverse_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, qh_v, q_v,
-                     lam);
+  hipLaunchKernelGGL((f2_mass_inverse_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, qh_v,
+                     q_v, lam);
   return hipGetLastError();
 }
 
@@ -461,27 +452,28 @@ template <typename T>
 hipError_t f2_setup(const F2Geom &g, const double *c, double c_const, const double *fre,
                     const double *fim, const double *gre, const double *gim, T *lam, T *Fre, T *Fim,
                     hipStream_t s) {
-  hipLaunchKernelGGL((f2_setup_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, c, c_const, fre,
+  hipLaunchKernelGGL((f2_setup_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, c, c_const, fre,
                      fim, gre, gim, lam, Fre, Fim);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t f2_unpack(const F2Geom &g, const double *packed, T *dev, int nfields, hipStream_t s) {
-  hipLaunchKernelGGL((f2_unpack_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, packed, dev,
+  hipLaunchKernelGGL((f2_unpack_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, packed, dev,
                      nfields);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, hipStream_t s) {
-  hipLaunchKernelGGL((f2_pack_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g, dev, packed,
+  hipLaunchKernelGGL((f2_pack_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, dev, packed,
                      nfields);
   return hipGetLastError();
 }
 
 #define INST(T)                                                                                   \
   template hipError_t f2_march<T>(int, const F2Geom &, const F2Args<T> &, hipStream_t);          \
+  template hipError_t f2_psi_scale<T>(const F2Geom &, const T *, const T *, T *, hipStream_t);   \
   template hipError_t f2_cg_update<T>(const F2Geom &, double *, double *, double *, const T *,   \
                                       const double *, const T *, const T *, const double *,      \
                                       double *, hipStream_t);                                    \

@@ -256,21 +256,24 @@ class F2Solver final : public Solver {
     return CMCG_OK;
   }
 
-  // out = E^T y (- sub)
+  // out = E^T y (- sub), run in the scaled adjoint variable g = psi a (psi = lambda R /
+  // ((1 + beta) eta)), in which every interior transposed step is the homogeneous forward step
   template <typename T>
   cmcg_status adj_t(const F2Set &b, const T *y, T *out, const T *sub) {
     const int N = cfg.N;
     F2Args<T> p;
     p.lam = tpc<T>(b.lam);
     T *buf[3] = {tp<T>(b.A), tp<T>(b.B), tp<T>(b.C)};
-    // transposed end map: a_0 (A), b_0 (B)
-    p.st = y + g.fs;
+    // g_y = psi y_v (C)
+    CMCG_HIP(f2_psi_scale<T>(g, y + g.fs, p.lam, buf[2], s));
+    // transposed end map: g_0 (A), psi b_0 (B)
+    p.st = buf[2];
     p.aux = y;
     p.out = buf[0];
     p.out2 = buf[1];
     CMCG_HIP(f2_march<T>(kF2AdjInit, g, p, s));
     p.out2 = nullptr;
-    // first transposed step: a_1 = K^T a_0 + b_0 -> C
+    // first transposed step: g_1 = K g_0 + psi b_0 -> C
     p.st = buf[0];
     p.aux = buf[1];
     p.out = buf[2];
@@ -281,11 +284,11 @@ class F2Solver final : public Solver {
       p.st = buf[cur];
       p.aux = buf[prev];
       p.out = buf[nxt];
-      CMCG_HIP(f2_march<T>(kF2AdjStep, g, p, s));
+      CMCG_HIP(f2_march<T>(kF2FwdStep, g, p, s));
       prev = cur;
       cur = nxt;
     }
-    // transposed start map
+    // transposed start map, back to the adjoint state
     p.st = buf[cur];
     p.aux = buf[prev];
     p.out = out;
@@ -321,7 +324,12 @@ class F2Solver final : public Solver {
   cmcg_status riesz_u(const void *qh_u, int is_float, double *out) {
     int it = 0;
     CMCG_HIP(hipEventRecord(ev[8], s));
-    CMCG_TRY(mg.solve(qh_u, is_float, out, riesz_tol, riesz_max, &it));
+    if (cfg.riesz_mode == CMCG_RIESZ_VCYCLE) {
+      CMCG_TRY(mg.apply_vcycle(qh_u, is_float, out));
+      it = 1;
+    } else {
+      CMCG_TRY(mg.solve(qh_u, is_float, out, riesz_tol, riesz_max, &it));
+    }
     CMCG_HIP(hipEventRecord(ev[9], s));
     CMCG_HIP(hipEventSynchronize(ev[9]));
     t_riesz += PhaseEvents::seconds(ev[8], ev[9]);

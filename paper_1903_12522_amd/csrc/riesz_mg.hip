@@ -41,32 +41,24 @@ __device__ __forceinline__ double lap7(const F2Geom &g, const double *x, int i, 
                     x[g.idx(i, j, mir(k - 1, g.nz))] + x[g.idx(i, j, mir(k + 1, g.nz))]);
 }
 
-#define NODE_LOOP(g)                                                                       \
-  const size_t stride_ = (size_t)gridDim.x * blockDim.x;                                   \
-  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < (g).fs; o += stride_) { \
-    const int i = (int)(o % (g).px);                                                       \
-    const int j = (int)((o / (g).px) % ((g).ny + 1));                                      \
-    const int k = (int)(o / (g).plane);                                                    \
-    if (i > (g).nx) continue;
-
 // y = R S x
 __global__ void s_apply_kernel(F2Geom g, const double *x, double *y) {
-  NODE_LOOP(g)
+  F2_ROWS(g)
   y[o] = msk(g, i, j, k) ? 0.0 : g.h * eta3(g, i, j, k) * lap7(g, x, i, j, k);
-  }
+  F2_ROWS_END
 }
 
 // r = R (b - S x)
 __global__ void residual_kernel(F2Geom g, const double *x, const double *b, double *r) {
-  NODE_LOOP(g)
+  F2_ROWS(g)
   r[o] = msk(g, i, j, k) ? 0.0 : b[o] - g.h * eta3(g, i, j, k) * lap7(g, x, i, j, k);
-  }
+  F2_ROWS_END
 }
 
 // damped Jacobi: xo = R (x + omega (b - S x) / (6 h eta))
 __global__ void jacobi_kernel(F2Geom g, const double *x, const double *b, double *xo, double omega,
                               int from_zero) {
-  NODE_LOOP(g)
+  F2_ROWS(g)
   if (msk(g, i, j, k)) {
     xo[o] = 0.0;
     continue;
@@ -77,12 +69,12 @@ __global__ void jacobi_kernel(F2Geom g, const double *x, const double *b, double
   } else {
     xo[o] = x[o] + omega * (b[o] - he * lap7(g, x, i, j, k)) / (6.0 * he);
   }
-  }
+  F2_ROWS_END
 }
 
 // bc = R_c P^T rf  (full weighting over the 27 fine neighbours of the coarse node's position)
 __global__ void restrict_kernel(F2Geom gf, F2Geom gc, const double *rf, double *bc) {
-  NODE_LOOP(gc)
+  F2_ROWS(gc)
   if (msk(gc, i, j, k)) {
     bc[o] = 0.0;
     continue;
@@ -103,12 +95,12 @@ __global__ void restrict_kernel(F2Geom gf, F2Geom gc, const double *rf, double *
     }
   }
   bc[o] = acc;
-  }
+  F2_ROWS_END
 }
 
 // xf += R_f P xc  (trilinear interpolation)
 __global__ void prolong_add_kernel(F2Geom gf, F2Geom gc, const double *xc, double *xf) {
-  NODE_LOOP(gf)
+  F2_ROWS(gf)
   if (msk(gf, i, j, k)) {
     xf[o] = 0.0;
     continue;
@@ -124,22 +116,46 @@ __global__ void prolong_add_kernel(F2Geom gf, F2Geom gc, const double *xc, doubl
     for (int b = 0; b < nj; ++b)
       for (int a = 0; a < ni; ++a) acc += wi * wj * wk * xc[gc.idx(is[a], js[b], ks[c])];
   xf[o] += acc;
-  }
+  F2_ROWS_END
 }
 
 // coarse mask: node I sound-soft iff the fine node 2I is
 __global__ void coarse_mask_kernel(F2Geom gf, F2Geom gc, const uint8_t *mf, uint8_t *mc) {
-  NODE_LOOP(gc)
+  F2_ROWS(gc)
   mc[o] = mf[gf.idx(2 * i, 2 * j, 2 * k)];
+  F2_ROWS_END
+}
+
+__device__ __forceinline__ double wsum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// per-block partial sums of v over the real nodes (fixed order)
+__global__ __launch_bounds__(kRedThreads) void sum_kernel(F2Geom g, const double *v,
+                                                          double *partials) {
+  __shared__ double part[kRedThreads / 64];
+  double acc = 0.0;
+  F2_ROWS(g)
+  acc += v[o];
+  F2_ROWS_END
+  acc = wsum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) t += part[w];
+    partials[blockIdx.x] = t;
   }
 }
 
-// v -= s[slot] / count on real nodes (mean removal)
+// v -= s[slot] / count on the real nodes (mean removal)
 __global__ void sub_mean_kernel(F2Geom g, double *v, const double *sc, int slot, double count) {
   const double m = sc[slot] / count;
-  NODE_LOOP(g)
+  F2_ROWS(g)
   v[o] -= m;
-  }
+  F2_ROWS_END
 }
 
 __global__ void axpy2_kernel(double *x, double *r, const double *p, const double *q, double alpha,
@@ -157,9 +173,11 @@ __global__ void xpay_kernel(double *p, const double *z, double beta, size_t n) {
     p[k] = z[k] + beta * p[k];
 }
 
-__global__ void ones_kernel(double *v, size_t n) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) v[k] = 1.0;
+// blocks for a row loop: four rows per 256-thread block
+int rows_grid(const F2Geom &g) {
+  const long rows = (long)(g.ny + 1) * (g.nz + 1);
+  const long b = (rows + 3) / 4;
+  return (int)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
 int gridn(size_t n) {
@@ -210,7 +228,7 @@ cmcg_status RieszMG::build(const F2Geom &fine, DeviceArena &arena, hipStream_t s
     CMCG_TRY(arena.alloc_n(L.g.fs, &L.t, s));
     if (l > 0 && fine.mask) {
       CMCG_TRY(arena.alloc_n(L.g.fs, &L.maskbuf, s));
-      hipLaunchKernelGGL(coarse_mask_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s, lv_[l - 1].g,
+      hipLaunchKernelGGL(coarse_mask_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s, lv_[l - 1].g,
                          L.g, lv_[l - 1].g.mask, L.maskbuf);
       CMCG_HIP(hipGetLastError());
       L.g.mask = L.maskbuf;
@@ -240,15 +258,12 @@ cmcg_status RieszMG::dot(const double *a, const double *b, size_t n, double *out
 }
 
 cmcg_status RieszMG::project(double *v, int l) {
-  // v <- v - (sum v) / count on real nodes (pure Neumann only); padding stays 0 in the sum
+  // v <- v - (sum v) / count over the real nodes (pure Neumann only)
   const F2Geom &g = lv_[l].g;
-  hipLaunchKernelGGL(ones_kernel, dim3(gridn(g.fs)), dim3(256), 0, s_, lv_[l].t, g.fs);
+  hipLaunchKernelGGL(sum_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s_, g, v, partials_);
   CMCG_HIP(hipGetLastError());
-  // padding of t must not count: the plain sum of v over all entries is its sum over real
-  // nodes because v is zero on padding
-  CMCG_HIP(dot_plain<double, double>(v, lv_[l].t, g.fs, partials_, s_));
   CMCG_HIP(finalize(partials_, kRedBlocks, scal_, kFinStore, 1, s_));
-  hipLaunchKernelGGL(sub_mean_kernel, dim3(gridn(g.fs)), dim3(256), 0, s_, g, v, scal_, 1,
+  hipLaunchKernelGGL(sub_mean_kernel, dim3(rows_grid(g)), dim3(256), 0, s_, g, v, scal_, 1,
                      (double)lv_[l].nfree);
   CMCG_HIP(hipGetLastError());
   return CMCG_OK;
@@ -259,7 +274,7 @@ cmcg_status RieszMG::smooth(int l, int sweeps) {
   MGLevel &L = lv_[l];
   double *cur = L.x, *other = L.t;
   for (int k = 0; k < sweeps; ++k) {
-    hipLaunchKernelGGL(jacobi_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s_, L.g, cur, L.b, other,
+    hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, cur, L.b, other,
                        omega_, k == 0 ? 1 : 0);
     CMCG_HIP(hipGetLastError());
     std::swap(cur, other);
@@ -277,18 +292,18 @@ cmcg_status RieszMG::vcycle_level(int l) {
     return CMCG_OK;
   }
   CMCG_TRY(smooth(l, pre_));
-  hipLaunchKernelGGL(residual_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s_, L.g, L.x, L.b, L.r);
+  hipLaunchKernelGGL(residual_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, L.x, L.b, L.r);
   CMCG_HIP(hipGetLastError());
   MGLevel &C = lv_[l + 1];
-  hipLaunchKernelGGL(restrict_kernel, dim3(gridn(C.g.fs)), dim3(256), 0, s_, L.g, C.g, L.r, C.b);
+  hipLaunchKernelGGL(restrict_kernel, dim3(rows_grid(C.g)), dim3(256), 0, s_, L.g, C.g, L.r, C.b);
   CMCG_HIP(hipGetLastError());
   CMCG_TRY(vcycle_level(l + 1));
-  hipLaunchKernelGGL(prolong_add_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s_, L.g, C.g, C.x, L.x);
+  hipLaunchKernelGGL(prolong_add_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, C.g, C.x, L.x);
   CMCG_HIP(hipGetLastError());
   // post-smoothing continues from the corrected x: x <- x + omega D^{-1}(b - S x), `post` times
   double *cur = L.x, *other = L.t;
   for (int k = 0; k < post_; ++k) {
-    hipLaunchKernelGGL(jacobi_kernel, dim3(gridn(L.g.fs)), dim3(256), 0, s_, L.g, cur, L.b, other,
+    hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, cur, L.b, other,
                        omega_, 0);
     CMCG_HIP(hipGetLastError());
     std::swap(cur, other);
@@ -305,6 +320,16 @@ cmcg_status RieszMG::vcycle(const double *b, double *x) {
   CMCG_TRY(vcycle_level(0));
   if (neumann_) CMCG_TRY(project(x, 0));
   return CMCG_OK;
+}
+
+cmcg_status RieszMG::apply_vcycle(const void *b, int b_is_float, double *x) {
+  const size_t n = lv_[0].g.fs;
+  if (b_is_float)
+    CMCG_HIP(convert<double, float>(pr_, static_cast<const float *>(b), n, s_));
+  else
+    CMCG_HIP(hipMemcpyAsync(pr_, b, n * sizeof(double), hipMemcpyDeviceToDevice, s_));
+  if (neumann_) CMCG_TRY(project(pr_, 0));
+  return vcycle(pr_, x);
 }
 
 cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol, int max_iter,
@@ -326,7 +351,7 @@ cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol,
   double rz = 0.0;
   CMCG_TRY(dot(pr_, pz_, n, &rz));
   for (int it = 1; it <= max_iter; ++it) {
-    hipLaunchKernelGGL(s_apply_kernel, dim3(gridn(n)), dim3(256), 0, s_, g, pp_, pq_);
+    hipLaunchKernelGGL(s_apply_kernel, dim3(rows_grid(g)), dim3(256), 0, s_, g, pp_, pq_);
     CMCG_HIP(hipGetLastError());
     double pq = 0.0;
     CMCG_TRY(dot(pp_, pq_, n, &pq));

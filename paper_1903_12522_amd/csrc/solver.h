@@ -18,6 +18,7 @@ struct SolverConfig {
   double refresh = 0.1;    // FP32-mixed: FP64 residual refresh factor (<= 0: never)
   double riesz_tol = 0.0;
   int riesz_max_iter = 0;
+  int riesz_mode = CMCG_RIESZ_SOLVE;   // resolved: CMCG_RIESZ_SOLVE or CMCG_RIESZ_VCYCLE
   hipStream_t stream = nullptr;
   double h = 0, omega = 0, T = 0, dt = 0;
   int N = 0;

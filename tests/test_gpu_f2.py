@@ -174,3 +174,42 @@ def test_paper_1d_examples_as_3d_channels(cm, example):
         assert np.max(np.abs(uh + np.exp(1j * k * x))) < 0.01
     else:
         assert np.max(np.abs(U - 16 * x ** 2 * (x - 1) ** 2)) < 0.07
+
+
+@pytest.mark.parametrize("masked", [True, False])
+def test_vcycle_riesz_is_symmetric_positive(cm, masked):
+    """The fixed V-cycle that stands in for S^{-1} is a symmetric positive operator (on zero-sum
+    vectors when S is singular) and spectrally close to S^{-1}: CG with it minimises the same J."""
+    prob = _mixed3d(n=(16, 12, 8), seed=11, masked=masked)
+    o = F2(prob)
+    rng = np.random.default_rng(12)
+    fr = np.concatenate([o.free.ravel()] * 2)
+    x = rng.standard_normal(o.size) * fr
+    y = rng.standard_normal(o.size) * fr
+    u = slice(0, o.nn)
+    if not masked:
+        x[u] -= x[u].mean()
+        y[u] -= y[u].mean()
+    with cm.Solver(prob, "fp64", riesz_mode="vcycle") as s:
+        Px = s.apply(cm.OP_RIESZ, x)
+        Py = s.apply(cm.OP_RIESZ, y)
+    assert abs(Px[u] @ y[u] - x[u] @ Py[u]) <= 1e-12 * np.linalg.norm(Px[u]) * np.linalg.norm(y[u])
+    assert Px[u] @ x[u] > 0 and Py[u] @ y[u] > 0
+    Ex = o.riesz(x)[u]
+    assert 0.2 < (Px[u] @ x[u]) / (Ex @ x[u]) < 5.0
+    # the velocity block is the exact M^{-1} in both modes
+    assert _rel(Px[o.nn:], o.riesz(x)[o.nn:]) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["inclusions", "sphere"])
+def test_vcycle_riesz_reaches_the_same_solution(cm, kind):
+    if kind == "inclusions":
+        prob = ci.inclusions_3d(n=16, freq=1.5, n_incl=6, seed=9, width=0.12, r_range=(0.1, 0.25))
+    else:
+        prob = ci.sound_soft_sphere_3d(n=16, freq=1.2, radius=0.2)
+    o = F2(prob)
+    Ud, _ = o.direct()
+    with cm.Solver(prob, "fp64", tol=1e-11, max_iter=4000, riesz_mode="vcycle") as s:
+        U, rep = s.solve()
+    assert rep["converged"]
+    assert _rel(U, Ud) < 1e-8
