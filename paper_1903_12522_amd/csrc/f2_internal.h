@@ -15,7 +15,7 @@ struct F2Geom {
   double lam_const = 0;              // (c dt / h)^2 when c is constant (lam array absent)
   const uint8_t *mask = nullptr;     // sound-soft nodes (device layout), or null
   int mlo[3] = {0, 0, 0}, mhi[3] = {-1, -1, -1};   // bounding box of the sound-soft nodes
-  int kchunk = 64;                   // planes per thread column
+  int kchunk = 16;                   // planes per thread column
   __host__ __device__ size_t idx(int i, int j, int k) const {
     return (size_t)k * plane + (size_t)j * px + i;
   }

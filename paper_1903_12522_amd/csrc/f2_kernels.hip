@@ -80,11 +80,116 @@ __device__ __forceinline__ T sval(const F2Geom &g, const T *f, const T *lam, int
   return a;
 }
 
+// Output of one node of one sweep, given the stencilled centre value zc, the 7-point operator
+// lap of the stencilled field, the node's second input aux, lambda and the source value F.
+template <typename T, int MODE>
+__device__ __forceinline__ void node_update(const F2Geom &g, const F2Args<T> &p, size_t o, int i,
+                                            int j, int k, T zc, T lap, T aux, T l, T F) {
+  const T dt = (T)g.dt;
+  const bool R = !masked(g, i, j, k);
+  const int m = abs_faces(g, i, j, k);
+  const T beta = m ? (T)m * sqrt(l) : T(0);
+  if (MODE == kF2FwdStart) {
+    // u^1 = R(u^0 + dt (1-beta) v^0 - (lambda L u^0 - F^0) / 2)
+    if (p.ure) {
+      p.ure[o] += (double)zc * p.wcos;
+      p.uim[o] += (double)zc * p.wsin;
+    }
+    p.out[o] = R ? zc + dt * (T(1) - beta) * aux - T(0.5) * (l * lap - F) : T(0);
+  } else if (MODE == kF2FwdStep) {
+    if (p.ure) {
+      p.ure[o] += (double)zc * p.wcos;
+      p.uim[o] += (double)zc * p.wsin;
+    }
+    T un;
+    if (m == 0) un = fma(-l, lap, T(2) * zc - aux) + F;
+    else un = (T(2) * zc - (T(1) - beta) * aux - (l * lap - F)) / (T(1) + beta);
+    p.out[o] = R ? un : T(0);
+  } else if (MODE == kF2FwdEnd) {
+    // out = (u^N, (u^{N+1} - u^{N-1}) / (2 dt)) - sub
+    T up;
+    if (m == 0) up = fma(-l, lap, T(2) * zc - aux) + F;
+    else up = (T(2) * zc - (T(1) - beta) * aux - (l * lap - F)) / (T(1) + beta);
+    if (!R) up = T(0);
+    T ou = zc, ov = (up - aux) / (T(2) * dt);
+    if (p.sub) {
+      ou -= p.sub[o];
+      ov -= p.sub[o + g.fs];
+    }
+    p.out[o] = ou;
+    p.out[o + g.fs] = ov;
+  } else if (MODE == kF2Metric) {
+    // y = M_E w = (S w_u, M w_v) on the free nodes
+    const T eta = (T)eta_of(g, i, j, k);
+    const T h = (T)g.h;
+    const T c2 = l * (T)(g.h * g.h / (g.dt * g.dt));
+    p.out[o] = R ? h * eta * lap : T(0);
+    p.out[o + g.fs] = (R && c2 > T(0)) ? h * h * h * eta / c2 * aux : T(0);
+  } else if (MODE == kF2AdjInit) {
+    // st = g_y = psi y_v, aux = y_u:  g_0 = psi y_u + K g_y / (2 dt),
+    //                                 psi b_0 = (Lb - 1) g_y / (2 dt) = -g_y / ((1+beta) dt)
+    const T eta = (T)eta_of(g, i, j, k);
+    const T psi = R ? l / ((T(1) + beta) * eta) : T(0);
+    const T Kg = R ? (T(2) * zc - l * lap) / (T(1) + beta) : T(0);
+    p.out[o] = psi * aux + Kg / (T(2) * dt);
+    p.out2[o] = R ? -zc / ((T(1) + beta) * dt) : T(0);
+  } else if (MODE == kF2AdjStepFirst) {
+    // g_1 = K g_0 + psi b_0
+    T gn;
+    if (m == 0) gn = fma(-l, lap, T(2) * zc);
+    else gn = (T(2) * zc - l * lap) / (T(1) + beta);
+    p.out[o] = R ? gn + aux : T(0);
+  } else if (MODE == kF2AdjEnd) {
+    // st = g_M (stencilled as (1+beta) g), aux = g_{M-1}; a = (1+beta) eta g / lambda:
+    //   u_0 = R(a - eta L((1+beta) g) / 2) + Lb a_{M-1},  Lb a_{M-1} = -(1-beta) eta g_{M-1} / lambda
+    //   v_0 = R dt (1-beta) a
+    const T eta = (T)eta_of(g, i, j, k);
+    const T a = eta * zc / l;
+    T ou = R ? a - T(0.5) * eta * lap - (T(1) - beta) * eta * aux / l : T(0);
+    T ov = R ? dt * (T(1) - beta) * a : T(0);
+    if (p.sub) {
+      ou -= p.sub[o];
+      ov -= p.sub[o + g.fs];
+    }
+    p.out[o] = ou;
+    p.out[o + g.fs] = ov;
+  }
+}
+
+// The loads one plane's update needs (raw values of the plainly stencilled sweeps).
+template <typename T>
+struct PlaneLoads {
+  T zp, xe, ym, yp, aux, lam, fr, fi;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void plane_loads(const F2Geom &g, const F2Args<T> &p, int ic, int xend,
+                                            int j, int jm, int jp, int k, PlaneLoads<T> &q) {
+  q.zp = p.st[g.idx(ic, j, mirror(k + 1, g.nz))];
+  q.xe = p.st[g.idx(xend, j, k)];
+  q.ym = p.st[g.idx(ic, jm, k)];
+  q.yp = p.st[g.idx(ic, jp, k)];
+  const size_t o = g.idx(ic, j, k);
+  q.aux = p.aux[o];
+  q.lam = lam_at(g, p.lam, o);
+  q.fr = q.fi = T(0);
+  if (MODE == kF2FwdStart || MODE == kF2FwdStep || MODE == kF2FwdEnd) {
+    if (p.forced) {
+      q.fr = p.fre[o];
+      if (p.fim) q.fi = p.fim[o];
+    }
+  }
+}
+
 // The grid is (x tiles of 64 nodes, y tiles of 4 rows, z chunks); each wavefront owns one row.
 // Lanes past the last node shadow it so that every lane takes part in the DPP shifts; they
-// never store.
+// never store.  The two end lanes of a wavefront load their outer x neighbour in the same load
+// instruction in which the other lanes reload their own node (a cache hit).  Sweeps that
+// stencil the field as stored issue the loads of plane k+1 before computing plane k (register
+// double buffering), which doubles the bytes each wavefront keeps in flight.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
+  constexpr bool kPlain = MODE != kF2Metric && MODE != kF2AdjEnd;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 64 + lane;
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -93,106 +198,50 @@ __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
   const int ic = live ? i : g.nx;
   const bool last = ic == g.nx;              // right neighbour is the mirrored left one
   const int iml = mirror(ic - 1, g.nx), ipl = mirror(ic + 1, g.nx);
+  const int xend = lane == 0 ? iml : (lane == 63 ? ipl : ic);
   const int jm = mirror(j - 1, g.ny), jp = mirror(j + 1, g.ny);
   const int k0 = blockIdx.z * g.kchunk;
   const int k1 = min(k0 + g.kchunk, g.nz + 1);
-  const T dt = (T)g.dt;
   T zm = sval<T, MODE>(g, p.st, p.lam, ic, j, mirror(k0 - 1, g.nz));
   T zc = sval<T, MODE>(g, p.st, p.lam, ic, j, k0);
-  for (int k = k0; k < k1; ++k) {
-    const T zp = sval<T, MODE>(g, p.st, p.lam, ic, j, mirror(k + 1, g.nz));
-    T xl = lane_from_left(zc);
-    T xr = lane_from_right(zc);
-    if (lane == 0) xl = sval<T, MODE>(g, p.st, p.lam, iml, j, k);
-    if (lane == 63) xr = sval<T, MODE>(g, p.st, p.lam, ipl, j, k);
-    if (last) xr = xl;
-    const T ym = sval<T, MODE>(g, p.st, p.lam, ic, jm, k);
-    const T yp = sval<T, MODE>(g, p.st, p.lam, ic, jp, k);
-    const T lap = T(6) * zc - (zm + zp + xl + xr + ym + yp);
-    if (live) {
-      const size_t o = g.idx(ic, j, k);
-      const bool R = !masked(g, ic, j, k);
-      const T l = lam_at(g, p.lam, o);
-      const int m = abs_faces(g, ic, j, k);
-      const T beta = m ? (T)m * sqrt(l) : T(0);
-      T F = T(0);
-      if (MODE == kF2FwdStart || MODE == kF2FwdStep || MODE == kF2FwdEnd) {
-        if (p.forced) {
-          F = p.fre[o] * (T)p.fcos;
-          if (p.fim) F = fma(p.fim[o], (T)p.fsin, F);
-        }
+  if (kPlain) {
+    PlaneLoads<T> nxt;
+    plane_loads<T, MODE>(g, p, ic, xend, j, jm, jp, k0, nxt);
+    for (int k = k0; k < k1; ++k) {
+      const PlaneLoads<T> q = nxt;
+      if (k + 1 < k1) plane_loads<T, MODE>(g, p, ic, xend, j, jm, jp, k + 1, nxt);
+      T xl = lane_from_left(zc);
+      T xr = lane_from_right(zc);
+      if (lane == 0) xl = q.xe;
+      if (lane == 63) xr = q.xe;
+      if (last) xr = xl;
+      const T lap = T(6) * zc - (zm + q.zp + xl + xr + q.ym + q.yp);
+      if (live) {
+        const T F = fma(q.fi, (T)p.fsin, q.fr * (T)p.fcos);
+        node_update<T, MODE>(g, p, g.idx(ic, j, k), ic, j, k, zc, lap, q.aux, q.lam, F);
       }
-      if (MODE == kF2FwdStart) {
-        // u^1 = R(u^0 + dt (1-beta) v^0 - (lambda L u^0 - F^0) / 2)
-        const T u0 = zc, v0 = p.aux[o];
-        if (p.ure) {
-          p.ure[o] += (double)u0 * p.wcos;
-          p.uim[o] += (double)u0 * p.wsin;
-        }
-        p.out[o] = R ? u0 + dt * (T(1) - beta) * v0 - T(0.5) * (l * lap - F) : T(0);
-      } else if (MODE == kF2FwdStep) {
-        const T u = zc, um = p.aux[o];
-        if (p.ure) {
-          p.ure[o] += (double)u * p.wcos;
-          p.uim[o] += (double)u * p.wsin;
-        }
-        T un;
-        if (m == 0) un = fma(-l, lap, T(2) * u - um) + F;
-        else un = (T(2) * u - (T(1) - beta) * um - (l * lap - F)) / (T(1) + beta);
-        p.out[o] = R ? un : T(0);
-      } else if (MODE == kF2FwdEnd) {
-        // out = (u^N, (u^{N+1} - u^{N-1}) / (2 dt)) - sub
-        const T u = zc, um = p.aux[o];
-        T up;
-        if (m == 0) up = fma(-l, lap, T(2) * u - um) + F;
-        else up = (T(2) * u - (T(1) - beta) * um - (l * lap - F)) / (T(1) + beta);
-        if (!R) up = T(0);
-        T ou = u, ov = (up - um) / (T(2) * dt);
-        if (p.sub) {
-          ou -= p.sub[o];
-          ov -= p.sub[o + g.fs];
-        }
-        p.out[o] = ou;
-        p.out[o + g.fs] = ov;
-      } else if (MODE == kF2Metric) {
-        // y = M_E w = (S w_u, M w_v) on the free nodes
-        const T eta = (T)eta_of(g, ic, j, k);
-        const T h = (T)g.h;
-        const T c2 = l * (T)(g.h * g.h / (g.dt * g.dt));
-        p.out[o] = R ? h * eta * lap : T(0);
-        p.out[o + g.fs] = (R && c2 > T(0)) ? h * h * h * eta / c2 * p.aux[o] : T(0);
-      } else if (MODE == kF2AdjInit) {
-        // st = g_y = psi y_v, aux = y_u:  g_0 = psi y_u + K g_y / (2 dt),
-        //                                 psi b_0 = (Lb - 1) g_y / (2 dt) = -g_y / ((1+beta) dt)
-        const T eta = (T)eta_of(g, ic, j, k);
-        const T psi = R ? l / ((T(1) + beta) * eta) : T(0);
-        const T Kg = R ? (T(2) * zc - l * lap) / (T(1) + beta) : T(0);
-        p.out[o] = psi * p.aux[o] + Kg / (T(2) * dt);
-        p.out2[o] = R ? -zc / ((T(1) + beta) * dt) : T(0);
-      } else if (MODE == kF2AdjStepFirst) {
-        // g_1 = K g_0 + psi b_0
-        T gn;
-        if (m == 0) gn = fma(-l, lap, T(2) * zc);
-        else gn = (T(2) * zc - l * lap) / (T(1) + beta);
-        p.out[o] = R ? gn + p.aux[o] : T(0);
-      } else if (MODE == kF2AdjEnd) {
-        // st = g_M (stencilled as (1+beta) g), aux = g_{M-1}; a = (1+beta) eta g / lambda:
-        //   u_0 = R(a - eta L((1+beta) g) / 2) + Lb a_{M-1},  Lb a_{M-1} = -(1-beta) eta g_{M-1} / lambda
-        //   v_0 = R dt (1-beta) a
-        const T eta = (T)eta_of(g, ic, j, k);
-        const T a = eta * zc / l;
-        T ou = R ? a - T(0.5) * eta * lap - (T(1) - beta) * eta * p.aux[o] / l : T(0);
-        T ov = R ? dt * (T(1) - beta) * a : T(0);
-        if (p.sub) {
-          ou -= p.sub[o];
-          ov -= p.sub[o + g.fs];
-        }
-        p.out[o] = ou;
-        p.out[o + g.fs] = ov;
-      }
+      zm = zc;
+      zc = q.zp;
     }
-    zm = zc;
-    zc = zp;
+  } else {
+    for (int k = k0; k < k1; ++k) {
+      const T zp = sval<T, MODE>(g, p.st, p.lam, ic, j, mirror(k + 1, g.nz));
+      const T xe = sval<T, MODE>(g, p.st, p.lam, xend, j, k);
+      T xl = lane_from_left(zc);
+      T xr = lane_from_right(zc);
+      if (lane == 0) xl = xe;
+      if (lane == 63) xr = xe;
+      if (last) xr = xl;
+      const T ym = sval<T, MODE>(g, p.st, p.lam, ic, jm, k);
+      const T yp = sval<T, MODE>(g, p.st, p.lam, ic, jp, k);
+      const T lap = T(6) * zc - (zm + zp + xl + xr + ym + yp);
+      if (live) {
+        const size_t o = g.idx(ic, j, k);
+        node_update<T, MODE>(g, p, o, ic, j, k, zc, lap, p.aux[o], lam_at(g, p.lam, o), T(0));
+      }
+      zm = zc;
+      zc = zp;
+    }
   }
 }
 

@@ -115,7 +115,7 @@ class F2Solver final : public Solver {
     g.dt = cfg.dt;
     for (int f = 0; f < 6; ++f) g.abs_face[f] = P->face_bc[f] == CMCG_ABSORBING ? 1 : 0;
     g.lam_const = (P->c_const * cfg.dt / cfg.h) * (P->c_const * cfg.dt / cfg.h);
-    g.kchunk = 64;
+    g.kchunk = 16;
     mixed = cfg.prec == CMCG_FP32_MIXED;
     riesz_tol = cfg.riesz_tol > 0 ? cfg.riesz_tol : 1e-10;
     riesz_max = cfg.riesz_max_iter > 0 ? cfg.riesz_max_iter : 500;
