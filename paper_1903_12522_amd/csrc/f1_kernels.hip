@@ -221,97 +221,161 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
   }
 }
 
-// The common case, fully specialised: a wavefront whose 64 columns are interior, a band whose
+// Raw buffer access for the fast variant: one resource per array (wave-uniform base and byte
+// size), the lane's column offset in a VGPR and the row/field offset in an SGPR, so a row costs
+// no per-lane address arithmetic.  Every resource is below 2^31 bytes and every scalar offset
+// below 2^31, so a lane offset of 2^31 is out of range whatever is added to it: the hardware's
+// range check drops such a lane's store (and returns 0 for its load).  Halo lanes and rows
+// outside the band store with that offset instead of branching around the store, so every row
+// iteration issues the same memory operations and the compiler can wait for exactly the loads it
+// needs rather than for everything outstanding.
+constexpr int kBufWord3 = 0x00020000;      // gfx9 resource word 3: raw (unswizzled) access
+constexpr unsigned kBufDrop = 0x80000000u;
+constexpr unsigned long long kBufMax = 0x7fffffffull;
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kBufWord3);
+}
+__device__ __forceinline__ void buf_ld(float &x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  x = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ void buf_ld(double &x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ void buf_st(float x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(x), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void buf_st(double x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i32x2, x), r, (int)vo, (int)so, 0);
+}
+
+// Resources and offsets of one fast-variant wavefront.
+struct FastIO {
+  __amdgpu_buffer_rsrc_t in, cc, out;
+  unsigned vo;        // this lane's column offset (bytes)
+  unsigned vo_st;     // column offset for stores: vo, or out of range for a halo lane
+  unsigned pitchb, fsb;
+};
+
+// One row iteration of the fast variant: level 0 takes row j (v, Px, kap and the Py face above
+// the row; the face below is held from the previous iteration), level k advances row j - k from
+// level k-1 using the previous iteration's emissions (*p arrays) and writes this iteration's
+// (*c arrays); row j - K leaves the pipeline.
+template <typename T, int K, bool ADJ>
+__device__ __forceinline__ void f1_fast_row(const FastIO &io, const F1Launch &L, const int j,
+                                            const int s0, const int s1, const T dth, const T hdth,
+                                            const T in_v, const T in_px, const T in_py,
+                                            const T in_cc, const T (&Vp)[K + 1],
+                                            const T (&PXp)[K + 1], const T (&PYp)[K + 1],
+                                            const T (&CCp)[K + 1], T (&Vc)[K + 1],
+                                            T (&PXc)[K + 1], T (&PYc)[K + 1], T (&CCc)[K + 1],
+                                            T (&HOLD)[K + 1]) {
+  Vc[0] = in_v;
+  PXc[0] = in_px;
+  PYc[0] = HOLD[0];          // Py(j-1)
+  HOLD[0] = in_py;
+  CCc[0] = in_cc;
+#pragma unroll
+  for (int k = 1; k <= K; ++k) {
+    const bool lastk = L.last && k == K;
+    if (!ADJ) {
+      const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
+      const T kap = CCp[k - 1];
+      const T kick_h = lastk ? hdth : dth;
+      const T pl = lane_from_left(px);
+      const T vn = fma(kap, (px - pl) + (pyr - pyrm1), v);
+      const T vr = lane_from_right(vn);
+      Vc[k] = vn;
+      PXc[k] = fma(kick_h, vr - vn, px);
+      PYc[k] = fma(kick_h, vn - Vp[k], pyrm1);
+      CCc[k] = kap;
+    } else {
+      const T vA = Vc[k - 1], vB = Vp[k - 1], pxB = PXp[k - 1], pyB = PYc[k - 1];
+      const T kB = CCp[k - 1];
+      const T wBr = lane_from_right(vB);
+      const T pxn = fma(-dth, wBr - vB, pxB);
+      const T pyn = fma(-dth, vA - vB, pyB);
+      const T pl = lane_from_left(pxn);
+      Vc[k] = fma(lastk ? T(-0.5) * kB : -kB, (pxn - pl) + (pyn - HOLD[k]), vB);
+      PXc[k] = pxn;
+      PYc[k] = HOLD[k];
+      HOLD[k] = pyn;
+      CCc[k] = kB;
+    }
+  }
+  // row ro = j - K: Px and v; row ro - 1: Py (its upper face is complete only now)
+  const int ro = j - K;
+  const unsigned voA = (ro >= s0 && ro < s1) ? io.vo_st : kBufDrop;
+  const unsigned voB = (ro - 1 >= s0 && ro - 1 < s1) ? io.vo_st : kBufDrop;
+  const unsigned soA = (unsigned)ro * io.pitchb, soB = (unsigned)(ro - 1) * io.pitchb;
+  buf_st(PXc[K], io.out, voA, soA);
+  buf_st(Vc[K], io.out, voA, soA + 2 * io.fsb);
+  buf_st(PYc[K], io.out, voB, soB + io.fsb);
+}
+
+// Fast variant of the body for wavefronts whose 64 columns are interior (1 <= i <= nx-2), whose
 // rows (with its pipeline margin) are interior, and a launch with no opening kick, no source and
-// no filter.  No masks and no per-row branches remain; the arithmetic per cell is identical to
-// the general body's, so results do not depend on which variant ran.
+// no filter and no subtrahend (every launch of a period but the last), on arrays below 2^31 bytes.
+// No masks and no branches remain in the row loop; the
+// arithmetic per cell is identical to the general body's, so results do not depend on which
+// variant ran.  The row loop is unrolled by two with the previous/current register sets trading
+// roles (no register copies), and each row's loads are issued one row ahead of their use.
 template <typename T, int K, bool ADJ>
 __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, const int i, const int lane,
                                                const int s0, const int s1) {
   constexpr int H = K + 1;
-  const size_t pitch = (size_t)g.pitch, fs = p.fs;
   const T dth = (T)(g.dt / g.h);
   const T hdth = T(0.5) * dth;
-  const bool laneOut = lane >= H && lane < 64 - H;
-  T Vp[K + 1], PXp[K + 1], PYp[K + 1], CCp[K + 1];
-  T Vc[K + 1], PXc[K + 1], PYc[K + 1], CCc[K + 1];
+  FastIO io;
+  io.fsb = (unsigned)(p.fs * sizeof(T));
+  io.pitchb = (unsigned)((size_t)g.pitch * sizeof(T));
+  io.in = buf_rsrc(p.in, 3 * io.fsb);
+  io.cc = buf_rsrc(p.cc, io.fsb);
+  io.out = buf_rsrc(p.out, 3 * io.fsb);
+  io.vo = (unsigned)i * (unsigned)sizeof(T);
+  io.vo_st = (lane >= H && lane < 64 - H) ? io.vo : kBufDrop;
+  T Va[K + 1], PXa[K + 1], PYa[K + 1], CCa[K + 1];
+  T Vb[K + 1], PXb[K + 1], PYb[K + 1], CCb[K + 1];
   T HOLD[K + 1];
 #pragma unroll
   for (int k = 0; k <= K; ++k) {
-    Vp[k] = PXp[k] = PYp[k] = CCp[k] = T(0);
-    Vc[k] = PXc[k] = PYc[k] = CCc[k] = T(0);
+    Va[k] = PXa[k] = PYa[k] = CCa[k] = T(0);
+    Vb[k] = PXb[k] = PYb[k] = CCb[k] = T(0);
     HOLD[k] = T(0);
   }
   const int jstart = s0 - K - 2, jend = s1 + K;
-  const T *pin = p.in + (size_t)jstart * pitch + i;
-  const T *pcc = p.cc + (size_t)jstart * pitch + i;
-  HOLD[0] = pin[fs - pitch];
-  for (int j = jstart; j <= jend; ++j, pin += pitch, pcc += pitch) {
-    Vc[0] = pin[2 * fs];
-    PXc[0] = pin[0];
-    PYc[0] = HOLD[0];          // Py(j-1)
-    HOLD[0] = pin[fs];
-    CCc[0] = pcc[0];
-#pragma unroll
-    for (int k = 1; k <= K; ++k) {
-      const bool lastk = L.last && k == K;
-      if (!ADJ) {
-        const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
-        const T kap = CCp[k - 1];
-        const T kick_h = lastk ? hdth : dth;
-        const T pl = lane_from_left(px);
-        const T vn = fma(kap, (px - pl) + (pyr - pyrm1), v);
-        const T vr = lane_from_right(vn);
-        Vc[k] = vn;
-        PXc[k] = fma(kick_h, vr - vn, px);
-        PYc[k] = fma(kick_h, vn - Vp[k], pyrm1);
-        CCc[k] = kap;
-      } else {
-        const T vA = Vc[k - 1], vB = Vp[k - 1], pxB = PXp[k - 1], pyB = PYc[k - 1];
-        const T kB = CCp[k - 1];
-        const T wBr = lane_from_right(vB);
-        const T pxn = fma(-dth, wBr - vB, pxB);
-        const T pyn = fma(-dth, vA - vB, pyB);
-        const T pl = lane_from_left(pxn);
-        Vc[k] = fma(lastk ? T(-0.5) * kB : -kB, (pxn - pl) + (pyn - HOLD[k]), vB);
-        PXc[k] = pxn;
-        PYc[k] = HOLD[k];
-        HOLD[k] = pyn;
-        CCc[k] = kB;
-      }
-    }
-    if (laneOut) {
-      const int ro = j - K;
-      if (ro >= s0 && ro < s1) {
-        const size_t o = (size_t)ro * pitch + i;
-        T a = PXc[K], c = Vc[K];
-        if (p.sub) {
-          a -= p.sub[o];
-          c -= p.sub[o + 2 * fs];
-        }
-        p.out[o] = a;
-        p.out[o + 2 * fs] = c;
-      }
-      if (ro - 1 >= s0 && ro - 1 < s1) {
-        const size_t o = (size_t)(ro - 1) * pitch + i;
-        T b = PYc[K];
-        if (p.sub) b -= p.sub[o + fs];
-        p.out[o + fs] = b;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k <= K; ++k) {
-      Vp[k] = Vc[k];
-      PXp[k] = PXc[k];
-      PYp[k] = PYc[k];
-      CCp[k] = CCc[k];
-    }
+  buf_ld(HOLD[0], io.in, io.vo, (unsigned)(jstart - 1) * io.pitchb + io.fsb);
+  // level-0 inputs of the next row, loaded one row ahead of their use
+  T nv, npx, npy, ncc;
+  auto load_row = [&](int r) {
+    const unsigned so = (unsigned)r * io.pitchb;
+    buf_ld(nv, io.in, io.vo, so + 2 * io.fsb);
+    buf_ld(npx, io.in, io.vo, so);
+    buf_ld(npy, io.in, io.vo, so + io.fsb);
+    buf_ld(ncc, io.cc, io.vo, so);
+  };
+  load_row(jstart);
+  int j = jstart;
+  for (; j + 1 <= jend; j += 2) {
+    const T v0 = nv, px0 = npx, py0 = npy, cc0 = ncc;
+    load_row(j + 1);
+    f1_fast_row<T, K, ADJ>(io, L, j, s0, s1, dth, hdth, v0, px0, py0, cc0, Va, PXa, PYa, CCa, Vb,
+                           PXb, PYb, CCb, HOLD);
+    const T v1 = nv, px1 = npx, py1 = npy, cc1 = ncc;
+    if (j + 2 <= jend) load_row(j + 2);
+    f1_fast_row<T, K, ADJ>(io, L, j + 1, s0, s1, dth, hdth, v1, px1, py1, cc1, Vb, PXb, PYb, CCb,
+                           Va, PXa, PYa, CCa, HOLD);
   }
+  if (j <= jend)
+    f1_fast_row<T, K, ADJ>(io, L, j, s0, s1, dth, hdth, nv, npx, npy, ncc, Va, PXa, PYa, CCa, Vb,
+                           PXb, PYb, CCb, HOLD);
 }
 
 // Tile (bx, by) of a launch: wavefront w of the workgroup owns column strip 4 bx + w of the
-// band of rows by.  Interior wavefronts (all 64 columns in 1..nx-2) take the unmasked variant.
+// band of rows by.  Interior wavefronts (all 64 columns in 1..nx-2) of interior bands take the
+// fast variant.
 template <typename T, int K, bool ADJ>
 __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, int band, int bx, int by) {
@@ -325,7 +389,8 @@ __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> 
   const int s1 = min(s0 + band, g.ny);
   const bool inner_cols = i0 >= 1 && i0 + 63 <= g.nx - 2;
   const bool inner_rows = s0 >= 2 * K + 3 && s1 + K <= g.ny - 2;
-  if (inner_cols && inner_rows && !L.first && !L.forced && !L.accumulate)
+  const bool small = 3ull * p.fs * sizeof(T) <= kBufMax;
+  if (inner_cols && inner_rows && small && !p.sub && !L.first && !L.forced && !L.accumulate)
     f1_stream_fast<T, K, ADJ>(g, p, L, i0 + lane, lane, s0, s1);
   else if (inner_cols)
     f1_stream_body<T, K, ADJ, false>(g, p, L, i0 + lane, lane, s0, s1);

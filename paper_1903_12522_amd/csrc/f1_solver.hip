@@ -11,9 +11,10 @@
 // convergence), the true gradient at the FP64 iterate is recomputed with one FP64 forward and one
 // FP64 backward period and replaces r; the search direction is kept.  The initial gradient and the
 // output filter period are FP64 as well.
+#include <cstring>
 #include <deque>
 #include <map>
-#include <cstring>
+#include <type_traits>
 
 #include "solver.h"
 
@@ -527,16 +528,10 @@ struct ServeRequest {
   cmcg_report rep{};
 };
 
-template <typename T>
-struct GroupKey {
-  bool adj;
-  int ns;
-};
-
 class F1Server final : public Server {
  public:
   int64_t budget = 0;
-  int max_slots = 16, kblock = 4, device = 0;
+  int max_slots = 16, kblock = 0, device = 0;
   hipStream_t s = nullptr;
   std::map<int64_t, ServeRequest *> reqs;
   std::deque<int64_t> queue;
@@ -643,13 +638,23 @@ class F1Server final : public Server {
     }
   }
 
+  // One batched launch planned for this tick: `count` descriptors at byte offset `off` of the
+  // descriptor staging buffer, all of one precision, direction and step count.
+  struct PlannedLaunch {
+    int prec, ns, adj, count, blocks;
+    size_t off;
+  };
+
+  // Append this round's launches of the solves in `sel` (all of precision T) to the plan: the
+  // solves are grouped by (direction, steps), each group one batched launch; every solve's step
+  // counter advances.  Returns false when the staging buffer cannot hold the round.
   template <typename T>
-  cmcg_status launch_groups(std::vector<ServeRequest *> &slots, const std::vector<int> &sel,
-                            size_t &off) {
-    // group by (direction, steps); each group is one batched launch
+  bool plan_round(const std::vector<ServeRequest *> &sel, size_t &off,
+                  std::vector<PlannedLaunch> &plan, double &work) {
+    if (sel.empty()) return true;
+    if (off + sel.size() * sizeof(F1SlotLaunch<T>) + 2 * 256 > desc_cap) return false;
     std::map<std::pair<int, int>, std::vector<F1SlotLaunch<T>>> groups;
-    for (int idx : sel) {
-      ServeRequest *R = slots[idx];
+    for (ServeRequest *R : sel) {
       F1Solver *S = R->S;
       const F1Set *b;
       bool adj, forced, filter;
@@ -667,7 +672,9 @@ class F1Server final : public Server {
       d.nblocks = d.nbx * nby;
       groups[{adj ? 1 : 0, ns}].push_back(d);
       R->n0 += ns;
-      S->updates += (double)ns * S->g.nx * S->g.ny;
+      const double u = (double)ns * S->g.nx * S->g.ny;
+      S->updates += u;
+      work += u;
     }
     for (auto &kv : groups) {
       auto &v = kv.second;
@@ -677,26 +684,25 @@ class F1Server final : public Server {
         blocks += d.nblocks;
       }
       const size_t bytes = v.size() * sizeof(F1SlotLaunch<T>);
-      if (off + bytes > desc_cap) return set_error("server descriptor buffer full"), CMCG_ENOMEM;
       std::memcpy(static_cast<char *>(h_desc) + off, v.data(), bytes);
-      auto *dd = reinterpret_cast<F1SlotLaunch<T> *>(static_cast<char *>(d_desc) + off);
-      CMCG_HIP(hipMemcpyAsync(dd, static_cast<char *>(h_desc) + off, bytes, hipMemcpyHostToDevice, s));
-      CMCG_HIP(f1_multi_launch<T>(kv.first.second, kv.first.first != 0, dd, (int)v.size(), blocks, s));
+      plan.push_back({std::is_same<T, double>::value ? CMCG_FP64 : CMCG_FP32_MIXED,
+                      kv.first.second, kv.first.first, (int)v.size(), blocks, off});
       off = (off + bytes + 255) / 256 * 256;
     }
+    return true;
+  }
+
+  template <typename T>
+  cmcg_status launch_planned(const PlannedLaunch &L) {
+    auto *dd = reinterpret_cast<const F1SlotLaunch<T> *>(static_cast<const char *>(d_desc) + L.off);
+    CMCG_HIP(f1_multi_launch<T>(L.ns, L.adj != 0, dd, L.count, L.blocks, s));
     return CMCG_OK;
   }
 
   // reductions and CG update after a period ended (issued on the stream, read after the sync)
   cmcg_status post_period(ServeRequest *R) {
     F1Solver *S = R->S;
-    if (R->phase == kPhGradFwd) {
-      R->phase = kPhGradAdj;
-      R->n0 = 0;
-    } else if (R->phase == kPhFwd) {
-      R->phase = kPhAdj;
-      R->n0 = 0;
-    } else if (R->phase == kPhGradAdj) {
+    if (R->phase == kPhGradAdj) {
       CMCG_HIP(hipMemcpyAsync(S->R, S->hi.Q, S->vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
       CMCG_HIP(f1_dot<double, double>(S->g, S->R, S->R, S->hi.cc, 1, S->fs, S->partials, s));
       CMCG_HIP(finalize(S->partials, kRedBlocks, S->scalars, R->grad_mode, 0, s));
@@ -820,29 +826,62 @@ class F1Server final : public Server {
     active.erase(std::remove(active.begin(), active.end(), R->id), active.end());
   }
 
+  // One tick.  Rounds of batched launches are planned on the host (each round advances every
+  // running solve by one launch) until the tick holds about kTickUpdates cell-updates or every
+  // solve waits for a host decision; a forward period that ends hands over to its backward period
+  // within the tick (no decision is needed there).  The descriptors of all rounds go to the
+  // device in one copy, the launches and the end-of-period reductions are queued, and the host
+  // synchronises once to take the CG decisions (Steps 5.6-5.8, refresh, completion).
+  static constexpr double kTickUpdates = 2.0e9;
+  static constexpr int kMaxRounds = 64;
+
   cmcg_status step(int *n_active, int *n_queued) override {
     CMCG_HIP(hipSetDevice(device));
     CMCG_TRY(admit());
-    std::vector<ServeRequest *> slots;
-    std::vector<int> sel32, sel64;
+    std::vector<ServeRequest *> running;
     for (int64_t id : active) {
       ServeRequest *R = reqs[id];
-      if (R->phase == kPhDone) continue;
-      slots.push_back(R);
-      const F1Set *b;
-      bool adj, forced, filter;
-      const void *in, *sub;
-      void *out;
-      job(R, &b, &adj, &forced, &in, &out, &sub, &filter);
-      (b->prec == CMCG_FP64 ? sel64 : sel32).push_back((int)slots.size() - 1);
+      if (R->phase != kPhDone && !R->pending) running.push_back(R);
     }
+    std::vector<PlannedLaunch> plan;
+    std::vector<ServeRequest *> ended;     // solves waiting for reductions and a decision
     size_t off = 0;
-    CMCG_TRY(launch_groups<float>(slots, sel32, off));
-    CMCG_TRY(launch_groups<double>(slots, sel64, off));
-    for (ServeRequest *R : slots)
-      if (R->n0 >= R->S->cfg.N) CMCG_TRY(post_period(R));
+    double work = 0.0;
+    for (int round = 0; round < kMaxRounds && !running.empty() && work < kTickUpdates; ++round) {
+      std::vector<ServeRequest *> sel32, sel64;
+      for (ServeRequest *R : running) {
+        const F1Set *b;
+        bool adj, forced, filter;
+        const void *in, *sub;
+        void *out;
+        job(R, &b, &adj, &forced, &in, &out, &sub, &filter);
+        (b->prec == CMCG_FP64 ? sel64 : sel32).push_back(R);
+      }
+      if (!plan_round<float>(sel32, off, plan, work)) break;
+      if (!plan_round<double>(sel64, off, plan, work)) break;
+      std::vector<ServeRequest *> still;
+      for (ServeRequest *R : running) {
+        if (R->n0 < R->S->cfg.N) {
+          still.push_back(R);
+        } else if (R->phase == kPhGradFwd || R->phase == kPhFwd) {
+          R->phase = R->phase == kPhGradFwd ? kPhGradAdj : kPhAdj;   // forward -> backward
+          R->n0 = 0;
+          still.push_back(R);
+        } else {
+          ended.push_back(R);
+        }
+      }
+      running.swap(still);
+    }
+    if (off > 0)
+      CMCG_HIP(hipMemcpyAsync(d_desc, h_desc, off, hipMemcpyHostToDevice, s));
+    for (const PlannedLaunch &L : plan) {
+      if (L.prec == CMCG_FP64) CMCG_TRY(launch_planned<double>(L));
+      else CMCG_TRY(launch_planned<float>(L));
+    }
+    for (ServeRequest *R : ended) CMCG_TRY(post_period(R));
     CMCG_HIP(hipStreamSynchronize(s));
-    for (ServeRequest *R : slots)
+    for (ServeRequest *R : ended)
       if (R->pending) CMCG_TRY(decide(R));
     if (n_active) *n_active = (int)active.size();
     if (n_queued) *n_queued = (int)queue.size();
@@ -878,7 +917,7 @@ cmcg_status make_f1_server(const cmcg_server_options *o, hipStream_t s, Server *
   auto *S = new F1Server();
   S->budget = o->hbm_budget_bytes;
   S->max_slots = o->max_slots > 0 ? o->max_slots : 16;
-  S->kblock = o->steps_per_launch > 0 ? o->steps_per_launch : 4;
+  S->kblock = o->steps_per_launch > 0 ? o->steps_per_launch : 0;   // 0: per-solve default
   S->device = o->device;
   S->s = s;
   cmcg_status st = S->init();
