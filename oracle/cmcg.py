@@ -31,12 +31,14 @@ def cmcg(phi: Callable[[np.ndarray], np.ndarray],
          riesz: Callable[[np.ndarray], np.ndarray],
          size: int, tol: float, max_iter: int,
          z0: Optional[np.ndarray] = None,
-         record: Optional[List[np.ndarray]] = None):
+         record: Optional[List[np.ndarray]] = None,
+         delta_ref: Optional[float] = None):
     """Run CMCG from z0 (default 0, as in the paper's experiments) until the relative
-    energy-norm residual sqrt(rhat^T r / rhat0^T r0) <= tol (Step 5.8) or max_iter
-    iterations.  Returns (z, history, iterations) with history[l] the relative residual
-    after iteration l (history[0] = 1 for the start).  If `record` is a list, every iterate
-    z_l (including z_0) is appended to it."""
+    energy-norm residual sqrt(rhat^T r / delta_ref) <= tol (Step 5.8) or max_iter
+    iterations; delta_ref defaults to the start's own rhat0^T r0.  (A start from a run-up
+    state passes the value at z = 0, so that it stops at the accuracy a start from rest
+    stops at.)  Returns (z, history, iterations) with history[l] the relative residual after
+    iteration l.  If `record` is a list, every iterate z_l (including z_0) is appended."""
     z = np.zeros(size) if z0 is None else np.array(z0, dtype=np.float64)
     if record is not None:
         record.append(z.copy())
@@ -47,9 +49,9 @@ def cmcg(phi: Callable[[np.ndarray], np.ndarray],
     r = riesz(rhat)
     d = r.copy()
     delta = float(rhat @ r)
-    delta0 = delta
-    history = [1.0]
-    if delta0 == 0.0:
+    delta0 = delta if delta_ref is None else float(delta_ref)
+    history = [math.sqrt(delta / delta0) if delta0 > 0.0 else 0.0]
+    if delta == 0.0 or history[0] <= tol:
         return z, history, 0
     it = 0
     for it in range(1, max_iter + 1):
@@ -79,7 +81,34 @@ def cmcg(phi: Callable[[np.ndarray], np.ndarray],
     return z, history, it
 
 
+def gradient_delta(phi, ET, ME, riesz, size: int) -> float:
+    """rhat^T r of the gradient at z = 0 (Steps 2-3 from rest)."""
+    w = phi(np.zeros(size))
+    rhat = ET(ME(w)) - ME(w)
+    return float(rhat @ riesz(rhat))
+
+
 def functional(phi, ME, z: np.ndarray) -> float:
     """J(z) = 1/2 (Phi(z) - z)^T M_E (Phi(z) - z)  (eq. cost_functional_J, discrete)."""
     w = phi(z) - z
     return 0.5 * float(w @ ME(w))
+
+
+def transient(t: float, t_tr: float) -> float:
+    """Mur's smooth switch-on of the time-harmonic source (Sec. 4.2.3, eq. transientfunction):
+    theta(t) = (2 - sin(s)) sin(s) with s = (t / t_tr) pi / 2 while t <= t_tr, and 1 after.
+    It rises from 0 to 1 with zero slope at t_tr."""
+    if t >= t_tr:
+        return 1.0
+    s = 0.5 * math.pi * t / t_tr
+    return (2.0 - math.sin(s)) * math.sin(s)
+
+
+def runup(period_at: Callable[[np.ndarray, int], np.ndarray], size: int, periods: int) -> np.ndarray:
+    """Time integration of the forced wave equation from rest over `periods` periods (the
+    run-up of Sec. 4.2.3 or the do-nothing long-time solve of Sec. 4.2.2): period p maps the
+    state at t = pT to the state at (p + 1)T, `period_at(z, p)`."""
+    z = np.zeros(size)
+    for p in range(periods):
+        z = period_at(z, p)
+    return z

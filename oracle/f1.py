@@ -140,14 +140,17 @@ class F1:
         return F
 
     # ---------------------------------------------------------------- time stepping
-    def step(self, Px, Py, v, n: int, forced: bool):
+    def step(self, Px, Py, v, n: int, forced: bool, ramp=None):
+        """Step n (t_n -> t_{n+1}); the source is sampled at t_{n+1/2} and multiplied by
+        ramp(t_{n+1/2}) when a ramp is given."""
         dt, c, gam = self.dt, self.c, self.gamma
         gx, gy = self.grad(v)
         Px = Px + 0.5 * dt * gx
         Py = Py + 0.5 * dt * gy
         rhs = self.div(Px, Py)
         if forced:
-            rhs = rhs + self.source((n + 0.5) * dt)
+            t = (n + 0.5) * dt
+            rhs = rhs + (1.0 if ramp is None else ramp(t)) * self.source(t)
         v = ((1.0 - gam) * v + dt * c * c * rhs) / (1.0 + gam)
         gx, gy = self.grad(v)
         Px = Px + 0.5 * dt * gx
@@ -172,12 +175,22 @@ class F1:
         return Px, Py, v
 
     def period(self, z: np.ndarray, forced: bool, t0_step: int = 0,
-               steps: Optional[int] = None) -> np.ndarray:
-        """Phi(z) (forced) or E z (homogeneous): N leapfrog steps from t = 0."""
+               steps: Optional[int] = None, ramp=None) -> np.ndarray:
+        """Phi(z) (forced) or E z (homogeneous): N leapfrog steps from t = t0_step dt, the
+        source optionally multiplied by ramp(t)."""
         Px, Py, v = self.unpack(z)
         for n in range(self.N if steps is None else steps):
-            Px, Py, v = self.step(Px, Py, v, t0_step + n, forced)
+            Px, Py, v = self.step(Px, Py, v, t0_step + n, forced, ramp)
         return self.pack(Px, Py, v)
+
+    def runup(self, periods: int, ramp: bool) -> np.ndarray:
+        """State at t = periods T of the forced scheme started from rest, with the source
+        switched on by Mur's transient over the whole interval if `ramp` (Sec. 4.2.3), or at
+        once (the do-nothing long-time solve of Sec. 4.2.2)."""
+        t_tr = periods * self.T
+        th = (lambda t: _cmcg.transient(t, t_tr)) if ramp else None
+        return _cmcg.runup(lambda z, p: self.period(z, True, t0_step=p * self.N, ramp=th),
+                           self.size, periods)
 
     def period_T(self, y: np.ndarray, steps: Optional[int] = None) -> np.ndarray:
         """E^T y: the transposed steps, last step first (all steps are equal here)."""
@@ -209,11 +222,19 @@ class F1:
                 + 0.5 * h2 * np.sum(v * v / (self.c * self.c)))
 
     # ---------------------------------------------------------------- CMCG and output
-    def solve(self, tol: float, max_iter: int = 10000, z0=None, record=None):
+    def solve(self, tol: float, max_iter: int = 10000, z0=None, record=None,
+              runup_periods: int = 0):
+        """CMCG from rest, or from the state of a ramped run-up of `runup_periods` periods
+        (Sec. 4.2.3) with the stopping test measured against the residual at rest."""
+        ref = None
+        if runup_periods > 0:
+            z0 = self.runup(runup_periods, True)
+            ref = _cmcg.gradient_delta(lambda x: self.period(x, True), self.period_T, self.ME,
+                                       self.riesz, self.size)
         z, hist, it = _cmcg.cmcg(lambda x: self.period(x, True),
                                  lambda x: self.period(x, False),
                                  self.period_T, self.ME, self.riesz,
-                                 self.size, tol, max_iter, z0=z0, record=record)
+                                 self.size, tol, max_iter, z0=z0, record=record, delta_ref=ref)
         return z, hist, it
 
     def filter(self, z: np.ndarray) -> np.ndarray:

@@ -143,13 +143,20 @@ class F2:
             r = r - F
         return self.dt ** 2 * r / self.M
 
-    def period(self, z: np.ndarray, forced: bool, U_acc: Optional[np.ndarray] = None):
-        """Phi(z) (forced) or E z (homogeneous).  If U_acc is given, u^n e^{i w t_n} for
-        n < N is accumulated into it (the filter sum)."""
+    def period(self, z: np.ndarray, forced: bool, U_acc: Optional[np.ndarray] = None,
+               t0: float = 0.0, ramp=None):
+        """Phi(z) (forced) or E z (homogeneous) over [t0, t0 + T], the load at t_n = t0 + n dt
+        optionally multiplied by ramp(t_n).  If U_acc is given, u^n e^{i w t_n} for n < N is
+        accumulated into it (the filter sum, t0 = 0)."""
         dt, beta, R = self.dt, self.beta, self.free
         u0 = R * z[: self.nn].reshape(self.shape)
         v0 = R * z[self.nn:].reshape(self.shape)
-        F = (lambda n: self.load(n * dt)) if forced else (lambda n: None)
+        if not forced:
+            F = lambda n: None
+        elif ramp is None:
+            F = lambda n: self.load(t0 + n * dt)
+        else:
+            F = lambda n: ramp(t0 + n * dt) * self.load(t0 + n * dt)
         um = u0
         u = R * (u0 + dt * (1.0 - beta) * v0 - 0.5 * self._accel(u0, F(0)))
         if U_acc is not None:
@@ -162,6 +169,14 @@ class F2:
                 vN = (up - um) / (2.0 * dt)
                 return np.concatenate([u.ravel(), vN.ravel()])
             um, u = u, up
+
+    def runup(self, periods: int, ramp: bool) -> np.ndarray:
+        """State (u, v) at t = periods T of the forced scheme started from rest, the load
+        switched on by Mur's transient if `ramp` (Sec. 4.2.3), else at once (Sec. 4.2.2)."""
+        t_tr = periods * self.T
+        th = (lambda t: _cmcg.transient(t, t_tr)) if ramp else None
+        return _cmcg.runup(lambda z, p: self.period(z, True, t0=p * self.T, ramp=th),
+                           self.size, periods)
 
     def period_T(self, y: np.ndarray) -> np.ndarray:
         """E^T y, with E = (end map) (step map)^{N-1} (start map) on the states
@@ -247,10 +262,18 @@ class F2:
         return 0.5 * float(np.sum(dl * self.M * dl)) + 0.5 * float(np.sum(u_next * self.S(u)))
 
     # ---------------------------------------------------------------- CMCG and output
-    def solve(self, tol: float, max_iter: int = 10000, z0=None, record=None):
+    def solve(self, tol: float, max_iter: int = 10000, z0=None, record=None,
+              runup_periods: int = 0):
+        """CMCG from rest, or from the state of a ramped run-up of `runup_periods` periods
+        (Sec. 4.2.3) with the stopping test measured against the residual at rest."""
+        ref = None
+        if runup_periods > 0:
+            z0 = self.runup(runup_periods, True)
+            ref = _cmcg.gradient_delta(lambda x: self.period(x, True), self.period_T, self.ME,
+                                       self.riesz, self.size)
         return _cmcg.cmcg(lambda x: self.period(x, True), lambda x: self.period(x, False),
                           self.period_T, self.ME, self.riesz, self.size, tol, max_iter,
-                          z0=z0, record=record)
+                          z0=z0, record=record, delta_ref=ref)
 
     def filter(self, z: np.ndarray) -> np.ndarray:
         """U = (2/N) sum_{n<N} u^n e^{i w t_n} over one forced period from z."""
