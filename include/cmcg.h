@@ -94,6 +94,13 @@ typedef struct {
                                   symmetric multigrid V-cycle B ~ S^{-1} (an SPD stand-in: CG
                                   converges to the same minimiser, the stopping norm is the B
                                   one); 0 = default: SOLVE for FP64, VCYCLE for FP32-mixed      */
+  int32_t runup_periods;       /* initial run-up (Sec. 4.2.3): before the CG iteration, integrate
+                                  the forced scheme from rest over this many periods with the
+                                  source switched on by Mur's transient theta_tr (t_tr = the
+                                  run-up's length) and start CG from the state reached; the
+                                  stopping test then compares with the residual at rest, so the
+                                  solve stops at the accuracy a start from rest stops at.
+                                  0 = start from rest.  Run in FP64.                           */
 } cmcg_options;
 
 enum { CMCG_RIESZ_DEFAULT = 0, CMCG_RIESZ_SOLVE = 1, CMCG_RIESZ_VCYCLE = 2 };
@@ -108,6 +115,8 @@ typedef struct {
   double grid_updates;         /* grid-point updates (cell- or node-steps) of the last solve   */
   int64_t riesz_iterations;    /* F2: total inner PCG iterations                               */
   int32_t fp64_refreshes;      /* FP32-mixed: number of FP64 true-gradient refreshes           */
+  int32_t runup_periods;       /* periods of initial run-up done by the last cmcg_begin         */
+  double seconds_runup;        /* device time of that run-up (part of seconds)                 */
 } cmcg_report;
 
 /* Create a solver for `problem`: validates it, sets T, N and dt, allocates the device state and
@@ -170,6 +179,18 @@ cmcg_status cmcg_finish(cmcg_handle *h, double *u_re, double *u_im, cmcg_report 
 /* Copy the current CG iterate z (which = 0), residual r (1) or direction d (2) into a packed
  * FP64 device vector. */
 cmcg_status cmcg_get_state(cmcg_handle *h, int32_t which, double *out);
+
+/* Long-time integration without controllability (Sec. 4.2.2, the "do-nothing" approach) and
+ * the run-up of Sec. 4.2.3: the forced scheme from rest over `periods` >= 1 periods, in FP64,
+ * the source multiplied by Mur's transient theta_tr (t_tr = periods T) if ramp != 0.  Writes
+ * the state at t = periods T into z_out (packed FP64 device vector of state_len; cmcg_filter
+ * extracts U from it).  Does not touch the CG state. */
+cmcg_status cmcg_runup(cmcg_handle *h, int32_t periods, int32_t ramp, double *z_out);
+
+/* Periodicity misfit J(z) = 1/2 (Phi(z) - z)^T M_E (Phi(z) - z) of a packed FP64 device state
+ * (eq. cost_functional_J / eq. mix_cost_functional_J, discrete), computed with one FP64 forced
+ * period.  The paper's relative misfit divides sqrt(J) by ||f|| + ||g_S|| (Sec. 4.2.1). */
+cmcg_status cmcg_misfit(cmcg_handle *h, const double *z, double *J);
 
 /* ---- continuous-batching server (first-order 2D solves) ----
  * Solves of different grid sizes and frequencies share the GPU: submitted requests wait in

@@ -45,7 +45,8 @@ class _Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("hip_stream", ctypes.c_void_p), ("steps_per_launch", ctypes.c_int32),
                 ("riesz_max_iter", ctypes.c_int32), ("riesz_tol", ctypes.c_double),
-                ("fp64_refresh", ctypes.c_double), ("riesz_mode", ctypes.c_int32)]
+                ("fp64_refresh", ctypes.c_double), ("riesz_mode", ctypes.c_int32),
+                ("runup_periods", ctypes.c_int32)]
 
 
 class _Report(ctypes.Structure):
@@ -54,7 +55,8 @@ class _Report(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("seconds_fwd", ctypes.c_double),
                 ("seconds_adj", ctypes.c_double), ("seconds_riesz", ctypes.c_double),
                 ("seconds_other", ctypes.c_double), ("grid_updates", ctypes.c_double),
-                ("riesz_iterations", ctypes.c_int64), ("fp64_refreshes", ctypes.c_int32)]
+                ("riesz_iterations", ctypes.c_int64), ("fp64_refreshes", ctypes.c_int32),
+                ("runup_periods", ctypes.c_int32), ("seconds_runup", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -86,6 +88,8 @@ _sig = {
                                     ctypes.POINTER(_Report)]),
     "cmcg_finish": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Report)]),
     "cmcg_get_state": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_void_p]),
+    "cmcg_runup": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "cmcg_misfit": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "cmcg_server_create": (ctypes.c_int, [ctypes.POINTER(_ServerOptions), ctypes.POINTER(_H)]),
     "cmcg_server_submit": (ctypes.c_int, [_H, ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
                                           ctypes.POINTER(ctypes.c_int64)]),
@@ -141,13 +145,13 @@ class Solver:
     def __init__(self, problem, precision: str = "fp64", tol: float = 1e-6, max_iter: int = 1000,
                  device: int = 0, steps_per_launch: int = 0, stream=None,
                  riesz_tol: float = 0.0, riesz_max_iter: int = 0, fp64_refresh: float = 0.0,
-                 riesz_mode="default"):
+                 riesz_mode="default", runup_periods: int = 0):
         import torch  # device memory and streams
         self._torch = torch
         self.problem = problem
         p, self._keep = marshal_problem(problem)
         o = make_options(precision, tol, max_iter, device, steps_per_launch, riesz_tol,
-                         riesz_max_iter, fp64_refresh, riesz_mode)
+                         riesz_max_iter, fp64_refresh, riesz_mode, runup_periods)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
@@ -229,6 +233,25 @@ class Solver:
         _check(_lib.cmcg_filter(self._h, ctypes.c_void_p(zin.data_ptr()), ure, uim), "cmcg_filter")
         return self._out_value(keep, False)
 
+    def runup(self, periods: int, ramp: bool = True):
+        """State (packed FP64 torch device vector) after `periods` periods of the forced scheme
+        from rest, the source switched on by Mur's transient if `ramp` (cmcg_runup)."""
+        torch = self._torch
+        out = torch.empty(self.info["state_len"], dtype=torch.float64, device="cuda")
+        _check(_lib.cmcg_runup(self._h, int(periods), 1 if ramp else 0,
+                               ctypes.c_void_p(out.data_ptr())), "cmcg_runup")
+        return out
+
+    def misfit(self, z) -> float:
+        """J(z) = 1/2 ||Phi(z) - z||_E^2 (cmcg_misfit); z a packed state (NumPy or device)."""
+        torch = self._torch
+        zin = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64)).cuda() \
+            if isinstance(z, np.ndarray) else z.contiguous()
+        J = ctypes.c_double(0.0)
+        _check(_lib.cmcg_misfit(self._h, ctypes.c_void_p(zin.data_ptr()), ctypes.byref(J)),
+               "cmcg_misfit")
+        return J.value
+
     def state(self, which: int = 0) -> np.ndarray:
         torch = self._torch
         out = torch.empty(self.info["state_len"], dtype=torch.float64, device="cuda")
@@ -302,7 +325,7 @@ _RIESZ = {"default": RIESZ_DEFAULT, "solve": RIESZ_SOLVE, "vcycle": RIESZ_VCYCLE
 
 def make_options(precision="fp64", tol=1e-6, max_iter=1000, device=0, steps_per_launch=0,
                  riesz_tol=0.0, riesz_max_iter=0, fp64_refresh=0.0,
-                 riesz_mode="default") -> _Options:
+                 riesz_mode="default", runup_periods=0) -> _Options:
     o = _Options()
     o.precision = FP64 if precision == "fp64" else FP32_MIXED
     o.tol = float(tol)
@@ -313,6 +336,7 @@ def make_options(precision="fp64", tol=1e-6, max_iter=1000, device=0, steps_per_
     o.riesz_max_iter = int(riesz_max_iter)
     o.fp64_refresh = float(fp64_refresh)
     o.riesz_mode = _RIESZ[riesz_mode] if isinstance(riesz_mode, str) else int(riesz_mode)
+    o.runup_periods = int(runup_periods)
     return o
 
 
@@ -357,9 +381,9 @@ class Server:
         self.close()
 
     def submit(self, problem, precision: str = "fp32", tol: float = 1e-6,
-               max_iter: int = 1000) -> int:
+               max_iter: int = 1000, runup_periods: int = 0) -> int:
         p, keep = marshal_problem(problem)
-        o = make_options(precision, tol, max_iter)
+        o = make_options(precision, tol, max_iter, runup_periods=runup_periods)
         rid = ctypes.c_int64(0)
         _check(_lib.cmcg_server_submit(self._h, ctypes.byref(p), ctypes.byref(o),
                                        ctypes.byref(rid)), "cmcg_server_submit")

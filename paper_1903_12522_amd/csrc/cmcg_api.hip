@@ -42,6 +42,8 @@ cmcg_status validate_problem(const cmcg_problem *P, const cmcg_options *O) {
   if (O->riesz_mode != CMCG_RIESZ_DEFAULT && O->riesz_mode != CMCG_RIESZ_SOLVE &&
       O->riesz_mode != CMCG_RIESZ_VCYCLE)
     return set_error("riesz_mode must be CMCG_RIESZ_DEFAULT, _SOLVE or _VCYCLE"), CMCG_EINVAL;
+  if (O->runup_periods < 0 || O->runup_periods > 1000000)
+    return set_error("runup_periods must be in [0, 1e6]"), CMCG_EINVAL;
   if (O->steps_per_launch < 0 || O->steps_per_launch > kMaxBlockSteps)
     return set_error("steps_per_launch must be in 0..8"), CMCG_EINVAL;
   if (!((P->dim == 2 && P->formulation == 1) || (P->dim == 3 && P->formulation == 2)))
@@ -73,6 +75,7 @@ cmcg_status make_config(const cmcg_problem *P, const cmcg_options *O, hipStream_
   cfg->refresh = O->fp64_refresh == 0.0 ? 0.1 : O->fp64_refresh;
   cfg->riesz_tol = O->riesz_tol;
   cfg->riesz_max_iter = O->riesz_max_iter;
+  cfg->runup = O->runup_periods;
   cfg->riesz_mode = O->riesz_mode != CMCG_RIESZ_DEFAULT
                         ? O->riesz_mode
                         : (O->precision == CMCG_FP64 ? CMCG_RIESZ_SOLVE : CMCG_RIESZ_VCYCLE);
@@ -220,6 +223,19 @@ cmcg_status cmcg_get_state(cmcg_handle *H, int32_t which, double *out) {
   if (!H || !out || which < 0 || which > 2) return set_error("bad argument"), CMCG_EINVAL;
   CMCG_HIP(hipSetDevice(H->device));
   return H->solver->get_state(which, out);
+}
+
+cmcg_status cmcg_runup(cmcg_handle *H, int32_t periods, int32_t ramp, double *z_out) {
+  if (!H || !z_out || periods < 1 || periods > 1000000)
+    return set_error("cmcg_runup: handle, z_out and periods in [1, 1e6] required"), CMCG_EINVAL;
+  CMCG_HIP(hipSetDevice(H->device));
+  return H->solver->runup(periods, ramp, z_out);
+}
+
+cmcg_status cmcg_misfit(cmcg_handle *H, const double *z, double *J) {
+  if (!H || !z || !J) return set_error("cmcg_misfit: null argument"), CMCG_EINVAL;
+  CMCG_HIP(hipSetDevice(H->device));
+  return H->solver->misfit(z, J);
 }
 
 }  // extern "C"

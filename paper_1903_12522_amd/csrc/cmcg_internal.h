@@ -48,6 +48,7 @@ enum Scalar : int {
   kBreak = 6,     // 1 if breakdown
   kTmp = 7,
   kRz = 8,        // Riesz PCG scalars from here on
+  kMisfit = 20,   // 2 J(z) of cmcg_misfit
   kNumScalars = 24
 };
 

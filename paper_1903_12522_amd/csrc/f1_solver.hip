@@ -110,9 +110,12 @@ class F1Solver final : public Solver {
   double *Z = nullptr, *R = nullptr, *Ure = nullptr, *Uim = nullptr;
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
   bool started = false;
-  int iter = 0, refreshes = 0, last_refresh = 0;
+  int iter = 0, refreshes = 0, last_refresh = 0, runup_done = 0;
   double rel = 1.0, delta_at_refresh = 0.0;
-  double t_fwd = 0, t_adj = 0, t_other = 0, t_total = 0, updates = 0;
+  double t_fwd = 0, t_adj = 0, t_other = 0, t_total = 0, t_runup = 0, updates = 0;
+  // source ramp of forced periods: absolute start time of the period and switch-on length
+  // (t_tr = 0: no ramp)
+  double t_offset = 0.0, t_tr = 0.0;
 
   ~F1Solver() override {
     if (s) (void)hipStreamSynchronize(s);
@@ -134,7 +137,7 @@ class F1Solver final : public Solver {
     fs = (size_t)ny * g.pitch;
     vecN = 3 * fs;
     mixed = cfg.prec == CMCG_FP32_MIXED;
-    CMCG_TRY(ev.init(8));
+    CMCG_TRY(ev.init(10));
     CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
     std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
     const bool has_im = P->f_im || P->gS_im;
@@ -208,8 +211,9 @@ class F1Solver final : public Solver {
     L.accumulate = filter ? 1 : 0;
     for (int k = 0; k < ns; ++k) {
       const double t = (n0 + k + 0.5) * cfg.dt;      // source at t_{n+1/2}
-      L.cs[k] = std::cos(cfg.omega * t);
-      L.sn[k] = std::sin(cfg.omega * t);
+      const double amp = transient(t_offset + t, t_tr);
+      L.cs[k] = amp * std::cos(cfg.omega * t);
+      L.sn[k] = amp * std::sin(cfg.omega * t);
     }
     L.fcos = std::cos(cfg.omega * n0 * cfg.dt);       // filter weight at t_n
     L.fsin = std::sin(cfg.omega * n0 * cfg.dt);
@@ -280,20 +284,55 @@ class F1Solver final : public Solver {
   }
 
   // ------------------------------------------------------------------ CG driver
+  // The forced scheme from rest over `periods` periods (FP64), the source ramped by Mur's
+  // transient over the whole interval if `ramp`; the final state goes to `state` (FP64 device
+  // layout).  Uses hi.W and hi.Q as the two state buffers.
+  cmcg_status run_forced_periods(int periods, bool ramp, double *state) {
+    double *a = tp<double>(hi.Q), *b = tp<double>(hi.W);
+    CMCG_HIP(hipMemsetAsync(a, 0, vecN * sizeof(double), s));
+    t_tr = ramp ? periods * cfg.T : 0.0;
+    for (int p = 0; p < periods; ++p) {
+      t_offset = p * cfg.T;
+      const cmcg_status st = period(hi, false, true, a, b, nullptr, cfg.N, false);
+      if (st != CMCG_OK) {
+        t_offset = t_tr = 0.0;
+        return st;
+      }
+      std::swap(a, b);
+    }
+    t_offset = t_tr = 0.0;
+    CMCG_HIP(hipMemcpyAsync(state, a, vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return CMCG_OK;
+  }
+
   cmcg_status begin() override {
-    t_fwd = t_adj = t_other = t_total = 0.0;
+    t_fwd = t_adj = t_other = t_total = t_runup = 0.0;
     updates = 0;
-    iter = refreshes = last_refresh = 0;
+    iter = refreshes = last_refresh = runup_done = 0;
     CMCG_HIP(hipEventRecord(ev[0], s));
     // Steps 1-4: z = 0, gradient, r = d = gradient (the Riesz map M_E^{-1} is built into E*)
     CMCG_HIP(hipMemsetAsync(Z, 0, vecN * sizeof(double), s));
     CMCG_TRY(true_gradient(kFinStart));
+    if (cfg.runup > 0) {
+      // start from the run-up state; delta0 stays the residual at rest (stopping reference)
+      CMCG_HIP(hipEventRecord(ev[8], s));
+      CMCG_TRY(run_forced_periods(cfg.runup, true, Z));
+      CMCG_HIP(hipEventRecord(ev[9], s));
+      CMCG_HIP(hipMemcpyAsync(scalars + kTmp, scalars + kDelta, sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+      CMCG_TRY(true_gradient(kFinRefresh));
+      runup_done = cfg.runup;
+    }
     if (mixed) CMCG_HIP(convert<float, double>(tp<float>(D), R, vecN, s));
     else CMCG_HIP(hipMemcpyAsync(D, R, vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
     CMCG_HIP(hipEventRecord(ev[1], s));
     CMCG_TRY(read_scalars());
     t_other += PhaseEvents::seconds(ev[0], ev[1]);
-    rel = 1.0;
+    if (runup_done) {
+      t_runup = PhaseEvents::seconds(ev[8], ev[9]);
+      t_other -= t_runup;
+    }
+    rel = h_scalars[kRel];
     delta_at_refresh = h_scalars[kDelta];
     started = true;
     if (h_scalars[kBreak] != 0.0) return set_error("non-finite initial gradient"), CMCG_EBREAKDOWN;
@@ -439,6 +478,25 @@ class F1Solver final : public Solver {
     return CMCG_OK;
   }
 
+  cmcg_status runup(int periods, int ramp, double *z_out) override {
+    CMCG_TRY(run_forced_periods(periods, ramp != 0, tp<double>(hi.W)));
+    CMCG_HIP(f1_pack<double>(g, tp<double>(hi.W), z_out, fs, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status misfit(const double *z, double *J) override {
+    // w = Phi(z) - z with one FP64 forced period; J = <w, w>_E / 2
+    double *a = tp<double>(hi.Q), *w = tp<double>(hi.W);
+    CMCG_HIP(f1_unpack<double>(g, z, a, fs, s));
+    CMCG_TRY(period(hi, false, true, a, w, a, cfg.N, false));
+    CMCG_HIP(f1_dot<double, double>(g, w, w, hi.cc, 1, fs, partials, s));
+    CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinStore, kMisfit, s));
+    CMCG_TRY(read_scalars());
+    *J = 0.5 * h_scalars[kMisfit];
+    return CMCG_OK;
+  }
+
   void report(cmcg_report *r) const override {
     r->iterations = iter;
     r->steps_per_period = cfg.N;
@@ -452,6 +510,8 @@ class F1Solver final : public Solver {
     r->grid_updates = updates;
     r->riesz_iterations = 0;
     r->fp64_refreshes = refreshes;
+    r->runup_periods = runup_done;
+    r->seconds_runup = t_runup;
   }
 
   void info(cmcg_info *i) const override {
@@ -564,6 +624,9 @@ class F1Server final : public Server {
     CMCG_TRY(validate_problem(P, O));
     if (P->formulation != 1 || P->dim != 2)
       return set_error("the server batches first-order 2D solves"), CMCG_EUNSUPPORTED;
+    if (O->runup_periods > 0)
+      return set_error("the server starts every solve from rest (runup_periods must be 0)"),
+             CMCG_EUNSUPPORTED;
     auto *R = new ServeRequest();
     R->id = next_id++;
     R->P = *P;

@@ -81,7 +81,11 @@ class F2Solver final : public Solver {
   double rel = 1.0, delta_at_refresh = 0.0;
   double riesz_tol = 1e-10;
   int riesz_max = 500;
-  double t_fwd = 0, t_adj = 0, t_riesz = 0, t_other = 0, t_total = 0, updates = 0;
+  double t_fwd = 0, t_adj = 0, t_riesz = 0, t_other = 0, t_total = 0, t_runup = 0, updates = 0;
+  int runup_done = 0;
+  // source ramp of forced periods: absolute start time of the period and switch-on length
+  // (t_tr = 0: no ramp)
+  double t_offset = 0.0, t_tr = 0.0;
 
   ~F2Solver() override {
     if (s) (void)hipStreamSynchronize(s);
@@ -119,7 +123,7 @@ class F2Solver final : public Solver {
     mixed = cfg.prec == CMCG_FP32_MIXED;
     riesz_tol = cfg.riesz_tol > 0 ? cfg.riesz_tol : 1e-10;
     riesz_max = cfg.riesz_max_iter > 0 ? cfg.riesz_max_iter : 500;
-    CMCG_TRY(ev.init(10));
+    CMCG_TRY(ev.init(12));
     CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
     std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
     const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
@@ -211,7 +215,7 @@ class F2Solver final : public Solver {
     p.st = zin;
     p.aux = zin + g.fs;
     p.out = buf[0];
-    p.fcos = 1.0;
+    p.fcos = transient(t_offset, t_tr);
     p.fsin = 0.0;
     p.wcos = 1.0;
     p.wsin = 0.0;
@@ -220,10 +224,11 @@ class F2Solver final : public Solver {
     int cur = 0;
     for (int n = 1; n < N; ++n) {
       const double t = n * cfg.dt;
-      p.fcos = std::cos(cfg.omega * t);
-      p.fsin = std::sin(cfg.omega * t);
-      p.wcos = p.fcos;
-      p.wsin = p.fsin;
+      const double amp = transient(t_offset + t, t_tr);
+      p.wcos = std::cos(cfg.omega * t);
+      p.wsin = std::sin(cfg.omega * t);
+      p.fcos = amp * p.wcos;
+      p.fsin = amp * p.wsin;
       const int nxt = (cur + 1) % 3;
       p.st = buf[cur];
       p.aux = prev;
@@ -234,8 +239,9 @@ class F2Solver final : public Solver {
     }
     // end map: (u^N, v^N) with v^N = (u^{N+1} - u^{N-1}) / (2 dt)
     p.ure = p.uim = nullptr;
-    p.fcos = std::cos(cfg.omega * N * cfg.dt);
-    p.fsin = std::sin(cfg.omega * N * cfg.dt);
+    const double ampN = transient(t_offset + N * cfg.dt, t_tr);
+    p.fcos = ampN * std::cos(cfg.omega * N * cfg.dt);
+    p.fsin = ampN * std::sin(cfg.omega * N * cfg.dt);
     p.st = buf[cur];
     p.aux = prev;
     p.out = out;
@@ -361,19 +367,54 @@ class F2Solver final : public Solver {
   }
 
   // ------------------------------------------------------------------ CG driver
+  // The forced scheme from rest over `periods` periods (FP64), the load ramped by Mur's
+  // transient over the whole interval if `ramp`; the final state (u, v) goes to `state` (two
+  // FP64 fields).  Uses hi.Y and hi.W as the two state buffers.
+  cmcg_status run_forced_periods(int periods, bool ramp, double *state) {
+    double *a = tp<double>(hi.Y), *b = tp<double>(hi.W);
+    CMCG_HIP(hipMemsetAsync(a, 0, 2 * g.fs * sizeof(double), s));
+    t_tr = ramp ? periods * cfg.T : 0.0;
+    for (int p = 0; p < periods; ++p) {
+      t_offset = p * cfg.T;
+      const cmcg_status st = fwd(hi, true, a, b, nullptr, false);
+      if (st != CMCG_OK) {
+        t_offset = t_tr = 0.0;
+        return st;
+      }
+      std::swap(a, b);
+    }
+    t_offset = t_tr = 0.0;
+    CMCG_HIP(hipMemcpyAsync(state, a, 2 * g.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return CMCG_OK;
+  }
+
   cmcg_status begin() override {
-    t_fwd = t_adj = t_riesz = t_other = t_total = 0.0;
+    t_fwd = t_adj = t_riesz = t_other = t_total = t_runup = 0.0;
     updates = 0;
-    iter = refreshes = 0;
+    iter = refreshes = runup_done = 0;
     riesz_iters = 0;
     CMCG_HIP(hipEventRecord(ev[0], s));
     CMCG_HIP(hipMemsetAsync(Z, 0, 2 * g.fs * sizeof(double), s));
     CMCG_TRY(true_gradient(kFinStart));
+    if (cfg.runup > 0) {
+      // start from the run-up state; delta0 stays the residual at rest (stopping reference)
+      CMCG_HIP(hipEventRecord(ev[10], s));
+      CMCG_TRY(run_forced_periods(cfg.runup, true, Z));
+      CMCG_HIP(hipEventRecord(ev[11], s));
+      CMCG_HIP(hipMemcpyAsync(scalars + kTmp, scalars + kDelta, sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+      CMCG_TRY(true_gradient(kFinRefresh));
+      runup_done = cfg.runup;
+    }
     CMCG_TRY(direction(1));
     CMCG_HIP(hipEventRecord(ev[1], s));
     CMCG_TRY(read_scalars());
     t_other += PhaseEvents::seconds(ev[0], ev[1]);
-    rel = 1.0;
+    if (runup_done) {
+      t_runup = PhaseEvents::seconds(ev[10], ev[11]);
+      t_other -= t_runup;
+    }
+    rel = h_scalars[kRel];
     delta_at_refresh = h_scalars[kDelta];
     started = true;
     if (h_scalars[kBreak] != 0.0) return set_error("non-finite initial gradient"), CMCG_EBREAKDOWN;
@@ -531,6 +572,26 @@ class F2Solver final : public Solver {
     return CMCG_OK;
   }
 
+  cmcg_status runup(int periods, int ramp, double *z_out) override {
+    CMCG_TRY(run_forced_periods(periods, ramp != 0, tp<double>(hi.W)));
+    CMCG_HIP(f2_pack<double>(g, tp<double>(hi.W), z_out, 2, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status misfit(const double *z, double *J) override {
+    // w = Phi(z) - z with one FP64 forced period, y = M_E w, J = w . y / 2
+    double *a = tp<double>(hi.Y), *w = tp<double>(hi.W);
+    CMCG_HIP(f2_unpack<double>(g, z, a, 2, s));
+    CMCG_TRY(fwd(hi, true, a, w, a, false));
+    CMCG_TRY(metric(hi, w, a));
+    CMCG_HIP(dot_plain<double, double>(w, a, 2 * g.fs, partials, s));
+    CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinStore, kMisfit, s));
+    CMCG_TRY(read_scalars());
+    *J = 0.5 * h_scalars[kMisfit];
+    return CMCG_OK;
+  }
+
   void report(cmcg_report *r) const override {
     r->iterations = iter;
     r->steps_per_period = cfg.N;
@@ -544,6 +605,8 @@ class F2Solver final : public Solver {
     r->grid_updates = updates;
     r->riesz_iterations = riesz_iters;
     r->fp64_refreshes = refreshes;
+    r->runup_periods = runup_done;
+    r->seconds_runup = t_runup;
   }
 
   void info(cmcg_info *i) const override {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,7 @@ struct SolverConfig {
   double riesz_tol = 0.0;
   int riesz_max_iter = 0;
   int riesz_mode = CMCG_RIESZ_SOLVE;   // resolved: CMCG_RIESZ_SOLVE or CMCG_RIESZ_VCYCLE
+  int runup = 0;           // initial run-up periods before the CG iteration
   hipStream_t stream = nullptr;
   double h = 0, omega = 0, T = 0, dt = 0;
   int N = 0;
@@ -95,6 +97,8 @@ class Solver {
   virtual cmcg_status apply(int op, int steps, const double *in, double *out) = 0;
   virtual cmcg_status filter(const double *z, double *u_re, double *u_im) = 0;
   virtual cmcg_status get_state(int which, double *out) = 0;
+  virtual cmcg_status runup(int periods, int ramp, double *z_out) = 0;
+  virtual cmcg_status misfit(const double *z, double *J) = 0;
   virtual void report(cmcg_report *r) const = 0;
   virtual void info(cmcg_info *i) const = 0;
   virtual size_t device_bytes() const = 0;
@@ -120,6 +124,14 @@ class Server {
   virtual void stats(int64_t *used_bytes, int *n_active, int *n_queued) const = 0;
 };
 cmcg_status make_f1_server(const cmcg_server_options *o, hipStream_t s, Server **out);
+
+// Mur's switch-on of the time-harmonic source (Sec. 4.2.3, eq. transientfunction):
+// (2 - sin s) sin s with s = (t / t_tr) pi / 2 for t < t_tr, 1 afterwards.
+inline double transient(double t, double t_tr) {
+  if (!(t_tr > 0.0) || t >= t_tr) return 1.0;
+  const double s = 0.5 * 3.14159265358979323846 * t / t_tr;
+  return (2.0 - std::sin(s)) * std::sin(s);
+}
 
 inline int grid_for(size_t n, int threads = 256) {
   size_t b = (n + threads - 1) / threads;
