@@ -130,6 +130,52 @@ def serving_run(count: int):
     return summ
 
 
+def runup_study(prob, runups=(0, 4, 16, 32), longtime=(16, 64, 256)):
+    """Initial run-up and do-nothing long-time solve on a first-order workload.
+    * FP32-mixed CMCG to 1e-6 after a ramped run-up of L periods: time, CG iterations and the
+      total number of periods integrated (2 per CG iteration, 2 per FP64 refresh, L, and the
+      reference gradient at rest when L > 0).
+    * The do-nothing solve (source switched on at once) after L periods: relative periodicity
+      misfit sqrt(J(z_L) / J(0)) and the error of its filtered output against the CMCG solution."""
+    import numpy as np
+    import torch
+    from paper_1903_12522_amd import cmcg
+    out = {"cmcg": [], "do_nothing": []}
+    U_ref = None
+    for L in runups:
+        with cmcg.Solver(prob, "fp32", tol=1e-6, max_iter=20000, runup_periods=L) as s:
+            s.solve(device_output=True)                 # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U, rep = s.solve(device_output=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        periods = 2 * rep["iterations"] + 2 * rep["fp64_refreshes"] + L + (2 if L > 0 else 0) + 2
+        out["cmcg"].append({"runup_periods": L, "seconds": round(wall, 3),
+                            "iterations": rep["iterations"], "converged": rep["converged"],
+                            "seconds_runup": round(rep["seconds_runup"], 3),
+                            "total_periods": periods})
+        log(f"run-up {L}: {wall:.2f} s, {rep['iterations']} iterations, {periods} periods")
+        if U_ref is None:
+            U_ref = torch.complex(U[0], U[1])
+    with cmcg.Solver(prob, "fp64") as s:
+        J0 = s.misfit(np.zeros(s.info["state_len"]))
+        for L in longtime:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            z = s.runup(L, ramp=False)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            J = s.misfit(z)
+            Uz = s.filter(z)
+            err = float(np.linalg.norm(Uz - U_ref.cpu().numpy()) / torch.linalg.vector_norm(U_ref).item())
+            out["do_nothing"].append({"periods": L, "seconds": round(wall, 3),
+                                      "relative_misfit": float(np.sqrt(J / J0)),
+                                      "filtered_rel_error_vs_cmcg": err})
+            log(f"do-nothing {L} periods: misfit {np.sqrt(J / J0):.3e}, error {err:.3e}")
+    return out
+
+
 def cpu_baseline(prob, steps: int = 20):
     """The oracle as it stands, on the full grid: `steps` forward leapfrog steps plus `steps`
     transposed steps (the two halves of a CG iteration), timed on one host core."""
@@ -165,6 +211,8 @@ def main():
     ap.add_argument("--nodal-max-iter", type=int, default=3000)
     ap.add_argument("--nodal-precisions", default="fp32", help="comma list of fp32,fp64")
     ap.add_argument("--serving", type=int, default=0, help="replay this many serving requests")
+    ap.add_argument("--runup-study", action="store_true",
+                    help="run-up and do-nothing long-time solve on the 4096^2 workload")
     args = ap.parse_args()
 
     if args.calibrate_copy:
@@ -269,6 +317,8 @@ def main():
                                  for p in args.nodal_precisions.split(",") if p}
     if args.serving > 0:
         out["serving"] = serving_run(args.serving)
+    if args.runup_study:
+        out["runup_study"] = runup_study(prob)
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu:
