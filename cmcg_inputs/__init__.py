@@ -32,8 +32,9 @@ NEUMANN = 1
 @dataclasses.dataclass
 class Problem:
     """Helmholtz problem  -lap u - k^2 u = f,  du/dn - i k u = gS on absorbing faces,
-    du/dn = 0 on Neumann faces, u = 0 on sound-soft nodes (eq. HE), posed on the box
-    [0, n_x h] x [0, n_y h] (x [0, n_z h]) with h = 1 / n_x."""
+    du/dn = gN on Neumann faces, u = gD on sound-soft nodes (eq. HE), posed on the box
+    [0, n_x h] x [0, n_y h] (x [0, n_z h]) with h = 1 / n_x.  The per-face data `gS` holds gS on
+    absorbing faces and gN on Neumann faces."""
 
     dim: int
     formulation: int                      # 1 = first-order staggered, 2 = second-order nodal
@@ -42,8 +43,9 @@ class Problem:
     c: Optional[np.ndarray] = None        # wave speed on the F1 cells / F2 nodes; None -> c_const
     c_const: float = 1.0
     f: Optional[np.ndarray] = None        # complex source amplitude, same layout as c
-    gS: Optional[List[np.ndarray]] = None  # complex absorbing-boundary data per face
-    sound_soft: Optional[np.ndarray] = None  # F2 only: uint8 node mask, 1 = homogeneous Dirichlet
+    gS: Optional[List[np.ndarray]] = None  # complex boundary data per face (gS or gN)
+    sound_soft: Optional[np.ndarray] = None  # F2 only: uint8 node mask, 1 = Dirichlet node
+    gD: Optional[np.ndarray] = None       # F2 only: complex Dirichlet data (layout of c), or 0
     face_bc: Sequence[int] = (ABSORBING,) * 6
     courant: float = 0.5
     name: str = ""
@@ -268,6 +270,51 @@ def channel_plane_wave_f2(n: Sequence[int], k: float, dirichlet_at_zero: bool = 
     return Problem(dim=dim, formulation=2, n=tuple(n), omega=k, c=None, c_const=1.0, f=None,
                    gS=gS, sound_soft=mask, face_bc=tuple(bc), courant=0.5,
                    name="f2_channel" + ("_dirichlet" if dirichlet_at_zero else ""))
+
+
+def channel_dirichlet_f2(n: Sequence[int], k: float, u0: complex) -> Problem:
+    """Channel with Dirichlet data: the nodes of the plane x = 0 are Dirichlet nodes with
+    u = u0, the face x = L is absorbing with no data, the lateral faces are Neumann; c = 1,
+    omega = k, f = 0.  The exact Helmholtz solution is u0 exp(i k x)."""
+    dim = len(n)
+    shp = tuple(m + 1 for m in reversed(n))
+    face_shapes = []
+    for axis in range(dim):
+        others = [a for a in range(dim) if a != axis]
+        face_shapes.append(tuple(n[a] + 1 for a in reversed(others)))
+    gS = [np.zeros(face_shapes[a // 2], dtype=np.complex128) for a in range(2 * dim)]
+    bc = [NEUMANN] * (2 * dim)
+    bc[1] = ABSORBING
+    mask = np.zeros(shp, dtype=np.uint8)
+    mask[..., 0] = 1
+    gD = np.zeros(shp, dtype=np.complex128)
+    gD[..., 0] = u0
+    return Problem(dim=dim, formulation=2, n=tuple(n), omega=k, c=None, c_const=1.0, f=None,
+                   gS=gS, sound_soft=mask, gD=gD, face_bc=tuple(bc), courant=0.5,
+                   name="f2_channel_dirichlet_data")
+
+
+def channel_neumann_data(formulation: int, n: Sequence[int], k: float) -> Problem:
+    """Channel with Neumann data: u = exp(i k x) has outward derivative -u'(0) = -i k on the
+    face x = 0, which is a Neumann face carrying gN = -i k; the face x = L is absorbing with no
+    data, the lateral faces are Neumann with no data; c = 1, omega = k, f = 0."""
+    dim = len(n)
+    if formulation == 1:
+        nx, ny = n
+        g = [np.full(ny, -1j * k), np.zeros(ny, complex), np.zeros(nx, complex),
+             np.zeros(nx, complex)]
+    else:
+        g = []
+        for axis in range(dim):
+            others = [a for a in range(dim) if a != axis]
+            fshape = tuple(n[a] + 1 for a in reversed(others))
+            g += [np.zeros(fshape, dtype=np.complex128), np.zeros(fshape, dtype=np.complex128)]
+        g[0][...] = -1j * k
+    bc = [NEUMANN] * (2 * dim)
+    bc[1] = ABSORBING
+    return Problem(dim=dim, formulation=formulation, n=tuple(n), omega=k, c=None, c_const=1.0,
+                   f=None, gS=g, face_bc=tuple(bc), courant=0.5,
+                   name=f"f{formulation}_channel_neumann_data")
 
 
 def channel_bounded_neumann_f2(n: Sequence[int], k: float) -> Problem:

@@ -125,18 +125,16 @@ class F1:
         return (v[:, :-1] - v[:, 1:]) / h, (v[:-1, :] - v[1:, :]) / h
 
     def source(self, t: float) -> np.ndarray:
-        """Re(f e^{-iwt}) + (1/h) sum over absorbing boundary faces of Re(gS e^{-iwt})."""
+        """Re(f e^{-iwt}) + (1/h) sum over the boundary faces of Re(g e^{-iwt}): the prescribed
+        part of the outward flux p.n, gS on absorbing faces (p.n = gS - v/c) and gN on Neumann
+        faces (p.n = gN)."""
         e = np.exp(-1j * self.omega * t)
         F = (self.f * e).real
         h = self.h
-        if self.bc[0] == ABSORBING:
-            F[:, 0] += (self.g[0] * e).real / h
-        if self.bc[1] == ABSORBING:
-            F[:, -1] += (self.g[1] * e).real / h
-        if self.bc[2] == ABSORBING:
-            F[0, :] += (self.g[2] * e).real / h
-        if self.bc[3] == ABSORBING:
-            F[-1, :] += (self.g[3] * e).real / h
+        F[:, 0] += (self.g[0] * e).real / h
+        F[:, -1] += (self.g[1] * e).real / h
+        F[0, :] += (self.g[2] * e).real / h
+        F[-1, :] += (self.g[3] * e).real / h
         return F
 
     # ---------------------------------------------------------------- time stepping
@@ -258,7 +256,7 @@ class F1:
         v^n = Re(V e^{-iwt_n}), p^{n+1/2} = Re(Q e^{-iwt_{n+1/2}}), theta = w dt / 2:
             -2 i sin(theta) Q - dt G V = 0
             (-2 i sin(theta) + 2 gamma cos(theta)) V - dt c^2 D Q = dt c^2 Fhat,
-        Fhat = f + (1/h) sum_abs gS."""
+        Fhat = f + (1/h) sum over the boundary faces of g (gS or gN)."""
         nx, ny, h, dt = self.nx, self.ny, self.h, self.dt
         th = 0.5 * self.omega * dt
 
@@ -276,14 +274,10 @@ class F1:
                      [-dt * sp.diags(c2) @ D,
                       sp.diags(-2j * math.sin(th) + 2.0 * gam * math.cos(th))]]).tocsc()
         Fhat = self.f.copy()
-        if self.bc[0] == ABSORBING:
-            Fhat[:, 0] += self.g[0] / h
-        if self.bc[1] == ABSORBING:
-            Fhat[:, -1] += self.g[1] / h
-        if self.bc[2] == ABSORBING:
-            Fhat[0, :] += self.g[2] / h
-        if self.bc[3] == ABSORBING:
-            Fhat[-1, :] += self.g[3] / h
+        Fhat[:, 0] += self.g[0] / h
+        Fhat[:, -1] += self.g[1] / h
+        Fhat[0, :] += self.g[2] / h
+        Fhat[-1, :] += self.g[3] / h
         rhs = np.concatenate([np.zeros(nf, complex), dt * c2 * Fhat.ravel()])
         return A, rhs, nf
 

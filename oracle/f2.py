@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY (see the oracle package docstring).
 
 Continuous system (eq. WE):  (1/c^2) y_tt - lap y = Re(f e^{-iwt}),
-dy/dn + (1/c) y_t = Re(gS e^{-iwt}) on absorbing faces, dy/dn = 0 on Neumann faces,
-y = 0 on the sound-soft set D (homogeneous Dirichlet, eq. WE_DBC with g_D = 0).
+dy/dn + (1/c) y_t = Re(gS e^{-iwt}) on absorbing faces, dy/dn = Re(gN e^{-iwt}) on Neumann
+faces, y = Re(gD e^{-iwt}) on the sound-soft (Dirichlet) set D (eq. WE_DBC).
 
 Space (reading of the paper's mass-lumped P1 FE on a structured grid): nodes x_I = I h,
 I in {0..n}^d.  Lumped mass w_I = h^d prod_k (1/2 if I_k is 0 or n_k), M = diag(w / c^2).
@@ -12,7 +12,9 @@ Stiffness (S u)_I = sum over the axis edges e = (I, J) of a_e (u_I - u_J), with
 a_e = h^{d-2} prod over the other axes k' of (1/2 if the edge lies in a boundary plane
 x_k' = 0 or 1).  Absorbing faces add the boundary mass B_I = (1/c_I) sum over absorbing
 faces containing I of the lumped face weight h^{d-1} prod (1/2 on the face's own edges).
-Load F^n = w Re(f e^{-iwt_n}) + sum_abs (face weight) Re(gS e^{-iwt_n}).
+Load F^n = w Re(f e^{-iwt_n}) + sum over faces (face weight) Re(g e^{-iwt_n}), g = gS or gN.
+Dirichlet nodes are not unknowns: forced periods hold them at Re(gD e^{-iwt_n}) (their state
+entries stay zero), homogeneous ones at zero.
 
 Time (leapfrog, damping centred), t_n = n dt:
     (M + dt/2 B) u^{n+1} = 2 M u^n - (M - dt/2 B) u^{n-1} - dt^2 (S u^n - F^n),  u = 0 on D
@@ -100,6 +102,8 @@ class F2:
         self.f = (np.zeros(self.shape, complex) if prob.f is None
                   else np.asarray(prob.f, dtype=complex).reshape(self.shape))
         self.g = None if prob.gS is None else [np.asarray(a, dtype=complex) for a in prob.gS]
+        self.gD = (None if prob.gD is None or prob.sound_soft is None
+                   else (1.0 - self.free) * np.asarray(prob.gD, dtype=complex).reshape(self.shape))
         self.nn = int(np.prod(self.shape))
         self.size = 2 * self.nn
         self._S_lu = None
@@ -131,8 +135,7 @@ class F2:
         F = self.w * (self.f * e).real
         if self.g is not None:
             for idx, (sel, fw) in enumerate(self.face_w):
-                if self.bc[idx] == ABSORBING:
-                    F[sel] += fw * (self.g[idx].reshape(fw.shape) * e).real
+                F[sel] += fw * (self.g[idx].reshape(fw.shape) * e).real
         return F
 
     # ---------------------------------------------------------------- time stepping
@@ -149,25 +152,30 @@ class F2:
         optionally multiplied by ramp(t_n).  If U_acc is given, u^n e^{i w t_n} for n < N is
         accumulated into it (the filter sum, t0 = 0)."""
         dt, beta, R = self.dt, self.beta, self.free
-        u0 = R * z[: self.nn].reshape(self.shape)
-        v0 = R * z[self.nn:].reshape(self.shape)
+        amp = (lambda t: 1.0) if ramp is None else ramp
         if not forced:
             F = lambda n: None
-        elif ramp is None:
-            F = lambda n: self.load(t0 + n * dt)
         else:
-            F = lambda n: ramp(t0 + n * dt) * self.load(t0 + n * dt)
+            F = lambda n: amp(t0 + n * dt) * self.load(t0 + n * dt)
+        # values on the Dirichlet nodes at t_n (zero unless forced with data)
+        if forced and self.gD is not None:
+            dirichlet = lambda n: amp(t0 + n * dt) * (self.gD * np.exp(-1j * self.omega * (t0 + n * dt))).real
+        else:
+            dirichlet = lambda n: 0.0
+        u0 = R * z[: self.nn].reshape(self.shape) + dirichlet(0)
+        v0 = R * z[self.nn:].reshape(self.shape)
         um = u0
-        u = R * (u0 + dt * (1.0 - beta) * v0 - 0.5 * self._accel(u0, F(0)))
+        u = R * (u0 + dt * (1.0 - beta) * v0 - 0.5 * self._accel(u0, F(0))) + dirichlet(1)
         if U_acc is not None:
             U_acc += um
         for n in range(1, self.N + 1):
             if U_acc is not None and n < self.N:
                 U_acc += u * np.exp(1j * self.omega * n * dt)
-            up = R * ((2.0 * u - (1.0 - beta) * um - self._accel(u, F(n))) / (1.0 + beta))
+            up = R * ((2.0 * u - (1.0 - beta) * um - self._accel(u, F(n))) / (1.0 + beta)) \
+                + dirichlet(n + 1)
             if n == self.N:
-                vN = (up - um) / (2.0 * dt)
-                return np.concatenate([u.ravel(), vN.ravel()])
+                vN = R * (up - um) / (2.0 * dt)
+                return np.concatenate([(R * u).ravel(), vN.ravel()])
             um, u = u, up
 
     def runup(self, periods: int, ramp: bool) -> np.ndarray:
@@ -291,8 +299,9 @@ class F2:
     # ---------------------------------------------------------------- direct solve
     def direct(self):
         """Direct sparse solve of [S - wt^2 M - i wh B] U = Fhat on the free nodes with
-        wt = (2/dt) sin(w dt / 2), wh = sin(w dt) / dt, Fhat = w f + sum_abs (face weight) gS.
-        Returns (U, z_periodic) with z = (Re U, wh Im U)."""
+        wt = (2/dt) sin(w dt / 2), wh = sin(w dt) / dt, Fhat = w f + sum over faces (face
+        weight) g, and U = gD on the Dirichlet nodes.  Returns (U, z_periodic) with
+        z = (Re U, wh Im U) on the free nodes."""
         dt = self.dt
         wt2 = (2.0 / dt * math.sin(0.5 * self.omega * dt)) ** 2
         wh = math.sin(self.omega * dt) / dt
@@ -301,10 +310,17 @@ class F2:
         Fh = self.w * self.f
         if self.g is not None:
             for idx, (sel, fw) in enumerate(self.face_w):
-                if self.bc[idx] == ABSORBING:
-                    Fh[sel] += fw * self.g[idx].reshape(fw.shape)
+                Fh[sel] += fw * self.g[idx].reshape(fw.shape)
         free = np.flatnonzero(self.free.ravel() > 0.5)
         U = np.zeros(self.nn, complex)
-        U[free] = spla.spsolve(A[free][:, free].tocsc(), Fh.ravel()[free])
-        z = np.concatenate([U.real, wh * U.imag])
+        rhs = Fh.ravel()[free]
+        if self.gD is not None:
+            # Dirichlet values are known: move their couplings to the right-hand side
+            dnodes = np.flatnonzero(self.free.ravel() < 0.5)
+            gd = self.gD.ravel()[dnodes]
+            rhs = rhs - A[free][:, dnodes] @ gd
+            U[dnodes] = gd
+        U[free] = spla.spsolve(A[free][:, free].tocsc(), rhs)
+        R = self.free.ravel()
+        z = np.concatenate([R * U.real, R * wh * U.imag])
         return U.reshape(self.shape), z

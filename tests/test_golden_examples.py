@@ -124,3 +124,29 @@ def test_bounded_domain_example_needs_the_filter(ex):
             assert np.ptp(shift) < 1e-6 * np.max(np.abs(shift))
     for r in _ratios(errs):
         assert 3.8 < r < 4.2
+
+
+@pytest.mark.parametrize("name,u0", [("semi_discrete_convergence", 1.0),
+                                     ("convergence_rates", -1.0)])
+def test_examples_with_their_dirichlet_data(ex, name, u0):
+    """The two Dirichlet examples exactly as stated: u(0) = 1 with k = 6 pi (Sec. 4.1) and
+    u(0) = -1 with k = 5 pi / 4 (Sec. 3.4), the plane x = 0 carrying the Dirichlet data and x = 1
+    absorbing.  Nodal errors against u0 exp(i k x) fall as h^2; CMCG reproduces the direct
+    solve, Dirichlet nodes included."""
+    e = ex[name]
+    k = _num(e["k"])
+    sizes = (64, 128, 256) if name == "semi_discrete_convergence" else \
+        [int(round(1.0 / h)) for h in e["meshes_h"]]
+    errs = []
+    for nx in sizes:
+        s = F2(ci.channel_dirichlet_f2((nx, 2), k, u0))
+        U, _ = s.direct()
+        x = np.arange(nx + 1) / nx
+        errs.append(np.max(np.abs(U - u0 * np.exp(1j * k * x)[None, :])))
+        if nx == sizes[1]:
+            z, _, _ = s.solve(tol=e["cg_tol"] if e["cg_tol"] >= 1e-12 else 1e-12, max_iter=5000)
+            Uc = s.filter(z)
+            assert np.linalg.norm(Uc - U) <= 1e-9 * np.linalg.norm(U)
+            assert np.max(np.abs(Uc[:, 0] - u0)) < 1e-9
+    for r in _ratios(errs):
+        assert 3.7 < r < 4.4
