@@ -67,8 +67,12 @@ typedef struct {
   const double *c;             /* wave speed > 0 (cell or node field); NULL -> c_const         */
   double c_const;
   const double *f_re, *f_im;   /* source amplitude (same layout as c); either may be NULL      */
-  const double *gS_re, *gS_im; /* absorbing-boundary data, concatenated faces; may be NULL     */
-  const uint8_t *sound_soft;   /* F2: 1 = homogeneous Dirichlet node; NULL = none               */
+  const double *gS_re, *gS_im; /* boundary data, concatenated faces: gS on absorbing faces
+                                  (du/dn - i k u = gS), gN on Neumann faces (du/dn = gN);
+                                  either may be NULL (zero)                                    */
+  const uint8_t *sound_soft;   /* F2: 1 = Dirichlet node; NULL = none                          */
+  const double *gD_re, *gD_im; /* F2: Dirichlet data u = gD on the sound-soft nodes (layout of
+                                  c, read on those nodes only); NULL = homogeneous              */
   int32_t face_bc[6];          /* -x,+x,-y,+y,-z,+z: CMCG_ABSORBING or CMCG_NEUMANN            */
   double courant;              /* sigma in (0, 1/sqrt(dim)); 0 -> 0.5                          */
 } cmcg_problem;

@@ -36,7 +36,7 @@ class _Problem(ctypes.Structure):
                 ("n", ctypes.c_int64 * 3), ("omega", ctypes.c_double),
                 ("c", _dp), ("c_const", ctypes.c_double),
                 ("f_re", _dp), ("f_im", _dp), ("gS_re", _dp), ("gS_im", _dp),
-                ("sound_soft", ctypes.POINTER(ctypes.c_uint8)),
+                ("sound_soft", ctypes.POINTER(ctypes.c_uint8)), ("gD_re", _dp), ("gD_im", _dp),
                 ("face_bc", ctypes.c_int32 * 6), ("courant", ctypes.c_double)]
 
 
@@ -312,6 +312,11 @@ def marshal_problem(problem):
     if problem.sound_soft is not None:
         m = arr(problem.sound_soft, np.uint8)
         p.sound_soft = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    if getattr(problem, "gD", None) is not None:
+        d = np.asarray(problem.gD, dtype=np.complex128)
+        p.gD_re = _ptr(arr(d.real))
+        if np.any(d.imag != 0):
+            p.gD_im = _ptr(arr(d.imag))
     bc = list(problem.face_bc) + [1] * 6
     for k in range(6):
         p.face_bc[k] = int(bc[k])

@@ -49,6 +49,17 @@ cmcg_status validate_problem(const cmcg_problem *P, const cmcg_options *O) {
   if (!((P->dim == 2 && P->formulation == 1) || (P->dim == 3 && P->formulation == 2)))
     return set_error("supported: dim 2 with formulation 1, dim 3 with formulation 2"),
            CMCG_EUNSUPPORTED;
+  if ((P->gD_re || P->gD_im) && (P->formulation != 2 || !P->sound_soft))
+    return set_error("Dirichlet data needs the nodal formulation and a sound-soft mask"),
+           CMCG_EINVAL;
+  if (O->runup_periods > 0) {
+    // a closed box without absorption or Dirichlet nodes drifts linearly under a source with
+    // non-zero mean (the eta mode of Sec. 2.2), which the run-up start would carry into CG
+    bool damped = P->sound_soft != nullptr;
+    for (int f = 0; f < 2 * P->dim; ++f) damped = damped || P->face_bc[f] == CMCG_ABSORBING;
+    if (!damped)
+      return set_error("the run-up needs an absorbing face or Dirichlet nodes"), CMCG_EUNSUPPORTED;
+  }
   return CMCG_OK;
 }
 

@@ -50,7 +50,7 @@ __global__ void f1_setup_kernel(F1Geom g, const double *c, double c_const, const
       const bool on[4] = {i == 0, i == nx - 1, j == 0, j == ny - 1};
       const int along[4] = {j, j, i, i};
       for (int f = 0; f < 4; ++f) {
-        if (!on[f] || !g.abs_face[f]) continue;
+        if (!on[f]) continue;
         if (gre) ar += gre[off[f] + along[f]] * ih;
         if (gim) ai += gim[off[f] + along[f]] * ih;
       }

@@ -62,6 +62,11 @@ struct F2Args {
   int forced = 0;
   double fcos = 1, fsin = 0;                // source phase cos/sin(omega t_n)
   double wcos = 1, wsin = 0;                // filter weight cos/sin(omega t_n)
+  // Dirichlet data Re(gD e^{-i w t}) on the sound-soft nodes of a forced period (null: zero):
+  // the value at time t is dre * dcos + dim * dsin with dcos, dsin = cos, sin(w t) (times the
+  // source ramp).  *0: the sweep's input time (start map), *1: its output time.
+  const double *dre = nullptr, *dim = nullptr;
+  double dcos0 = 0, dsin0 = 0, dcos1 = 0, dsin1 = 0;
 };
 
 template <typename T>

@@ -10,6 +10,9 @@
 // lambda = (c dt / h)^2.  Absorbing faces add beta = sqrt(lambda) m (m = number of absorbing faces
 // at the node), the load enters as F = dt^2 c^2 Re(G e^{-i w t}), G = f + (2/h) sum_abs gS, and
 // sound-soft nodes are held at zero (R = 1 - mask).
+// Forced periods of a problem with Dirichlet data hold the sound-soft nodes at Re(gD e^{-iwt})
+// (the start map reads the data at its input time on those nodes, every forced sweep writes it
+// at its output time there); the period's output state stays zero on them.
 //   start:  u^1 = R(u^0 + dt (1-beta) v^0 - (lambda L u^0 - F^0)/2)
 //   step:   u^{n+1} = R(2 u^n - (1-beta) u^{n-1} - lambda L u^n + F^n) / (1+beta)
 //   end:    v^N = (u^{N+1} - u^{N-1}) / (2 dt),  Phi(u^0, v^0) = (u^N, v^N)
@@ -65,6 +68,14 @@ __device__ __forceinline__ T lam_at(const F2Geom &g, const T *lam, size_t o) {
   return lam ? lam[o] : (T)g.lam_const;
 }
 
+// Dirichlet data value at device index o (dc, ds: cos/sin weights of the time)
+template <typename T>
+__device__ __forceinline__ T dirichlet_at(const F2Args<T> &p, size_t o, double dc, double ds) {
+  double v = p.dre[o] * dc;
+  if (p.dim) v = fma(p.dim[o], ds, v);
+  return (T)v;
+}
+
 // value of the stencilled field at a node, per sweep
 template <typename T, int MODE>
 __device__ __forceinline__ T sval(const F2Geom &g, const T *f, const T *lam, int i, int j, int k) {
@@ -95,7 +106,8 @@ __device__ __forceinline__ void node_update(const F2Geom &g, const F2Args<T> &p,
       p.ure[o] += (double)zc * p.wcos;
       p.uim[o] += (double)zc * p.wsin;
     }
-    p.out[o] = R ? zc + dt * (T(1) - beta) * aux - T(0.5) * (l * lap - F) : T(0);
+    const T hold = p.dre ? dirichlet_at(p, o, p.dcos1, p.dsin1) : T(0);
+    p.out[o] = R ? zc + dt * (T(1) - beta) * aux - T(0.5) * (l * lap - F) : hold;
   } else if (MODE == kF2FwdStep) {
     if (p.ure) {
       p.ure[o] += (double)zc * p.wcos;
@@ -104,20 +116,20 @@ __device__ __forceinline__ void node_update(const F2Geom &g, const F2Args<T> &p,
     T un;
     if (m == 0) un = fma(-l, lap, T(2) * zc - aux) + F;
     else un = (T(2) * zc - (T(1) - beta) * aux - (l * lap - F)) / (T(1) + beta);
-    p.out[o] = R ? un : T(0);
+    const T hold = (!R && p.dre) ? dirichlet_at(p, o, p.dcos1, p.dsin1) : T(0);
+    p.out[o] = R ? un : hold;
   } else if (MODE == kF2FwdEnd) {
     // out = (u^N, (u^{N+1} - u^{N-1}) / (2 dt)) - sub
     T up;
     if (m == 0) up = fma(-l, lap, T(2) * zc - aux) + F;
     else up = (T(2) * zc - (T(1) - beta) * aux - (l * lap - F)) / (T(1) + beta);
-    if (!R) up = T(0);
     T ou = zc, ov = (up - aux) / (T(2) * dt);
     if (p.sub) {
       ou -= p.sub[o];
       ov -= p.sub[o + g.fs];
     }
-    p.out[o] = ou;
-    p.out[o + g.fs] = ov;
+    p.out[o] = R ? ou : T(0);                // the state is zero on Dirichlet nodes
+    p.out[o + g.fs] = R ? ov : T(0);
   } else if (MODE == kF2Metric) {
     // y = M_E w = (S w_u, M w_v) on the free nodes
     const T eta = (T)eta_of(g, i, j, k);
@@ -189,7 +201,7 @@ __device__ __forceinline__ void plane_loads(const F2Geom &g, const F2Args<T> &p,
 // double buffering), which doubles the bytes each wavefront keeps in flight.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
-  constexpr bool kPlain = MODE != kF2Metric && MODE != kF2AdjEnd;
+  constexpr bool kPlain = MODE != kF2Metric && MODE != kF2AdjEnd && MODE != kF2FwdStart;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 64 + lane;
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -224,20 +236,36 @@ __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
       zc = q.zp;
     }
   } else {
+    // the start map of a forced period with Dirichlet data reads the data (at the period's
+    // start) where the input state holds zero
+    const bool din = MODE == kF2FwdStart && p.dre != nullptr;
+    auto val = [&](int a, int b, int c) -> T {
+      if (din && masked(g, a, b, c)) return dirichlet_at(p, g.idx(a, b, c), p.dcos0, p.dsin0);
+      return sval<T, MODE>(g, p.st, p.lam, a, b, c);
+    };
+    if (din) {
+      zm = val(ic, j, mirror(k0 - 1, g.nz));
+      zc = val(ic, j, k0);
+    }
     for (int k = k0; k < k1; ++k) {
-      const T zp = sval<T, MODE>(g, p.st, p.lam, ic, j, mirror(k + 1, g.nz));
-      const T xe = sval<T, MODE>(g, p.st, p.lam, xend, j, k);
+      const T zp = val(ic, j, mirror(k + 1, g.nz));
+      const T xe = val(xend, j, k);
       T xl = lane_from_left(zc);
       T xr = lane_from_right(zc);
       if (lane == 0) xl = xe;
       if (lane == 63) xr = xe;
       if (last) xr = xl;
-      const T ym = sval<T, MODE>(g, p.st, p.lam, ic, jm, k);
-      const T yp = sval<T, MODE>(g, p.st, p.lam, ic, jp, k);
+      const T ym = val(ic, jm, k);
+      const T yp = val(ic, jp, k);
       const T lap = T(6) * zc - (zm + zp + xl + xr + ym + yp);
       if (live) {
         const size_t o = g.idx(ic, j, k);
-        node_update<T, MODE>(g, p, o, ic, j, k, zc, lap, p.aux[o], lam_at(g, p.lam, o), T(0));
+        T F = T(0);
+        if (MODE == kF2FwdStart && p.forced) {
+          F = p.fre[o] * (T)p.fcos;
+          if (p.fim) F = fma(p.fim[o], (T)p.fsin, F);
+        }
+        node_update<T, MODE>(g, p, o, ic, j, k, zc, lap, p.aux[o], lam_at(g, p.lam, o), F);
       }
       zm = zc;
       zc = zp;
@@ -390,7 +418,7 @@ __global__ void f2_setup_kernel(F2Geom g, const double *c, double c_const, const
                                (size_t)k * (nx + 1) + i, (size_t)k * (nx + 1) + i,
                                (size_t)j * (nx + 1) + i, (size_t)j * (nx + 1) + i};
       for (int f = 0; f < 6; ++f) {
-        if (!on[f] || !g.abs_face[f]) continue;
+        if (!on[f]) continue;
         if (gre) ar += 2.0 / g.h * gre[off[f] + along[f]];
         if (gim) ai += 2.0 / g.h * gim[off[f] + along[f]];
       }

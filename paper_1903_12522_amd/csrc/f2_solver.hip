@@ -30,6 +30,20 @@ __global__ void mask_unpack_kernel(F2Geom g, const uint8_t *packed, uint8_t *dev
   }
 }
 
+// Dirichlet data of the sound-soft nodes: packed user node array -> device layout (zero on the
+// other nodes)
+__global__ void dirichlet_unpack_kernel(F2Geom g, const double *packed, double *dev) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < g.fs; o += stride) {
+    const int i = (int)(o % g.px);
+    const int j = (int)((o / g.px) % (g.ny + 1));
+    const int k = (int)(o / g.plane);
+    double v = 0.0;
+    if (i <= g.nx && g.mask[o]) v = packed[((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i];
+    dev[o] = v;
+  }
+}
+
 // filter output u = (2/N) (Ure + i Uim), copied into a contiguous node array
 __global__ void f2_output_kernel(F2Geom g, const double *ure, const double *uim, double scale,
                                  double *ore, double *oim) {
@@ -73,6 +87,7 @@ class F2Solver final : public Solver {
   double *RH = nullptr;              // dual residual (two fields)
   double *QU = nullptr;              // Riesz output, u block
   double *Ure = nullptr, *Uim = nullptr;
+  double *Dre = nullptr, *Dim = nullptr;   // Dirichlet data on the sound-soft nodes, or null
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
   RieszMG mg;
   bool started = false;
@@ -193,6 +208,27 @@ class F2Solver final : public Solver {
                                  tp<float>(lo.lam), tp<float>(lo.Fre), tp<float>(lo.Fim), s));
       CMCG_HIP(hipStreamSynchronize(s));
     }
+    // Dirichlet data (only where there are sound-soft nodes)
+    if (g.mask && (P->gD_re || P->gD_im)) {
+      DeviceArena tmp;
+      const double *src[2] = {P->gD_re, P->gD_im};
+      double **dst[2] = {&Dre, &Dim};
+      for (int k = 0; k < 2; ++k) {
+        if (!src[k]) continue;
+        double *dpk = nullptr;
+        CMCG_TRY(tmp.alloc_n(nn, &dpk, s));
+        CMCG_HIP(hipMemcpyAsync(dpk, src[k], nn * sizeof(double), hipMemcpyHostToDevice, s));
+        CMCG_TRY(arena.alloc_n(g.fs, dst[k], s));
+        hipLaunchKernelGGL(dirichlet_unpack_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, dpk,
+                           *dst[k]);
+        CMCG_HIP(hipGetLastError());
+      }
+      if (!Dre) {
+        // only an imaginary part given: a zero real part keeps the kernels' reads valid
+        CMCG_TRY(arena.alloc_n(g.fs, &Dre, s));
+      }
+      CMCG_HIP(hipStreamSynchronize(s));
+    }
     CMCG_TRY(mg.build(g, arena, s));
     return CMCG_OK;
   }
@@ -210,6 +246,16 @@ class F2Solver final : public Solver {
       p.ure = Ure;
       p.uim = Uim;
     }
+    if (forced && Dre) {
+      p.dre = Dre;
+      p.dim = Dim;
+    }
+    // weights of Re(g e^{-i w t}) at the step time t_n = n dt of this period (ramped)
+    auto phase = [&](int n, double *c, double *sn) {
+      const double t = n * cfg.dt, amp = transient(t_offset + t, t_tr);
+      *c = amp * std::cos(cfg.omega * t);
+      *sn = amp * std::sin(cfg.omega * t);
+    };
     T *buf[3] = {tp<T>(b.A), tp<T>(b.B), tp<T>(b.C)};
     // start map: u^1 from (u^0, v^0)
     p.st = zin;
@@ -219,6 +265,8 @@ class F2Solver final : public Solver {
     p.fsin = 0.0;
     p.wcos = 1.0;
     p.wsin = 0.0;
+    phase(0, &p.dcos0, &p.dsin0);
+    phase(1, &p.dcos1, &p.dsin1);
     CMCG_HIP(f2_march<T>(kF2FwdStart, g, p, s));
     const T *prev = zin;
     int cur = 0;
@@ -229,6 +277,7 @@ class F2Solver final : public Solver {
       p.wsin = std::sin(cfg.omega * t);
       p.fcos = amp * p.wcos;
       p.fsin = amp * p.wsin;
+      phase(n + 1, &p.dcos1, &p.dsin1);
       const int nxt = (cur + 1) % 3;
       p.st = buf[cur];
       p.aux = prev;

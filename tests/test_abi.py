@@ -49,7 +49,14 @@ def _problem(cm, **kw):
     p.courant = kw.get("courant", 0.5)
     for k in range(6):
         p.face_bc[k] = kw.get("bc", 0)
+    if kw.get("gD"):
+        data = np.ones(17 * 17)
+        _KEEP.append(data)
+        p.gD_re = data.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return p
+
+
+_KEEP = []
 
 
 def _create(cm, p, **ok):
@@ -57,6 +64,8 @@ def _create(cm, p, **ok):
     o.precision = ok.get("precision", 0)
     o.tol = ok.get("tol", 1e-6)
     o.max_iter = ok.get("max_iter", 10)
+    o.riesz_mode = ok.get("riesz_mode", 0)
+    o.runup_periods = ok.get("runup_periods", 0)
     h = cm._H()
     st = cm._lib.cmcg_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h))
     return st, h
@@ -73,6 +82,10 @@ def _create(cm, p, **ok):
     (dict(), dict(precision=5), -1),
     (dict(), dict(max_iter=0), -1),
     (dict(dim=3, formulation=1, n=(8, 8, 8)), {}, -6),   # first-order 3D is not provided
+    (dict(), dict(riesz_mode=7), -1),
+    (dict(), dict(runup_periods=-1), -1),
+    (dict(gD=True), {}, -1),                            # Dirichlet data needs the nodal system
+    (dict(bc=1), dict(runup_periods=2), -6),            # run-up of a closed undamped box
 ])
 def test_invalid_inputs_rejected_before_device(kw, opt, expect):
     from paper_1903_12522_amd import cmcg as cm
