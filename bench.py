@@ -176,6 +176,50 @@ def runup_study(prob, runups=(0, 4, 16, 32), longtime=(16, 64, 256)):
     return out
 
 
+def obstacle_study(n: int = 128, freq: float = 6.0, longtime=(16, 64, 256, 1024)):
+    """CMCG against the do-nothing long-time solve for a convex (ball) and a nonconvex (open
+    box-shaped cavity) sound-soft obstacle under the same plane-wave data, second-order n^3.
+    CMCG: FP32-mixed to 1e-6.  Do-nothing: FP64, relative misfit sqrt(J(z_L) / J(0)) and the
+    filtered output's error against the CMCG solution after L periods."""
+    import numpy as np
+    import torch
+    import cmcg_inputs as ci
+    from paper_1903_12522_amd import cmcg
+    out = {}
+    for name, prob in (("ball", ci.sound_soft_sphere_3d(n=n, freq=freq, radius=0.2)),
+                       ("cavity", ci.sound_soft_cavity_3d(n=n, freq=freq))):
+        torch.cuda.empty_cache()
+        with cmcg.Solver(prob, "fp32", tol=1e-6, max_iter=20000) as s:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U, rep = s.solve(device_output=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            Uref = torch.complex(U[0], U[1]).cpu().numpy()
+        res = {"workload": f"second-order {n}^3, sound-soft {name}, {freq} wavelengths",
+               "cmcg": {"seconds": round(wall, 3), "iterations": rep["iterations"],
+                        "converged": rep["converged"],
+                        "periods": 2 * rep["iterations"] + 2 * rep["fp64_refreshes"] + 3},
+               "do_nothing": []}
+        log(f"{name}: CMCG {wall:.2f} s, {rep['iterations']} iterations")
+        with cmcg.Solver(prob, "fp64") as s:
+            J0 = s.misfit(np.zeros(s.info["state_len"]))
+            for L in longtime:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                z = s.runup(L, ramp=False)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                J = s.misfit(z)
+                err = float(np.linalg.norm(s.filter(z) - Uref) / np.linalg.norm(Uref))
+                res["do_nothing"].append({"periods": L, "seconds": round(wall, 3),
+                                          "relative_misfit": float(np.sqrt(J / J0)),
+                                          "filtered_rel_error_vs_cmcg": err})
+                log(f"{name}: do-nothing {L} periods: misfit {np.sqrt(J / J0):.3e}, error {err:.3e}")
+        out[name] = res
+    return out
+
+
 def cpu_baseline(prob, steps: int = 20):
     """The oracle as it stands, on the full grid: `steps` forward leapfrog steps plus `steps`
     transposed steps (the two halves of a CG iteration), timed on one host core."""
@@ -213,6 +257,8 @@ def main():
     ap.add_argument("--serving", type=int, default=0, help="replay this many serving requests")
     ap.add_argument("--runup-study", action="store_true",
                     help="run-up and do-nothing long-time solve on the 4096^2 workload")
+    ap.add_argument("--obstacle-study", action="store_true",
+                    help="CMCG vs the do-nothing solve for a convex and a nonconvex obstacle")
     args = ap.parse_args()
 
     if args.calibrate_copy:
@@ -319,6 +365,8 @@ def main():
         out["serving"] = serving_run(args.serving)
     if args.runup_study:
         out["runup_study"] = runup_study(prob)
+    if args.obstacle_study:
+        out["obstacle_study"] = obstacle_study()
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu:

@@ -237,6 +237,38 @@ def sound_soft_sphere_3d(n: int = 1024, freq: float = 100.0, radius: float = 0.1
                    name=f"f2_sphere_{n}")
 
 
+def cavity_mask(n: Sequence[int], h: float, lo: float = 0.3, hi: float = 0.7,
+                wall: Optional[float] = None, aperture: Optional[float] = 0.08) -> np.ndarray:
+    """uint8 node mask of a box-shaped shell [lo, hi]^3 of wall thickness `wall` (default two
+    cells or 0.02, whichever is larger) with a square opening of half-width `aperture` in the
+    middle of its +x face (None: the whole face open): a nonconvex obstacle whose interior
+    traps waves."""
+    wall = max(2.0 * h, 0.02) if wall is None else wall
+    x, y, z = node_coords(n, h)
+    inside_outer = (x >= lo) & (x <= hi) & (y >= lo) & (y <= hi) & (z >= lo) & (z <= hi)
+    inside_inner = ((x > lo + wall) & (x < hi - wall) & (y > lo + wall) & (y < hi - wall)
+                    & (z > lo + wall) & (z < hi - wall))
+    mid = 0.5 * (lo + hi)
+    a = (hi - lo) if aperture is None else aperture
+    opening = (x >= hi - wall) & (np.abs(y - mid) < a) & (np.abs(z - mid) < a)
+    return (inside_outer & ~inside_inner & ~opening).astype(np.uint8)
+
+
+def sound_soft_cavity_3d(n: int = 128, freq: float = 6.0, direction=(-1.0, -1.0, -1.0)) -> Problem:
+    """3D unit cube, n^3 cells, second-order nodal system, c = 1, total-field scattering of the
+    plane wave exp(i k d.x), d = direction / |direction| (arriving from the open side), by a
+    sound-soft box-shaped cavity [0.3, 0.7]^3 with a square opening (half-width 0.08) in its +x
+    face; absorbing outer faces carry gS = (d/dn - i k) u_in.  Stands in for the nonconvex
+    cavity of the paper's scattering tests.""" 
+    h = 1.0 / n
+    k = 2 * math.pi * freq
+    gS = plane_wave_face_data((n, n, n), h, k, direction)
+    mask = cavity_mask((n, n, n), h)
+    return Problem(dim=3, formulation=2, n=(n, n, n), omega=k, c=None, c_const=1.0, f=None,
+                   gS=gS, sound_soft=mask, face_bc=(ABSORBING,) * 6, courant=0.5,
+                   name=f"f2_cavity_{n}")
+
+
 def channel_plane_wave_f2(n: Sequence[int], k: float, dirichlet_at_zero: bool = False) -> Problem:
     """Channel versions of the paper's 1D closed forms on the F2 nodal grid (c = 1, f = 0,
     lateral faces Neumann so the solution does not vary across the channel):

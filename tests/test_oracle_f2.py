@@ -229,3 +229,16 @@ def test_sound_soft_sphere_small():
     Ud, _ = s.direct()
     assert np.linalg.norm(U - Ud) / np.linalg.norm(Ud) < 1e-9
     assert np.max(np.abs(U[prob.sound_soft.astype(bool)])) == 0.0
+
+
+def test_sound_soft_cavity_small():
+    """A nonconvex obstacle (a box-shaped shell open on one face): CMCG still equals the direct
+    solve of the time-discrete system, and the field vanishes on the obstacle."""
+    prob = ci.sound_soft_cavity_3d(n=16, freq=1.0)
+    s = F2(prob)
+    assert 0 < int(prob.sound_soft.sum()) < s.nn
+    z, _, _ = s.solve(tol=1e-12, max_iter=4000)
+    U = s.filter(z)
+    Ud, _ = s.direct()
+    assert np.linalg.norm(U - Ud) / np.linalg.norm(Ud) < 1e-9
+    assert np.max(np.abs(U[prob.sound_soft.astype(bool)])) == 0.0
