@@ -30,6 +30,17 @@ NEUMANN = 1
 
 
 @dataclasses.dataclass
+class Shot:
+    """One time-harmonic component of a multi-frequency ("super-shot") source: data f, gS/gN
+    and gD as in `Problem`, oscillating at `harmonic` times the problem's base frequency."""
+
+    harmonic: int
+    f: Optional[np.ndarray] = None
+    gS: Optional[List[np.ndarray]] = None
+    gD: Optional[np.ndarray] = None
+
+
+@dataclasses.dataclass
 class Problem:
     """Helmholtz problem  -lap u - k^2 u = f,  du/dn - i k u = gS on absorbing faces,
     du/dn = gN on Neumann faces, u = gD on sound-soft nodes (eq. HE), posed on the box
@@ -50,6 +61,9 @@ class Problem:
     courant: float = 0.5
     name: str = ""
     spacing: Optional[float] = None       # grid spacing; None -> 1 / n_x (unit-width box)
+    # multi-frequency source: the sum of these components, omega being their base frequency
+    # (then f, gS and gD above stay None); None -> the single component (1, f, gS, gD)
+    shots: Optional[List[Shot]] = None
 
     @property
     def h(self) -> float:
@@ -140,6 +154,28 @@ def random_medium_2d(n: int = 4096, freq: float = 100.0, n_src: int = 8, seed: i
     f = gaussian_bumps_2d(n, n, h, [tuple(p) for p in centres], w).astype(np.complex128)
     return Problem(dim=2, formulation=1, n=(n, n), omega=2 * math.pi * freq, c=c, f=f,
                    face_bc=(ABSORBING,) * 4, courant=0.5, name=f"f1_random_{n}")
+
+
+def supershot_2d(n: int = 256, base_freq: float = 4.0, harmonics=(1, 2, 3), seed: int = 99,
+                 corr_len: float = 0.05, c=None) -> Problem:
+    """Multi-frequency source on the first-order 2D random medium: c a seeded Gaussian random
+    field in [1, 2] (or the given array), base frequency omega = 2 pi base_freq, and for each
+    harmonic m one Gaussian source of width 1 / (4 m base_freq) at a seeded position in
+    [0.2, 0.8]^2 with a seeded complex amplitude of modulus 1, absorbing on all sides.  The
+    period T = 1 / base_freq is common to all components."""
+    h = 1.0 / n
+    if c is None:
+        c = gaussian_random_field((n, n), h, corr_len, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    shots = []
+    for m in harmonics:
+        pos = rng.uniform(0.2, 0.8, size=2)
+        phase = np.exp(2j * math.pi * rng.uniform())
+        f = phase * gaussian_bumps_2d(n, n, h, [tuple(pos)], 1.0 / (4.0 * m * base_freq))
+        shots.append(Shot(int(m), f=f.astype(np.complex128)))
+    return Problem(dim=2, formulation=1, n=(n, n), omega=2 * math.pi * base_freq, c=c,
+                   face_bc=(ABSORBING,) * 4, courant=0.5, shots=shots,
+                   name=f"f1_supershot_{n}_{'_'.join(str(m) for m in harmonics)}")
 
 
 def channel_plane_wave_f1(nx: int, ny: int, k: float) -> Problem:
@@ -235,6 +271,25 @@ def sound_soft_sphere_3d(n: int = 1024, freq: float = 100.0, radius: float = 0.1
     return Problem(dim=3, formulation=2, n=(n, n, n), omega=k, c=None, c_const=1.0, f=None,
                    gS=gS, sound_soft=mask, face_bc=(ABSORBING,) * 6, courant=0.5,
                    name=f"f2_sphere_{n}")
+
+
+def supershot_sphere_3d(n: int = 128, base_freq: float = 2.0, harmonics=(1, 2, 3),
+                        radius: float = 0.15, seed: int = 5) -> Problem:
+    """Multi-frequency scattering by the sound-soft ball of `sound_soft_sphere_3d`: base
+    frequency omega = 2 pi base_freq, and for each harmonic m an incident plane wave
+    exp(i m omega d_m.x) with a seeded direction d_m, entering through the absorbing faces as
+    gS = (d/dn - i k_m) u_in (c = 1)."""
+    h = 1.0 / n
+    k0 = 2 * math.pi * base_freq
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shots = []
+    for m in harmonics:
+        d = rng.standard_normal(3)
+        shots.append(Shot(int(m), gS=plane_wave_face_data((n, n, n), h, m * k0, tuple(d))))
+    mask = sphere_mask((n, n, n), h, (0.5, 0.5, 0.5), radius)
+    return Problem(dim=3, formulation=2, n=(n, n, n), omega=k0, c=None, c_const=1.0,
+                   sound_soft=mask, face_bc=(ABSORBING,) * 6, courant=0.5, shots=shots,
+                   name=f"f2_supershot_sphere_{n}")
 
 
 def cavity_mask(n: Sequence[int], h: float, lo: float = 0.3, hi: float = 0.7,

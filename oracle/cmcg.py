@@ -112,3 +112,16 @@ def runup(period_at: Callable[[np.ndarray, int], np.ndarray], size: int, periods
     for p in range(periods):
         z = period_at(z, p)
     return z
+
+
+def components(prob):
+    """The time-harmonic components of a problem's data, as (m, f, gS, gD) with angular
+    frequency m * omega.  A multi-frequency ("super-shot") problem superposes several
+    harmonics of one base frequency omega (Concluding remarks): the forced wave equation then
+    has the common period T = 2 pi / omega, and each component's Helmholtz solution is the
+    filter of the one periodic solution at that component's frequency.  A problem without
+    shots is the single component m = 1 carrying its own data."""
+    shots = getattr(prob, "shots", None)
+    if shots:
+        return [(int(s.harmonic), s.f, s.gS, s.gD) for s in shots]
+    return [(1, prob.f, prob.gS, prob.gD)]

@@ -71,13 +71,17 @@ class F1:
             m[-1, :] += 1
         self.m = m
         self.gamma = self.dt * self.c * m / (2.0 * self.h)
-        self.f = (np.zeros((self.ny, self.nx), complex) if prob.f is None
-                  else np.asarray(prob.f, dtype=complex).reshape(self.ny, self.nx))
-        if prob.gS is None:
-            self.g = [np.zeros(self.ny, complex), np.zeros(self.ny, complex),
-                      np.zeros(self.nx, complex), np.zeros(self.nx, complex)]
-        else:
-            self.g = [np.asarray(a, dtype=complex).reshape(-1) for a in prob.gS[:4]]
+        # data of each time-harmonic component: (m, f, g), angular frequency m * omega
+        self.comps = []
+        for m, f, gS, _ in _cmcg.components(prob):
+            f = (np.zeros((self.ny, self.nx), complex) if f is None
+                 else np.asarray(f, dtype=complex).reshape(self.ny, self.nx))
+            if gS is None:
+                g = [np.zeros(self.ny, complex), np.zeros(self.ny, complex),
+                     np.zeros(self.nx, complex), np.zeros(self.nx, complex)]
+            else:
+                g = [np.asarray(a, dtype=complex).reshape(-1) for a in gS[:4]]
+            self.comps.append((m, f, g))
         self.shapes = [(self.ny, self.nx - 1), (self.ny - 1, self.nx), (self.ny, self.nx)]
         self.sizes = [a * b for a, b in self.shapes]
         self.size = sum(self.sizes)
@@ -127,14 +131,16 @@ class F1:
     def source(self, t: float) -> np.ndarray:
         """Re(f e^{-iwt}) + (1/h) sum over the boundary faces of Re(g e^{-iwt}): the prescribed
         part of the outward flux p.n, gS on absorbing faces (p.n = gS - v/c) and gN on Neumann
-        faces (p.n = gN)."""
-        e = np.exp(-1j * self.omega * t)
-        F = (self.f * e).real
+        faces (p.n = gN); summed over the components, each at its own frequency m w."""
         h = self.h
-        F[:, 0] += (self.g[0] * e).real / h
-        F[:, -1] += (self.g[1] * e).real / h
-        F[0, :] += (self.g[2] * e).real / h
-        F[-1, :] += (self.g[3] * e).real / h
+        F = np.zeros((self.ny, self.nx))
+        for m, f, g in self.comps:
+            e = np.exp(-1j * m * self.omega * t)
+            F += (f * e).real
+            F[:, 0] += (g[0] * e).real / h
+            F[:, -1] += (g[1] * e).real / h
+            F[0, :] += (g[2] * e).real / h
+            F[-1, :] += (g[3] * e).real / h
         return F
 
     # ---------------------------------------------------------------- time stepping
@@ -237,28 +243,33 @@ class F1:
 
     def filter(self, z: np.ndarray) -> np.ndarray:
         """u = i V / omega with V = (2/N) sum_{n<N} v^n e^{i w t_n} over one forced period
-        from z (eq. TH_FILTERED_MIXED_SOLUTION with the rectangle rule)."""
+        from z (eq. TH_FILTERED_MIXED_SOLUTION with the rectangle rule).  With several
+        components, one such sum per component at its frequency m w (u = i V / (m w)) over the
+        same period; the result is then stacked, shape (components, ny, nx)."""
         Px, Py, v = self.unpack(z)
-        V = np.zeros((self.ny, self.nx), complex)
+        V = [np.zeros((self.ny, self.nx), complex) for _ in self.comps]
         for n in range(self.N):
-            V += v * np.exp(1j * self.omega * n * self.dt)
+            for c, (m, _, _) in enumerate(self.comps):
+                V[c] += v * np.exp(1j * m * self.omega * n * self.dt)
             Px, Py, v = self.step(Px, Py, v, n, True)
-        V *= 2.0 / self.N
-        return 1j * V / self.omega
+        U = [1j * (2.0 / self.N) * Vc / (m * self.omega) for Vc, (m, _, _) in zip(V, self.comps)]
+        return U[0] if len(U) == 1 else np.stack(U)
 
     def functional(self, z):
         return _cmcg.functional(lambda x: self.period(x, True), self.ME, z)
 
     # ---------------------------------------------------------------- direct solve
-    def frequency_system(self):
+    def frequency_system(self, comp: int = 0):
         """Sparse time-discretised Helmholtz system for the amplitudes V (cells) and Q
         (faces, at half steps) of the discrete periodic solution
         v^n = Re(V e^{-iwt_n}), p^{n+1/2} = Re(Q e^{-iwt_{n+1/2}}), theta = w dt / 2:
             -2 i sin(theta) Q - dt G V = 0
             (-2 i sin(theta) + 2 gamma cos(theta)) V - dt c^2 D Q = dt c^2 Fhat,
-        Fhat = f + (1/h) sum over the boundary faces of g (gS or gN)."""
+        Fhat = f + (1/h) sum over the boundary faces of g (gS or gN), for component `comp`
+        (w its frequency m omega, same dt)."""
         nx, ny, h, dt = self.nx, self.ny, self.h, self.dt
-        th = 0.5 * self.omega * dt
+        m, f, g = self.comps[comp]
+        th = 0.5 * m * self.omega * dt
 
         def d1(m):
             return sp.diags([-np.ones(m - 1), np.ones(m - 1)], [0, 1], shape=(m - 1, m)) / h
@@ -273,23 +284,29 @@ class F1:
         A = sp.bmat([[-2j * math.sin(th) * sp.identity(nf), -dt * G],
                      [-dt * sp.diags(c2) @ D,
                       sp.diags(-2j * math.sin(th) + 2.0 * gam * math.cos(th))]]).tocsc()
-        Fhat = self.f.copy()
-        Fhat[:, 0] += self.g[0] / h
-        Fhat[:, -1] += self.g[1] / h
-        Fhat[0, :] += self.g[2] / h
-        Fhat[-1, :] += self.g[3] / h
+        Fhat = f.copy()
+        Fhat[:, 0] += g[0] / h
+        Fhat[:, -1] += g[1] / h
+        Fhat[0, :] += g[2] / h
+        Fhat[-1, :] += g[3] / h
         rhs = np.concatenate([np.zeros(nf, complex), dt * c2 * Fhat.ravel()])
         return A, rhs, nf
 
     def direct(self):
         """Direct sparse solve of the frequency-domain system.  Returns (u, z_periodic):
-        u = i V / omega and the periodic state (P^0, v^0) = (cos(theta) Re Q, Re V)."""
-        A, rhs, nf = self.frequency_system()
-        x = spla.spsolve(A, rhs)
-        Q, V = x[:nf], x[nf:]
-        th = 0.5 * self.omega * self.dt
-        z = np.concatenate([math.cos(th) * Q.real, V.real])
-        return (1j * V / self.omega).reshape(self.ny, self.nx), z
+        u = i V / omega and the periodic state (P^0, v^0) = (cos(theta) Re Q, Re V).  With
+        several components, u is stacked per component (u = i V / (m omega) at theta =
+        m omega dt / 2) and the periodic state is the sum of the components' states (the
+        scheme is linear)."""
+        U, z = [], np.zeros(self.size)
+        for c, (m, _, _) in enumerate(self.comps):
+            A, rhs, nf = self.frequency_system(c)
+            x = spla.spsolve(A, rhs)
+            Q, V = x[:nf], x[nf:]
+            th = 0.5 * m * self.omega * self.dt
+            z = z + np.concatenate([math.cos(th) * Q.real, V.real])
+            U.append((1j * V / (m * self.omega)).reshape(self.ny, self.nx))
+        return (U[0] if len(U) == 1 else np.stack(U)), z
 
 
 def window(prob, i0: int, i1: int, j0: int, j1: int):

@@ -33,7 +33,7 @@ State vector: [u (all nodes), v (all nodes)], sound-soft entries zero.
 from __future__ import annotations
 
 import math
-from typing import Optional
+from typing import List, Optional
 
 import numpy as np
 import scipy.sparse as sp
@@ -99,11 +99,17 @@ class F2:
                     B[tuple(sel)] += fw[tuple(sel)] / self.c[tuple(sel)]
         self.B = B
         self.beta = 0.5 * self.dt * B / self.M
-        self.f = (np.zeros(self.shape, complex) if prob.f is None
-                  else np.asarray(prob.f, dtype=complex).reshape(self.shape))
-        self.g = None if prob.gS is None else [np.asarray(a, dtype=complex) for a in prob.gS]
-        self.gD = (None if prob.gD is None or prob.sound_soft is None
-                   else (1.0 - self.free) * np.asarray(prob.gD, dtype=complex).reshape(self.shape))
+        # data of each time-harmonic component: (m, f, g, gD), angular frequency m * omega;
+        # gD is kept on the sound-soft nodes only
+        self.comps = []
+        for m, f, gS, gD in _cmcg.components(prob):
+            f = (np.zeros(self.shape, complex) if f is None
+                 else np.asarray(f, dtype=complex).reshape(self.shape))
+            g = None if gS is None else [np.asarray(a, dtype=complex) for a in gS]
+            gD = (None if gD is None or prob.sound_soft is None
+                  else (1.0 - self.free) * np.asarray(gD, dtype=complex).reshape(self.shape))
+            self.comps.append((m, f, g, gD))
+        self.has_gD = any(c[3] is not None for c in self.comps)
         self.nn = int(np.prod(self.shape))
         self.size = 2 * self.nn
         self._S_lu = None
@@ -131,12 +137,24 @@ class F2:
         return out
 
     def load(self, t: float) -> np.ndarray:
-        e = np.exp(-1j * self.omega * t)
-        F = self.w * (self.f * e).real
-        if self.g is not None:
-            for idx, (sel, fw) in enumerate(self.face_w):
-                F[sel] += fw * (self.g[idx].reshape(fw.shape) * e).real
+        """Lumped load at time t: w Re(f e^{-i m w t}) plus the face weight times
+        Re(g e^{-i m w t}) on the boundary nodes, summed over the components."""
+        F = np.zeros(self.shape)
+        for m, f, g, _ in self.comps:
+            e = np.exp(-1j * m * self.omega * t)
+            F += self.w * (f * e).real
+            if g is not None:
+                for idx, (sel, fw) in enumerate(self.face_w):
+                    F[sel] += fw * (g[idx].reshape(fw.shape) * e).real
         return F
+
+    def dirichlet_value(self, t: float) -> np.ndarray:
+        """Re(gD e^{-i m w t}) on the sound-soft nodes, summed over the components."""
+        out = np.zeros(self.shape)
+        for m, _, _, gD in self.comps:
+            if gD is not None:
+                out += (gD * np.exp(-1j * m * self.omega * t)).real
+        return out
 
     # ---------------------------------------------------------------- time stepping
     def _accel(self, u, F):
@@ -146,11 +164,11 @@ class F2:
             r = r - F
         return self.dt ** 2 * r / self.M
 
-    def period(self, z: np.ndarray, forced: bool, U_acc: Optional[np.ndarray] = None,
+    def period(self, z: np.ndarray, forced: bool, U_acc: Optional[List[np.ndarray]] = None,
                t0: float = 0.0, ramp=None):
         """Phi(z) (forced) or E z (homogeneous) over [t0, t0 + T], the load at t_n = t0 + n dt
-        optionally multiplied by ramp(t_n).  If U_acc is given, u^n e^{i w t_n} for n < N is
-        accumulated into it (the filter sum, t0 = 0)."""
+        optionally multiplied by ramp(t_n).  If U_acc is given (one array per component),
+        u^n e^{i m w t_n} for n < N is accumulated into U_acc[c] (the filter sums, t0 = 0)."""
         dt, beta, R = self.dt, self.beta, self.free
         amp = (lambda t: 1.0) if ramp is None else ramp
         if not forced:
@@ -158,19 +176,23 @@ class F2:
         else:
             F = lambda n: amp(t0 + n * dt) * self.load(t0 + n * dt)
         # values on the Dirichlet nodes at t_n (zero unless forced with data)
-        if forced and self.gD is not None:
-            dirichlet = lambda n: amp(t0 + n * dt) * (self.gD * np.exp(-1j * self.omega * (t0 + n * dt))).real
+        if forced and self.has_gD:
+            dirichlet = lambda n: amp(t0 + n * dt) * self.dirichlet_value(t0 + n * dt)
         else:
             dirichlet = lambda n: 0.0
+
+        def accumulate(u, n):
+            for c, (m, _, _, _) in enumerate(self.comps):
+                U_acc[c] += u * np.exp(1j * m * self.omega * n * dt)
         u0 = R * z[: self.nn].reshape(self.shape) + dirichlet(0)
         v0 = R * z[self.nn:].reshape(self.shape)
         um = u0
         u = R * (u0 + dt * (1.0 - beta) * v0 - 0.5 * self._accel(u0, F(0))) + dirichlet(1)
         if U_acc is not None:
-            U_acc += um
+            accumulate(um, 0)
         for n in range(1, self.N + 1):
             if U_acc is not None and n < self.N:
-                U_acc += u * np.exp(1j * self.omega * n * dt)
+                accumulate(u, n)
             up = R * ((2.0 * u - (1.0 - beta) * um - self._accel(u, F(n))) / (1.0 + beta)) \
                 + dirichlet(n + 1)
             if n == self.N:
@@ -284,10 +306,13 @@ class F2:
                           z0=z0, record=record, delta_ref=ref)
 
     def filter(self, z: np.ndarray) -> np.ndarray:
-        """U = (2/N) sum_{n<N} u^n e^{i w t_n} over one forced period from z."""
-        U = np.zeros(self.shape, complex)
+        """U = (2/N) sum_{n<N} u^n e^{i w t_n} over one forced period from z.  With several
+        components, one such sum per component at its frequency m w over the same period,
+        stacked (shape (components,) + node shape)."""
+        U = [np.zeros(self.shape, complex) for _ in self.comps]
         self.period(z, True, U_acc=U)
-        return 2.0 * U / self.N
+        U = [2.0 * Uc / self.N for Uc in U]
+        return U[0] if len(U) == 1 else np.stack(U)
 
     def step6_output(self, z: np.ndarray) -> np.ndarray:
         """The paper's Step 6 output u = v_0 + (i / omega) v_1."""
@@ -301,26 +326,32 @@ class F2:
         """Direct sparse solve of [S - wt^2 M - i wh B] U = Fhat on the free nodes with
         wt = (2/dt) sin(w dt / 2), wh = sin(w dt) / dt, Fhat = w f + sum over faces (face
         weight) g, and U = gD on the Dirichlet nodes.  Returns (U, z_periodic) with
-        z = (Re U, wh Im U) on the free nodes."""
+        z = (Re U, wh Im U) on the free nodes.  With several components: one solve per
+        component at its frequency m omega (same dt), U stacked per component and z the sum
+        of the components' periodic states (the scheme is linear)."""
         dt = self.dt
-        wt2 = (2.0 / dt * math.sin(0.5 * self.omega * dt)) ** 2
-        wh = math.sin(self.omega * dt) / dt
         S = self.stiffness_matrix()
-        A = (S - wt2 * sp.diags(self.M.ravel()) - 1j * wh * sp.diags(self.B.ravel())).tocsr()
-        Fh = self.w * self.f
-        if self.g is not None:
-            for idx, (sel, fw) in enumerate(self.face_w):
-                Fh[sel] += fw * self.g[idx].reshape(fw.shape)
         free = np.flatnonzero(self.free.ravel() > 0.5)
-        U = np.zeros(self.nn, complex)
-        rhs = Fh.ravel()[free]
-        if self.gD is not None:
-            # Dirichlet values are known: move their couplings to the right-hand side
-            dnodes = np.flatnonzero(self.free.ravel() < 0.5)
-            gd = self.gD.ravel()[dnodes]
-            rhs = rhs - A[free][:, dnodes] @ gd
-            U[dnodes] = gd
-        U[free] = spla.spsolve(A[free][:, free].tocsc(), rhs)
         R = self.free.ravel()
-        z = np.concatenate([R * U.real, R * wh * U.imag])
-        return U.reshape(self.shape), z
+        Us, z = [], np.zeros(self.size)
+        for m, f, g, gD in self.comps:
+            w = m * self.omega
+            wt2 = (2.0 / dt * math.sin(0.5 * w * dt)) ** 2
+            wh = math.sin(w * dt) / dt
+            A = (S - wt2 * sp.diags(self.M.ravel()) - 1j * wh * sp.diags(self.B.ravel())).tocsr()
+            Fh = self.w * f
+            if g is not None:
+                for idx, (sel, fw) in enumerate(self.face_w):
+                    Fh[sel] += fw * g[idx].reshape(fw.shape)
+            U = np.zeros(self.nn, complex)
+            rhs = Fh.ravel()[free]
+            if gD is not None:
+                # Dirichlet values are known: move their couplings to the right-hand side
+                dnodes = np.flatnonzero(self.free.ravel() < 0.5)
+                gd = gD.ravel()[dnodes]
+                rhs = rhs - A[free][:, dnodes] @ gd
+                U[dnodes] = gd
+            U[free] = spla.spsolve(A[free][:, free].tocsc(), rhs)
+            z = z + np.concatenate([R * U.real, R * wh * U.imag])
+            Us.append(U.reshape(self.shape))
+        return (Us[0] if len(Us) == 1 else np.stack(Us)), z

@@ -40,7 +40,7 @@ def test_dispersion_closed_form(n, modes):
     th = 2 * math.asin(math.sqrt(lam))
     z = np.concatenate([mode.ravel(), np.zeros(mode.size)])
     U = np.zeros(mode.shape, complex)
-    out = s.period(z, False, U_acc=U)
+    out = s.period(z, False, U_acc=[U])
     ref_U = sum(math.cos(k * th) * np.exp(1j * s.omega * k * s.dt) for k in range(s.N))
     assert np.max(np.abs(U - ref_U * mode)) < 1e-11
     assert np.max(np.abs(out[: s.nn] - math.cos(s.N * th) * mode.ravel())) < 1e-12
