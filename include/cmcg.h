@@ -59,6 +59,21 @@ typedef enum {
 enum { CMCG_ABSORBING = 0, CMCG_NEUMANN = 1 };
 enum { CMCG_FP64 = 0, CMCG_FP32_MIXED = 1 };
 
+#define CMCG_MAX_SHOTS 8
+
+/* One component of a multi-frequency ("super-shot") source (Concluding remarks): a source that
+ * superposes time-harmonic components at integer multiples of one base frequency omega has the
+ * common period T = 2 pi / omega, so one CMCG solve finds its periodic solution and the filter
+ * at each component's frequency extracts that component's Helmholtz solution.  The arrays have
+ * the layouts of the cmcg_problem fields of the same names and the same NULL rules. */
+typedef struct {
+  int32_t harmonic;            /* m >= 1: the component oscillates as e^{-i m omega t}; the
+                                  harmonics of a problem are distinct and 2 m < N              */
+  const double *f_re, *f_im;
+  const double *gS_re, *gS_im;
+  const double *gD_re, *gD_im;
+} cmcg_shot;
+
 typedef struct {
   int32_t dim;                 /* 2 (F1) or 3 (F2)                                           */
   int32_t formulation;         /* 1 = first-order staggered, 2 = second-order nodal           */
@@ -75,6 +90,14 @@ typedef struct {
                                   c, read on those nodes only); NULL = homogeneous              */
   int32_t face_bc[6];          /* -x,+x,-y,+y,-z,+z: CMCG_ABSORBING or CMCG_NEUMANN            */
   double courant;              /* sigma in (0, 1/sqrt(dim)); 0 -> 0.5                          */
+  int32_t n_shots;             /* 0: one time-harmonic source at omega with the data above.
+                                  1..CMCG_MAX_SHOTS: the source is the sum of `shots`, omega is
+                                  their base frequency (T = 2 pi / omega, N from T as above),
+                                  and f, gS and gD above must be NULL.  The filter outputs
+                                  (cmcg_solve, cmcg_finish, cmcg_filter) then hold n_shots
+                                  fields, one per shot in shot order, each of field_len values;
+                                  the first-order field is u = i V / (m omega).                */
+  const cmcg_shot *shots;      /* n_shots components (copied at create), or NULL               */
 } cmcg_problem;
 
 typedef struct {
@@ -131,7 +154,8 @@ cmcg_status cmcg_create(const cmcg_problem *problem, const cmcg_options *opts, c
 /* Full CMCG solve from z = 0 (Steps 1-6) followed by the fundamental-frequency filter
  * (eq. fundamental-frequency-solution for F2, eq. TH_FILTERED_MIXED_SOLUTION for F1).
  * u_re, u_im: caller-allocated, host or device, same layout as c (either may be NULL to skip
- * the copy).  May be called repeatedly.  Returns CMCG_ENOTCONV when max_iter is reached. */
+ * the copy), n_fields such fields back to back (cmcg_info).  May be called repeatedly.
+ * Returns CMCG_ENOTCONV when max_iter is reached. */
 cmcg_status cmcg_solve(cmcg_handle *h, double *u_re, double *u_im, cmcg_report *rep);
 
 /* NULL-safe. */
@@ -149,6 +173,7 @@ typedef struct {
   int64_t state_len;           /* length of a packed state vector                             */
   int64_t field_len;           /* length of the output field u                                */
   int64_t device_bytes;        /* device memory held by the handle                            */
+  int32_t n_fields;            /* fields written by the filter outputs: n_shots, or 1          */
 } cmcg_info;
 
 cmcg_status cmcg_get_info(const cmcg_handle *h, cmcg_info *info);
@@ -170,7 +195,8 @@ cmcg_status cmcg_apply(cmcg_handle *h, int32_t op, int32_t steps, const double *
 
 /* Filter output from an explicit initial state z (packed FP64 device vector): one forced period
  * from z with the accumulation of eq. fundamental-frequency-solution / eq.
- * TH_FILTERED_MIXED_SOLUTION.  u_re, u_im: host or device, layout of c. */
+ * TH_FILTERED_MIXED_SOLUTION (one accumulation per shot, at its frequency).  u_re, u_im: host
+ * or device, n_fields fields of the layout of c. */
 cmcg_status cmcg_filter(cmcg_handle *h, const double *z, double *u_re, double *u_im);
 
 /* The solve split in three: cmcg_begin (z = 0, Steps 1-4), cmcg_iterate (up to `iters` CG
@@ -217,7 +243,9 @@ enum { CMCG_REQ_QUEUED = 0, CMCG_REQ_RUNNING = 1, CMCG_REQ_DONE = 2, CMCG_REQ_FA
 
 cmcg_status cmcg_server_create(const cmcg_server_options *opts, cmcg_server **out);
 /* Copies the problem's host arrays; the request starts queued.  opts->precision, tol and
- * max_iter apply to this solve; its stream is the server's.  *id identifies it in poll. */
+ * max_iter apply to this solve; its stream is the server's.  *id identifies it in poll.
+ * Served solves start from rest and have a single-frequency source (CMCG_EUNSUPPORTED for a
+ * run-up or shots). */
 cmcg_status cmcg_server_submit(cmcg_server *s, const cmcg_problem *p, const cmcg_options *opts,
                                int64_t *id);
 /* One tick: admit what fits, advance running solves, finish converged ones.  Optional counts. */

@@ -31,13 +31,22 @@ OP_FORWARD, OP_FORCED, OP_ADJOINT, OP_RIESZ = 0, 1, 2, 3
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
+MAX_SHOTS = 8
+
+
+class _Shot(ctypes.Structure):
+    _fields_ = [("harmonic", ctypes.c_int32), ("f_re", _dp), ("f_im", _dp),
+                ("gS_re", _dp), ("gS_im", _dp), ("gD_re", _dp), ("gD_im", _dp)]
+
+
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("formulation", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("omega", ctypes.c_double),
                 ("c", _dp), ("c_const", ctypes.c_double),
                 ("f_re", _dp), ("f_im", _dp), ("gS_re", _dp), ("gS_im", _dp),
                 ("sound_soft", ctypes.POINTER(ctypes.c_uint8)), ("gD_re", _dp), ("gD_im", _dp),
-                ("face_bc", ctypes.c_int32 * 6), ("courant", ctypes.c_double)]
+                ("face_bc", ctypes.c_int32 * 6), ("courant", ctypes.c_double),
+                ("n_shots", ctypes.c_int32), ("shots", ctypes.POINTER(_Shot))]
 
 
 class _Options(ctypes.Structure):
@@ -62,7 +71,8 @@ class _Report(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("steps_per_period", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("T", ctypes.c_double), ("h", ctypes.c_double), ("state_len", ctypes.c_int64),
-                ("field_len", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("field_len", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("n_fields", ctypes.c_int32)]
 
 
 class _ServerOptions(ctypes.Structure):
@@ -163,7 +173,10 @@ class Solver:
         info = _Info()
         _check(_lib.cmcg_get_info(h, ctypes.byref(info)), "cmcg_get_info")
         self.info = {k: getattr(info, k) for k, _ in _Info._fields_}
-        self.field_shape = problem.field_shape()
+        # with several shots, the outputs stack one field per shot
+        shots = getattr(problem, "shots", None)
+        self.field_shape = ((len(shots),) if shots and len(shots) > 1 else ()) + \
+            tuple(problem.field_shape())
 
     # ------------------------------------------------------------------ lifetime
     def close(self):
@@ -185,8 +198,9 @@ class Solver:
 
     # ------------------------------------------------------------------ solve
     def solve(self, device_output: bool = False) -> Tuple[object, dict]:
-        """Full CMCG solve; returns (u, report).  u is a complex NumPy array of the field shape,
-        or a pair of torch FP64 device tensors (re, im) if device_output."""
+        """Full CMCG solve; returns (u, report).  u is a complex NumPy array of the field shape
+        (with several shots: one field per shot, stacked on a leading axis), or a pair of torch
+        FP64 device tensors (re, im) if device_output."""
         rep = _Report()
         ure, uim, keep = self._out_buffers(device_output)
         st = _check(_lib.cmcg_solve(self._h, ure, uim, ctypes.byref(rep)), "cmcg_solve",
@@ -299,24 +313,39 @@ def marshal_problem(problem):
     if problem.c is not None:
         p.c = _ptr(arr(problem.c))
     p.c_const = float(problem.c_const)
-    if problem.f is not None:
-        f = np.asarray(problem.f)
-        p.f_re = _ptr(arr(f.real))
-        if np.iscomplexobj(f) and np.any(f.imag != 0):
-            p.f_im = _ptr(arr(f.imag))
-    if problem.gS is not None:
-        g = _concat_faces(problem.gS, np.complex128)
-        p.gS_re = _ptr(arr(g.real))
-        if np.any(g.imag != 0):
-            p.gS_im = _ptr(arr(g.imag))
+
+    def data(dst, f, gS, gD):
+        # source, boundary and Dirichlet data into a _Problem or _Shot (imaginary parts only
+        # when non-zero)
+        if f is not None:
+            f = np.asarray(f)
+            dst.f_re = _ptr(arr(f.real))
+            if np.iscomplexobj(f) and np.any(f.imag != 0):
+                dst.f_im = _ptr(arr(f.imag))
+        if gS is not None:
+            g = _concat_faces(gS, np.complex128)
+            dst.gS_re = _ptr(arr(g.real))
+            if np.any(g.imag != 0):
+                dst.gS_im = _ptr(arr(g.imag))
+        if gD is not None:
+            d = np.asarray(gD, dtype=np.complex128)
+            dst.gD_re = _ptr(arr(d.real))
+            if np.any(d.imag != 0):
+                dst.gD_im = _ptr(arr(d.imag))
+
+    data(p, problem.f, problem.gS, getattr(problem, "gD", None))
+    shots = getattr(problem, "shots", None)
+    if shots:
+        table = (_Shot * len(shots))()
+        for k, sh in enumerate(shots):
+            table[k].harmonic = int(sh.harmonic)
+            data(table[k], sh.f, sh.gS, sh.gD)
+        keep.append(table)
+        p.n_shots = len(shots)
+        p.shots = ctypes.cast(table, ctypes.POINTER(_Shot))
     if problem.sound_soft is not None:
         m = arr(problem.sound_soft, np.uint8)
         p.sound_soft = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-    if getattr(problem, "gD", None) is not None:
-        d = np.asarray(problem.gD, dtype=np.complex128)
-        p.gD_re = _ptr(arr(d.real))
-        if np.any(d.imag != 0):
-            p.gD_im = _ptr(arr(d.imag))
     bc = list(problem.face_bc) + [1] * 6
     for k in range(6):
         p.face_bc[k] = int(bc[k])

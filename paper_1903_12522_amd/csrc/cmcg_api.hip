@@ -49,9 +49,23 @@ cmcg_status validate_problem(const cmcg_problem *P, const cmcg_options *O) {
   if (!((P->dim == 2 && P->formulation == 1) || (P->dim == 3 && P->formulation == 2)))
     return set_error("supported: dim 2 with formulation 1, dim 3 with formulation 2"),
            CMCG_EUNSUPPORTED;
-  if ((P->gD_re || P->gD_im) && (P->formulation != 2 || !P->sound_soft))
-    return set_error("Dirichlet data needs the nodal formulation and a sound-soft mask"),
-           CMCG_EINVAL;
+  if (P->n_shots < 0 || P->n_shots > CMCG_MAX_SHOTS)
+    return set_error("n_shots must be in 0..CMCG_MAX_SHOTS"), CMCG_EINVAL;
+  if (P->n_shots > 0) {
+    if (!P->shots) return set_error("n_shots > 0 needs the shots array"), CMCG_EINVAL;
+    if (P->f_re || P->f_im || P->gS_re || P->gS_im || P->gD_re || P->gD_im)
+      return set_error("with shots, the source and boundary data go in the shots"), CMCG_EINVAL;
+    for (int j = 0; j < P->n_shots; ++j) {
+      if (P->shots[j].harmonic < 1) return set_error("shot harmonics must be >= 1"), CMCG_EINVAL;
+      for (int k = 0; k < j; ++k)
+        if (P->shots[k].harmonic == P->shots[j].harmonic)
+          return set_error("shot harmonics must be distinct"), CMCG_EINVAL;
+    }
+  }
+  for (const cmcg_shot &sh : shots_of(P))
+    if ((sh.gD_re || sh.gD_im) && (P->formulation != 2 || !P->sound_soft))
+      return set_error("Dirichlet data needs the nodal formulation and a sound-soft mask"),
+             CMCG_EINVAL;
   if (O->runup_periods > 0) {
     // a closed box without absorption or Dirichlet nodes drifts linearly under a source with
     // non-zero mean (the eta mode of Sec. 2.2), which the run-up start would carry into CG
@@ -98,6 +112,16 @@ cmcg_status make_config(const cmcg_problem *P, const cmcg_options *O, hipStream_
   // integer number of leapfrog steps per period, c_max dt / h <= sigma
   cfg->N = std::max(3, (int)std::ceil(cfg->T * cmax / (sigma * cfg->h)));
   cfg->dt = cfg->T / cfg->N;
+  const std::vector<cmcg_shot> shots = shots_of(P);
+  cfg->nshots = (int)shots.size();
+  for (int j = 0; j < cfg->nshots; ++j) {
+    cfg->harmonic[j] = shots[j].harmonic;
+    // the filters of distinct harmonics m < N / 2 are orthogonal over the N steps of a period
+    if (2 * (int64_t)shots[j].harmonic >= cfg->N)
+      return set_error("shot harmonic m needs more than 2 m leapfrog steps per base period (N = " +
+                       std::to_string(cfg->N) + ")"),
+             CMCG_EINVAL;
+  }
   return CMCG_OK;
 }
 

@@ -70,6 +70,45 @@ __global__ void f1_output_kernel(const double *ure, const double *uim, double sc
   }
 }
 
+// Weights (c, s)_j of the components at one time: amp (cos, sin)(m_j omega t), amp the ramp.
+struct ShotWeights {
+  int nshots = 0;
+  double c[CMCG_MAX_SHOTS] = {}, s[CMCG_MAX_SHOTS] = {};
+};
+
+// Source field of one step of a multi-frequency forced period: sum_j (Fre_j c_j + Fim_j s_j) at
+// the step's source time (h Fhat summed over the components), which the streaming kernel then
+// reads with weight 1 as it reads a single component's field.
+template <typename T>
+__global__ void f1_combine_kernel(const T *Fre, const T *Fim, ShotWeights w, T *out, size_t fs) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < CMCG_MAX_SHOTS; ++j) {
+      if (j >= w.nshots) break;
+      a = fma((double)Fre[j * fs + o], w.c[j], a);
+      if (Fim) a = fma((double)Fim[j * fs + o], w.s[j], a);
+    }
+    out[o] = (T)a;
+  }
+}
+
+// Filter sums of a multi-frequency problem at one step: (Ure_j, Uim_j) += v (cos, sin)(m_j w t_n)
+__global__ void f1_accumulate_kernel(const double *v, ShotWeights w, double *ure, double *uim,
+                                     size_t fs) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
+    const double x = v[o];
+#pragma unroll
+    for (int j = 0; j < CMCG_MAX_SHOTS; ++j) {
+      if (j >= w.nshots) break;
+      ure[j * fs + o] += x * w.c[j];
+      uim[j * fs + o] += x * w.s[j];
+    }
+  }
+}
+
 // Riesz map of the first-order formulation, M_E^{-1} y (the control space is L^2): faces 1/h^2,
 // cells c^2 / h^2 = kap / (h dt)
 template <typename T>
@@ -84,11 +123,12 @@ __global__ void f1_riesz_kernel(F1Geom g, T *y, const T *cc, size_t fs) {
 }
 
 // One precision's working set: two ping-pong states, the period output w and the backward
-// output q, and the coefficient and forcing fields.
+// output q, the coefficient field, the forcing fields (one pair per source component) and, with
+// several components, the summed source field of one step.
 struct F1Set {
   int prec = CMCG_FP64;
   void *S0 = nullptr, *S1 = nullptr, *W = nullptr, *Q = nullptr;
-  void *cc = nullptr, *Fre = nullptr, *Fim = nullptr;
+  void *cc = nullptr, *Fre = nullptr, *Fim = nullptr, *Fk = nullptr;
 };
 
 template <typename T>
@@ -107,9 +147,10 @@ class F1Solver final : public Solver {
   F1Set lo, hi;          // lo: precision of the CG periods; hi: FP64 (the same set in FP64 mode)
   bool mixed = false;
   void *D = nullptr;     // search direction, lo precision
-  double *Z = nullptr, *R = nullptr, *Ure = nullptr, *Uim = nullptr;
+  double *Z = nullptr, *R = nullptr, *Ure = nullptr, *Uim = nullptr;   // filter sums: nshots fields
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
   bool started = false;
+  bool multi = false;    // several source components: per-step source fields, separate filter sums
   int iter = 0, refreshes = 0, last_refresh = 0, runup_done = 0;
   double rel = 1.0, delta_at_refresh = 0.0;
   double t_fwd = 0, t_adj = 0, t_other = 0, t_total = 0, t_runup = 0, updates = 0;
@@ -137,49 +178,56 @@ class F1Solver final : public Solver {
     fs = (size_t)ny * g.pitch;
     vecN = 3 * fs;
     mixed = cfg.prec == CMCG_FP32_MIXED;
+    const std::vector<cmcg_shot> shots = shots_of(P);
+    const int J = (int)shots.size();
+    multi = J > 1;
     CMCG_TRY(ev.init(10));
     CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
     std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
-    const bool has_im = P->f_im || P->gS_im;
-    CMCG_TRY(alloc_set(hi, CMCG_FP64, has_im));
+    bool has_im = false;
+    for (const cmcg_shot &sh : shots) has_im = has_im || sh.f_im || sh.gS_im;
+    CMCG_TRY(alloc_set(hi, CMCG_FP64, has_im, J));
     if (mixed) {
-      CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, has_im));
+      CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, has_im, J));
     } else {
       lo = hi;
     }
     CMCG_TRY(arena.alloc(vecN * (mixed ? sizeof(float) : sizeof(double)), &D, s));
     CMCG_TRY(arena.alloc_n(vecN, &Z, s));
     CMCG_TRY(arena.alloc_n(vecN, &R, s));
-    CMCG_TRY(arena.alloc_n(fs, &Ure, s));
-    CMCG_TRY(arena.alloc_n(fs, &Uim, s));
+    CMCG_TRY(arena.alloc_n(J * fs, &Ure, s));
+    CMCG_TRY(arena.alloc_n(J * fs, &Uim, s));
     CMCG_TRY(arena.alloc_n(kRedBlocks, &partials, s));
     CMCG_TRY(arena.alloc_n(kNumScalars, &scalars, s));
-    // host inputs -> temporary device copies -> setup kernels for each set
+    // host inputs -> temporary device copies -> setup kernels for each set and component
     const size_t ncell = (size_t)nx * ny, nface = 2 * (size_t)ny + 2 * (size_t)nx;
-    DeviceArena tmp;
-    const double *src[5] = {P->c, P->f_re, P->f_im, P->gS_re, P->gS_im};
-    const size_t len[5] = {ncell, ncell, ncell, nface, nface};
-    double *dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    for (int k = 0; k < 5; ++k) {
-      if (!src[k]) continue;
-      CMCG_TRY(tmp.alloc_n(len[k], &dev[k], s));
-      CMCG_HIP(hipMemcpyAsync(dev[k], src[k], len[k] * sizeof(double), hipMemcpyHostToDevice, s));
-    }
-    hipLaunchKernelGGL((f1_setup_kernel<double>), dim3(grid_for(fs)), dim3(256), 0, s, g, dev[0],
-                       P->c_const, dev[1], dev[2], dev[3], dev[4], tp<double>(hi.cc),
-                       tp<double>(hi.Fre), tp<double>(hi.Fim), fs);
-    CMCG_HIP(hipGetLastError());
-    if (mixed) {
-      hipLaunchKernelGGL((f1_setup_kernel<float>), dim3(grid_for(fs)), dim3(256), 0, s, g, dev[0],
-                         P->c_const, dev[1], dev[2], dev[3], dev[4], tp<float>(lo.cc),
-                         tp<float>(lo.Fre), tp<float>(lo.Fim), fs);
+    for (int j = 0; j < J; ++j) {
+      DeviceArena tmp;
+      const double *src[5] = {P->c, shots[j].f_re, shots[j].f_im, shots[j].gS_re, shots[j].gS_im};
+      const size_t len[5] = {ncell, ncell, ncell, nface, nface};
+      double *dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+      for (int k = 0; k < 5; ++k) {
+        if (!src[k]) continue;
+        CMCG_TRY(tmp.alloc_n(len[k], &dev[k], s));
+        CMCG_HIP(hipMemcpyAsync(dev[k], src[k], len[k] * sizeof(double), hipMemcpyHostToDevice, s));
+      }
+      const size_t off = (size_t)j * fs;
+      hipLaunchKernelGGL((f1_setup_kernel<double>), dim3(grid_for(fs)), dim3(256), 0, s, g, dev[0],
+                         P->c_const, dev[1], dev[2], dev[3], dev[4], tp<double>(hi.cc),
+                         tp<double>(hi.Fre) + off, hi.Fim ? tp<double>(hi.Fim) + off : nullptr, fs);
       CMCG_HIP(hipGetLastError());
+      if (mixed) {
+        hipLaunchKernelGGL((f1_setup_kernel<float>), dim3(grid_for(fs)), dim3(256), 0, s, g,
+                           dev[0], P->c_const, dev[1], dev[2], dev[3], dev[4], tp<float>(lo.cc),
+                           tp<float>(lo.Fre) + off, lo.Fim ? tp<float>(lo.Fim) + off : nullptr, fs);
+        CMCG_HIP(hipGetLastError());
+      }
+      CMCG_HIP(hipStreamSynchronize(s));
     }
-    CMCG_HIP(hipStreamSynchronize(s));
     return CMCG_OK;
   }
 
-  cmcg_status alloc_set(F1Set &b, int prec, bool has_im) {
+  cmcg_status alloc_set(F1Set &b, int prec, bool has_im, int J) {
     const size_t esz = prec == CMCG_FP64 ? sizeof(double) : sizeof(float);
     b.prec = prec;
     CMCG_TRY(arena.alloc(vecN * esz, &b.S0, s));
@@ -187,8 +235,9 @@ class F1Solver final : public Solver {
     CMCG_TRY(arena.alloc(vecN * esz, &b.W, s));
     CMCG_TRY(arena.alloc(vecN * esz, &b.Q, s));
     CMCG_TRY(arena.alloc(fs * esz, &b.cc, s));
-    CMCG_TRY(arena.alloc(fs * esz, &b.Fre, s));
-    if (has_im) CMCG_TRY(arena.alloc(fs * esz, &b.Fim, s));
+    CMCG_TRY(arena.alloc(J * fs * esz, &b.Fre, s));
+    if (has_im) CMCG_TRY(arena.alloc(J * fs * esz, &b.Fim, s));
+    if (J > 1) CMCG_TRY(arena.alloc(fs * esz, &b.Fk, s));
     return CMCG_OK;
   }
 
@@ -208,22 +257,25 @@ class F1Solver final : public Solver {
     L.first = (n0 == 0);
     L.last = lastl;
     L.forced = forced ? 1 : 0;
-    L.accumulate = filter ? 1 : 0;
+    // several components: forced launches take one step each and read the field that
+    // `combine` writes for it (weight 1); the filter sums run in `f1_accumulate_kernel`
+    L.accumulate = (filter && !multi) ? 1 : 0;
+    const double w0 = cfg.omega_of(0);
     for (int k = 0; k < ns; ++k) {
       const double t = (n0 + k + 0.5) * cfg.dt;      // source at t_{n+1/2}
       const double amp = transient(t_offset + t, t_tr);
-      L.cs[k] = amp * std::cos(cfg.omega * t);
-      L.sn[k] = amp * std::sin(cfg.omega * t);
+      L.cs[k] = multi ? 1.0 : amp * std::cos(w0 * t);
+      L.sn[k] = multi ? 0.0 : amp * std::sin(w0 * t);
     }
-    L.fcos = std::cos(cfg.omega * n0 * cfg.dt);       // filter weight at t_n
-    L.fsin = std::sin(cfg.omega * n0 * cfg.dt);
+    L.fcos = std::cos(w0 * n0 * cfg.dt);              // filter weight at t_n
+    L.fsin = std::sin(w0 * n0 * cfg.dt);
     F1Ptrs<T> p{};
     p.in = (l == 0) ? in : S[(l - 1) & 1];
     p.out = lastl ? out : S[l & 1];
     p.sub = lastl ? sub : nullptr;
     p.cc = tp<T>(b.cc);
-    p.fre = tp<T>(b.Fre);
-    p.fim = tp<T>(b.Fim);
+    p.fre = multi ? tp<T>(b.Fk) : tp<T>(b.Fre);
+    p.fim = multi ? nullptr : tp<T>(b.Fim);
     p.ure = Ure;
     p.uim = Uim;
     p.fs = fs;
@@ -232,14 +284,62 @@ class F1Solver final : public Solver {
     return ns;
   }
 
+  // Weights of the components at step n: the source at t_{n+1/2} (ramped) if `source`, else
+  // the filter weight at t_n.
+  ShotWeights shot_weights(int n, bool source) const {
+    ShotWeights w;
+    w.nshots = cfg.nshots;
+    const double t = source ? (n + 0.5) * cfg.dt : n * cfg.dt;
+    const double amp = source ? transient(t_offset + t, t_tr) : 1.0;
+    for (int j = 0; j < cfg.nshots; ++j) {
+      w.c[j] = amp * std::cos(cfg.omega_of(j) * t);
+      w.s[j] = amp * std::sin(cfg.omega_of(j) * t);
+    }
+    return w;
+  }
+
+  // u = i V / (m omega) with V = (2/N) (Ure + i Uim) for each component, staged in `stage` (two
+  // fields) and copied to the caller's n_fields output fields
+  cmcg_status output_fields(double *stage, double *u_re, double *u_im) {
+    double *ore = stage, *oim = stage + fs;
+    const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
+    const size_t flen = (size_t)g.nx * g.ny;
+    for (int j = 0; j < cfg.nshots; ++j) {
+      hipLaunchKernelGGL(f1_output_kernel, dim3(grid_for(fs)), dim3(256), 0, s, Ure + j * fs,
+                         Uim + j * fs, 2.0 / (cfg.N * cfg.omega_of(j)), ore, oim, fs);
+      CMCG_HIP(hipGetLastError());
+      if (u_re)
+        CMCG_HIP(hipMemcpy2DAsync(u_re + j * flen, row, ore, pitchb, row, g.ny, hipMemcpyDefault, s));
+      if (u_im)
+        CMCG_HIP(hipMemcpy2DAsync(u_im + j * flen, row, oim, pitchb, row, g.ny, hipMemcpyDefault, s));
+    }
+    return CMCG_OK;
+  }
+
   template <typename T>
   cmcg_status period_t(const F1Set &b, bool adjoint, bool forced, const T *in, T *out, const T *sub,
                        int steps, bool filter) {
-    const int K = filter ? 1 : cfg.kblock;
+    // the filter accumulates every step's state, and a multi-frequency source is summed per
+    // step: such periods take one step per launch
+    const int K = (filter || (multi && forced)) ? 1 : cfg.kblock;
+    if (multi && filter && !std::is_same<T, double>::value)
+      return set_error("the filter period runs in FP64"), CMCG_EINVAL;
     for (int n0 = 0; n0 < steps;) {
       F1Ptrs<T> p;
       F1Launch L;
       const int ns = build_launch<T>(b, forced, in, out, sub, steps, n0, K, filter, &p, &L);
+      if (multi && forced) {
+        hipLaunchKernelGGL((f1_combine_kernel<T>), dim3(grid_for(fs)), dim3(256), 0, s,
+                           tpc<T>(b.Fre), tpc<T>(b.Fim), shot_weights(n0, true), tp<T>(b.Fk), fs);
+        CMCG_HIP(hipGetLastError());
+      }
+      if (multi && filter) {
+        // v^n of the launch's input state
+        hipLaunchKernelGGL(f1_accumulate_kernel, dim3(grid_for(fs)), dim3(256), 0, s,
+                           reinterpret_cast<const double *>(p.in) + 2 * fs,
+                           shot_weights(n0, false), Ure, Uim, fs);
+        CMCG_HIP(hipGetLastError());
+      }
       CMCG_HIP(adjoint ? f1_adjoint_launch<T>(g, p, L, K, s) : f1_forward_launch<T>(g, p, L, K, s));
       n0 += ns;
     }
@@ -394,17 +494,11 @@ class F1Solver final : public Solver {
   }
 
   cmcg_status filter_from_hi(const double *z, double *u_re, double *u_im) {
-    CMCG_HIP(hipMemsetAsync(Ure, 0, fs * sizeof(double), s));
-    CMCG_HIP(hipMemsetAsync(Uim, 0, fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Ure, 0, cfg.nshots * fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Uim, 0, cfg.nshots * fs * sizeof(double), s));
     CMCG_TRY(period(hi, false, true, z, hi.Q, nullptr, cfg.N, true));
-    double *ore = tp<double>(hi.W), *oim = tp<double>(hi.W) + fs;
-    hipLaunchKernelGGL(f1_output_kernel, dim3(grid_for(fs)), dim3(256), 0, s, Ure, Uim,
-                       2.0 / (cfg.N * cfg.omega), ore, oim, fs);
-    CMCG_HIP(hipGetLastError());
     CMCG_HIP(hipEventRecord(ev[6], s));
-    const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
-    if (u_re) CMCG_HIP(hipMemcpy2DAsync(u_re, row, ore, pitchb, row, g.ny, hipMemcpyDefault, s));
-    if (u_im) CMCG_HIP(hipMemcpy2DAsync(u_im, row, oim, pitchb, row, g.ny, hipMemcpyDefault, s));
+    CMCG_TRY(output_fields(tp<double>(hi.W), u_re, u_im));
     CMCG_HIP(hipStreamSynchronize(s));
     return CMCG_OK;
   }
@@ -455,16 +549,10 @@ class F1Solver final : public Solver {
   cmcg_status filter(const double *z, double *u_re, double *u_im) override {
     // the period reads its input only in its first launch and never writes hi.W
     CMCG_HIP(f1_unpack<double>(g, z, tp<double>(hi.W), fs, s));
-    CMCG_HIP(hipMemsetAsync(Ure, 0, fs * sizeof(double), s));
-    CMCG_HIP(hipMemsetAsync(Uim, 0, fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Ure, 0, cfg.nshots * fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Uim, 0, cfg.nshots * fs * sizeof(double), s));
     CMCG_TRY(period(hi, false, true, hi.W, hi.Q, nullptr, cfg.N, true));
-    double *ore = tp<double>(hi.S1), *oim = tp<double>(hi.S1) + fs;
-    hipLaunchKernelGGL(f1_output_kernel, dim3(grid_for(fs)), dim3(256), 0, s, Ure, Uim,
-                       2.0 / (cfg.N * cfg.omega), ore, oim, fs);
-    CMCG_HIP(hipGetLastError());
-    const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
-    if (u_re) CMCG_HIP(hipMemcpy2DAsync(u_re, row, ore, pitchb, row, g.ny, hipMemcpyDefault, s));
-    if (u_im) CMCG_HIP(hipMemcpy2DAsync(u_im, row, oim, pitchb, row, g.ny, hipMemcpyDefault, s));
+    CMCG_TRY(output_fields(tp<double>(hi.S1), u_re, u_im));
     CMCG_HIP(hipStreamSynchronize(s));
     return CMCG_OK;
   }
@@ -523,6 +611,7 @@ class F1Solver final : public Solver {
     i->state_len = ny * (nx - 1) + (ny - 1) * nx + nx * ny;
     i->field_len = nx * ny;
     i->device_bytes = (int64_t)arena.bytes();
+    i->n_fields = cfg.nshots;
   }
 };
 
@@ -626,6 +715,9 @@ class F1Server final : public Server {
       return set_error("the server batches first-order 2D solves"), CMCG_EUNSUPPORTED;
     if (O->runup_periods > 0)
       return set_error("the server starts every solve from rest (runup_periods must be 0)"),
+             CMCG_EUNSUPPORTED;
+    if (P->n_shots > 0)
+      return set_error("the server takes single-frequency sources (n_shots must be 0)"),
              CMCG_EUNSUPPORTED;
     auto *R = new ServeRequest();
     R->id = next_id++;

@@ -9,6 +9,8 @@
 // Precision policy as in the first-order solver: FP32-mixed runs the CG periods in FP32 and
 // refreshes the true gradient with FP64 periods (reliable updates); z, residuals, the Riesz solve
 // and every reduction are FP64.
+#include <type_traits>
+
 #include "f2_internal.h"
 #include "solver.h"
 
@@ -59,16 +61,81 @@ __global__ void f2_output_kernel(F2Geom g, const double *ure, const double *uim,
   }
 }
 
+// Weights of the source components at one time: (c, s)_j = amp (cos, sin)(m_j omega t).
+struct ShotPhase {
+  double c[CMCG_MAX_SHOTS] = {}, s[CMCG_MAX_SHOTS] = {};
+};
+
+// Per-step fields of a multi-frequency forced sweep: the load sum_j (Fre_j c_j + Fim_j s_j) at
+// the sweep's source time into Fc (if Fre), and the Dirichlet values sum_j Re(gD_j e^{-i m_j w t})
+// at its output time into D1 and, for the start map, at its input time into D0 (if Dre).
+template <typename T>
+__global__ void f2_combine_kernel(size_t fs, int nshots, const T *Fre, const T *Fim, ShotPhase wf,
+                                  T *Fc, const double *Dre, const double *Dim, ShotPhase w1,
+                                  double *D1, ShotPhase w0, double *D0) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
+    if (Fc) {
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < CMCG_MAX_SHOTS; ++j) {
+        if (j >= nshots) break;
+        a = fma((double)Fre[j * fs + o], wf.c[j], a);
+        if (Fim) a = fma((double)Fim[j * fs + o], wf.s[j], a);
+      }
+      Fc[o] = (T)a;
+    }
+    if (Dre) {
+      double a1 = 0.0, a0 = 0.0;
+#pragma unroll
+      for (int j = 0; j < CMCG_MAX_SHOTS; ++j) {
+        if (j >= nshots) break;
+        const double dr = Dre[j * fs + o], di = Dim ? Dim[j * fs + o] : 0.0;
+        a1 = fma(dr, w1.c[j], fma(di, w1.s[j], a1));
+        a0 = fma(dr, w0.c[j], fma(di, w0.s[j], a0));
+      }
+      D1[o] = a1;
+      if (D0) D0[o] = a0;
+    }
+  }
+}
+
+// Filter sums of a multi-frequency problem at step n: (Ure_j, Uim_j) += u^n (cos, sin)(m_j w t_n).
+// At n = 0 the state u^0 is the input's free-node values plus the Dirichlet values d0 (zero
+// without data) on the sound-soft nodes; later states hold both already.
+__global__ void f2_accumulate_kernel(F2Geom g, int nshots, const double *u, int first,
+                                     const double *d0, ShotPhase w, double *ure, double *uim) {
+  F2_ROWS(g)
+  double x = u[o];
+  if (first && g.mask && g.mask[o]) x = d0 ? d0[o] : 0.0;
+#pragma unroll
+  for (int jj = 0; jj < CMCG_MAX_SHOTS; ++jj) {
+    if (jj >= nshots) break;
+    ure[jj * g.fs + o] += x * w.c[jj];
+    uim[jj * g.fs + o] += x * w.s[jj];
+  }
+  F2_ROWS_END
+}
+
 int gridn(size_t n) {
   size_t b = (n + 255) / 256;
   return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+// blocks for a node-row loop: four rows per 256-thread block
+int rows_grid_of(const F2Geom &g) {
+  const long rows = (long)(g.ny + 1) * (g.nz + 1);
+  const long b = (rows + 3) / 4;
+  return (int)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
 struct F2Set {
   int prec = CMCG_FP64;
   void *A = nullptr, *B = nullptr, *C = nullptr;   // three-level state buffers (one field each)
   void *W = nullptr, *Y = nullptr;                 // two-field: period output / metric output
-  void *lam = nullptr, *Fre = nullptr, *Fim = nullptr;
+  void *lam = nullptr;
+  void *Fre = nullptr, *Fim = nullptr;             // load amplitudes, one field per component
+  void *Fc = nullptr;                              // several components: the load of one sweep
 };
 
 class F2Solver final : public Solver {
@@ -86,8 +153,11 @@ class F2Solver final : public Solver {
   double *RU = nullptr;              // primal residual, u block
   double *RH = nullptr;              // dual residual (two fields)
   double *QU = nullptr;              // Riesz output, u block
-  double *Ure = nullptr, *Uim = nullptr;
-  double *Dre = nullptr, *Dim = nullptr;   // Dirichlet data on the sound-soft nodes, or null
+  double *Ure = nullptr, *Uim = nullptr;   // filter sums, one field per component
+  double *Dre = nullptr, *Dim = nullptr;   // Dirichlet data on the sound-soft nodes (one field per
+                                           // component), or null
+  bool multi = false;                      // several source components
+  double *DA = nullptr, *DB = nullptr;     // several components: Dirichlet values of one sweep
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
   RieszMG mg;
   bool started = false;
@@ -108,7 +178,7 @@ class F2Solver final : public Solver {
   }
   size_t device_bytes() const override { return arena.bytes(); }
 
-  cmcg_status alloc_set(F2Set &b, int prec, bool var_c, bool forced, bool has_im) {
+  cmcg_status alloc_set(F2Set &b, int prec, bool var_c, bool forced, bool has_im, int J) {
     const size_t esz = prec == CMCG_FP64 ? sizeof(double) : sizeof(float);
     b.prec = prec;
     CMCG_TRY(arena.alloc(g.fs * esz, &b.A, s));
@@ -117,8 +187,9 @@ class F2Solver final : public Solver {
     CMCG_TRY(arena.alloc(2 * g.fs * esz, &b.W, s));
     CMCG_TRY(arena.alloc(2 * g.fs * esz, &b.Y, s));
     if (var_c) CMCG_TRY(arena.alloc(g.fs * esz, &b.lam, s));
-    if (forced) CMCG_TRY(arena.alloc(g.fs * esz, &b.Fre, s));
-    if (forced && has_im) CMCG_TRY(arena.alloc(g.fs * esz, &b.Fim, s));
+    if (forced) CMCG_TRY(arena.alloc(J * g.fs * esz, &b.Fre, s));
+    if (forced && has_im) CMCG_TRY(arena.alloc(J * g.fs * esz, &b.Fim, s));
+    if (forced && J > 1) CMCG_TRY(arena.alloc(g.fs * esz, &b.Fc, s));
     return CMCG_OK;
   }
 
@@ -172,28 +243,37 @@ class F2Solver final : public Solver {
         }
       }
     }
+    const std::vector<cmcg_shot> shots = shots_of(P);
+    const int J = (int)shots.size();
+    multi = J > 1;
     const bool var_c = P->c != nullptr;
-    const bool forced = P->f_re || P->f_im || P->gS_re || P->gS_im;
-    const bool has_im = P->f_im || P->gS_im;
-    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im));
-    if (mixed) CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, var_c, forced, has_im));
+    bool forced = false, has_im = false, has_d = false, has_dim = false;
+    for (const cmcg_shot &sh : shots) {
+      forced = forced || sh.f_re || sh.f_im || sh.gS_re || sh.gS_im;
+      has_im = has_im || sh.f_im || sh.gS_im;
+      has_d = has_d || sh.gD_re || sh.gD_im;
+      has_dim = has_dim || sh.gD_im;
+    }
+    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im, J));
+    if (mixed) CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, var_c, forced, has_im, J));
     else lo = hi;
     CMCG_TRY(arena.alloc(2 * g.fs * (mixed ? sizeof(float) : sizeof(double)), &D, s));
     CMCG_TRY(arena.alloc_n(2 * g.fs, &Z, s));
     CMCG_TRY(arena.alloc_n(g.fs, &RU, s));
     CMCG_TRY(arena.alloc_n(2 * g.fs, &RH, s));
     CMCG_TRY(arena.alloc_n(g.fs, &QU, s));
-    CMCG_TRY(arena.alloc_n(g.fs, &Ure, s));
-    CMCG_TRY(arena.alloc_n(g.fs, &Uim, s));
+    CMCG_TRY(arena.alloc_n(J * g.fs, &Ure, s));
+    CMCG_TRY(arena.alloc_n(J * g.fs, &Uim, s));
     CMCG_TRY(arena.alloc_n(kRedBlocks, &partials, s));
     CMCG_TRY(arena.alloc_n(kNumScalars, &scalars, s));
-    // coefficients and load
-    {
+    // coefficients and load, component by component (lambda is rewritten with equal values)
+    for (int jj = 0; jj < J; ++jj) {
       const size_t sx = (size_t)(g.nz + 1) * (g.ny + 1), sy = (size_t)(g.nz + 1) * (g.nx + 1),
                    sz = (size_t)(g.ny + 1) * (g.nx + 1);
       const size_t nface = 2 * (sx + sy + sz);
       DeviceArena tmp;
-      const double *src[5] = {P->c, P->f_re, P->f_im, P->gS_re, P->gS_im};
+      const double *src[5] = {P->c, shots[jj].f_re, shots[jj].f_im, shots[jj].gS_re,
+                              shots[jj].gS_im};
       const size_t len[5] = {nn, nn, nn, nface, nface};
       double *dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
       for (int k = 0; k < 5; ++k) {
@@ -201,87 +281,149 @@ class F2Solver final : public Solver {
         CMCG_TRY(tmp.alloc_n(len[k], &dev[k], s));
         CMCG_HIP(hipMemcpyAsync(dev[k], src[k], len[k] * sizeof(double), hipMemcpyHostToDevice, s));
       }
+      const size_t off = (size_t)jj * g.fs;
       CMCG_HIP(f2_setup<double>(g, dev[0], P->c_const, dev[1], dev[2], dev[3], dev[4],
-                                tp<double>(hi.lam), tp<double>(hi.Fre), tp<double>(hi.Fim), s));
+                                tp<double>(hi.lam), hi.Fre ? tp<double>(hi.Fre) + off : nullptr,
+                                hi.Fim ? tp<double>(hi.Fim) + off : nullptr, s));
       if (mixed)
         CMCG_HIP(f2_setup<float>(g, dev[0], P->c_const, dev[1], dev[2], dev[3], dev[4],
-                                 tp<float>(lo.lam), tp<float>(lo.Fre), tp<float>(lo.Fim), s));
+                                 tp<float>(lo.lam), lo.Fre ? tp<float>(lo.Fre) + off : nullptr,
+                                 lo.Fim ? tp<float>(lo.Fim) + off : nullptr, s));
       CMCG_HIP(hipStreamSynchronize(s));
     }
-    // Dirichlet data (only where there are sound-soft nodes)
-    if (g.mask && (P->gD_re || P->gD_im)) {
-      DeviceArena tmp;
-      const double *src[2] = {P->gD_re, P->gD_im};
-      double **dst[2] = {&Dre, &Dim};
-      for (int k = 0; k < 2; ++k) {
-        if (!src[k]) continue;
-        double *dpk = nullptr;
-        CMCG_TRY(tmp.alloc_n(nn, &dpk, s));
-        CMCG_HIP(hipMemcpyAsync(dpk, src[k], nn * sizeof(double), hipMemcpyHostToDevice, s));
-        CMCG_TRY(arena.alloc_n(g.fs, dst[k], s));
-        hipLaunchKernelGGL(dirichlet_unpack_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, dpk,
-                           *dst[k]);
-        CMCG_HIP(hipGetLastError());
+    // Dirichlet data (only where there are sound-soft nodes), one field per component; a zero
+    // real part is kept when only imaginary parts are given so that the kernels' reads are valid
+    if (g.mask && has_d) {
+      CMCG_TRY(arena.alloc_n(J * g.fs, &Dre, s));
+      if (has_dim) CMCG_TRY(arena.alloc_n(J * g.fs, &Dim, s));
+      for (int jj = 0; jj < J; ++jj) {
+        DeviceArena tmp;
+        const double *src[2] = {shots[jj].gD_re, shots[jj].gD_im};
+        double *dst[2] = {Dre + jj * g.fs, Dim ? Dim + jj * g.fs : nullptr};
+        for (int k = 0; k < 2; ++k) {
+          if (!src[k]) continue;
+          double *dpk = nullptr;
+          CMCG_TRY(tmp.alloc_n(nn, &dpk, s));
+          CMCG_HIP(hipMemcpyAsync(dpk, src[k], nn * sizeof(double), hipMemcpyHostToDevice, s));
+          hipLaunchKernelGGL(dirichlet_unpack_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, dpk,
+                             dst[k]);
+          CMCG_HIP(hipGetLastError());
+        }
+        CMCG_HIP(hipStreamSynchronize(s));
       }
-      if (!Dre) {
-        // only an imaginary part given: a zero real part keeps the kernels' reads valid
-        CMCG_TRY(arena.alloc_n(g.fs, &Dre, s));
+      if (multi) {
+        CMCG_TRY(arena.alloc_n(g.fs, &DA, s));
+        CMCG_TRY(arena.alloc_n(g.fs, &DB, s));
       }
-      CMCG_HIP(hipStreamSynchronize(s));
     }
     CMCG_TRY(mg.build(g, arena, s));
     return CMCG_OK;
   }
 
   // ------------------------------------------------------------------ periods
+  // Component weights (cos, sin)(m_j omega t_n) at step time t_n = n dt, times the source ramp
+  // if `ramped`
+  ShotPhase shot_phase(int n, bool ramped) const {
+    ShotPhase w;
+    const double t = n * cfg.dt, amp = ramped ? transient(t_offset + t, t_tr) : 1.0;
+    for (int j = 0; j < cfg.nshots; ++j) {
+      w.c[j] = amp * std::cos(cfg.omega_of(j) * t);
+      w.s[j] = amp * std::sin(cfg.omega_of(j) * t);
+    }
+    return w;
+  }
+
+  // Several components: the load of the sweep whose source time is t_nf (into b.Fc) and the
+  // Dirichlet values at t_nd (into DB) and, if start, at t_0 (into DA).
+  template <typename T>
+  cmcg_status combine(const F2Set &b, bool load, bool dir, int nf, int nd, bool start) {
+    if (!load && !dir) return CMCG_OK;
+    hipLaunchKernelGGL((f2_combine_kernel<T>), dim3(gridn(g.fs)), dim3(256), 0, s, g.fs,
+                       cfg.nshots, tpc<T>(b.Fre), tpc<T>(b.Fim), shot_phase(nf, true),
+                       load ? tp<T>(b.Fc) : nullptr, dir ? Dre : nullptr, Dim,
+                       shot_phase(nd, true), DB, shot_phase(0, true), start ? DA : nullptr);
+    CMCG_HIP(hipGetLastError());
+    return CMCG_OK;
+  }
+
+  // Several components: filter sums of u^n (FP64 state)
+  cmcg_status accumulate(const double *u, int n) {
+    hipLaunchKernelGGL(f2_accumulate_kernel, dim3(rows_grid_of(g)), dim3(256), 0, s, g, cfg.nshots,
+                       u, n == 0 ? 1 : 0, n == 0 ? DA : nullptr, shot_phase(n, false), Ure, Uim);
+    CMCG_HIP(hipGetLastError());
+    return CMCG_OK;
+  }
+
+  // One component: its load enters the sweeps with the weights (cos, sin)(m omega t) of the
+  // sweep's time, and the filter sum runs inside the sweeps.  Several components: before each
+  // sweep, `combine` writes that sweep's summed load (read with weights (1, 0)) and Dirichlet
+  // values (DB at the output time, DA at the start map's input time, read through the data
+  // pointers with weights (1, 0) and (0, 1)), and `accumulate` adds u^n to every filter sum.
   template <typename T>
   cmcg_status fwd_t(const F2Set &b, bool forced, const T *zin, T *out, const T *sub, bool filter) {
     const int N = cfg.N;
+    const double w0 = cfg.omega_of(0);
+    const bool load = forced && b.Fre, dir = forced && Dre;
+    if (multi && filter && !std::is_same<T, double>::value)
+      return set_error("the filter period runs in FP64"), CMCG_EINVAL;
     F2Args<T> p;
     p.lam = tpc<T>(b.lam);
-    p.fre = tpc<T>(b.Fre);
-    p.fim = tpc<T>(b.Fim);
-    p.forced = (forced && b.Fre) ? 1 : 0;
-    if (filter) {
+    p.fre = multi ? tpc<T>(b.Fc) : tpc<T>(b.Fre);
+    p.fim = multi ? nullptr : tpc<T>(b.Fim);
+    p.forced = load ? 1 : 0;
+    if (filter && !multi) {
       p.ure = Ure;
       p.uim = Uim;
     }
-    if (forced && Dre) {
-      p.dre = Dre;
-      p.dim = Dim;
+    if (dir) {
+      p.dre = multi ? DB : Dre;
+      p.dim = multi ? DA : Dim;
     }
-    // weights of Re(g e^{-i w t}) at the step time t_n = n dt of this period (ramped)
+    // weights of Re(g e^{-i m w t}) at the step time t_n = n dt of this period (ramped)
     auto phase = [&](int n, double *c, double *sn) {
       const double t = n * cfg.dt, amp = transient(t_offset + t, t_tr);
-      *c = amp * std::cos(cfg.omega * t);
-      *sn = amp * std::sin(cfg.omega * t);
+      *c = multi ? 1.0 : amp * std::cos(w0 * t);
+      *sn = multi ? 0.0 : amp * std::sin(w0 * t);
     };
     T *buf[3] = {tp<T>(b.A), tp<T>(b.B), tp<T>(b.C)};
     // start map: u^1 from (u^0, v^0)
     p.st = zin;
     p.aux = zin + g.fs;
     p.out = buf[0];
-    p.fcos = transient(t_offset, t_tr);
+    p.fcos = multi ? 1.0 : transient(t_offset, t_tr);
     p.fsin = 0.0;
     p.wcos = 1.0;
     p.wsin = 0.0;
-    phase(0, &p.dcos0, &p.dsin0);
+    if (multi) {
+      p.dcos0 = 0.0;
+      p.dsin0 = 1.0;
+    } else {
+      phase(0, &p.dcos0, &p.dsin0);
+    }
     phase(1, &p.dcos1, &p.dsin1);
+    if (multi) {
+      CMCG_TRY(combine<T>(b, load, dir, 0, 1, true));
+      if (filter) CMCG_TRY(accumulate(reinterpret_cast<const double *>(zin), 0));
+    }
     CMCG_HIP(f2_march<T>(kF2FwdStart, g, p, s));
     const T *prev = zin;
     int cur = 0;
     for (int n = 1; n < N; ++n) {
       const double t = n * cfg.dt;
       const double amp = transient(t_offset + t, t_tr);
-      p.wcos = std::cos(cfg.omega * t);
-      p.wsin = std::sin(cfg.omega * t);
-      p.fcos = amp * p.wcos;
-      p.fsin = amp * p.wsin;
+      p.wcos = std::cos(w0 * t);
+      p.wsin = std::sin(w0 * t);
+      p.fcos = multi ? 1.0 : amp * p.wcos;
+      p.fsin = multi ? 0.0 : amp * p.wsin;
       phase(n + 1, &p.dcos1, &p.dsin1);
       const int nxt = (cur + 1) % 3;
       p.st = buf[cur];
       p.aux = prev;
       p.out = buf[nxt];
+      if (multi) {
+        CMCG_TRY(combine<T>(b, load, dir, n, n + 1, false));
+        if (filter) CMCG_TRY(accumulate(reinterpret_cast<const double *>(buf[cur]), n));
+      }
       CMCG_HIP(f2_march<T>(kF2FwdStep, g, p, s));
       prev = buf[cur];
       cur = nxt;
@@ -289,12 +431,13 @@ class F2Solver final : public Solver {
     // end map: (u^N, v^N) with v^N = (u^{N+1} - u^{N-1}) / (2 dt)
     p.ure = p.uim = nullptr;
     const double ampN = transient(t_offset + N * cfg.dt, t_tr);
-    p.fcos = ampN * std::cos(cfg.omega * N * cfg.dt);
-    p.fsin = ampN * std::sin(cfg.omega * N * cfg.dt);
+    p.fcos = multi ? 1.0 : ampN * std::cos(w0 * N * cfg.dt);
+    p.fsin = multi ? 0.0 : ampN * std::sin(w0 * N * cfg.dt);
     p.st = buf[cur];
     p.aux = prev;
     p.out = out;
     p.sub = sub;
+    if (multi) CMCG_TRY(combine<T>(b, load, false, N, N, false));
     CMCG_HIP(f2_march<T>(kF2FwdEnd, g, p, s));
     updates += (double)(N + 1) * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     return CMCG_OK;
@@ -526,19 +669,27 @@ class F2Solver final : public Solver {
     return CMCG_OK;
   }
 
-  cmcg_status output(const double *z, double *u_re, double *u_im, bool record) {
-    CMCG_HIP(hipMemsetAsync(Ure, 0, g.fs * sizeof(double), s));
-    CMCG_HIP(hipMemsetAsync(Uim, 0, g.fs * sizeof(double), s));
-    CMCG_TRY(fwd(hi, true, z, hi.W, nullptr, true));
-    // contiguous node output staged in hi.Y (two fields of fs >= nn values)
-    double *ore = tp<double>(hi.Y), *oim = tp<double>(hi.Y) + g.fs;
-    hipLaunchKernelGGL(f2_output_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, Ure, Uim,
-                       2.0 / cfg.N, ore, oim);
-    CMCG_HIP(hipGetLastError());
-    if (record) CMCG_HIP(hipEventRecord(ev[7], s));
+  // U = (2/N) (Ure + i Uim) per component, staged in `stage` (two fields of fs >= nn values) as
+  // contiguous node arrays and copied to the caller's n_fields output fields
+  cmcg_status output_fields(double *stage, double *u_re, double *u_im) {
+    double *ore = stage, *oim = stage + g.fs;
     const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
-    if (u_re) CMCG_HIP(hipMemcpyAsync(u_re, ore, nn * sizeof(double), hipMemcpyDefault, s));
-    if (u_im) CMCG_HIP(hipMemcpyAsync(u_im, oim, nn * sizeof(double), hipMemcpyDefault, s));
+    for (int j = 0; j < cfg.nshots; ++j) {
+      hipLaunchKernelGGL(f2_output_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, Ure + j * g.fs,
+                         Uim + j * g.fs, 2.0 / cfg.N, ore, oim);
+      CMCG_HIP(hipGetLastError());
+      if (u_re) CMCG_HIP(hipMemcpyAsync(u_re + j * nn, ore, nn * sizeof(double), hipMemcpyDefault, s));
+      if (u_im) CMCG_HIP(hipMemcpyAsync(u_im + j * nn, oim, nn * sizeof(double), hipMemcpyDefault, s));
+    }
+    return CMCG_OK;
+  }
+
+  cmcg_status output(const double *z, double *u_re, double *u_im, bool record) {
+    CMCG_HIP(hipMemsetAsync(Ure, 0, cfg.nshots * g.fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Uim, 0, cfg.nshots * g.fs * sizeof(double), s));
+    CMCG_TRY(fwd(hi, true, z, hi.W, nullptr, true));
+    if (record) CMCG_HIP(hipEventRecord(ev[7], s));
+    CMCG_TRY(output_fields(tp<double>(hi.Y), u_re, u_im));
     CMCG_HIP(hipStreamSynchronize(s));
     return CMCG_OK;
   }
@@ -590,16 +741,10 @@ class F2Solver final : public Solver {
   cmcg_status filter(const double *z, double *u_re, double *u_im) override {
     // stage z in hi.W (the forced period writes only A/B/C and its output, here hi.Y is free)
     CMCG_HIP(f2_unpack<double>(g, z, tp<double>(hi.W), 2, s));
-    CMCG_HIP(hipMemsetAsync(Ure, 0, g.fs * sizeof(double), s));
-    CMCG_HIP(hipMemsetAsync(Uim, 0, g.fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Ure, 0, cfg.nshots * g.fs * sizeof(double), s));
+    CMCG_HIP(hipMemsetAsync(Uim, 0, cfg.nshots * g.fs * sizeof(double), s));
     CMCG_TRY(fwd(hi, true, hi.W, hi.Y, nullptr, true));
-    double *ore = tp<double>(hi.W), *oim = tp<double>(hi.W) + g.fs;
-    hipLaunchKernelGGL(f2_output_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, Ure, Uim,
-                       2.0 / cfg.N, ore, oim);
-    CMCG_HIP(hipGetLastError());
-    const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
-    if (u_re) CMCG_HIP(hipMemcpyAsync(u_re, ore, nn * sizeof(double), hipMemcpyDefault, s));
-    if (u_im) CMCG_HIP(hipMemcpyAsync(u_im, oim, nn * sizeof(double), hipMemcpyDefault, s));
+    CMCG_TRY(output_fields(tp<double>(hi.W), u_re, u_im));
     CMCG_HIP(hipStreamSynchronize(s));
     return CMCG_OK;
   }
@@ -667,6 +812,7 @@ class F2Solver final : public Solver {
     i->state_len = 2 * nn;
     i->field_len = nn;
     i->device_bytes = (int64_t)arena.bytes();
+    i->n_fields = cfg.nshots;
   }
 };
 

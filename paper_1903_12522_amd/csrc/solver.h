@@ -24,7 +24,19 @@ struct SolverConfig {
   hipStream_t stream = nullptr;
   double h = 0, omega = 0, T = 0, dt = 0;
   int N = 0;
+  // time-harmonic components of the source: harmonic[j] * omega is component j's frequency
+  int nshots = 1;
+  int harmonic[CMCG_MAX_SHOTS] = {1};
+  double omega_of(int j) const { return harmonic[j] * omega; }
 };
+
+// The components of a problem's source: its shots, or its own data as the single component at
+// the base frequency.
+inline std::vector<cmcg_shot> shots_of(const cmcg_problem *P) {
+  if (P->n_shots > 0) return std::vector<cmcg_shot>(P->shots, P->shots + P->n_shots);
+  cmcg_shot s{1, P->f_re, P->f_im, P->gS_re, P->gS_im, P->gD_re, P->gD_im};
+  return {s};
+}
 
 // Device allocations owned by one solver (freed in the destructor).
 class DeviceArena {

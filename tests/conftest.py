@@ -1,7 +1,11 @@
 import os
 import sys
 
-import pytest
+# The oracle's arrays are small: one BLAS thread per process avoids the spinning thread pools
+# that oversubscribe the cores when the suite runs in parallel workers.
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+
+import pytest  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:

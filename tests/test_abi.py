@@ -53,7 +53,28 @@ def _problem(cm, **kw):
         data = np.ones(17 * 17)
         _KEEP.append(data)
         p.gD_re = data.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if kw.get("f"):
+        p.f_re = _array(16 * 16)
+    shots = kw.get("shots")
+    if shots is not None:
+        # (harmonic, Dirichlet data?) per shot, each with a source
+        table = (cm._Shot * max(1, len(shots)))()
+        for k, (m, gd) in enumerate(shots):
+            table[k].harmonic = m
+            table[k].f_re = _array(16 * 16)
+            if gd:
+                table[k].gD_re = _array(17 * 17)
+        _KEEP.append(table)
+        p.n_shots = kw.get("n_shots", len(shots))
+        if not kw.get("null_shots"):
+            p.shots = ctypes.cast(table, ctypes.POINTER(cm._Shot))
     return p
+
+
+def _array(n):
+    data = np.ones(n)
+    _KEEP.append(data)
+    return data.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 _KEEP = []
@@ -86,6 +107,15 @@ def _create(cm, p, **ok):
     (dict(), dict(runup_periods=-1), -1),
     (dict(gD=True), {}, -1),                            # Dirichlet data needs the nodal system
     (dict(bc=1), dict(runup_periods=2), -6),            # run-up of a closed undamped box
+    # multi-frequency sources (N = 32 steps per base period here)
+    (dict(shots=[(1, 0), (1, 0)]), {}, -1),             # repeated harmonic
+    (dict(shots=[(0, 0)]), {}, -1),                     # harmonic below 1
+    (dict(shots=[(1, 0), (16, 0)]), {}, -1),            # 2 m >= N: filters not separable
+    (dict(shots=[(1, 0)] * 9, n_shots=9), {}, -1),      # more than CMCG_MAX_SHOTS
+    (dict(shots=[(1, 0), (2, 0)], f=True), {}, -1),     # data both in the problem and the shots
+    (dict(shots=[(1, 0), (2, 1)]), {}, -1),             # Dirichlet data on the first-order grid
+    (dict(shots=[(1, 0)], null_shots=True), {}, -1),    # n_shots without the array
+    (dict(shots=[(1, 0)], n_shots=-1), {}, -1),
 ])
 def test_invalid_inputs_rejected_before_device(kw, opt, expect):
     from paper_1903_12522_amd import cmcg as cm
@@ -93,6 +123,15 @@ def test_invalid_inputs_rejected_before_device(kw, opt, expect):
     assert st == expect
     assert not h.value
     assert cm._lib.cmcg_last_error().decode() != ""
+
+
+def test_valid_shots_pass_host_validation():
+    """Distinct harmonics below N / 2 pass validation (then the device is needed)."""
+    from paper_1903_12522_amd import cmcg as cm
+    st, h = _create(cm, _problem(cm, shots=[(1, 0), (3, 0), (15, 0)]))
+    assert st in (0, -4)
+    if h.value:
+        cm._lib.cmcg_destroy(h)
 
 
 def test_nan_wave_speed_rejected():
