@@ -220,6 +220,56 @@ def obstacle_study(n: int = 128, freq: float = 6.0, longtime=(16, 64, 256, 1024)
     return out
 
 
+def supershot_study(n: int = 2048, base_freq: float = 25.0, harmonics=(1, 2, 4)):
+    """One CMCG solve of a multi-frequency source against separate single-frequency solves of
+    its components (Concluding remarks), on the first-order n^2 random medium, FP32-mixed to
+    1e-6.  The harmonics divide the base period's step count, so every separate problem has the
+    super-shot's time step and both compute the same discrete solutions: their relative
+    difference is the solvers' tolerance."""
+    import copy
+    import numpy as np
+    import torch
+    import cmcg_inputs as ci
+    from paper_1903_12522_amd import cmcg
+
+    def timed(prob):
+        with cmcg.Solver(prob, "fp32", tol=1e-6, max_iter=20000) as s:
+            N = s.info["steps_per_period"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U, rep = s.solve()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        periods = 2 * rep["iterations"] + 2 * rep["fp64_refreshes"] + 3
+        return U, {"seconds": round(wall, 3), "iterations": rep["iterations"],
+                   "converged": rep["converged"], "steps_per_period": N,
+                   "leapfrog_steps": periods * N}
+
+    prob = ci.supershot_2d(n=n, base_freq=base_freq, harmonics=harmonics, seed=99)
+    log(f"super-shot {n}^2, base {base_freq}, harmonics {harmonics}")
+    U, sup = timed(prob)
+    log(f"super-shot: {sup['seconds']} s, {sup['iterations']} iterations")
+    separate = []
+    for k, sh in enumerate(prob.shots):
+        q = copy.copy(prob)
+        q.shots = None
+        q.omega = sh.harmonic * prob.omega
+        q.f, q.gS = sh.f, sh.gS
+        Uk, r = timed(q)
+        r["harmonic"] = sh.harmonic
+        r["rel_diff_vs_supershot"] = float(np.linalg.norm(U[k] - Uk) / np.linalg.norm(Uk))
+        separate.append(r)
+        log(f"harmonic {sh.harmonic}: {r['seconds']} s, {r['iterations']} iterations, "
+            f"difference {r['rel_diff_vs_supershot']:.2e}")
+    total = sum(r["seconds"] for r in separate)
+    return {"workload": f"first-order random medium {n}x{n}, {len(harmonics)} Gaussian sources at "
+                        f"harmonics {list(harmonics)} of {base_freq} (frequencies "
+                        f"{[m * base_freq for m in harmonics]}), FP32-mixed, tol 1e-6",
+            "supershot": sup, "separate": separate,
+            "separate_total_seconds": round(total, 3),
+            "separate_over_supershot": round(total / sup["seconds"], 3)}
+
+
 def cpu_baseline(prob, steps: int = 20):
     """The oracle as it stands, on the full grid: `steps` forward leapfrog steps plus `steps`
     transposed steps (the two halves of a CG iteration), timed on one host core."""
@@ -259,6 +309,8 @@ def main():
                     help="run-up and do-nothing long-time solve on the 4096^2 workload")
     ap.add_argument("--obstacle-study", action="store_true",
                     help="CMCG vs the do-nothing solve for a convex and a nonconvex obstacle")
+    ap.add_argument("--supershot-study", action="store_true",
+                    help="one multi-frequency CMCG solve vs separate single-frequency solves")
     args = ap.parse_args()
 
     if args.calibrate_copy:
@@ -367,6 +419,8 @@ def main():
         out["runup_study"] = runup_study(prob)
     if args.obstacle_study:
         out["obstacle_study"] = obstacle_study()
+    if args.supershot_study:
+        out["supershot_study"] = supershot_study()
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu:
