@@ -255,6 +255,34 @@ class F1:
         U = [1j * (2.0 / self.N) * Vc / (m * self.omega) for Vc, (m, _, _) in zip(V, self.comps)]
         return U[0] if len(U) == 1 else np.stack(U)
 
+    def step6_output(self, z: np.ndarray) -> np.ndarray:
+        """The solution read off the initial state alone (eq. mix_solution in time-discrete
+        form, single component).  The frequency system's face rows give the flux amplitude
+        Q = i dt G V / (2 sin(theta)); with Re V = v_0 and Re Q = P_0 / cos(theta) this gives
+        Q = P_0 / cos(theta) + i dt G v_0 / (2 sin(theta)), and the cell rows then give
+        V = dt c^2 (Fhat + D Q) / (-2 i sin(theta) + 2 gamma cos(theta)), u = i V / omega.
+        Divergence-free flux fields (the non-uniqueness of Thm 2) drop out through D."""
+        assert len(self.comps) == 1, "Step 6 output of a single-frequency problem"
+        Px, Py, v = self.unpack(z)
+        dt, h = self.dt, self.h
+        th = 0.5 * self.omega * dt
+        gx, gy = self.grad(v)
+        Qx = Px / math.cos(th) + 1j * dt * gx / (2.0 * math.sin(th))
+        Qy = Py / math.cos(th) + 1j * dt * gy / (2.0 * math.sin(th))
+        DQ = np.zeros((self.ny, self.nx), complex)
+        DQ[:, :-1] += Qx / h
+        DQ[:, 1:] -= Qx / h
+        DQ[:-1, :] += Qy / h
+        DQ[1:, :] -= Qy / h
+        _, f, g = self.comps[0]
+        Fhat = f.copy()
+        Fhat[:, 0] += g[0] / h
+        Fhat[:, -1] += g[1] / h
+        Fhat[0, :] += g[2] / h
+        Fhat[-1, :] += g[3] / h
+        V = dt * self.c ** 2 * (Fhat + DQ) / (-2j * math.sin(th) + 2.0 * self.gamma * math.cos(th))
+        return 1j * V / self.omega
+
     def functional(self, z):
         return _cmcg.functional(lambda x: self.period(x, True), self.ME, z)
 

@@ -308,15 +308,61 @@ class F2:
     def filter(self, z: np.ndarray) -> np.ndarray:
         """U = (2/N) sum_{n<N} u^n e^{i w t_n} over one forced period from z.  With several
         components, one such sum per component at its frequency m w over the same period,
-        stacked (shape (components,) + node shape)."""
+        stacked (shape (components,) + node shape).  On a pure-Neumann box the sums are then
+        shifted by the constant that the compatibility condition fixes (`compatible`)."""
         U = [np.zeros(self.shape, complex) for _ in self.comps]
         self.period(z, True, U_acc=U)
         U = [2.0 * Uc / self.N for Uc in U]
+        if self.pure_neumann():
+            U = [self.compatible(Uc, c) for c, Uc in enumerate(U)]
         return U[0] if len(U) == 1 else np.stack(U)
+
+    def pure_neumann(self) -> bool:
+        """No absorbing face and no sound-soft node."""
+        return all(b != ABSORBING for b in self.bc) and bool(self.free.min() > 0.5)
+
+    def compatible(self, V: np.ndarray, comp: int = 0) -> np.ndarray:
+        """V - lam with the constant lam for which V - lam satisfies the compatibility condition
+        of the time-discrete system, 1^T [S - wt^2 M - i wh B] U = 1^T Fhat (eq. CC for the
+        absorbing case, eq. cc_neumann / eq. cc_neumann_eta for the pure-Neumann case; the
+        stiffness drops out because S 1 = 0).  With the frequency m omega of component
+        `comp`:  lam = (1^T Fhat + wt^2 1^T M V + i wh 1^T B V) / (wt^2 1^T M + i wh 1^T B).
+        Only meaningful without sound-soft nodes (then the constant is a free mode)."""
+        m, f, g, _ = self.comps[comp]
+        w, dt = m * self.omega, self.dt
+        wt2 = (2.0 / dt * math.sin(0.5 * w * dt)) ** 2
+        wh = math.sin(w * dt) / dt
+        Fh = self.w * f
+        if g is not None:
+            for idx, (sel, fw) in enumerate(self.face_w):
+                Fh[sel] += fw * g[idx].reshape(fw.shape)
+        lam = (Fh.sum() + wt2 * np.sum(self.M * V) + 1j * wh * np.sum(self.B * V)) / \
+            (wt2 * self.M.sum() + 1j * wh * self.B.sum())
+        return V - lam
 
     def step6_output(self, z: np.ndarray) -> np.ndarray:
         """The paper's Step 6 output u = v_0 + (i / omega) v_1."""
         return (z[: self.nn] + 1j * z[self.nn:] / self.omega).reshape(self.shape)
+
+    def step6_discrete(self, z: np.ndarray) -> np.ndarray:
+        """Step 6 read off the time-discrete periodic state (single component): the periodic
+        state of a time-harmonic U is (Re U, wh Im U) with wh = sin(w dt) / dt, so
+        v = u_0 + i v_1 / wh; the Dirichlet data on the sound-soft nodes.  Without sound-soft
+        nodes a minimiser may carry a constant shift lam in u_0 (Thm 1), removed by the
+        compatibility condition (eq. CC, `compatible`).  A pure-Neumann box also admits the
+        mode eta, which this output cannot see: use the filter there."""
+        assert len(self.comps) == 1, "Step 6 output of a single-frequency problem"
+        if self.pure_neumann():
+            raise ValueError("pure Neumann: the Step 6 output is undetermined (eta)")
+        wh = math.sin(self.omega * self.dt) / self.dt
+        R = self.free
+        V = R * (z[: self.nn].reshape(self.shape) + 1j * z[self.nn:].reshape(self.shape) / wh)
+        gD = self.comps[0][3]
+        if gD is not None:
+            V = V + gD
+        if self.free.min() > 0.5:
+            V = self.compatible(V)
+        return V
 
     def functional(self, z):
         return _cmcg.functional(lambda x: self.period(x, True), self.ME, z)
