@@ -128,7 +128,17 @@ typedef struct {
                                   stopping test then compares with the residual at rest, so the
                                   solve stops at the accuracy a start from rest stops at.
                                   0 = start from rest.  Run in FP64.                           */
+  int32_t output;              /* how cmcg_solve / cmcg_finish turn the minimiser into u:
+                                  CMCG_OUTPUT_FILTER (0, default): the fundamental-frequency
+                                  filter over one forced period (eq. fundamental-frequency-
+                                  solution / eq. TH_FILTERED_MIXED_SOLUTION); on a pure-Neumann
+                                  nodal box its result is shifted by the constant that the
+                                  compatibility condition fixes (eq. cc_neumann_eta).
+                                  CMCG_OUTPUT_STEP6: read u off the state itself, as cmcg_step6
+                                  does (single-frequency sources; not on a pure-Neumann box)   */
 } cmcg_options;
+
+enum { CMCG_OUTPUT_FILTER = 0, CMCG_OUTPUT_STEP6 = 1 };
 
 enum { CMCG_RIESZ_DEFAULT = 0, CMCG_RIESZ_SOLVE = 1, CMCG_RIESZ_VCYCLE = 2 };
 
@@ -198,6 +208,22 @@ cmcg_status cmcg_apply(cmcg_handle *h, int32_t op, int32_t steps, const double *
  * TH_FILTERED_MIXED_SOLUTION (one accumulation per shot, at its frequency).  u_re, u_im: host
  * or device, n_fields fields of the layout of c. */
 cmcg_status cmcg_filter(cmcg_handle *h, const double *z, double *u_re, double *u_im);
+
+/* The solution read off a state z (packed FP64 device vector) without time stepping: the paper's
+ * Step 6 output in time-discrete form, exact for the time-discrete periodic state.
+ *  F2 (Step 6, eq. TH_SOLUTION): u = u_0 + i v_1 / wh with wh = sin(omega dt) / dt on the free
+ *    nodes, gD on the sound-soft nodes.  Without sound-soft nodes a minimiser may be shifted by
+ *    a constant (Thm 1), which is removed by the compatibility condition (eq. CC):
+ *    the constant lam with 1^T [S - wt^2 M - i wh B] (u - lam) = 1^T Fhat, wt = 2 sin(omega dt
+ *    / 2) / dt.  A pure-Neumann box returns CMCG_EUNSUPPORTED (its mode eta is invisible here;
+ *    the filter handles it).
+ *  F1 (eq. mix_solution): u = i V / omega from the cell rows of the time-discrete system,
+ *    V = dt c^2 (Fhat + D Q) / (-2 i sin(theta) + 2 gamma cos(theta)), theta = omega dt / 2,
+ *    with the flux amplitude Q = P_0 / cos(theta) + i dt G v_0 / (2 sin(theta)); divergence-free
+ *    flux fields (the non-uniqueness of Thm 2) do not change it.
+ * Single-frequency sources only (CMCG_EINVAL with shots).  u_re, u_im: host or device, layout
+ * of c. */
+cmcg_status cmcg_step6(cmcg_handle *h, const double *z, double *u_re, double *u_im);
 
 /* The solve split in three: cmcg_begin (z = 0, Steps 1-4), cmcg_iterate (up to `iters` CG
  * iterations of Step 5; stops early at tol), cmcg_finish (filter + copy out).  cmcg_solve is

@@ -55,7 +55,7 @@ class _Options(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("steps_per_launch", ctypes.c_int32),
                 ("riesz_max_iter", ctypes.c_int32), ("riesz_tol", ctypes.c_double),
                 ("fp64_refresh", ctypes.c_double), ("riesz_mode", ctypes.c_int32),
-                ("runup_periods", ctypes.c_int32)]
+                ("runup_periods", ctypes.c_int32), ("output", ctypes.c_int32)]
 
 
 class _Report(ctypes.Structure):
@@ -93,6 +93,7 @@ _sig = {
     "cmcg_apply": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_void_p]),
     "cmcg_filter": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cmcg_step6": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cmcg_begin": (ctypes.c_int, [_H]),
     "cmcg_iterate": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(_Report)]),
@@ -155,13 +156,13 @@ class Solver:
     def __init__(self, problem, precision: str = "fp64", tol: float = 1e-6, max_iter: int = 1000,
                  device: int = 0, steps_per_launch: int = 0, stream=None,
                  riesz_tol: float = 0.0, riesz_max_iter: int = 0, fp64_refresh: float = 0.0,
-                 riesz_mode="default", runup_periods: int = 0):
+                 riesz_mode="default", runup_periods: int = 0, output="filter"):
         import torch  # device memory and streams
         self._torch = torch
         self.problem = problem
         p, self._keep = marshal_problem(problem)
         o = make_options(precision, tol, max_iter, device, steps_per_launch, riesz_tol,
-                         riesz_max_iter, fp64_refresh, riesz_mode, runup_periods)
+                         riesz_max_iter, fp64_refresh, riesz_mode, runup_periods, output)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
@@ -245,6 +246,15 @@ class Solver:
             if isinstance(z, np.ndarray) else z.contiguous()
         ure, uim, keep = self._out_buffers(False)
         _check(_lib.cmcg_filter(self._h, ctypes.c_void_p(zin.data_ptr()), ure, uim), "cmcg_filter")
+        return self._out_value(keep, False)
+
+    def step6(self, z) -> np.ndarray:
+        """u read off a packed state without time stepping (cmcg_step6)."""
+        torch = self._torch
+        zin = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64)).cuda() \
+            if isinstance(z, np.ndarray) else z.contiguous()
+        ure, uim, keep = self._out_buffers(False)
+        _check(_lib.cmcg_step6(self._h, ctypes.c_void_p(zin.data_ptr()), ure, uim), "cmcg_step6")
         return self._out_value(keep, False)
 
     def runup(self, periods: int, ramp: bool = True):
@@ -355,11 +365,13 @@ def marshal_problem(problem):
 
 RIESZ_DEFAULT, RIESZ_SOLVE, RIESZ_VCYCLE = 0, 1, 2
 _RIESZ = {"default": RIESZ_DEFAULT, "solve": RIESZ_SOLVE, "vcycle": RIESZ_VCYCLE}
+OUTPUT_FILTER, OUTPUT_STEP6 = 0, 1
+_OUTPUT = {"filter": OUTPUT_FILTER, "step6": OUTPUT_STEP6}
 
 
 def make_options(precision="fp64", tol=1e-6, max_iter=1000, device=0, steps_per_launch=0,
                  riesz_tol=0.0, riesz_max_iter=0, fp64_refresh=0.0,
-                 riesz_mode="default", runup_periods=0) -> _Options:
+                 riesz_mode="default", runup_periods=0, output="filter") -> _Options:
     o = _Options()
     o.precision = FP64 if precision == "fp64" else FP32_MIXED
     o.tol = float(tol)
@@ -371,6 +383,7 @@ def make_options(precision="fp64", tol=1e-6, max_iter=1000, device=0, steps_per_
     o.fp64_refresh = float(fp64_refresh)
     o.riesz_mode = _RIESZ[riesz_mode] if isinstance(riesz_mode, str) else int(riesz_mode)
     o.runup_periods = int(runup_periods)
+    o.output = _OUTPUT[output] if isinstance(output, str) else int(output)
     return o
 
 

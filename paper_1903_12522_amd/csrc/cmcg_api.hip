@@ -66,6 +66,20 @@ cmcg_status validate_problem(const cmcg_problem *P, const cmcg_options *O) {
     if ((sh.gD_re || sh.gD_im) && (P->formulation != 2 || !P->sound_soft))
       return set_error("Dirichlet data needs the nodal formulation and a sound-soft mask"),
              CMCG_EINVAL;
+  if (O->output != CMCG_OUTPUT_FILTER && O->output != CMCG_OUTPUT_STEP6)
+    return set_error("output must be CMCG_OUTPUT_FILTER or CMCG_OUTPUT_STEP6"), CMCG_EINVAL;
+  if (O->output == CMCG_OUTPUT_STEP6) {
+    if (P->n_shots > 0)
+      return set_error("the Step 6 output reads one frequency off the state: no shots"),
+             CMCG_EINVAL;
+    if (P->formulation == 2 && !P->sound_soft) {
+      bool absorbing = false;
+      for (int f = 0; f < 2 * P->dim; ++f) absorbing = absorbing || P->face_bc[f] == CMCG_ABSORBING;
+      if (!absorbing)
+        return set_error("pure-Neumann box: the Step 6 output misses the mode eta; use the filter"),
+               CMCG_EUNSUPPORTED;
+    }
+  }
   if (O->runup_periods > 0) {
     // a closed box without absorption or Dirichlet nodes drifts linearly under a source with
     // non-zero mean (the eta mode of Sec. 2.2), which the run-up start would carry into CG
@@ -101,6 +115,7 @@ cmcg_status make_config(const cmcg_problem *P, const cmcg_options *O, hipStream_
   cfg->riesz_tol = O->riesz_tol;
   cfg->riesz_max_iter = O->riesz_max_iter;
   cfg->runup = O->runup_periods;
+  cfg->output = O->output;
   cfg->riesz_mode = O->riesz_mode != CMCG_RIESZ_DEFAULT
                         ? O->riesz_mode
                         : (O->precision == CMCG_FP64 ? CMCG_RIESZ_SOLVE : CMCG_RIESZ_VCYCLE);
@@ -252,6 +267,12 @@ cmcg_status cmcg_filter(cmcg_handle *H, const double *z, double *u_re, double *u
   if (!H || !z) return set_error("bad argument"), CMCG_EINVAL;
   CMCG_HIP(hipSetDevice(H->device));
   return H->solver->filter(z, u_re, u_im);
+}
+
+cmcg_status cmcg_step6(cmcg_handle *H, const double *z, double *u_re, double *u_im) {
+  if (!H || !z) return set_error("bad argument"), CMCG_EINVAL;
+  CMCG_HIP(hipSetDevice(H->device));
+  return H->solver->step6(z, u_re, u_im);
 }
 
 cmcg_status cmcg_get_state(cmcg_handle *H, int32_t which, double *out) {

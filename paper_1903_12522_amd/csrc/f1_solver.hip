@@ -109,6 +109,40 @@ __global__ void f1_accumulate_kernel(const double *v, ShotWeights w, double *ure
   }
 }
 
+// The solution read off a state (eq. mix_solution, time-discrete): per cell, the flux amplitudes
+// on its interior faces Q = P_0 / cos(theta) + i (dt/h) (difference of v_0 across the face) /
+// (2 sin(theta)), then V = kap (h Fhat + sum of signed face Q) / (-2 i sin(theta) +
+// 2 gamma cos(theta)) and u = i V / omega into (ure, uim) (device layout).  kap = dt c^2 / h.
+__global__ void f1_step6_kernel(F1Geom g, const double *z, const double *cc, const double *Fre,
+                                const double *Fim, double theta, double omega, double *ure,
+                                double *uim, size_t fs) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const int nx = g.nx, ny = g.ny;
+  const size_t pitch = (size_t)g.pitch;
+  const double dth = g.dt / g.h, ic = 1.0 / cos(theta), is2 = 0.5 / sin(theta);
+  const double *px = z, *py = z + fs, *v = z + 2 * fs;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
+    const int j = (int)(o / pitch), i = (int)(o % pitch);
+    if (i >= nx) continue;
+    const double vc = v[o];
+    double sr = 0.0, si = 0.0;           // sum over the faces of the outward flux amplitude
+    if (i <= nx - 2) { sr += px[o] * ic;          si += dth * (v[o + 1] - vc) * is2; }
+    if (i >= 1)      { sr -= px[o - 1] * ic;      si -= dth * (vc - v[o - 1]) * is2; }
+    if (j <= ny - 2) { sr += py[o] * ic;          si += dth * (v[o + pitch] - vc) * is2; }
+    if (j >= 1)      { sr -= py[o - pitch] * ic;  si -= dth * (vc - v[o - pitch]) * is2; }
+    const double kap = cc[o];
+    const double nr = kap * (Fre[o] + sr), ni = kap * ((Fim ? Fim[o] : 0.0) + si);
+    const int m = (i == 0 ? g.abs_face[0] : 0) + (i == nx - 1 ? g.abs_face[1] : 0) +
+                  (j == 0 ? g.abs_face[2] : 0) + (j == ny - 1 ? g.abs_face[3] : 0);
+    const double gam = 0.5 * m * sqrt(kap * dth);
+    const double dr = 2.0 * gam * cos(theta), di = -2.0 * sin(theta);
+    const double den = dr * dr + di * di;
+    const double Vr = (nr * dr + ni * di) / den, Vi = (ni * dr - nr * di) / den;
+    ure[o] = -Vi / omega;
+    uim[o] = Vr / omega;
+  }
+}
+
 // Riesz map of the first-order formulation, M_E^{-1} y (the control space is L^2): faces 1/h^2,
 // cells c^2 / h^2 = kap / (h dt)
 template <typename T>
@@ -505,8 +539,35 @@ class F1Solver final : public Solver {
 
   cmcg_status finish(double *u_re, double *u_im) override {
     if (!started) return set_error("cmcg_begin first"), CMCG_EINVAL;
+    if (cfg.output == CMCG_OUTPUT_STEP6) {
+      CMCG_TRY(step6_from(Z, u_re, u_im));
+      CMCG_HIP(hipEventRecord(ev[6], s));
+      return CMCG_OK;
+    }
     // Step 6 through the fundamental-frequency filter: one forced FP64 period from z
     return filter_from_hi(Z, u_re, u_im);
+  }
+
+  // u from a device-layout FP64 state (eq. mix_solution), staged in hi.S1
+  cmcg_status step6_from(const double *zdev, double *u_re, double *u_im) {
+    if (cfg.nshots > 1)
+      return set_error("the Step 6 output reads one frequency off the state: no shots"),
+             CMCG_EINVAL;
+    double *ore = tp<double>(hi.S1), *oim = tp<double>(hi.S1) + fs;
+    hipLaunchKernelGGL(f1_step6_kernel, dim3(grid_for(fs)), dim3(256), 0, s, g, zdev,
+                       tpc<double>(hi.cc), tpc<double>(hi.Fre), tpc<double>(hi.Fim),
+                       0.5 * cfg.omega * cfg.dt, cfg.omega, ore, oim, fs);
+    CMCG_HIP(hipGetLastError());
+    const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
+    if (u_re) CMCG_HIP(hipMemcpy2DAsync(u_re, row, ore, pitchb, row, g.ny, hipMemcpyDefault, s));
+    if (u_im) CMCG_HIP(hipMemcpy2DAsync(u_im, row, oim, pitchb, row, g.ny, hipMemcpyDefault, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status step6(const double *z, double *u_re, double *u_im) override {
+    CMCG_HIP(f1_unpack<double>(g, z, tp<double>(hi.W), fs, s));
+    return step6_from(tp<double>(hi.W), u_re, u_im);
   }
 
   cmcg_status solve(double *u_re, double *u_im) override {
@@ -719,6 +780,8 @@ class F1Server final : public Server {
     if (P->n_shots > 0)
       return set_error("the server takes single-frequency sources (n_shots must be 0)"),
              CMCG_EUNSUPPORTED;
+    if (O->output != CMCG_OUTPUT_FILTER)
+      return set_error("served solves return the filter output"), CMCG_EUNSUPPORTED;
     auto *R = new ServeRequest();
     R->id = next_id++;
     R->P = *P;

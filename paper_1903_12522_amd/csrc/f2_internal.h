@@ -88,6 +88,13 @@ hipError_t f2_direction(const F2Geom &g, T *d, const double *ru, const double *r
                         const double *sc, int first, hipStream_t s);
 template <typename T>
 hipError_t f2_mass_inverse(const F2Geom &g, const T *qh_v, double *q_v, const T *lam, hipStream_t s);
+// Partial sums (kCompatSums x kRedBlocks, sum-major) of the compatibility condition: sum M,
+// sum B, sum Fhat (re, im), sum M a (re, im), sum B a (re, im) with a = sa ar + i sb ai
+// (ai may be null); FP64 fields of the device layout.
+constexpr int kCompatSums = 8;
+hipError_t f2_compat_sums(const F2Geom &g, const double *lam, const double *Fre, const double *Fim,
+                          const double *ar, double sa, const double *ai, double sb,
+                          double *partials, hipStream_t s);
 template <typename T>
 hipError_t f2_setup(const F2Geom &g, const double *c, double c_const, const double *fre,
                     const double *fim, const double *gre, const double *gim, T *lam, T *Fre, T *Fim,

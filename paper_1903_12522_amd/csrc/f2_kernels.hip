@@ -388,6 +388,41 @@ __global__ void f2_direction_kernel(F2Geom g, T *d, const double *ru, const doub
   F2_ROWS_END
 }
 
+// Node sums of the compatibility condition 1^T [S - wt^2 M - i wh B] U = 1^T Fhat (S 1 = 0):
+// the lumped mass M = h eta dt^2 / lambda, the absorbing boundary mass B = 2 h eta dt m /
+// sqrt(lambda) (m absorbing faces at the node), the load Fhat = h eta F / lambda (F the device
+// load field dt^2 c^2 G), and M a, B a for a = sa ar + i sb ai.  One partial per block of each
+// of the kCompatSums sums, stored sum-major.
+__global__ __launch_bounds__(kRedThreads) void f2_compat_kernel(F2Geom g, const double *lam,
+                                                                const double *Fre,
+                                                                const double *Fim,
+                                                                const double *ar, double sa,
+                                                                const double *ai, double sb,
+                                                                double *partials) {
+  double acc[kCompatSums] = {};
+  F2_ROWS(g)
+  const double l = lam ? lam[o] : g.lam_const;
+  const double he = g.h * eta_of(g, i, j, k);
+  const int m = abs_faces(g, i, j, k);
+  const double M = he * g.dt * g.dt / l;
+  const double B = m ? 2.0 * he * g.dt * m / sqrt(l) : 0.0;
+  const double a = sa * ar[o], b = ai ? sb * ai[o] : 0.0;
+  acc[0] += M;
+  acc[1] += B;
+  acc[2] += Fre ? he * Fre[o] / l : 0.0;
+  acc[3] += Fim ? he * Fim[o] / l : 0.0;
+  acc[4] += M * a;
+  acc[5] += M * b;
+  acc[6] += B * a;
+  acc[7] += B * b;
+  F2_ROWS_END
+#pragma unroll
+  for (int q = 0; q < kCompatSums; ++q) {
+    const double t = block_sum(acc[q]);
+    if (threadIdx.x == 0) partials[(size_t)q * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 // q_v = M^{-1} qh_v on the free nodes (the velocity block of the Riesz map)
 template <typename T>
 __global__ void f2_mass_inverse_kernel(F2Geom g, const T *qh_v, double *q_v, const T *lam) {
@@ -522,6 +557,14 @@ hipError_t f2_mass_inverse(const F2Geom &g, const T *qh_v, double *q_v, const T 
                            hipStream_t s) {
   hipLaunchKernelGGL((f2_mass_inverse_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, qh_v,
                      q_v, lam);
+  return hipGetLastError();
+}
+
+hipError_t f2_compat_sums(const F2Geom &g, const double *lam, const double *Fre, const double *Fim,
+                          const double *ar, double sa, const double *ai, double sb,
+                          double *partials, hipStream_t s) {
+  hipLaunchKernelGGL(f2_compat_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, lam, Fre, Fim,
+                     ar, sa, ai, sb, partials);
   return hipGetLastError();
 }
 

@@ -117,6 +117,31 @@ __global__ void f2_accumulate_kernel(F2Geom g, int nshots, const double *u, int 
   F2_ROWS_END
 }
 
+// Step 6 read off a device-layout state z into contiguous node arrays: u = u_0 + i v_1 / wh on
+// the free nodes, the Dirichlet data (or 0) on the sound-soft nodes
+__global__ void f2_step6_kernel(F2Geom g, const double *z, double inv_wh, const double *dre,
+                                const double *dim, double *ore, double *oim) {
+  F2_ROWS(g)
+  const size_t u = ((size_t)k * (g.ny + 1) + j) * (g.nx + 1) + i;
+  if (g.mask && g.mask[o]) {
+    ore[u] = dre ? dre[o] : 0.0;
+    oim[u] = dim ? dim[o] : 0.0;
+  } else {
+    ore[u] = z[o];
+    oim[u] = z[g.fs + o] * inv_wh;
+  }
+  F2_ROWS_END
+}
+
+// (re, im) -= (a, b) over n contiguous values
+__global__ void shift_kernel(double *re, double *im, size_t n, double a, double b) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    re[k] -= a;
+    im[k] -= b;
+  }
+}
+
 int gridn(size_t n) {
   size_t b = (n + 255) / 256;
   return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
@@ -158,6 +183,8 @@ class F2Solver final : public Solver {
                                            // component), or null
   bool multi = false;                      // several source components
   double *DA = nullptr, *DB = nullptr;     // several components: Dirichlet values of one sweep
+  bool pure_neumann = false;               // no absorbing face and no sound-soft node
+  double *cpart = nullptr, *h_cpart = nullptr;   // compatibility sums: device partials, host copy
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
   RieszMG mg;
   bool started = false;
@@ -175,6 +202,7 @@ class F2Solver final : public Solver {
   ~F2Solver() override {
     if (s) (void)hipStreamSynchronize(s);
     if (h_scalars) (void)hipHostFree(h_scalars);
+    if (h_cpart) (void)hipHostFree(h_cpart);
   }
   size_t device_bytes() const override { return arena.bytes(); }
 
@@ -316,7 +344,43 @@ class F2Solver final : public Solver {
         CMCG_TRY(arena.alloc_n(g.fs, &DB, s));
       }
     }
+    bool absorbing = false;
+    for (int f = 0; f < 6; ++f) absorbing = absorbing || g.abs_face[f];
+    pure_neumann = !absorbing && !g.mask;
+    if (!g.mask) {
+      // the constant is a free mode: compatibility sums for the outputs
+      CMCG_TRY(arena.alloc_n((size_t)kCompatSums * kRedBlocks, &cpart, s));
+      CMCG_HIP(hipHostMalloc((void **)&h_cpart, (size_t)kCompatSums * kRedBlocks * sizeof(double)));
+    }
     CMCG_TRY(mg.build(g, arena, s));
+    return CMCG_OK;
+  }
+
+  // The constant lam that makes a - lam satisfy the compatibility condition of component j's
+  // time-discrete system, 1^T [S - wt^2 M - i wh B] (a - lam) = 1^T Fhat (eq. CC and eq.
+  // cc_neumann_eta; S 1 = 0), a = sa ar + i sb ai in the device layout:
+  //   lam = (sum Fhat + wt^2 sum M a + i wh sum B a) / (wt^2 sum M + i wh sum B).
+  // The sums are fixed-order block reductions, added on the host in block order.
+  cmcg_status compat_constant(int j, const double *ar, double sa, const double *ai, double sb,
+                              double *lre, double *lim) {
+    const double *Fr = hi.Fre ? tpc<double>(hi.Fre) + (size_t)j * g.fs : nullptr;
+    const double *Fi = hi.Fim ? tpc<double>(hi.Fim) + (size_t)j * g.fs : nullptr;
+    CMCG_HIP(f2_compat_sums(g, tpc<double>(hi.lam), Fr, Fi, ar, sa, ai, sb, cpart, s));
+    CMCG_HIP(hipMemcpyAsync(h_cpart, cpart, (size_t)kCompatSums * kRedBlocks * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    double S[kCompatSums] = {};
+    for (int q = 0; q < kCompatSums; ++q)
+      for (int b = 0; b < kRedBlocks; ++b) S[q] += h_cpart[(size_t)q * kRedBlocks + b];
+    const double w = cfg.omega_of(j), dt = cfg.dt;
+    const double wt2 = std::pow(2.0 / dt * std::sin(0.5 * w * dt), 2), wh = std::sin(w * dt) / dt;
+    // numerator n = Fhat + wt2 M a + i wh B a; denominator d = wt2 M + i wh B
+    const double nr = S[2] + wt2 * S[4] - wh * S[7], ni = S[3] + wt2 * S[5] + wh * S[6];
+    const double dr = wt2 * S[0], di = wh * S[1];
+    const double den = dr * dr + di * di;
+    if (!(den > 0.0)) return set_error("compatibility condition: zero mass"), CMCG_EBREAKDOWN;
+    *lre = (nr * dr + ni * di) / den;
+    *lim = (ni * dr - nr * di) / den;
     return CMCG_OK;
   }
 
@@ -678,6 +742,15 @@ class F2Solver final : public Solver {
       hipLaunchKernelGGL(f2_output_kernel, dim3(gridn(g.fs)), dim3(256), 0, s, g, Ure + j * g.fs,
                          Uim + j * g.fs, 2.0 / cfg.N, ore, oim);
       CMCG_HIP(hipGetLastError());
+      if (pure_neumann) {
+        // the mode eta of a closed box shifts the filter sums by a constant, which the
+        // compatibility condition fixes (eq. cc_neumann_eta)
+        double lr = 0.0, li = 0.0;
+        CMCG_TRY(compat_constant(j, Ure + j * g.fs, 2.0 / cfg.N, Uim + j * g.fs, 2.0 / cfg.N, &lr,
+                                 &li));
+        hipLaunchKernelGGL(shift_kernel, dim3(gridn(nn)), dim3(256), 0, s, ore, oim, nn, lr, li);
+        CMCG_HIP(hipGetLastError());
+      }
       if (u_re) CMCG_HIP(hipMemcpyAsync(u_re + j * nn, ore, nn * sizeof(double), hipMemcpyDefault, s));
       if (u_im) CMCG_HIP(hipMemcpyAsync(u_im + j * nn, oim, nn * sizeof(double), hipMemcpyDefault, s));
     }
@@ -696,7 +769,45 @@ class F2Solver final : public Solver {
 
   cmcg_status finish(double *u_re, double *u_im) override {
     if (!started) return set_error("cmcg_begin first"), CMCG_EINVAL;
+    if (cfg.output == CMCG_OUTPUT_STEP6) {
+      CMCG_TRY(step6_from(Z, u_re, u_im));
+      CMCG_HIP(hipEventRecord(ev[7], s));
+      return CMCG_OK;
+    }
     return output(Z, u_re, u_im, true);
+  }
+
+  // Step 6 read off a device-layout FP64 state (u_0 + i v_1 / wh, Dirichlet data on the
+  // sound-soft nodes), the constant shift removed by the compatibility condition when there is
+  // no sound-soft node (eq. CC); staged in hi.Y
+  cmcg_status step6_from(const double *zdev, double *u_re, double *u_im) {
+    if (cfg.nshots > 1)
+      return set_error("the Step 6 output reads one frequency off the state: no shots"),
+             CMCG_EINVAL;
+    if (pure_neumann)
+      return set_error("pure-Neumann box: the Step 6 output misses the mode eta; use the filter"),
+             CMCG_EUNSUPPORTED;
+    const double wh = std::sin(cfg.omega * cfg.dt) / cfg.dt;
+    double *ore = tp<double>(hi.Y), *oim = tp<double>(hi.Y) + g.fs;
+    hipLaunchKernelGGL(f2_step6_kernel, dim3(rows_grid_of(g)), dim3(256), 0, s, g, zdev, 1.0 / wh,
+                       Dre, Dim, ore, oim);
+    CMCG_HIP(hipGetLastError());
+    const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    if (!g.mask) {
+      double lr = 0.0, li = 0.0;
+      CMCG_TRY(compat_constant(0, zdev, 1.0, zdev + g.fs, 1.0 / wh, &lr, &li));
+      hipLaunchKernelGGL(shift_kernel, dim3(gridn(nn)), dim3(256), 0, s, ore, oim, nn, lr, li);
+      CMCG_HIP(hipGetLastError());
+    }
+    if (u_re) CMCG_HIP(hipMemcpyAsync(u_re, ore, nn * sizeof(double), hipMemcpyDefault, s));
+    if (u_im) CMCG_HIP(hipMemcpyAsync(u_im, oim, nn * sizeof(double), hipMemcpyDefault, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    return CMCG_OK;
+  }
+
+  cmcg_status step6(const double *z, double *u_re, double *u_im) override {
+    CMCG_HIP(f2_unpack<double>(g, z, tp<double>(hi.W), 2, s));
+    return step6_from(tp<double>(hi.W), u_re, u_im);
   }
 
   cmcg_status solve(double *u_re, double *u_im) override {

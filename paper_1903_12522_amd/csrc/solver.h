@@ -21,6 +21,7 @@ struct SolverConfig {
   int riesz_max_iter = 0;
   int riesz_mode = CMCG_RIESZ_SOLVE;   // resolved: CMCG_RIESZ_SOLVE or CMCG_RIESZ_VCYCLE
   int runup = 0;           // initial run-up periods before the CG iteration
+  int output = CMCG_OUTPUT_FILTER;   // how the minimiser becomes u
   hipStream_t stream = nullptr;
   double h = 0, omega = 0, T = 0, dt = 0;
   int N = 0;
@@ -108,6 +109,8 @@ class Solver {
   virtual cmcg_status solve(double *u_re, double *u_im) = 0;
   virtual cmcg_status apply(int op, int steps, const double *in, double *out) = 0;
   virtual cmcg_status filter(const double *z, double *u_re, double *u_im) = 0;
+  // the solution read off a packed state without time stepping (Step 6, time-discrete)
+  virtual cmcg_status step6(const double *z, double *u_re, double *u_im) = 0;
   virtual cmcg_status get_state(int which, double *out) = 0;
   virtual cmcg_status runup(int periods, int ramp, double *z_out) = 0;
   virtual cmcg_status misfit(const double *z, double *J) = 0;

@@ -17,7 +17,7 @@ LIB = os.path.join(ROOT, "paper_1903_12522_amd", "libcmcg.so")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cmcg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(cmcg_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -87,6 +87,7 @@ def _create(cm, p, **ok):
     o.max_iter = ok.get("max_iter", 10)
     o.riesz_mode = ok.get("riesz_mode", 0)
     o.runup_periods = ok.get("runup_periods", 0)
+    o.output = ok.get("output", 0)
     h = cm._H()
     st = cm._lib.cmcg_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h))
     return st, h
@@ -116,6 +117,10 @@ def _create(cm, p, **ok):
     (dict(shots=[(1, 0), (2, 1)]), {}, -1),             # Dirichlet data on the first-order grid
     (dict(shots=[(1, 0)], null_shots=True), {}, -1),    # n_shots without the array
     (dict(shots=[(1, 0)], n_shots=-1), {}, -1),
+    # output modes
+    (dict(), dict(output=5), -1),
+    (dict(shots=[(1, 0), (2, 0)]), dict(output=1), -1),   # Step 6 reads one frequency
+    (dict(dim=3, formulation=2, n=(8, 8, 8), bc=1), dict(output=1), -6),   # pure Neumann: eta
 ])
 def test_invalid_inputs_rejected_before_device(kw, opt, expect):
     from paper_1903_12522_amd import cmcg as cm
