@@ -55,8 +55,8 @@ class Problem:
     c_const: float = 1.0
     f: Optional[np.ndarray] = None        # complex source amplitude, same layout as c
     gS: Optional[List[np.ndarray]] = None  # complex boundary data per face (gS or gN)
-    sound_soft: Optional[np.ndarray] = None  # F2 only: uint8 node mask, 1 = Dirichlet node
-    gD: Optional[np.ndarray] = None       # F2 only: complex Dirichlet data (layout of c), or 0
+    sound_soft: Optional[np.ndarray] = None  # uint8 mask, 1 = Dirichlet node (F2) or cell (F1)
+    gD: Optional[np.ndarray] = None       # complex Dirichlet data u = gD there (layout of c), or 0
     face_bc: Sequence[int] = (ABSORBING,) * 6
     courant: float = 0.5
     name: str = ""
@@ -176,6 +176,49 @@ def supershot_2d(n: int = 256, base_freq: float = 4.0, harmonics=(1, 2, 3), seed
     return Problem(dim=2, formulation=1, n=(n, n), omega=2 * math.pi * base_freq, c=c,
                    face_bc=(ABSORBING,) * 4, courant=0.5, shots=shots,
                    name=f"f1_supershot_{n}_{'_'.join(str(m) for m in harmonics)}")
+
+
+def plane_wave_face_data_f1(nx: int, ny: int, h: float, k: float, direction) -> List[np.ndarray]:
+    """First-order boundary data gS = (d/dn - i k) u_in for the incident wave u_in = exp(i k
+    d.x), i.e. i k (d.n - 1) u_in at the boundary-face midpoints (faces -x, +x, -y, +y)."""
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    yc = (np.arange(ny) + 0.5) * h
+    xc = (np.arange(nx) + 0.5) * h
+    L, H = nx * h, ny * h
+    out = []
+    for normal, (x, y) in (((-1, 0), (np.zeros(ny), yc)), ((1, 0), (np.full(ny, L), yc)),
+                           ((0, -1), (xc, np.zeros(nx))), ((0, 1), (xc, np.full(nx, H)))):
+        uin = np.exp(1j * k * (d[0] * x + d[1] * y))
+        out.append(1j * k * (d[0] * normal[0] + d[1] * normal[1] - 1.0) * uin)
+    return out
+
+
+def sound_soft_square_2d(n: int = 256, freq: float = 10.0, side: float = 0.2,
+                         direction=(-1.0, 1.0), cavity: bool = False,
+                         wall: Optional[float] = None, aperture: float = 0.06) -> Problem:
+    """2D unit square, n x n cells, first-order system, c = 1, total-field scattering of the
+    plane wave exp(i k d.x) (k = 2 pi freq; the default direction is the angle 135 degrees) by
+    a sound-soft obstacle at the centre: the cells whose centres lie in a square of the given
+    side (convex), or, if `cavity`, in the walls of a square shell (wall thickness
+    max(2h, side / 10)) open by `aperture` in the middle of its -x wall (nonconvex).  Dirichlet
+    data 0 (total field), absorbing outer faces carry gS = (d/dn - i k) u_in."""
+    h = 1.0 / n
+    k = 2 * math.pi * freq
+    xc = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    lo, hi = 0.5 - side / 2, 0.5 + side / 2
+    inside = (X >= lo) & (X <= hi) & (Y >= lo) & (Y <= hi)
+    if cavity:
+        w = wall if wall is not None else max(2 * h, side / 10)
+        hollow = (X > lo + w) & (X < hi - w) & (Y > lo + w) & (Y < hi - w)
+        opening = (X < lo + w) & (np.abs(Y - 0.5) < aperture / 2)
+        inside = inside & ~hollow & ~opening
+    mask = inside.astype(np.uint8)
+    gS = plane_wave_face_data_f1(n, n, h, k, direction)
+    return Problem(dim=2, formulation=1, n=(n, n), omega=k, c=None, c_const=1.0, f=None, gS=gS,
+                   sound_soft=mask, face_bc=(ABSORBING,) * 4, courant=0.5,
+                   name=f"f1_sound_soft_{'cavity' if cavity else 'square'}_{n}")
 
 
 def channel_plane_wave_f1(nx: int, ny: int, k: float) -> Problem:

@@ -21,6 +21,11 @@ the cell:
 One period T = 2 pi / omega takes an integer number N = ceil(T c_max / (sigma h)) of
 steps (the paper uses a step count that divides the period), dt = T / N.
 
+Dirichlet data (eq. mixWE_DBC) lives on sound-soft cells (mask R = 0): their v is no unknown;
+the homogeneous step multiplies v by R on input and in the velocity update, and a forced step
+holds it at Re(-i w gD e^{-i w t}) at t_n (input) and t_{n+1} (output, ramped like the source).
+The state is zero there.
+
 Energy metric (eq. mix_cost_functional_J):  M_E = diag(h^2 on faces, h^2 / c^2 on cells).
 Riesz map: M_E^{-1} (the control space is L^2, so no elliptic solve is needed, Sec. 3).
 Output (eq. TH_FILTERED_MIXED_SOLUTION, discrete): V = (2/N) sum_{n<N} v^n e^{i w t_n},
@@ -71,9 +76,12 @@ class F1:
             m[-1, :] += 1
         self.m = m
         self.gamma = self.dt * self.c * m / (2.0 * self.h)
-        # data of each time-harmonic component: (m, f, g), angular frequency m * omega
+        # Dirichlet (sound-soft) cells: R = 0 there; v is held at the data, not an unknown
+        self.free = (np.ones((self.ny, self.nx)) if prob.sound_soft is None
+                     else 1.0 - np.asarray(prob.sound_soft, dtype=np.float64).reshape(self.ny, self.nx))
+        # data of each time-harmonic component: (m, f, g, gD), angular frequency m * omega
         self.comps = []
-        for m, f, gS, _ in _cmcg.components(prob):
+        for m, f, gS, gD in _cmcg.components(prob):
             f = (np.zeros((self.ny, self.nx), complex) if f is None
                  else np.asarray(f, dtype=complex).reshape(self.ny, self.nx))
             if gS is None:
@@ -81,7 +89,9 @@ class F1:
                      np.zeros(self.nx, complex), np.zeros(self.nx, complex)]
             else:
                 g = [np.asarray(a, dtype=complex).reshape(-1) for a in gS[:4]]
-            self.comps.append((m, f, g))
+            gD = (None if gD is None or prob.sound_soft is None
+                  else (1.0 - self.free) * np.asarray(gD, dtype=complex).reshape(self.ny, self.nx))
+            self.comps.append((m, f, g, gD))
         self.shapes = [(self.ny, self.nx - 1), (self.ny - 1, self.nx), (self.ny, self.nx)]
         self.sizes = [a * b for a, b in self.shapes]
         self.size = sum(self.sizes)
@@ -134,7 +144,7 @@ class F1:
         faces (p.n = gN); summed over the components, each at its own frequency m w."""
         h = self.h
         F = np.zeros((self.ny, self.nx))
-        for m, f, g in self.comps:
+        for m, f, g, _ in self.comps:
             e = np.exp(-1j * m * self.omega * t)
             F += (f * e).real
             F[:, 0] += (g[0] * e).real / h
@@ -143,40 +153,60 @@ class F1:
             F[-1, :] += (g[3] * e).real / h
         return F
 
+    def dirichlet_v(self, t: float) -> np.ndarray:
+        """v on the Dirichlet cells at time t (eq. mixWE_DBC): Re(-i m w gD e^{-i m w t}) summed
+        over the components (zero elsewhere)."""
+        out = np.zeros((self.ny, self.nx))
+        for m, _, _, gD in self.comps:
+            if gD is not None:
+                w = m * self.omega
+                out += (-1j * w * gD * np.exp(-1j * w * t)).real
+        return out
+
+    def has_dirichlet_data(self) -> bool:
+        return any(c[3] is not None for c in self.comps)
+
     # ---------------------------------------------------------------- time stepping
     def step(self, Px, Py, v, n: int, forced: bool, ramp=None):
         """Step n (t_n -> t_{n+1}); the source is sampled at t_{n+1/2} and multiplied by
-        ramp(t_{n+1/2}) when a ramp is given."""
-        dt, c, gam = self.dt, self.c, self.gamma
+        ramp(t_{n+1/2}) when a ramp is given.  On Dirichlet cells v is the data at t_n (input,
+        forced) or 0, and the data at t_{n+1} (ramped like the source) or 0 on output."""
+        dt, c, gam, R = self.dt, self.c, self.gamma, self.free
+        amp = (lambda t: 1.0) if ramp is None else ramp
+        dirichlet = forced and self.has_dirichlet_data()
+        v = R * v + ((1.0 - R) * amp(n * dt) * self.dirichlet_v(n * dt) if dirichlet else 0.0)
         gx, gy = self.grad(v)
         Px = Px + 0.5 * dt * gx
         Py = Py + 0.5 * dt * gy
         rhs = self.div(Px, Py)
         if forced:
             t = (n + 0.5) * dt
-            rhs = rhs + (1.0 if ramp is None else ramp(t)) * self.source(t)
-        v = ((1.0 - gam) * v + dt * c * c * rhs) / (1.0 + gam)
+            rhs = rhs + amp(t) * self.source(t)
+        v = R * ((1.0 - gam) * v + dt * c * c * rhs) / (1.0 + gam)
+        if dirichlet:
+            t1 = (n + 1) * dt
+            v = v + (1.0 - R) * amp(t1) * self.dirichlet_v(t1)
         gx, gy = self.grad(v)
         Px = Px + 0.5 * dt * gx
         Py = Py + 0.5 * dt * gy
         return Px, Py, v
 
     def step_T(self, Px, Py, v):
-        """Literal transpose of the homogeneous step: the transposes of its three sub-maps
-        (half kick, damped velocity update, half kick) applied in reverse order."""
-        dt, c, gam = self.dt, self.c, self.gamma
+        """Literal transpose of the homogeneous step: the transposes of its sub-maps (input
+        mask, half kick, masked damped velocity update, half kick) applied in reverse order."""
+        dt, c, gam, R = self.dt, self.c, self.gamma, self.free
         a = (1.0 - gam) / (1.0 + gam)
         b = dt * c * c / (1.0 + gam)
         # transpose of the second half kick  p <- p + dt/2 G v
         v = v + 0.5 * dt * self.grad_T(Px, Py)
-        # transpose of  v <- a v + b D p   (p unchanged)
-        tx, ty = self.div_T(b * v)
+        # transpose of  v <- R (a v + b D p)   (p unchanged)
+        tx, ty = self.div_T(b * R * v)
         Px = Px + tx
         Py = Py + ty
-        v = a * v
-        # transpose of the first half kick
+        v = a * R * v
+        # transpose of the first half kick, then of the input mask v <- R v
         v = v + 0.5 * dt * self.grad_T(Px, Py)
-        return Px, Py, v
+        return Px, Py, R * v
 
     def period(self, z: np.ndarray, forced: bool, t0_step: int = 0,
                steps: Optional[int] = None, ramp=None) -> np.ndarray:
@@ -185,7 +215,8 @@ class F1:
         Px, Py, v = self.unpack(z)
         for n in range(self.N if steps is None else steps):
             Px, Py, v = self.step(Px, Py, v, t0_step + n, forced, ramp)
-        return self.pack(Px, Py, v)
+        # the state is zero on the Dirichlet cells
+        return self.pack(Px, Py, self.free * v)
 
     def runup(self, periods: int, ramp: bool) -> np.ndarray:
         """State at t = periods T of the forced scheme started from rest, with the source
@@ -205,16 +236,21 @@ class F1:
 
     # ---------------------------------------------------------------- metric, Riesz
     def weights(self) -> np.ndarray:
-        """Diagonal of M_E."""
+        """Diagonal of M_E (zero on the Dirichlet cells, which carry no unknown)."""
         h2 = self.h * self.h
         return np.concatenate([np.full(self.sizes[0], h2), np.full(self.sizes[1], h2),
-                               (h2 / (self.c * self.c)).ravel()])
+                               (self.free * h2 / (self.c * self.c)).ravel()])
 
     def ME(self, w):
         return self.weights() * w
 
     def riesz(self, rhat):
-        return rhat / self.weights()
+        """M_E^{-1} on the unknowns (zero on the Dirichlet cells)."""
+        w = self.weights()
+        out = np.zeros_like(rhat)
+        nz = w > 0
+        out[nz] = rhat[nz] / w[nz]
+        return out
 
     def energy(self, Px, Py, v) -> float:
         """Discrete energy conserved by the undamped scheme:
@@ -247,12 +283,14 @@ class F1:
         components, one such sum per component at its frequency m w (u = i V / (m w)) over the
         same period; the result is then stacked, shape (components, ny, nx)."""
         Px, Py, v = self.unpack(z)
+        # v^0 on the Dirichlet cells is the data at t = 0
+        v = self.free * v + (1.0 - self.free) * self.dirichlet_v(0.0)
         V = [np.zeros((self.ny, self.nx), complex) for _ in self.comps]
         for n in range(self.N):
-            for c, (m, _, _) in enumerate(self.comps):
+            for c, (m, _, _, _) in enumerate(self.comps):
                 V[c] += v * np.exp(1j * m * self.omega * n * self.dt)
             Px, Py, v = self.step(Px, Py, v, n, True)
-        U = [1j * (2.0 / self.N) * Vc / (m * self.omega) for Vc, (m, _, _) in zip(V, self.comps)]
+        U = [1j * (2.0 / self.N) * Vc / (c[0] * self.omega) for Vc, c in zip(V, self.comps)]
         return U[0] if len(U) == 1 else np.stack(U)
 
     def step6_output(self, z: np.ndarray) -> np.ndarray:
@@ -266,6 +304,10 @@ class F1:
         Px, Py, v = self.unpack(z)
         dt, h = self.dt, self.h
         th = 0.5 * self.omega * dt
+        _, f, g, gD = self.comps[0]
+        # Dirichlet cells: V = -i omega gD is data; its real part is v_0 there
+        VD = np.zeros((self.ny, self.nx), complex) if gD is None else -1j * self.omega * gD
+        v = self.free * v + (1.0 - self.free) * VD.real
         gx, gy = self.grad(v)
         Qx = Px / math.cos(th) + 1j * dt * gx / (2.0 * math.sin(th))
         Qy = Py / math.cos(th) + 1j * dt * gy / (2.0 * math.sin(th))
@@ -274,13 +316,13 @@ class F1:
         DQ[:, 1:] -= Qx / h
         DQ[:-1, :] += Qy / h
         DQ[1:, :] -= Qy / h
-        _, f, g = self.comps[0]
         Fhat = f.copy()
         Fhat[:, 0] += g[0] / h
         Fhat[:, -1] += g[1] / h
         Fhat[0, :] += g[2] / h
         Fhat[-1, :] += g[3] / h
         V = dt * self.c ** 2 * (Fhat + DQ) / (-2j * math.sin(th) + 2.0 * self.gamma * math.cos(th))
+        V = self.free * V + (1.0 - self.free) * VD
         return 1j * V / self.omega
 
     def functional(self, z):
@@ -296,7 +338,7 @@ class F1:
         Fhat = f + (1/h) sum over the boundary faces of g (gS or gN), for component `comp`
         (w its frequency m omega, same dt)."""
         nx, ny, h, dt = self.nx, self.ny, self.h, self.dt
-        m, f, g = self.comps[comp]
+        m, f, g, gD = self.comps[comp]
         th = 0.5 * m * self.omega * dt
 
         def d1(m):
@@ -318,6 +360,16 @@ class F1:
         Fhat[0, :] += g[2] / h
         Fhat[-1, :] += g[3] / h
         rhs = np.concatenate([np.zeros(nf, complex), dt * c2 * Fhat.ravel()])
+        dcells = np.flatnonzero(self.free.ravel() < 0.5)
+        if dcells.size:
+            # Dirichlet cells: V = -i m omega gD is known (eq. mixWE_DBC); identity rows
+            rows = nf + dcells
+            A = A.tolil()
+            A[rows, :] = 0.0
+            A[rows, rows] = 1.0
+            A = A.tocsc()
+            VD = np.zeros(nx * ny, complex) if gD is None else -1j * m * self.omega * gD.ravel()
+            rhs[rows] = VD[dcells]
         return A, rhs, nf
 
     def direct(self):
@@ -327,12 +379,12 @@ class F1:
         m omega dt / 2) and the periodic state is the sum of the components' states (the
         scheme is linear)."""
         U, z = [], np.zeros(self.size)
-        for c, (m, _, _) in enumerate(self.comps):
+        for c, (m, _, _, _) in enumerate(self.comps):
             A, rhs, nf = self.frequency_system(c)
             x = spla.spsolve(A, rhs)
             Q, V = x[:nf], x[nf:]
             th = 0.5 * m * self.omega * self.dt
-            z = z + np.concatenate([math.cos(th) * Q.real, V.real])
+            z = z + np.concatenate([math.cos(th) * Q.real, self.free.ravel() * V.real])
             U.append((1j * V / (m * self.omega)).reshape(self.ny, self.nx))
         return (U[0] if len(U) == 1 else np.stack(U)), z
 
