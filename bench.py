@@ -270,6 +270,49 @@ def supershot_study(n: int = 2048, base_freq: float = 25.0, harmonics=(1, 2, 4))
             "separate_over_supershot": round(total / sup["seconds"], 3)}
 
 
+def obstacle_study_2d(n: int = 400, freq: float = 10.0, side: float = 0.3,
+                      longtime=(16, 64, 256, 1024)):
+    """The same comparison in 2D on the first-order scheme with Dirichlet cells: a box ten
+    wavelengths wide (c = 1, k = 2 pi freq, h = 1/n), plane wave at 135 degrees, a sound-soft
+    square of the given side or a square cavity of that size open on its -x wall."""
+    import numpy as np
+    import torch
+    import cmcg_inputs as ci
+    from paper_1903_12522_amd import cmcg
+    out = {}
+    for name, cav in (("square", False), ("cavity", True)):
+        prob = ci.sound_soft_square_2d(n=n, freq=freq, side=side, cavity=cav)
+        with cmcg.Solver(prob, "fp32", tol=1e-6, max_iter=20000) as s:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U, rep = s.solve()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        res = {"workload": f"first-order {n}^2, {freq:g} wavelengths across, sound-soft {name} "
+                           f"of side {side}, plane wave at 135 degrees",
+               "cmcg": {"seconds": round(wall, 3), "iterations": rep["iterations"],
+                        "converged": rep["converged"],
+                        "periods": 2 * rep["iterations"] + 2 * rep["fp64_refreshes"] + 3},
+               "do_nothing": []}
+        log(f"2D {name}: CMCG {wall:.2f} s, {rep['iterations']} iterations")
+        with cmcg.Solver(prob, "fp64") as s:
+            J0 = s.misfit(np.zeros(s.info["state_len"]))
+            for L in longtime:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                z = s.runup(L, ramp=False)
+                torch.cuda.synchronize()
+                w = time.perf_counter() - t0
+                J = s.misfit(z)
+                err = float(np.linalg.norm(s.filter(z) - U) / np.linalg.norm(U))
+                res["do_nothing"].append({"periods": L, "seconds": round(w, 3),
+                                          "relative_misfit": float(np.sqrt(J / J0)),
+                                          "filtered_rel_error_vs_cmcg": err})
+                log(f"2D {name}: do-nothing {L} periods: misfit {np.sqrt(J / J0):.3e}, error {err:.3e}")
+        out[name] = res
+    return out
+
+
 def cpu_baseline(prob, steps: int = 20):
     """The oracle as it stands, on the full grid: `steps` forward leapfrog steps plus `steps`
     transposed steps (the two halves of a CG iteration), timed on one host core."""
@@ -366,7 +409,7 @@ def main():
     alg_bytes = bytes_per_update * cells * kb       # per launch: kb leapfrog steps of every cell
     dom, dom_t, other_t = ("adjoint", adj, fwd) if adj >= fwd else ("forward", fwd, adj)
     achieved = alg_bytes / dom_t / 1e9
-    kname = f"f1_stream_kernel<float, {kb}, {'true' if dom == 'adjoint' else 'false'}>"
+    kname = f"f1_stream_kernel<float, {kb}, {'true' if dom == 'adjoint' else 'false'}, false>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 3),
                 "traffic": measured_traffic(kname),
@@ -419,6 +462,7 @@ def main():
         out["runup_study"] = runup_study(prob)
     if args.obstacle_study:
         out["obstacle_study"] = obstacle_study()
+        out["obstacle_study_2d"] = obstacle_study_2d()
     if args.supershot_study:
         out["supershot_study"] = supershot_study()
 

@@ -10,8 +10,8 @@
  * creates).  The handle owns all device memory it allocates until cmcg_destroy.
  *
  * Problem (eq. HE):  -lap u - k^2 u = f in the box [0, n_x h] x [0, n_y h] (x [0, n_z h]),
- * h = 1 / n_x, k = omega / c(x);  du/dn - i k u = gS on absorbing faces, du/dn = 0 on
- * Neumann faces, u = 0 on sound-soft nodes.  Time domain (eq. WE / eq. mixWE): the forced
+ * h = 1 / n_x, k = omega / c(x);  du/dn - i k u = gS on absorbing faces, du/dn = gN on
+ * Neumann faces, u = gD on sound-soft nodes (F2) or cells (F1).  Time domain (eq. WE / eq. mixWE): the forced
  * wave equation with source Re(f e^{-i omega t}) and boundary data Re(gS e^{-i omega t});
  * one period T = 2 pi / omega is N = ceil(T c_max / (courant h)) leapfrog steps, dt = T / N.
  *
@@ -85,9 +85,11 @@ typedef struct {
   const double *gS_re, *gS_im; /* boundary data, concatenated faces: gS on absorbing faces
                                   (du/dn - i k u = gS), gN on Neumann faces (du/dn = gN);
                                   either may be NULL (zero)                                    */
-  const uint8_t *sound_soft;   /* F2: 1 = Dirichlet node; NULL = none                          */
-  const double *gD_re, *gD_im; /* F2: Dirichlet data u = gD on the sound-soft nodes (layout of
-                                  c, read on those nodes only); NULL = homogeneous              */
+  const uint8_t *sound_soft;   /* 1 = Dirichlet node (F2) or cell (F1), layout of c; NULL = none.
+                                  F1 Dirichlet cells hold v = Re(-i omega gD e^{-i omega t})
+                                  (eq. mixWE_DBC) and carry no unknown                         */
+  const double *gD_re, *gD_im; /* Dirichlet data u = gD on the sound-soft nodes or cells (layout
+                                  of c, read there only); NULL = homogeneous                   */
   int32_t face_bc[6];          /* -x,+x,-y,+y,-z,+z: CMCG_ABSORBING or CMCG_NEUMANN            */
   double courant;              /* sigma in (0, 1/sqrt(dim)); 0 -> 0.5                          */
   int32_t n_shots;             /* 0: one time-harmonic source at omega with the data above.

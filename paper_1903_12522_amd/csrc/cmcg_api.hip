@@ -63,9 +63,8 @@ cmcg_status validate_problem(const cmcg_problem *P, const cmcg_options *O) {
     }
   }
   for (const cmcg_shot &sh : shots_of(P))
-    if ((sh.gD_re || sh.gD_im) && (P->formulation != 2 || !P->sound_soft))
-      return set_error("Dirichlet data needs the nodal formulation and a sound-soft mask"),
-             CMCG_EINVAL;
+    if ((sh.gD_re || sh.gD_im) && !P->sound_soft)
+      return set_error("Dirichlet data needs a sound-soft mask"), CMCG_EINVAL;
   if (O->output != CMCG_OUTPUT_FILTER && O->output != CMCG_OUTPUT_STEP6)
     return set_error("output must be CMCG_OUTPUT_FILTER or CMCG_OUTPUT_STEP6"), CMCG_EINVAL;
   if (O->output == CMCG_OUTPUT_STEP6) {

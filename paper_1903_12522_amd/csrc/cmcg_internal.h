@@ -75,6 +75,10 @@ struct F1Geom {
   int nx, ny, pitch;
   double h, dt;
   int abs_face[4];     // 1 if the -x, +x, -y, +y face is absorbing
+  // Dirichlet (sound-soft) cells, 1 per masked cell in the device layout, or null; the box of
+  // the masked cells: columns mlo[0]..mhi[0], rows mlo[1]..mhi[1]
+  const uint8_t *mask;
+  int mlo[2], mhi[2];
 };
 
 constexpr int kMaxBlockSteps = 8;
@@ -87,6 +91,9 @@ struct F1Launch {
   int accumulate;      // filter: add v^n (fc, fs) to (Ure, Uim) before stepping (KMAX = 1)
   double cs[kMaxBlockSteps], sn[kMaxBlockSteps];   // cos/sin(omega t) at each step's source time
   double fcos, fsin;   // filter weights cos/sin(omega t_n)
+  // Dirichlet cells of a forced period: v = dre dc[k] + dim ds[k] at the launch's input time
+  // (k = 0) and at the output time of level k (k >= 1)
+  double dc[kMaxBlockSteps + 1], ds[kMaxBlockSteps + 1];
 };
 
 template <typename T>
@@ -98,6 +105,7 @@ struct F1Ptrs {
   const T *fre, *fim;  // forcing amplitude per cell (fim may be nullptr)
   double *ure, *uim;   // filter accumulators (cell field, FP64)
   size_t fs;           // field stride in elements (ny * pitch)
+  const double *dre, *dim;   // Dirichlet data of v on the masked cells (dim may be null)
 };
 
 // One solve's share of a batched (multi-solve) launch.

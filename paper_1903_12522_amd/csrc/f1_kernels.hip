@@ -52,7 +52,18 @@ __device__ __forceinline__ void tile_of_block(int &bx, int &by) {
 // EDGE = false is the compile-time fast path of wavefronts whose 64 columns are all interior
 // (1 <= i <= nx-2): no column masks and no absorbing faces except on the first and last row,
 // which are wave-uniform branches.
-template <typename T, int K, bool ADJ, bool EDGE>
+// MASK = true handles Dirichlet (sound-soft) cells, R = 0: their v carries no unknown.  Forward:
+// a forced period holds v there at the data (at the input time when the period starts, at each
+// level's output time after its update), a homogeneous one at 0.  Backward (the transposed
+// step): v enters the velocity update as R v.  The period's last launch stores v = 0 there.
+template <typename T>
+__device__ __forceinline__ T f1_dirichlet(const F1Ptrs<T> &p, size_t o, double dc, double ds) {
+  double v = p.dre[o] * dc;
+  if (p.dim) v = fma(p.dim[o], ds, v);
+  return (T)v;
+}
+
+template <typename T, int K, bool ADJ, bool EDGE, bool MASK>
 __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, const int i, const int lane,
                                                const int s0, const int s1) {
@@ -72,11 +83,14 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
   T Vp[K + 1], PXp[K + 1], PYp[K + 1], CCp[K + 1];
   T Vc[K + 1], PXc[K + 1], PYc[K + 1], CCc[K + 1];
   T HOLD[K + 1];   // level 0: raw Py of the current row; adjoint level k: Py^k(r) one row ahead
+  T RMp[K + 1], RMc[K + 1];   // MASK: R of the emitted row (1 free, 0 Dirichlet)
+  const bool dirichlet = MASK && !ADJ && L.forced && p.dre != nullptr;
 #pragma unroll
   for (int k = 0; k <= K; ++k) {
     Vp[k] = PXp[k] = PYp[k] = CCp[k] = T(0);
     Vc[k] = PXc[k] = PYc[k] = CCc[k] = T(0);
     HOLD[k] = T(0);
+    RMp[k] = RMc[k] = T(1);
   }
   const int jstart = s0 - K - 2, jend = s1 + K;
   if (colIn && jstart - 1 >= 0 && jstart - 1 < ny) HOLD[0] = p.in[(size_t)(jstart - 1) * pitch + i + fs];
@@ -92,6 +106,12 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
       px0 = p.in[o0];
       py0 = p.in[o0 + fs];
       c0 = p.cc[o0];
+    }
+    T rm0 = T(1);
+    if (MASK) {
+      if (in0 && g.mask[o0]) rm0 = T(0);
+      // a period starts from a state that is zero on the Dirichlet cells
+      if (L.first && rm0 == T(0)) v0 = dirichlet ? f1_dirichlet(p, o0, L.dc[0], L.ds[0]) : T(0);
     }
     if (L.accumulate && laneOut && j >= s0 && j < s1) {
       const double vv = (double)v0;
@@ -116,6 +136,7 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
     PXc[0] = px0;
     PYc[0] = pyprev;
     CCc[0] = c0;
+    RMc[0] = rm0;
 
     // ---- levels 1..K
 #pragma unroll
@@ -148,6 +169,8 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
             vn = fma(kap, dsum, (T(1) - gam) * v) / (T(1) + gam);
           }
         }
+        if (MASK && cin && RMp[k - 1] == T(0))
+          vn = dirichlet ? f1_dirichlet(p, (size_t)r * pitch + i, L.dc[k], L.ds[k]) : T(0);
         const T vr = lane_from_right(vn);
         const T pxn = (cin && pxCol) ? fma(kick_h, vr - vn, px) : px;
         const bool pyv = colIn && (r - 1 >= 0) && (r - 1 <= ny - 2);
@@ -156,9 +179,13 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
         PXc[k] = pxn;
         PYc[k] = pyn;
         CCc[k] = kap;
+        RMc[k] = RMp[k - 1];
       } else {
-        // inputs: v^{k-1}(r+1) (current), v^{k-1}(r), Px^{k-1}(r) (previous), Py^{k-1}(r)
-        const T vA = Vc[k - 1], vB = Vp[k - 1], pxB = PXp[k - 1], pyB = PYc[k - 1];
+        // inputs: v^{k-1}(r+1) (current), v^{k-1}(r), Px^{k-1}(r) (previous), Py^{k-1}(r); the
+        // velocities enter as R v
+        const T vA = MASK ? Vc[k - 1] * RMc[k - 1] : Vc[k - 1];
+        const T vB = MASK ? Vp[k - 1] * RMp[k - 1] : Vp[k - 1];
+        const T pxB = PXp[k - 1], pyB = PYc[k - 1];
         const T kA = CCc[k - 1], kB = CCp[k - 1];
         const int rA = r + 1;
         T wA = vA, wB = vB, aB = T(1);
@@ -188,6 +215,7 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
         PYc[k] = HOLD[k];
         HOLD[k] = pyn;
         CCc[k] = kB;
+        RMc[k] = RMp[k - 1];
       }
     }
 
@@ -197,6 +225,7 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
       if (ro >= s0 && ro < s1) {
         const size_t o = (size_t)ro * pitch + i;
         T a = PXc[K], c = Vc[K];
+        if (MASK && L.last && RMc[K] == T(0)) c = T(0);   // the state is zero there
         if (p.sub) {
           a -= p.sub[o];
           c -= p.sub[o + 2 * fs];
@@ -217,6 +246,7 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
       PXp[k] = PXc[k];
       PYp[k] = PYc[k];
       CCp[k] = CCc[k];
+      RMp[k] = RMc[k];
     }
   }
 }
@@ -376,7 +406,7 @@ __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> 
 // Tile (bx, by) of a launch: wavefront w of the workgroup owns column strip 4 bx + w of the
 // band of rows by.  Interior wavefronts (all 64 columns in 1..nx-2) of interior bands take the
 // fast variant.
-template <typename T, int K, bool ADJ>
+template <typename T, int K, bool ADJ, bool MASK>
 __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, int band, int bx, int by) {
   constexpr int H = K + 1;             // lanes lost on each side: K levels + the opening kick
@@ -390,20 +420,31 @@ __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> 
   const bool inner_cols = i0 >= 1 && i0 + 63 <= g.nx - 2;
   const bool inner_rows = s0 >= 2 * K + 3 && s1 + K <= g.ny - 2;
   const bool small = 3ull * p.fs * sizeof(T) <= kBufMax;
+  if (MASK) {
+    // wavefronts whose columns and pipeline rows (s0 - K - 3 .. s1 + K) meet the box of the
+    // Dirichlet cells take the masked body; the others never touch a masked cell
+    const bool meets = i0 + 63 >= g.mlo[0] && i0 <= g.mhi[0] && s1 + K >= g.mlo[1] &&
+                       s0 - K - 3 <= g.mhi[1];
+    if (meets) {
+      if (inner_cols) f1_stream_body<T, K, ADJ, false, true>(g, p, L, i0 + lane, lane, s0, s1);
+      else f1_stream_body<T, K, ADJ, true, true>(g, p, L, i0 + lane, lane, s0, s1);
+      return;
+    }
+  }
   if (inner_cols && inner_rows && small && !p.sub && !L.first && !L.forced && !L.accumulate)
     f1_stream_fast<T, K, ADJ>(g, p, L, i0 + lane, lane, s0, s1);
   else if (inner_cols)
-    f1_stream_body<T, K, ADJ, false>(g, p, L, i0 + lane, lane, s0, s1);
+    f1_stream_body<T, K, ADJ, false, false>(g, p, L, i0 + lane, lane, s0, s1);
   else
-    f1_stream_body<T, K, ADJ, true>(g, p, L, i0 + lane, lane, s0, s1);
+    f1_stream_body<T, K, ADJ, true, false>(g, p, L, i0 + lane, lane, s0, s1);
 }
 
-template <typename T, int K, bool ADJ>
+template <typename T, int K, bool ADJ, bool MASK>
 __global__ __launch_bounds__(kThreads) void f1_stream_kernel(F1Geom g, F1Ptrs<T> p, F1Launch L,
                                                              int band) {
   int bx, by;
   tile_of_block(bx, by);
-  f1_stream_tile<T, K, ADJ>(g, p, L, band, bx, by);
+  f1_stream_tile<T, K, ADJ, MASK>(g, p, L, band, bx, by);
 }
 
 // Several independent solves in one launch (continuous batching): workgroup b belongs to the
@@ -419,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void f1_multi_kernel(const F1SlotLaunch<T
   const F1Ptrs<T> p = slots[s].p;
   const F1Launch L = slots[s].L;
   const int t = (int)blockIdx.x - slots[s].block0;
-  f1_stream_tile<T, K, ADJ>(g, p, L, slots[s].band, t % slots[s].nbx, t / slots[s].nbx);
+  f1_stream_tile<T, K, ADJ, false>(g, p, L, slots[s].band, t % slots[s].nbx, t / slots[s].nbx);
 }
 
 // Rows per band: enough wavefronts to fill 256 CUs several times over, long enough bands to
@@ -444,7 +485,12 @@ hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hi
   const int strips = (g.nx + OW - 1) / OW;
   const int band = band_rows(g.nx, g.ny, K);
   dim3 grid((strips + 3) / 4, (g.ny + band - 1) / band);
-  hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ>), grid, dim3(kThreads), 0, s, g, p, L, band);
+  if (g.mask)
+    hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ, true>), grid, dim3(kThreads), 0, s, g, p, L,
+                       band);
+  else
+    hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ, false>), grid, dim3(kThreads), 0, s, g, p, L,
+                       band);
   return hipGetLastError();
 }
 

@@ -78,9 +78,13 @@ struct ShotWeights {
 
 // Source field of one step of a multi-frequency forced period: sum_j (Fre_j c_j + Fim_j s_j) at
 // the step's source time (h Fhat summed over the components), which the streaming kernel then
-// reads with weight 1 as it reads a single component's field.
+// reads with weight 1 as it reads a single component's field; and, with Dirichlet data, v on the
+// Dirichlet cells summed over the components at the step's input time (DA, weights w0) and
+// output time (DB, weights w1).
 template <typename T>
-__global__ void f1_combine_kernel(const T *Fre, const T *Fim, ShotWeights w, T *out, size_t fs) {
+__global__ void f1_combine_kernel(const T *Fre, const T *Fim, ShotWeights w, T *out,
+                                  const double *Dre, const double *Dim, ShotWeights w0,
+                                  ShotWeights w1, double *DA, double *DB, size_t fs) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
     double a = 0.0;
@@ -91,15 +95,28 @@ __global__ void f1_combine_kernel(const T *Fre, const T *Fim, ShotWeights w, T *
       if (Fim) a = fma((double)Fim[j * fs + o], w.s[j], a);
     }
     out[o] = (T)a;
+    if (Dre) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < CMCG_MAX_SHOTS; ++j) {
+        if (j >= w.nshots) break;
+        const double dr = Dre[j * fs + o], di = Dim ? Dim[j * fs + o] : 0.0;
+        a0 = fma(dr, w0.c[j], fma(di, w0.s[j], a0));
+        a1 = fma(dr, w1.c[j], fma(di, w1.s[j], a1));
+      }
+      DA[o] = a0;
+      DB[o] = a1;
+    }
   }
 }
 
-// Filter sums of a multi-frequency problem at one step: (Ure_j, Uim_j) += v (cos, sin)(m_j w t_n)
-__global__ void f1_accumulate_kernel(const double *v, ShotWeights w, double *ure, double *uim,
-                                     size_t fs) {
+// Filter sums of a multi-frequency problem at one step: (Ure_j, Uim_j) += v (cos, sin)(m_j w t_n);
+// on the Dirichlet cells v is the data at t_n (DA)
+__global__ void f1_accumulate_kernel(const double *v, const uint8_t *mask, const double *DA,
+                                     ShotWeights w, double *ure, double *uim, size_t fs) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
-    const double x = v[o];
+    const double x = (mask && mask[o]) ? (DA ? DA[o] : 0.0) : v[o];
 #pragma unroll
     for (int j = 0; j < CMCG_MAX_SHOTS; ++j) {
       if (j >= w.nshots) break;
@@ -113,23 +130,38 @@ __global__ void f1_accumulate_kernel(const double *v, ShotWeights w, double *ure
 // on its interior faces Q = P_0 / cos(theta) + i (dt/h) (difference of v_0 across the face) /
 // (2 sin(theta)), then V = kap (h Fhat + sum of signed face Q) / (-2 i sin(theta) +
 // 2 gamma cos(theta)) and u = i V / omega into (ure, uim) (device layout).  kap = dt c^2 / h.
+// Dirichlet cells (mask): V = dre + i dim is data (the amplitude -i omega gD of v), its real
+// part stands for v_0 there.
+__device__ __forceinline__ double f1_v0(const double *v, const uint8_t *mask, const double *dre,
+                                        size_t o) {
+  if (mask && mask[o]) return dre ? dre[o] : 0.0;
+  return v[o];
+}
+
 __global__ void f1_step6_kernel(F1Geom g, const double *z, const double *cc, const double *Fre,
-                                const double *Fim, double theta, double omega, double *ure,
-                                double *uim, size_t fs) {
+                                const double *Fim, const double *dre, const double *dim,
+                                double theta, double omega, double *ure, double *uim, size_t fs) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const int nx = g.nx, ny = g.ny;
   const size_t pitch = (size_t)g.pitch;
   const double dth = g.dt / g.h, ic = 1.0 / cos(theta), is2 = 0.5 / sin(theta);
   const double *px = z, *py = z + fs, *v = z + 2 * fs;
+  const uint8_t *mask = g.mask;
   for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
     const int j = (int)(o / pitch), i = (int)(o % pitch);
     if (i >= nx) continue;
+    if (mask && mask[o]) {
+      const double Vr = dre ? dre[o] : 0.0, Vi = dim ? dim[o] : 0.0;
+      ure[o] = -Vi / omega;
+      uim[o] = Vr / omega;
+      continue;
+    }
     const double vc = v[o];
     double sr = 0.0, si = 0.0;           // sum over the faces of the outward flux amplitude
-    if (i <= nx - 2) { sr += px[o] * ic;          si += dth * (v[o + 1] - vc) * is2; }
-    if (i >= 1)      { sr -= px[o - 1] * ic;      si -= dth * (vc - v[o - 1]) * is2; }
-    if (j <= ny - 2) { sr += py[o] * ic;          si += dth * (v[o + pitch] - vc) * is2; }
-    if (j >= 1)      { sr -= py[o - pitch] * ic;  si -= dth * (vc - v[o - pitch]) * is2; }
+    if (i <= nx - 2) { sr += px[o] * ic;          si += dth * (f1_v0(v, mask, dre, o + 1) - vc) * is2; }
+    if (i >= 1)      { sr -= px[o - 1] * ic;      si -= dth * (vc - f1_v0(v, mask, dre, o - 1)) * is2; }
+    if (j <= ny - 2) { sr += py[o] * ic;          si += dth * (f1_v0(v, mask, dre, o + pitch) - vc) * is2; }
+    if (j >= 1)      { sr -= py[o - pitch] * ic;  si -= dth * (vc - f1_v0(v, mask, dre, o - pitch)) * is2; }
     const double kap = cc[o];
     const double nr = kap * (Fre[o] + sr), ni = kap * ((Fim ? Fim[o] : 0.0) + si);
     const int m = (i == 0 ? g.abs_face[0] : 0) + (i == nx - 1 ? g.abs_face[1] : 0) +
@@ -182,6 +214,11 @@ class F1Solver final : public Solver {
   bool mixed = false;
   void *D = nullptr;     // search direction, lo precision
   double *Z = nullptr, *R = nullptr, *Ure = nullptr, *Uim = nullptr;   // filter sums: nshots fields
+  uint8_t *mask = nullptr;     // Dirichlet cells (device layout), or null
+  // Dirichlet data of v, one field pair per component: v = Dre cos(m w t) + Dim sin(m w t),
+  // Dre = m w Im(gD), Dim = -m w Re(gD) (the real part of -i m w gD e^{-i m w t}); or null
+  double *Dre = nullptr, *Dim = nullptr;
+  double *DA = nullptr, *DB = nullptr;   // several components: v on the Dirichlet cells of a step
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
   bool started = false;
   bool multi = false;    // several source components: per-step source fields, separate filter sums
@@ -235,6 +272,7 @@ class F1Solver final : public Solver {
     CMCG_TRY(arena.alloc_n(kNumScalars, &scalars, s));
     // host inputs -> temporary device copies -> setup kernels for each set and component
     const size_t ncell = (size_t)nx * ny, nface = 2 * (size_t)ny + 2 * (size_t)nx;
+    if (P->sound_soft) CMCG_TRY(setup_dirichlet(P, shots));
     for (int j = 0; j < J; ++j) {
       DeviceArena tmp;
       const double *src[5] = {P->c, shots[j].f_re, shots[j].f_im, shots[j].gS_re, shots[j].gS_im};
@@ -255,6 +293,53 @@ class F1Solver final : public Solver {
                            dev[0], P->c_const, dev[1], dev[2], dev[3], dev[4], tp<float>(lo.cc),
                            tp<float>(lo.Fre) + off, lo.Fim ? tp<float>(lo.Fim) + off : nullptr, fs);
         CMCG_HIP(hipGetLastError());
+      }
+      CMCG_HIP(hipStreamSynchronize(s));
+    }
+    return CMCG_OK;
+  }
+
+  // Dirichlet cells: the mask in the device layout and its box, and the data fields of v
+  cmcg_status setup_dirichlet(const cmcg_problem *P, const std::vector<cmcg_shot> &shots) {
+    const int nx = g.nx, ny = g.ny, J = (int)shots.size();
+    int lo[2] = {1 << 30, 1 << 30}, hi2[2] = {-1, -1};
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        if (P->sound_soft[(size_t)j * nx + i]) {
+          lo[0] = std::min(lo[0], i), hi2[0] = std::max(hi2[0], i);
+          lo[1] = std::min(lo[1], j), hi2[1] = std::max(hi2[1], j);
+        }
+    if (hi2[0] < 0) return CMCG_OK;          // an empty mask
+    CMCG_TRY(arena.alloc_n(fs, &mask, s));
+    CMCG_HIP(hipMemcpy2DAsync(mask, g.pitch, P->sound_soft, nx, nx, ny, hipMemcpyHostToDevice, s));
+    g.mask = mask;
+    for (int a = 0; a < 2; ++a) {
+      g.mlo[a] = lo[a];
+      g.mhi[a] = hi2[a];
+    }
+    bool has_d = false;
+    for (const cmcg_shot &sh : shots) has_d = has_d || sh.gD_re || sh.gD_im;
+    if (has_d) {
+      std::vector<double> hre((size_t)J * fs, 0.0), him((size_t)J * fs, 0.0);
+      for (int c = 0; c < J; ++c) {
+        const double w = cfg.omega_of(c);
+        for (int j = 0; j < ny; ++j)
+          for (int i = 0; i < nx; ++i) {
+            const size_t u = (size_t)j * nx + i, o = (size_t)c * fs + (size_t)j * g.pitch + i;
+            if (!P->sound_soft[u]) continue;
+            const double gr = shots[c].gD_re ? shots[c].gD_re[u] : 0.0;
+            const double gi = shots[c].gD_im ? shots[c].gD_im[u] : 0.0;
+            hre[o] = w * gi;
+            him[o] = -w * gr;
+          }
+      }
+      CMCG_TRY(arena.alloc_n((size_t)J * fs, &Dre, s));
+      CMCG_TRY(arena.alloc_n((size_t)J * fs, &Dim, s));
+      CMCG_HIP(hipMemcpyAsync(Dre, hre.data(), hre.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      CMCG_HIP(hipMemcpyAsync(Dim, him.data(), him.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      if (J > 1) {
+        CMCG_TRY(arena.alloc_n(fs, &DA, s));
+        CMCG_TRY(arena.alloc_n(fs, &DB, s));
       }
       CMCG_HIP(hipStreamSynchronize(s));
     }
@@ -303,6 +388,14 @@ class F1Solver final : public Solver {
     }
     L.fcos = std::cos(w0 * n0 * cfg.dt);              // filter weight at t_n
     L.fsin = std::sin(w0 * n0 * cfg.dt);
+    // Dirichlet cells: the data at the launch's input time t_n0 (k = 0) and at each level's
+    // output time t_{n0+k}; several components read DB (output) and DA (input) with weights
+    // (1, 0) and (0, 1)
+    for (int k = 0; k <= ns; ++k) {
+      const double t = (n0 + k) * cfg.dt, amp = transient(t_offset + t, t_tr);
+      L.dc[k] = multi ? (k == 0 ? 0.0 : 1.0) : amp * std::cos(w0 * t);
+      L.ds[k] = multi ? (k == 0 ? 1.0 : 0.0) : amp * std::sin(w0 * t);
+    }
     F1Ptrs<T> p{};
     p.in = (l == 0) ? in : S[(l - 1) & 1];
     p.out = lastl ? out : S[l & 1];
@@ -313,9 +406,25 @@ class F1Solver final : public Solver {
     p.ure = Ure;
     p.uim = Uim;
     p.fs = fs;
+    if (forced && Dre) {
+      p.dre = multi ? DB : Dre;
+      p.dim = multi ? DA : Dim;
+    }
     *pp = p;
     *LL = L;
     return ns;
+  }
+
+  // Weights of the components' Dirichlet data at t_n (ramped)
+  ShotWeights dirichlet_weights(int n) const {
+    ShotWeights w;
+    w.nshots = cfg.nshots;
+    const double t = n * cfg.dt, amp = transient(t_offset + t, t_tr);
+    for (int j = 0; j < cfg.nshots; ++j) {
+      w.c[j] = amp * std::cos(cfg.omega_of(j) * t);
+      w.s[j] = amp * std::sin(cfg.omega_of(j) * t);
+    }
+    return w;
   }
 
   // Weights of the components at step n: the source at t_{n+1/2} (ramped) if `source`, else
@@ -364,13 +473,15 @@ class F1Solver final : public Solver {
       const int ns = build_launch<T>(b, forced, in, out, sub, steps, n0, K, filter, &p, &L);
       if (multi && forced) {
         hipLaunchKernelGGL((f1_combine_kernel<T>), dim3(grid_for(fs)), dim3(256), 0, s,
-                           tpc<T>(b.Fre), tpc<T>(b.Fim), shot_weights(n0, true), tp<T>(b.Fk), fs);
+                           tpc<T>(b.Fre), tpc<T>(b.Fim), shot_weights(n0, true), tp<T>(b.Fk),
+                           Dre, Dim, dirichlet_weights(n0), dirichlet_weights(n0 + 1), DA, DB,
+                           fs);
         CMCG_HIP(hipGetLastError());
       }
       if (multi && filter) {
-        // v^n of the launch's input state
+        // v^n of the launch's input state (the data on the Dirichlet cells)
         hipLaunchKernelGGL(f1_accumulate_kernel, dim3(grid_for(fs)), dim3(256), 0, s,
-                           reinterpret_cast<const double *>(p.in) + 2 * fs,
+                           reinterpret_cast<const double *>(p.in) + 2 * fs, mask, DA,
                            shot_weights(n0, false), Ure, Uim, fs);
         CMCG_HIP(hipGetLastError());
       }
@@ -555,8 +666,8 @@ class F1Solver final : public Solver {
              CMCG_EINVAL;
     double *ore = tp<double>(hi.S1), *oim = tp<double>(hi.S1) + fs;
     hipLaunchKernelGGL(f1_step6_kernel, dim3(grid_for(fs)), dim3(256), 0, s, g, zdev,
-                       tpc<double>(hi.cc), tpc<double>(hi.Fre), tpc<double>(hi.Fim),
-                       0.5 * cfg.omega * cfg.dt, cfg.omega, ore, oim, fs);
+                       tpc<double>(hi.cc), tpc<double>(hi.Fre), tpc<double>(hi.Fim), Dre, Dim,
+                       0.5 * cfg.omega_of(0) * cfg.dt, cfg.omega_of(0), ore, oim, fs);
     CMCG_HIP(hipGetLastError());
     const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
     if (u_re) CMCG_HIP(hipMemcpy2DAsync(u_re, row, ore, pitchb, row, g.ny, hipMemcpyDefault, s));
@@ -782,6 +893,8 @@ class F1Server final : public Server {
              CMCG_EUNSUPPORTED;
     if (O->output != CMCG_OUTPUT_FILTER)
       return set_error("served solves return the filter output"), CMCG_EUNSUPPORTED;
+    if (P->sound_soft)
+      return set_error("served solves have no Dirichlet cells"), CMCG_EUNSUPPORTED;
     auto *R = new ServeRequest();
     R->id = next_id++;
     R->P = *P;

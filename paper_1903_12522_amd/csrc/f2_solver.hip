@@ -787,7 +787,7 @@ class F2Solver final : public Solver {
     if (pure_neumann)
       return set_error("pure-Neumann box: the Step 6 output misses the mode eta; use the filter"),
              CMCG_EUNSUPPORTED;
-    const double wh = std::sin(cfg.omega * cfg.dt) / cfg.dt;
+    const double wh = std::sin(cfg.omega_of(0) * cfg.dt) / cfg.dt;
     double *ore = tp<double>(hi.Y), *oim = tp<double>(hi.Y) + g.fs;
     hipLaunchKernelGGL(f2_step6_kernel, dim3(rows_grid_of(g)), dim3(256), 0, s, g, zdev, 1.0 / wh,
                        Dre, Dim, ore, oim);

@@ -106,7 +106,7 @@ def _create(cm, p, **ok):
     (dict(dim=3, formulation=1, n=(8, 8, 8)), {}, -6),   # first-order 3D is not provided
     (dict(), dict(riesz_mode=7), -1),
     (dict(), dict(runup_periods=-1), -1),
-    (dict(gD=True), {}, -1),                            # Dirichlet data needs the nodal system
+    (dict(gD=True), {}, -1),                            # Dirichlet data needs a sound-soft mask
     (dict(bc=1), dict(runup_periods=2), -6),            # run-up of a closed undamped box
     # multi-frequency sources (N = 32 steps per base period here)
     (dict(shots=[(1, 0), (1, 0)]), {}, -1),             # repeated harmonic
@@ -114,7 +114,7 @@ def _create(cm, p, **ok):
     (dict(shots=[(1, 0), (16, 0)]), {}, -1),            # 2 m >= N: filters not separable
     (dict(shots=[(1, 0)] * 9, n_shots=9), {}, -1),      # more than CMCG_MAX_SHOTS
     (dict(shots=[(1, 0), (2, 0)], f=True), {}, -1),     # data both in the problem and the shots
-    (dict(shots=[(1, 0), (2, 1)]), {}, -1),             # Dirichlet data on the first-order grid
+    (dict(shots=[(1, 0), (2, 1)]), {}, -1),             # Dirichlet data without a mask
     (dict(shots=[(1, 0)], null_shots=True), {}, -1),    # n_shots without the array
     (dict(shots=[(1, 0)], n_shots=-1), {}, -1),
     # output modes
@@ -134,6 +134,22 @@ def test_valid_shots_pass_host_validation():
     """Distinct harmonics below N / 2 pass validation (then the device is needed)."""
     from paper_1903_12522_amd import cmcg as cm
     st, h = _create(cm, _problem(cm, shots=[(1, 0), (3, 0), (15, 0)]))
+    assert st in (0, -4)
+    if h.value:
+        cm._lib.cmcg_destroy(h)
+
+
+def test_first_order_dirichlet_cells_pass_host_validation():
+    """Dirichlet data on the first-order grid needs a sound-soft (cell) mask; with one it passes
+    validation (then the device is needed)."""
+    from paper_1903_12522_amd import cmcg as cm
+    p = _problem(cm)
+    mask = np.zeros(16 * 16, np.uint8)
+    mask[100:104] = 1
+    _KEEP.append(mask)
+    p.sound_soft = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    p.gD_re = _array(16 * 16)
+    st, h = _create(cm, p)
     assert st in (0, -4)
     if h.value:
         cm._lib.cmcg_destroy(h)
