@@ -71,6 +71,11 @@ struct F2Args {
 
 template <typename T>
 hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s);
+// K (2..4) homogeneous steps in one launch, temporally blocked: from u^n (cur) and u^{n-1}
+// (prev) to u^{n+K} (out_k) and u^{n+K-1} (out_km1); the outputs may alias neither input
+template <typename T>
+hipError_t f2_march_block(const F2Geom &g, const T *cur, const T *prev, const T *lam, T *out_k,
+                          T *out_km1, int K, hipStream_t s);
 // out = psi in, psi = lambda R / ((1 + beta) eta) (entry into the scaled adjoint variable)
 template <typename T>
 hipError_t f2_psi_scale(const F2Geom &g, const T *in, const T *lam, T *out, hipStream_t s);

@@ -273,6 +273,155 @@ __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
   }
 }
 
+// Temporal blocking of the homogeneous step u^{n+1} = R (2 u^n - (1-beta) u^{n-1} - lambda L u^n)
+// / (1 + beta) (every step of a forward period but its start and end, and every interior step of
+// the backward period in the scaled variable).  A workgroup of kBlockRows wavefronts owns a
+// (64 x kBlockRows) column tile and marches a chunk of kBlockChunk planes; the K steps of a
+// launch are K pipeline levels: at plane iteration p, level 0 loads plane p of u^n and u^{n-1},
+// and level s computes plane p - s of u^{n+s} from level s-1's planes p-s-1 .. p-s+1 (a register
+// window), level s-2's plane p-s (the older state) and the neighbours: x through lane shifts, y
+// through a double-buffered LDS plane per level (one barrier per plane iteration).  Each level
+// loses one lane, one row and one plane of validity at the tile's edges, so the tile writes its
+// inner (64 - 2K) x (kBlockRows - 2K) columns and the chunk's planes, preceded by K lead-in
+// planes; it writes u^{n+K} and u^{n+K-1}.  On the box faces a real node takes its mirrored
+// neighbour from the true node, as the single-step kernel does, so every real node sees the
+// same operands in the same order: blocked and single-step periods agree bit for bit.  Halo
+// lanes, rows and planes outside the box read clamped addresses and are never stored.
+constexpr int kBlockRows = 16;
+constexpr int kBlockChunk = 32;
+
+// INNER: the tile's columns and rows (halo included) hold no node on an x or y box face and no
+// sound-soft node, so the x/y mirror substitutions, the mask and the x/y absorbing faces drop
+// out; only the z face planes (plane-uniform) keep their mirror and absorption.
+template <typename T, int K, bool INNER>
+__device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, const T *prev,
+                                              const T *lam, T *out_k, T *out_km1,
+                                              T (&lds)[K][2][kBlockRows][64]) {
+  constexpr int TY = kBlockRows, OW = 64 - 2 * K, OH = TY - 2 * K;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * OW - K + lane;
+  const int j = blockIdx.y * OH - K + w;
+  const int k0 = blockIdx.z * kBlockChunk, k1 = min(k0 + kBlockChunk, g.nz + 1);
+  const int ic = INNER ? i : min(max(i, 0), g.nx), jc = INNER ? j : min(max(j, 0), g.ny);
+  const bool store = lane >= K && lane < 64 - K && w >= K && w < TY - K && i <= g.nx && j <= g.ny;
+  const int wm = w > 0 ? w - 1 : w, wp = w < TY - 1 ? w + 1 : w;
+  const size_t col = (size_t)jc * g.px + ic;
+  // absorbing faces at this column from the x and y faces (zero for INNER tiles)
+  const int mxy = INNER ? 0
+                        : (ic == 0 ? g.abs_face[0] : 0) + (ic == g.nx ? g.abs_face[1] : 0) +
+                              (jc == 0 ? g.abs_face[2] : 0) + (jc == g.ny ? g.abs_face[3] : 0);
+  T W[K][3];            // level s: its values at the three latest planes
+  T Ld[K + 1], Rd[K + 1];   // lambda and R at planes p, p-1, ..., p-K
+  T b1 = T(0);          // u^{n-1} at plane p-1 (the older state of level 1)
+#pragma unroll
+  for (int s = 0; s < K; ++s) W[s][0] = W[s][1] = W[s][2] = T(0);
+#pragma unroll
+  for (int d = 0; d <= K; ++d) Ld[d] = Rd[d] = T(1);
+  // The loads of plane p + 1 are issued before plane p is computed, into the other of two
+  // register sets (the loop is unrolled by two so that the sets trade roles without copies),
+  // and the barrier waits for LDS only: the loads stay in flight across it.
+  struct Plane {
+    T a, b, l, r;
+  };
+  auto load_plane = [&](int p, Plane &x) {
+    const int pc = min(max(p, 0), g.nz);
+    const size_t o = (size_t)pc * g.plane + col;
+    x.a = cur[o];
+    x.b = prev[o];
+    x.l = lam_at(g, lam, o);
+    x.r = INNER ? T(1) : (masked(g, ic, jc, pc) ? T(0) : T(1));
+  };
+  auto plane_iteration = [&](int p, const Plane &x) {
+#pragma unroll
+    for (int d = K; d > 0; --d) {
+      Ld[d] = Ld[d - 1];
+      if (!INNER) Rd[d] = Rd[d - 1];
+    }
+    Ld[0] = x.l;
+    if (!INNER) Rd[0] = x.r;
+    W[0][0] = W[0][1];
+    W[0][1] = W[0][2];
+    W[0][2] = x.a;
+    lds[0][p & 1][w][lane] = x.a;
+#pragma unroll
+    for (int s = 1; s <= K; ++s) {
+      const int q = p - s;
+      T zm = W[s - 1][0];
+      const T zc = W[s - 1][1];
+      T zp = W[s - 1][2];
+      T xl = lane_from_left(zc), xr = lane_from_right(zc);
+      T ym = lds[s - 1][(p - 1) & 1][wm][lane], yp = lds[s - 1][(p - 1) & 1][wp][lane];
+      if (!INNER) {
+        if (i == 0) xl = xr;
+        if (i == g.nx) xr = xl;
+        if (j == 0) ym = yp;
+        if (j == g.ny) yp = ym;
+      }
+      if (q == 0) zm = zp;
+      if (q == g.nz) zp = zm;
+      const T lap = T(6) * zc - (zm + zp + xl + xr + ym + yp);
+      const T l = Ld[s];
+      const T aux = s == 1 ? b1 : W[s >= 2 ? s - 2 : 0][0];
+      const int m = mxy + (q == 0 ? g.abs_face[4] : 0) + (q == g.nz ? g.abs_face[5] : 0);
+      T un;
+      if (m == 0) {
+        un = fma(-l, lap, T(2) * zc - aux);
+      } else {
+        const T beta = (T)m * sqrt(l);
+        un = (T(2) * zc - (T(1) - beta) * aux - l * lap) / (T(1) + beta);
+      }
+      if (!INNER) un = Rd[s] != T(0) ? un : T(0);
+      if (s < K) {
+        W[s][0] = W[s][1];
+        W[s][1] = W[s][2];
+        W[s][2] = un;
+        lds[s][p & 1][w][lane] = un;
+      }
+      if (store && q >= k0 && q < k1) {
+        if (s == K) out_k[(size_t)q * g.plane + col] = un;
+        if (s == K - 1) out_km1[(size_t)q * g.plane + col] = un;
+      }
+    }
+    b1 = x.b;
+    // LDS-only barrier: this plane's LDS writes are visible to the next iteration's reads,
+    // and the next iteration's writes (the other parity) follow this iteration's reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  };
+  const int pend = k1 + K - 1;
+  Plane x0, x1;
+  load_plane(k0 - K, x0);
+  // (the loads past the last plane read clamped planes and are not used: unconditional loads
+  // need no copies of the register set they replace)
+  for (int p = k0 - K; p <= pend; p += 2) {
+    load_plane(p + 1, x1);
+    __builtin_amdgcn_sched_barrier(0);   // issue the loads before this plane's work
+    plane_iteration(p, x0);
+    if (p + 1 > pend) break;
+    load_plane(p + 2, x0);
+    __builtin_amdgcn_sched_barrier(0);
+    plane_iteration(p + 1, x1);
+  }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(64 * kBlockRows) void f2_block_kernel(F2Geom g, const T *cur,
+                                                                    const T *prev, const T *lam,
+                                                                    T *out_k, T *out_km1) {
+  constexpr int OW = 64 - 2 * K, OH = kBlockRows - 2 * K;
+  __shared__ T lds[K][2][kBlockRows][64];
+  const int i0 = blockIdx.x * OW - K, j0 = blockIdx.y * OH - K;
+  const int i1 = i0 + 63, j1 = j0 + kBlockRows - 1;
+  const bool faces = i0 < 1 || i1 > g.nx - 1 || j0 < 1 || j1 > g.ny - 1;
+  const bool mask = g.mask && i1 >= g.mlo[0] && i0 <= g.mhi[0] && j1 >= g.mlo[1] &&
+                    j0 <= g.mhi[1];
+  if (!faces && !mask)
+    f2_block_tile<T, K, true>(g, cur, prev, lam, out_k, out_km1, lds);
+  else
+    f2_block_tile<T, K, false>(g, cur, prev, lam, out_k, out_km1, lds);
+}
+
 // out = psi in, psi = lambda R / ((1 + beta) eta)
 template <typename T>
 __global__ void f2_psi_scale_kernel(F2Geom g, const T *in, const T *lam, T *out) {
@@ -515,6 +664,24 @@ hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s
 }
 
 template <typename T>
+hipError_t f2_march_block(const F2Geom &g, const T *cur, const T *prev, const T *lam, T *out_k,
+                          T *out_km1, int K, hipStream_t s) {
+  dim3 block(64 * kBlockRows);
+  auto grid = [&](int k) {
+    return dim3((g.nx + 1 + 64 - 2 * k - 1) / (64 - 2 * k),
+                (g.ny + 1 + kBlockRows - 2 * k - 1) / (kBlockRows - 2 * k),
+                (g.nz + 1 + kBlockChunk - 1) / kBlockChunk);
+  };
+  switch (K) {
+    case 2: hipLaunchKernelGGL((f2_block_kernel<T, 2>), grid(2), block, 0, s, g, cur, prev, lam, out_k, out_km1); break;
+    case 3: hipLaunchKernelGGL((f2_block_kernel<T, 3>), grid(3), block, 0, s, g, cur, prev, lam, out_k, out_km1); break;
+    case 4: hipLaunchKernelGGL((f2_block_kernel<T, 4>), grid(4), block, 0, s, g, cur, prev, lam, out_k, out_km1); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t f2_psi_scale(const F2Geom &g, const T *in, const T *lam, T *out, hipStream_t s) {
   hipLaunchKernelGGL((f2_psi_scale_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, in, lam, out);
   return hipGetLastError();
@@ -594,6 +761,8 @@ hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, h
 #define INST(T)                                                                                   \
   template hipError_t f2_march<T>(int, const F2Geom &, const F2Args<T> &, hipStream_t);          \
   template hipError_t f2_psi_scale<T>(const F2Geom &, const T *, const T *, T *, hipStream_t);   \
+  template hipError_t f2_march_block<T>(const F2Geom &, const T *, const T *, const T *, T *,    \
+                                        T *, int, hipStream_t);                                  \
   template hipError_t f2_cg_update<T>(const F2Geom &, double *, double *, double *, const T *,   \
                                       const double *, const T *, const T *, const double *,      \
                                       double *, hipStream_t);                                    \

@@ -61,6 +61,9 @@ __global__ void f2_output_kernel(F2Geom g, const double *ure, const double *uim,
   }
 }
 
+// Homogeneous steps fused per launch by default (temporal blocking; 1 = one step per launch).
+constexpr int kF2DefaultBlock = 3;
+
 // Weights of the source components at one time: (c, s)_j = amp (cos, sin)(m_j omega t).
 struct ShotPhase {
   double c[CMCG_MAX_SHOTS] = {}, s[CMCG_MAX_SHOTS] = {};
@@ -157,6 +160,7 @@ int rows_grid_of(const F2Geom &g) {
 struct F2Set {
   int prec = CMCG_FP64;
   void *A = nullptr, *B = nullptr, *C = nullptr;   // three-level state buffers (one field each)
+  void *D = nullptr;                               // fourth one for blocked launches, or null
   void *W = nullptr, *Y = nullptr;                 // two-field: period output / metric output
   void *lam = nullptr;
   void *Fre = nullptr, *Fim = nullptr;             // load amplitudes, one field per component
@@ -184,6 +188,7 @@ class F2Solver final : public Solver {
   bool multi = false;                      // several source components
   double *DA = nullptr, *DB = nullptr;     // several components: Dirichlet values of one sweep
   bool pure_neumann = false;               // no absorbing face and no sound-soft node
+  int kstep = 1;                           // homogeneous steps per blocked launch
   double *cpart = nullptr, *h_cpart = nullptr;   // compatibility sums: device partials, host copy
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
   RieszMG mg;
@@ -206,12 +211,14 @@ class F2Solver final : public Solver {
   }
   size_t device_bytes() const override { return arena.bytes(); }
 
-  cmcg_status alloc_set(F2Set &b, int prec, bool var_c, bool forced, bool has_im, int J) {
+  cmcg_status alloc_set(F2Set &b, int prec, bool var_c, bool forced, bool has_im, int J,
+                        bool blocked) {
     const size_t esz = prec == CMCG_FP64 ? sizeof(double) : sizeof(float);
     b.prec = prec;
     CMCG_TRY(arena.alloc(g.fs * esz, &b.A, s));
     CMCG_TRY(arena.alloc(g.fs * esz, &b.B, s));
     CMCG_TRY(arena.alloc(g.fs * esz, &b.C, s));
+    if (blocked) CMCG_TRY(arena.alloc(g.fs * esz, &b.D, s));
     CMCG_TRY(arena.alloc(2 * g.fs * esz, &b.W, s));
     CMCG_TRY(arena.alloc(2 * g.fs * esz, &b.Y, s));
     if (var_c) CMCG_TRY(arena.alloc(g.fs * esz, &b.lam, s));
@@ -282,8 +289,11 @@ class F2Solver final : public Solver {
       has_d = has_d || sh.gD_re || sh.gD_im;
       has_dim = has_dim || sh.gD_im;
     }
-    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im, J));
-    if (mixed) CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, var_c, forced, has_im, J));
+    // temporal blocking of the homogeneous steps: K steps per launch (1 = off); the CG periods'
+    // set gets the fourth state buffer it needs
+    kstep = cfg.steps_request > 0 ? std::min(cfg.steps_request, 4) : kF2DefaultBlock;
+    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im, J, !mixed && kstep > 1));
+    if (mixed) CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, var_c, forced, has_im, J, kstep > 1));
     else lo = hi;
     CMCG_TRY(arena.alloc(2 * g.fs * (mixed ? sizeof(float) : sizeof(double)), &D, s));
     CMCG_TRY(arena.alloc_n(2 * g.fs, &Z, s));
@@ -385,6 +395,43 @@ class F2Solver final : public Solver {
   }
 
   // ------------------------------------------------------------------ periods
+  // `count` homogeneous steps from (cur, prev) = (u^n, u^{n-1}); on return they point to
+  // u^{n+count} and u^{n+count-1}.  With the set's fourth buffer, kstep steps per blocked launch
+  // (then the remainder one at a time); outputs always go to buffers that are not inputs.
+  template <typename T>
+  cmcg_status homogeneous_steps(const F2Set &b, const T *&cur, const T *&prev, int count,
+                                F2Args<T> p) {
+    T *pool[4] = {tp<T>(b.A), tp<T>(b.B), tp<T>(b.C), tp<T>(b.D)};
+    const int npool = b.D ? 4 : 3;
+    auto pick = [&](const T *x, const T *y, const T *z) -> T * {
+      for (int k = 0; k < npool; ++k)
+        if (pool[k] != x && pool[k] != y && pool[k] != z) return pool[k];
+      return nullptr;
+    };
+    while (count > 0) {
+      const int K = (b.D && kstep > 1 && count >= 2) ? std::min(kstep, count) : 1;
+      if (K >= 2) {
+        T *ok = pick(cur, prev, nullptr);
+        T *okm1 = pick(cur, prev, ok);
+        if (!ok || !okm1) return set_error("blocked march: no free buffer"), CMCG_EDEVICE;
+        CMCG_HIP(f2_march_block<T>(g, cur, prev, tpc<T>(b.lam), ok, okm1, K, s));
+        cur = ok;
+        prev = okm1;
+      } else {
+        T *o = pick(cur, prev, nullptr);
+        if (!o) return set_error("march: no free buffer"), CMCG_EDEVICE;
+        p.st = cur;
+        p.aux = prev;
+        p.out = o;
+        CMCG_HIP(f2_march<T>(kF2FwdStep, g, p, s));
+        prev = cur;
+        cur = o;
+      }
+      count -= K;
+    }
+    return CMCG_OK;
+  }
+
   // Component weights (cos, sin)(m_j omega t_n) at step time t_n = n dt, times the source ramp
   // if `ramped`
   ShotPhase shot_phase(int n, bool ramped) const {
@@ -472,7 +519,12 @@ class F2Solver final : public Solver {
     CMCG_HIP(f2_march<T>(kF2FwdStart, g, p, s));
     const T *prev = zin;
     int cur = 0;
-    for (int n = 1; n < N; ++n) {
+    const T *curp = buf[0];
+    if (!load && !dir && !filter) {
+      // homogeneous steps 1 .. N-1, temporally blocked
+      CMCG_TRY(homogeneous_steps<T>(b, curp, prev, N - 1, p));
+    }
+    for (int n = 1; n < N && (load || dir || filter); ++n) {
       const double t = n * cfg.dt;
       const double amp = transient(t_offset + t, t_tr);
       p.wcos = std::cos(w0 * t);
@@ -491,13 +543,14 @@ class F2Solver final : public Solver {
       CMCG_HIP(f2_march<T>(kF2FwdStep, g, p, s));
       prev = buf[cur];
       cur = nxt;
+      curp = buf[cur];
     }
     // end map: (u^N, v^N) with v^N = (u^{N+1} - u^{N-1}) / (2 dt)
     p.ure = p.uim = nullptr;
     const double ampN = transient(t_offset + N * cfg.dt, t_tr);
     p.fcos = multi ? 1.0 : ampN * std::cos(w0 * N * cfg.dt);
     p.fsin = multi ? 0.0 : ampN * std::sin(w0 * N * cfg.dt);
-    p.st = buf[cur];
+    p.st = curp;
     p.aux = prev;
     p.out = out;
     p.sub = sub;
@@ -540,19 +593,12 @@ class F2Solver final : public Solver {
     p.aux = buf[1];
     p.out = buf[2];
     CMCG_HIP(f2_march<T>(kF2AdjStepFirst, g, p, s));
-    int prev = 0, cur = 2;
-    for (int m = 1; m < N - 1; ++m) {
-      const int nxt = 3 - prev - cur;
-      p.st = buf[cur];
-      p.aux = buf[prev];
-      p.out = buf[nxt];
-      CMCG_HIP(f2_march<T>(kF2FwdStep, g, p, s));
-      prev = cur;
-      cur = nxt;
-    }
+    // interior transposed steps 1 .. N-2: forward homogeneous steps in g (temporally blocked)
+    const T *curp = buf[2], *prevp = buf[0];
+    CMCG_TRY(homogeneous_steps<T>(b, curp, prevp, N - 2, p));
     // transposed start map, back to the adjoint state
-    p.st = buf[cur];
-    p.aux = buf[prev];
+    p.st = curp;
+    p.aux = prevp;
     p.out = out;
     p.sub = sub;
     CMCG_HIP(f2_march<T>(kF2AdjEnd, g, p, s));

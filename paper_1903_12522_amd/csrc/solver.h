@@ -16,6 +16,7 @@ struct SolverConfig {
   double tol = 1e-6;
   int max_iter = 1000;
   int kblock = 4;          // leapfrog steps per launch
+  int steps_request = 0;   // cmcg_options.steps_per_launch as given (0: library default)
   double refresh = 0.1;    // FP32-mixed: FP64 residual refresh factor (<= 0: never)
   double riesz_tol = 0.0;
   int riesz_max_iter = 0;
