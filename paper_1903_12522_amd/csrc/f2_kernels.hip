@@ -34,6 +34,9 @@
 // neighbours from the rows that the neighbouring wavefronts load anyway (L1/L2 hits), so HBM sees
 // each field once per sweep.  Interior nodes (no absorbing face, beta = 0) take a division-free
 // update.
+#include <algorithm>
+#include <cstdlib>
+
 #include "f2_internal.h"
 #include "dpp.h"
 
@@ -290,18 +293,37 @@ __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
 constexpr int kBlockRows = 16;
 constexpr int kBlockChunk = 32;
 
+// Launch shape of the blocked sweep: planes per workgroup and whether workgroups are dealt to
+// the 8 XCDs in contiguous runs (so that neighbouring tiles, whose halos overlap, share an L2).
+struct F2BlockShape {
+  int chunk = kBlockChunk;
+  int xcd = 0;
+};
+
+// Tile (bx, by, bz) of workgroup blockIdx: in launch order, or XCD-aware (consecutive workgroup
+// ids go round-robin over the XCDs; the remap gives each XCD a contiguous run of tiles).
+__device__ __forceinline__ void block_tile(int xcd, int &bx, int &by, int &bz) {
+  const int gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+  int b = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+  if (xcd && nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
+  bx = b % gx;
+  by = (b / gx) % gy;
+  bz = b / (gx * gy);
+}
+
 // INNER: the tile's columns and rows (halo included) hold no node on an x or y box face and no
 // sound-soft node, so the x/y mirror substitutions, the mask and the x/y absorbing faces drop
 // out; only the z face planes (plane-uniform) keep their mirror and absorption.
 template <typename T, int K, bool INNER>
 __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, const T *prev,
                                               const T *lam, T *out_k, T *out_km1,
-                                              T (&lds)[K][2][kBlockRows][64]) {
+                                              T (&lds)[K][2][kBlockRows][64], int bx, int by,
+                                              int bz, int chunk) {
   constexpr int TY = kBlockRows, OW = 64 - 2 * K, OH = TY - 2 * K;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = blockIdx.x * OW - K + lane;
-  const int j = blockIdx.y * OH - K + w;
-  const int k0 = blockIdx.z * kBlockChunk, k1 = min(k0 + kBlockChunk, g.nz + 1);
+  const int i = bx * OW - K + lane;
+  const int j = by * OH - K + w;
+  const int k0 = bz * chunk, k1 = min(k0 + chunk, g.nz + 1);
   const int ic = INNER ? i : min(max(i, 0), g.nx), jc = INNER ? j : min(max(j, 0), g.ny);
   const bool store = lane >= K && lane < 64 - K && w >= K && w < TY - K && i <= g.nx && j <= g.ny;
   const int wm = w > 0 ? w - 1 : w, wp = w < TY - 1 ? w + 1 : w;
@@ -319,7 +341,8 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
   for (int d = 0; d <= K; ++d) Ld[d] = Rd[d] = T(1);
   // The loads of plane p + 1 are issued before plane p is computed, into the other of two
   // register sets (the loop is unrolled by two so that the sets trade roles without copies),
-  // and the barrier waits for LDS only: the loads stay in flight across it.
+  // and the barrier waits for LDS only: the loads stay in flight across it.  (Loads two planes
+  // ahead, with three register sets, measured slower.)
   struct Plane {
     T a, b, l, r;
   };
@@ -408,18 +431,21 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
 template <typename T, int K>
 __global__ __launch_bounds__(64 * kBlockRows) void f2_block_kernel(F2Geom g, const T *cur,
                                                                     const T *prev, const T *lam,
-                                                                    T *out_k, T *out_km1) {
+                                                                    T *out_k, T *out_km1,
+                                                                    F2BlockShape shape) {
   constexpr int OW = 64 - 2 * K, OH = kBlockRows - 2 * K;
   __shared__ T lds[K][2][kBlockRows][64];
-  const int i0 = blockIdx.x * OW - K, j0 = blockIdx.y * OH - K;
+  int bx, by, bz;
+  block_tile(shape.xcd, bx, by, bz);
+  const int i0 = bx * OW - K, j0 = by * OH - K;
   const int i1 = i0 + 63, j1 = j0 + kBlockRows - 1;
   const bool faces = i0 < 1 || i1 > g.nx - 1 || j0 < 1 || j1 > g.ny - 1;
   const bool mask = g.mask && i1 >= g.mlo[0] && i0 <= g.mhi[0] && j1 >= g.mlo[1] &&
                     j0 <= g.mhi[1];
   if (!faces && !mask)
-    f2_block_tile<T, K, true>(g, cur, prev, lam, out_k, out_km1, lds);
+    f2_block_tile<T, K, true>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz, shape.chunk);
   else
-    f2_block_tile<T, K, false>(g, cur, prev, lam, out_k, out_km1, lds);
+    f2_block_tile<T, K, false>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz, shape.chunk);
 }
 
 // out = psi in, psi = lambda R / ((1 + beta) eta)
@@ -666,16 +692,24 @@ hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s
 template <typename T>
 hipError_t f2_march_block(const F2Geom &g, const T *cur, const T *prev, const T *lam, T *out_k,
                           T *out_km1, int K, hipStream_t s) {
+  // CMCG_F2_CHUNK and CMCG_F2_XCD (environment, read once) override the launch shape for
+  // sweeps
+  static const F2BlockShape shape = [] {
+    F2BlockShape sh;
+    if (const char *e = std::getenv("CMCG_F2_CHUNK")) sh.chunk = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("CMCG_F2_XCD")) sh.xcd = std::atoi(e);
+    return sh;
+  }();
   dim3 block(64 * kBlockRows);
   auto grid = [&](int k) {
     return dim3((g.nx + 1 + 64 - 2 * k - 1) / (64 - 2 * k),
                 (g.ny + 1 + kBlockRows - 2 * k - 1) / (kBlockRows - 2 * k),
-                (g.nz + 1 + kBlockChunk - 1) / kBlockChunk);
+                (g.nz + 1 + shape.chunk - 1) / shape.chunk);
   };
   switch (K) {
-    case 2: hipLaunchKernelGGL((f2_block_kernel<T, 2>), grid(2), block, 0, s, g, cur, prev, lam, out_k, out_km1); break;
-    case 3: hipLaunchKernelGGL((f2_block_kernel<T, 3>), grid(3), block, 0, s, g, cur, prev, lam, out_k, out_km1); break;
-    case 4: hipLaunchKernelGGL((f2_block_kernel<T, 4>), grid(4), block, 0, s, g, cur, prev, lam, out_k, out_km1); break;
+    case 2: hipLaunchKernelGGL((f2_block_kernel<T, 2>), grid(2), block, 0, s, g, cur, prev, lam, out_k, out_km1, shape); break;
+    case 3: hipLaunchKernelGGL((f2_block_kernel<T, 3>), grid(3), block, 0, s, g, cur, prev, lam, out_k, out_km1, shape); break;
+    case 4: hipLaunchKernelGGL((f2_block_kernel<T, 4>), grid(4), block, 0, s, g, cur, prev, lam, out_k, out_km1, shape); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
