@@ -1,7 +1,8 @@
 """Python binding of libcmcg (include/cmcg.h): argument marshalling only.
 
 Every step of the solver runs in the HIP library; this module converts NumPy inputs to the C
-structs, passes torch device pointers and the current torch stream, and converts outputs back.
+structs, passes torch device pointers and a torch stream that each call orders after the
+caller's current stream, and converts outputs back.
 If the built library is missing, importing this module raises: there is no fallback.
 """
 from __future__ import annotations
@@ -150,8 +151,19 @@ def _concat_faces(parts, dtype) -> np.ndarray:
     return np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=dtype).ravel() for p in parts]))
 
 
+def _handle_stream(torch, stream, device):
+    """The stream a handle runs on: the caller's non-default stream, else a dedicated one of
+    default priority.  (Torch's default stream has the null handle, which the C ABI reads as
+    "create your own stream": the handle's work would then be unordered with the caller's.)"""
+    if stream is None or stream.cuda_stream == 0:
+        stream = torch.cuda.Stream(device=device)
+    return stream
+
+
 class Solver:
-    """One CMCG problem on the GPU.  `problem` is a cmcg_inputs.Problem."""
+    """One CMCG problem on the GPU.  `problem` is a cmcg_inputs.Problem.  Every call first makes
+    the handle's stream wait for the caller's current stream, so device inputs written by torch
+    are complete; every call returns after the handle's stream has finished."""
 
     def __init__(self, problem, precision: str = "fp64", tol: float = 1e-6, max_iter: int = 1000,
                  device: int = 0, steps_per_launch: int = 0, stream=None,
@@ -163,11 +175,11 @@ class Solver:
         p, self._keep = marshal_problem(problem)
         o = make_options(precision, tol, max_iter, device, steps_per_launch, riesz_tol,
                          riesz_max_iter, fp64_refresh, riesz_mode, runup_periods, output)
-        if stream is None:
-            stream = torch.cuda.current_stream(device)
-        self.stream = stream
-        o.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+        self.device = device
+        self.stream = _handle_stream(torch, stream, device)
+        o.hip_stream = ctypes.c_void_p(self.stream.cuda_stream)
         h = _H()
+        self._order()
         _check(_lib.cmcg_create(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h)), "cmcg_create")
         self._h = h
         self.precision = precision
@@ -180,6 +192,10 @@ class Solver:
             tuple(problem.field_shape())
 
     # ------------------------------------------------------------------ lifetime
+    def _order(self):
+        """The handle's stream waits for the caller's current stream."""
+        self.stream.wait_stream(self._torch.cuda.current_stream(self.device))
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.cmcg_destroy(self._h)
@@ -204,6 +220,7 @@ class Solver:
         FP64 device tensors (re, im) if device_output."""
         rep = _Report()
         ure, uim, keep = self._out_buffers(device_output)
+        self._order()
         st = _check(_lib.cmcg_solve(self._h, ure, uim, ctypes.byref(rep)), "cmcg_solve",
                     allow_notconv=True)
         d = _report_dict(rep)
@@ -211,11 +228,13 @@ class Solver:
         return self._out_value(keep, device_output), d
 
     def begin(self):
+        self._order()
         _check(_lib.cmcg_begin(self._h), "cmcg_begin")
 
     def iterate(self, iters: int) -> Tuple[bool, dict]:
         conv = ctypes.c_int32(0)
         rep = _Report()
+        self._order()
         _check(_lib.cmcg_iterate(self._h, int(iters), ctypes.byref(conv), ctypes.byref(rep)),
                "cmcg_iterate")
         return bool(conv.value), _report_dict(rep)
@@ -223,6 +242,7 @@ class Solver:
     def finish(self, device_output: bool = False):
         rep = _Report()
         ure, uim, keep = self._out_buffers(device_output)
+        self._order()
         _check(_lib.cmcg_finish(self._h, ure, uim, ctypes.byref(rep)), "cmcg_finish")
         return self._out_value(keep, device_output), _report_dict(rep)
 
@@ -236,6 +256,7 @@ class Solver:
         assert zin.dtype == torch.float64 and zin.is_cuda and zin.numel() == self.info["state_len"]
         zin = zin.contiguous()
         out = torch.empty_like(zin)
+        self._order()
         _check(_lib.cmcg_apply(self._h, int(op), int(steps), ctypes.c_void_p(zin.data_ptr()),
                                ctypes.c_void_p(out.data_ptr())), "cmcg_apply")
         return out.cpu().numpy() if as_np else out
@@ -245,6 +266,7 @@ class Solver:
         zin = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64)).cuda() \
             if isinstance(z, np.ndarray) else z.contiguous()
         ure, uim, keep = self._out_buffers(False)
+        self._order()
         _check(_lib.cmcg_filter(self._h, ctypes.c_void_p(zin.data_ptr()), ure, uim), "cmcg_filter")
         return self._out_value(keep, False)
 
@@ -254,6 +276,7 @@ class Solver:
         zin = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64)).cuda() \
             if isinstance(z, np.ndarray) else z.contiguous()
         ure, uim, keep = self._out_buffers(False)
+        self._order()
         _check(_lib.cmcg_step6(self._h, ctypes.c_void_p(zin.data_ptr()), ure, uim), "cmcg_step6")
         return self._out_value(keep, False)
 
@@ -262,6 +285,7 @@ class Solver:
         from rest, the source switched on by Mur's transient if `ramp` (cmcg_runup)."""
         torch = self._torch
         out = torch.empty(self.info["state_len"], dtype=torch.float64, device="cuda")
+        self._order()
         _check(_lib.cmcg_runup(self._h, int(periods), 1 if ramp else 0,
                                ctypes.c_void_p(out.data_ptr())), "cmcg_runup")
         return out
@@ -272,6 +296,7 @@ class Solver:
         zin = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64)).cuda() \
             if isinstance(z, np.ndarray) else z.contiguous()
         J = ctypes.c_double(0.0)
+        self._order()
         _check(_lib.cmcg_misfit(self._h, ctypes.c_void_p(zin.data_ptr()), ctypes.byref(J)),
                "cmcg_misfit")
         return J.value
@@ -279,6 +304,7 @@ class Solver:
     def state(self, which: int = 0) -> np.ndarray:
         torch = self._torch
         out = torch.empty(self.info["state_len"], dtype=torch.float64, device="cuda")
+        self._order()
         _check(_lib.cmcg_get_state(self._h, int(which), ctypes.c_void_p(out.data_ptr())),
                "cmcg_get_state")
         return out.cpu().numpy()
@@ -401,10 +427,8 @@ class Server:
         o.max_slots = int(max_slots)
         o.steps_per_launch = int(steps_per_launch)
         o.device = int(device)
-        if stream is None:
-            stream = torch.cuda.current_stream(device)
-        self.stream = stream
-        o.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+        self.stream = _handle_stream(torch, stream, device)
+        o.hip_stream = ctypes.c_void_p(self.stream.cuda_stream)
         h = _H()
         _check(_lib.cmcg_server_create(ctypes.byref(o), ctypes.byref(h)), "cmcg_server_create")
         self._h = h

@@ -235,3 +235,62 @@ def test_vcycle_riesz_reaches_the_same_solution(cm, kind):
         U, rep = s.solve()
     assert rep["converged"]
     assert _rel(U, Ud) < 1e-8
+
+
+# Full size (512^3 inclusions): the blocked launch configuration the benchmark times, checked by
+# properties that hold at any size (the oracle's dependency cone of N = 123 steps spans the box)
+@pytest.fixture(scope="module")
+def c3():
+    return ci.inclusions_3d()
+
+
+def test_full_size_blocked_period_is_bitwise(cm, c3):
+    """512^3, FP32: forward and backward homogeneous periods with 3 steps per launch (the
+    default) equal one step per launch bit for bit."""
+    import torch
+    outs = []
+    for k in (1, 3):
+        with cm.Solver(c3, "fp32", steps_per_launch=k) as s:
+            n = s.info["state_len"]
+            g = torch.Generator(device="cuda").manual_seed(11)
+            z = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+            outs.append((s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z)))
+            del z
+            torch.cuda.synchronize()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
+def test_full_size_adjoint_identity_fp64(cm, c3):
+    """512^3, FP64, default blocking: <E z, y> = <z, E^T y> for random device vectors z, y (the
+    backward period is the literal transpose of the forward one), to rounding relative to
+    |E z| |y|.  The inputs are written by torch on the caller's stream just before the calls."""
+    import torch
+    with cm.Solver(c3, "fp64") as s:
+        n = s.info["state_len"]
+        g = torch.Generator(device="cuda").manual_seed(12)
+        z = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        y = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        Ez = s.apply(cm.OP_FORWARD, z)
+        ETy = s.apply(cm.OP_ADJOINT, y)
+        lhs, rhs = torch.dot(Ez, y).item(), torch.dot(z, ETy).item()
+        bound = 1e-13 * (torch.linalg.vector_norm(Ez) * torch.linalg.vector_norm(y)).item()
+    assert abs(lhs - rhs) <= bound, (lhs, rhs, bound)
+
+
+def test_device_inputs_are_ordered_after_the_callers_stream(cm):
+    """A device input that torch writes on the caller's (default) stream right before the call
+    is complete when the library reads it: the binding runs each handle on its own stream and
+    makes it wait for the caller's.  (Reading it early made periods differ run to run on a
+    prefix of planes.)"""
+    import torch
+    prob = ci.inclusions_3d(n=256, freq=12.5)
+    with cm.Solver(prob, "fp64") as s:
+        n = s.info["state_len"]
+        outs = []
+        for _ in range(2):
+            g = torch.Generator(device="cuda").manual_seed(13)
+            z = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+            outs.append(s.apply(cm.OP_FORWARD, z))
+            del z
+    assert torch.equal(outs[0], outs[1])
