@@ -392,7 +392,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, rep1 = s.iterate(0)
-        kb = spl if spl > 0 else 6
+        kb = s.info["steps_per_launch"]
         dev_bytes = s.info["device_bytes"]
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -409,7 +409,8 @@ def main():
     alg_bytes = bytes_per_update * cells * kb       # per launch: kb leapfrog steps of every cell
     dom, dom_t, other_t = ("adjoint", adj, fwd) if adj >= fwd else ("forward", fwd, adj)
     achieved = alg_bytes / dom_t / 1e9
-    kname = f"f1_stream_kernel<float, {kb}, {'true' if dom == 'adjoint' else 'false'}, false>"
+    # the instance the launches between a period's first and last run (no mask, middle set)
+    kname = f"f1_stream_kernel<float, {kb}, {'true' if dom == 'adjoint' else 'false'}, false, 0>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 3),
                 "traffic": measured_traffic(kname),

@@ -89,6 +89,7 @@ struct F1Launch {
   int last;            // the last step of the period ends with a half-step
   int forced;          // add the source term
   int accumulate;      // filter: add v^n (fc, fs) to (Ure, Uim) before stepping (KMAX = 1)
+  int general;         // run every tile through the general body (a bitwise check of the fast one)
   double cs[kMaxBlockSteps], sn[kMaxBlockSteps];   // cos/sin(omega t) at each step's source time
   double fcos, fsin;   // filter weights cos/sin(omega t_n)
   // Dirichlet cells of a forced period: v = dre dc[k] + dim ds[k] at the launch's input time

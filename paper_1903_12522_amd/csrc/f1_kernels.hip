@@ -282,28 +282,56 @@ __device__ __forceinline__ void buf_st(double x, __amdgpu_buffer_rsrc_t r, unsig
 
 // Resources and offsets of one fast-variant wavefront.
 struct FastIO {
-  __amdgpu_buffer_rsrc_t in, cc, out;
+  __amdgpu_buffer_rsrc_t in, cc, out, sub;
   unsigned vo;        // this lane's column offset (bytes)
   unsigned vo_st;     // column offset for stores: vo, or out of range for a halo lane
   unsigned pitchb, fsb;
 };
 
+// Column offsets of the rows that row iteration j stores: Px and v of row j - K (A) and Py of
+// row j - K - 1 (B), or out of range outside the band.
+template <int K>
+__device__ __forceinline__ void fast_store_rows(const FastIO &io, int j, int s0, int s1,
+                                                unsigned &voA, unsigned &soA, unsigned &voB,
+                                                unsigned &soB) {
+  const int ro = j - K;
+  voA = (ro >= s0 && ro < s1) ? io.vo_st : kBufDrop;
+  voB = (ro - 1 >= s0 && ro - 1 < s1) ? io.vo_st : kBufDrop;
+  soA = (unsigned)ro * io.pitchb;
+  soB = (unsigned)(ro - 1) * io.pitchb;
+}
+
 // One row iteration of the fast variant: level 0 takes row j (v, Px, kap and the Py face above
 // the row; the face below is held from the previous iteration), level k advances row j - k from
 // level k-1 using the previous iteration's emissions (*p arrays) and writes this iteration's
 // (*c arrays); row j - K leaves the pipeline.
-template <typename T, int K, bool ADJ>
+// FIRST: the period's opening half kick at level 0 (forward p += dt/2 G v, backward
+// v -= dt/2 c^2 D p, on the raw input).  SUB: the stored values less the subtrahend (sub_a: Px,
+// sub_c: v of row j - K; sub_b: Py of row j - K - 1), loaded one row ahead with the inputs.
+template <typename T, int K, bool ADJ, bool FIRST, bool SUB>
 __device__ __forceinline__ void f1_fast_row(const FastIO &io, const F1Launch &L, const int j,
                                             const int s0, const int s1, const T dth, const T hdth,
-                                            const T in_v, const T in_px, const T in_py,
-                                            const T in_cc, const T (&Vp)[K + 1],
+                                            T in_v, T in_px, const T in_py, const T in_cc,
+                                            const T sub_a, const T sub_b, const T sub_c,
+                                            const T (&Vp)[K + 1],
                                             const T (&PXp)[K + 1], const T (&PYp)[K + 1],
                                             const T (&CCp)[K + 1], T (&Vc)[K + 1],
                                             T (&PXc)[K + 1], T (&PYc)[K + 1], T (&CCc)[K + 1],
                                             T (&HOLD)[K + 1]) {
+  T pyprev = HOLD[0];        // Py(j-1)
+  if (FIRST) {
+    if (!ADJ) {
+      const T vr = lane_from_right(in_v);
+      in_px = fma(hdth, vr - in_v, in_px);
+      pyprev = fma(hdth, in_v - Vp[0], pyprev);
+    } else {
+      const T pl = lane_from_left(in_px);
+      in_v = fma(T(-0.5) * in_cc, (in_px - pl) + (in_py - pyprev), in_v);
+    }
+  }
   Vc[0] = in_v;
   PXc[0] = in_px;
-  PYc[0] = HOLD[0];          // Py(j-1)
+  PYc[0] = pyprev;
   HOLD[0] = in_py;
   CCc[0] = in_cc;
 #pragma unroll
@@ -335,23 +363,27 @@ __device__ __forceinline__ void f1_fast_row(const FastIO &io, const F1Launch &L,
     }
   }
   // row ro = j - K: Px and v; row ro - 1: Py (its upper face is complete only now)
-  const int ro = j - K;
-  const unsigned voA = (ro >= s0 && ro < s1) ? io.vo_st : kBufDrop;
-  const unsigned voB = (ro - 1 >= s0 && ro - 1 < s1) ? io.vo_st : kBufDrop;
-  const unsigned soA = (unsigned)ro * io.pitchb, soB = (unsigned)(ro - 1) * io.pitchb;
-  buf_st(PXc[K], io.out, voA, soA);
-  buf_st(Vc[K], io.out, voA, soA + 2 * io.fsb);
-  buf_st(PYc[K], io.out, voB, soB + io.fsb);
+  unsigned voA, soA, voB, soB;
+  fast_store_rows<K>(io, j, s0, s1, voA, soA, voB, soB);
+  T a = PXc[K], b = PYc[K], c = Vc[K];
+  if (SUB) {
+    a -= sub_a;
+    b -= sub_b;
+    c -= sub_c;
+  }
+  buf_st(a, io.out, voA, soA);
+  buf_st(c, io.out, voA, soA + 2 * io.fsb);
+  buf_st(b, io.out, voB, soB + io.fsb);
 }
 
 // Fast variant of the body for wavefronts whose 64 columns are interior (1 <= i <= nx-2), whose
-// rows (with its pipeline margin) are interior, and a launch with no opening kick, no source and
-// no filter and no subtrahend (every launch of a period but the last), on arrays below 2^31 bytes.
-// No masks and no branches remain in the row loop; the
+// rows (with its pipeline margin) are interior, and a launch with no source and no filter, on
+// arrays below 2^31 bytes.  FIRST (the period's first launch) and SUB (its last, out = result -
+// sub) are compile-time variants.  No masks and no branches remain in the row loop; the
 // arithmetic per cell is identical to the general body's, so results do not depend on which
 // variant ran.  The row loop is unrolled by two with the previous/current register sets trading
 // roles (no register copies), and each row's loads are issued one row ahead of their use.
-template <typename T, int K, bool ADJ>
+template <typename T, int K, bool ADJ, bool FIRST, bool SUB>
 __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, const int i, const int lane,
                                                const int s0, const int s1) {
@@ -364,6 +396,7 @@ __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> 
   io.in = buf_rsrc(p.in, 3 * io.fsb);
   io.cc = buf_rsrc(p.cc, io.fsb);
   io.out = buf_rsrc(p.out, 3 * io.fsb);
+  io.sub = buf_rsrc(SUB ? p.sub : p.in, 3 * io.fsb);
   io.vo = (unsigned)i * (unsigned)sizeof(T);
   io.vo_st = (lane >= H && lane < 64 - H) ? io.vo : kBufDrop;
   T Va[K + 1], PXa[K + 1], PYa[K + 1], CCa[K + 1];
@@ -377,36 +410,62 @@ __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> 
   }
   const int jstart = s0 - K - 2, jend = s1 + K;
   buf_ld(HOLD[0], io.in, io.vo, (unsigned)(jstart - 1) * io.pitchb + io.fsb);
-  // level-0 inputs of the next row, loaded one row ahead of their use
-  T nv, npx, npy, ncc;
-  auto load_row = [&](int r) {
-    const unsigned so = (unsigned)r * io.pitchb;
-    buf_ld(nv, io.in, io.vo, so + 2 * io.fsb);
-    buf_ld(npx, io.in, io.vo, so);
-    buf_ld(npy, io.in, io.vo, so + io.fsb);
-    buf_ld(ncc, io.cc, io.vo, so);
+  // level-0 inputs of a row iteration (and the subtrahend of the rows it stores), loaded one
+  // iteration ahead of their use
+  struct RowIn {
+    T v, px, py, cc, sa, sb, sc;
   };
-  load_row(jstart);
+  auto load_row = [&](int r, RowIn &x) {
+    x.sa = x.sb = x.sc = T(0);
+    if (SUB) {
+      unsigned voA, soA, voB, soB;
+      fast_store_rows<K>(io, r, s0, s1, voA, soA, voB, soB);
+      buf_ld(x.sa, io.sub, voA, soA);
+      buf_ld(x.sc, io.sub, voA, soA + 2 * io.fsb);
+      buf_ld(x.sb, io.sub, voB, soB + io.fsb);
+    }
+    const unsigned so = (unsigned)r * io.pitchb;
+    buf_ld(x.v, io.in, io.vo, so + 2 * io.fsb);
+    buf_ld(x.px, io.in, io.vo, so);
+    buf_ld(x.py, io.in, io.vo, so + io.fsb);
+    buf_ld(x.cc, io.cc, io.vo, so);
+  };
+  // Schedules, chosen by measurement on a 4096^2 grid: the FP32 forward sweep is fastest with
+  // the next row's loads issued unconditionally (row jend + 1 <= ny - 1 is in range) and held
+  // ahead of the row's arithmetic by a scheduling barrier; the backward sweep, and FP64 (whose
+  // register count that barrier raises past an occupancy step), with the compiler's schedule.
+  constexpr bool pinned = !ADJ && sizeof(T) == 4;
+  RowIn A;
+  load_row(jstart, A);
   int j = jstart;
   for (; j + 1 <= jend; j += 2) {
-    const T v0 = nv, px0 = npx, py0 = npy, cc0 = ncc;
-    load_row(j + 1);
-    f1_fast_row<T, K, ADJ>(io, L, j, s0, s1, dth, hdth, v0, px0, py0, cc0, Va, PXa, PYa, CCa, Vb,
-                           PXb, PYb, CCb, HOLD);
-    const T v1 = nv, px1 = npx, py1 = npy, cc1 = ncc;
-    if (j + 2 <= jend) load_row(j + 2);
-    f1_fast_row<T, K, ADJ>(io, L, j + 1, s0, s1, dth, hdth, v1, px1, py1, cc1, Vb, PXb, PYb, CCb,
-                           Va, PXa, PYa, CCa, HOLD);
+    const RowIn x0 = A;
+    load_row(j + 1, A);
+    if (pinned) __builtin_amdgcn_sched_barrier(0);
+    f1_fast_row<T, K, ADJ, FIRST, SUB>(io, L, j, s0, s1, dth, hdth, x0.v, x0.px, x0.py, x0.cc,
+                                       x0.sa, x0.sb, x0.sc, Va, PXa, PYa, CCa, Vb, PXb, PYb, CCb,
+                                       HOLD);
+    const RowIn x1 = A;
+    if (pinned || j + 2 <= jend) load_row(j + 2, A);
+    if (pinned) __builtin_amdgcn_sched_barrier(0);
+    f1_fast_row<T, K, ADJ, FIRST, SUB>(io, L, j + 1, s0, s1, dth, hdth, x1.v, x1.px, x1.py,
+                                       x1.cc, x1.sa, x1.sb, x1.sc, Vb, PXb, PYb, CCb, Va, PXa,
+                                       PYa, CCa, HOLD);
   }
   if (j <= jend)
-    f1_fast_row<T, K, ADJ>(io, L, j, s0, s1, dth, hdth, nv, npx, npy, ncc, Va, PXa, PYa, CCa, Vb,
-                           PXb, PYb, CCb, HOLD);
+    f1_fast_row<T, K, ADJ, FIRST, SUB>(io, L, j, s0, s1, dth, hdth, A.v, A.px, A.py, A.cc, A.sa,
+                                       A.sb, A.sc, Va, PXa, PYa, CCa, Vb, PXb, PYb, CCb, HOLD);
 }
+
+// Which fast variants a kernel instance holds.  The first and last launches of a period run
+// their own instances, so that the register allocation of the instance every other launch runs
+// is not raised by variants it never takes.
+enum F1FastSet { kFastMiddle = 0, kFastEnds = 1, kFastAll = 2 };
 
 // Tile (bx, by) of a launch: wavefront w of the workgroup owns column strip 4 bx + w of the
 // band of rows by.  Interior wavefronts (all 64 columns in 1..nx-2) of interior bands take the
 // fast variant.
-template <typename T, int K, bool ADJ, bool MASK>
+template <typename T, int K, bool ADJ, bool MASK, int SET>
 __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, int band, int bx, int by) {
   constexpr int H = K + 1;             // lanes lost on each side: K levels + the opening kick
@@ -431,20 +490,27 @@ __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> 
       return;
     }
   }
-  if (inner_cols && inner_rows && small && !p.sub && !L.first && !L.forced && !L.accumulate)
-    f1_stream_fast<T, K, ADJ>(g, p, L, i0 + lane, lane, s0, s1);
+  const bool fast = inner_cols && inner_rows && small && !L.forced && !L.accumulate &&
+                    !L.general && !(L.first && p.sub);
+  const bool ends = L.first || p.sub;
+  if (SET != kFastMiddle && fast && L.first)
+    f1_stream_fast<T, K, ADJ, true, false>(g, p, L, i0 + lane, lane, s0, s1);
+  else if (SET != kFastMiddle && fast && p.sub)
+    f1_stream_fast<T, K, ADJ, false, true>(g, p, L, i0 + lane, lane, s0, s1);
+  else if (SET != kFastEnds && fast && !ends)
+    f1_stream_fast<T, K, ADJ, false, false>(g, p, L, i0 + lane, lane, s0, s1);
   else if (inner_cols)
     f1_stream_body<T, K, ADJ, false, false>(g, p, L, i0 + lane, lane, s0, s1);
   else
     f1_stream_body<T, K, ADJ, true, false>(g, p, L, i0 + lane, lane, s0, s1);
 }
 
-template <typename T, int K, bool ADJ, bool MASK>
+template <typename T, int K, bool ADJ, bool MASK, int SET>
 __global__ __launch_bounds__(kThreads) void f1_stream_kernel(F1Geom g, F1Ptrs<T> p, F1Launch L,
                                                              int band) {
   int bx, by;
   tile_of_block(bx, by);
-  f1_stream_tile<T, K, ADJ, MASK>(g, p, L, band, bx, by);
+  f1_stream_tile<T, K, ADJ, MASK, SET>(g, p, L, band, bx, by);
 }
 
 // Several independent solves in one launch (continuous batching): workgroup b belongs to the
@@ -460,7 +526,8 @@ __global__ __launch_bounds__(kThreads) void f1_multi_kernel(const F1SlotLaunch<T
   const F1Ptrs<T> p = slots[s].p;
   const F1Launch L = slots[s].L;
   const int t = (int)blockIdx.x - slots[s].block0;
-  f1_stream_tile<T, K, ADJ, false>(g, p, L, slots[s].band, t % slots[s].nbx, t / slots[s].nbx);
+  f1_stream_tile<T, K, ADJ, false, kFastAll>(g, p, L, slots[s].band, t % slots[s].nbx,
+                                             t / slots[s].nbx);
 }
 
 // Rows per band: enough wavefronts to fill 256 CUs several times over, long enough bands to
@@ -485,12 +552,23 @@ hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hi
   const int strips = (g.nx + OW - 1) / OW;
   const int band = band_rows(g.nx, g.ny, K);
   dim3 grid((strips + 3) / 4, (g.ny + band - 1) / band);
-  if (g.mask)
-    hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ, true>), grid, dim3(kThreads), 0, s, g, p, L,
-                       band);
-  else
-    hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ, false>), grid, dim3(kThreads), 0, s, g, p, L,
-                       band);
+  // CMCG_F1_GENERAL=1 (environment) runs every tile through the general body, so that tests can
+  // compare the fast variants with it bit for bit
+  const char *gen = std::getenv("CMCG_F1_GENERAL");
+  F1Launch Lx = L;
+  Lx.general = (gen && gen[0] == '1') ? 1 : 0;
+  const bool ends = L.first || p.sub;
+#define CMCG_F1_LAUNCH(MASK, SET)                                                              \
+  hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ, MASK, SET>), grid, dim3(kThreads), 0, s, g, p, \
+                     Lx, band)
+  if (g.mask) {
+    if (ends) CMCG_F1_LAUNCH(true, kFastEnds);
+    else CMCG_F1_LAUNCH(true, kFastMiddle);
+  } else {
+    if (ends) CMCG_F1_LAUNCH(false, kFastEnds);
+    else CMCG_F1_LAUNCH(false, kFastMiddle);
+  }
+#undef CMCG_F1_LAUNCH
   return hipGetLastError();
 }
 

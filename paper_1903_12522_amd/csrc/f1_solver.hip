@@ -784,6 +784,7 @@ class F1Solver final : public Solver {
     i->field_len = nx * ny;
     i->device_bytes = (int64_t)arena.bytes();
     i->n_fields = cfg.nshots;
+    i->steps_per_launch = cfg.kblock;
   }
 };
 

@@ -970,6 +970,7 @@ class F2Solver final : public Solver {
     i->field_len = nn;
     i->device_bytes = (int64_t)arena.bytes();
     i->n_fields = cfg.nshots;
+    i->steps_per_launch = kstep;
   }
 };
 

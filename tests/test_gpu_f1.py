@@ -92,6 +92,34 @@ def test_temporal_blocking_is_bitwise_fp32(cm):
         assert np.array_equal(b, outs[0][1]), (k, np.max(np.abs(b - outs[0][1])))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fast_variants_match_general_body_bitwise(cm, prec, monkeypatch):
+    """Interior tiles of the first launch of a period (opening half kick), of its last launch
+    (output less a subtrahend, as in each CG iteration's E d - d) and of the launches between
+    run register-streamed fast variants; CMCG_F1_GENERAL=1 sends every tile through the general
+    body instead.  Both must give the same bits for the periods and for CG iterates."""
+    prob = _mixed_problem(nx=420, ny=260, seed=8)
+    z = np.random.default_rng(4).standard_normal(F1(prob).size)
+
+    def run(k):
+        with cm.Solver(prob, prec, tol=0.0, max_iter=50, steps_per_launch=k) as s:
+            out = [s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z),
+                   s.apply(cm.OP_FORWARD, z, steps=k)]
+            s.begin()
+            s.iterate(3)
+            out.append(s.state(0))
+        return out
+
+    for k in (1, 3, 7, 8):
+        monkeypatch.delenv("CMCG_F1_GENERAL", raising=False)
+        fast = run(k)
+        monkeypatch.setenv("CMCG_F1_GENERAL", "1")
+        gen = run(k)
+        monkeypatch.delenv("CMCG_F1_GENERAL")
+        for n, (a, b) in enumerate(zip(fast, gen)):
+            assert np.array_equal(a, b), (k, n, np.max(np.abs(a - b)))
+
+
 def test_adjoint_identity_on_gpu(cm):
     """<E z, y>_E = <z, E* y>_E to 1e-13 through the GPU alone."""
     prob = ci.random_medium_2d(n=96, freq=4.0, n_src=3, seed=7)
