@@ -530,19 +530,21 @@ __global__ __launch_bounds__(kThreads) void f1_multi_kernel(const F1SlotLaunch<T
                                              t / slots[s].nbx);
 }
 
-// Rows per band: enough wavefronts to fill 256 CUs several times over, long enough bands to
-// keep the pipeline fill (2K+3 rows) small.
+// Rows per band.  Besides its band, each wavefront loads 2K + 3 rows to fill its pipeline, so
+// taller bands waste fewer loads and shorter ones give more wavefronts to hide latency with.  On
+// n x n grids from 128^2 to 4096^2 (FP32 with K = 7, FP64 with K = 8) the fastest height was
+// ny / 128 rounded down to a power of two: one row at 128^2, 32 rows at 4096^2.
 // CMCG_F1_BAND (environment, read once) overrides the band height for launch-shape sweeps.
 inline int band_rows(int nx, int ny, int K) {
+  (void)nx;
+  (void)K;
   static const int forced = [] {
     const char *e = std::getenv("CMCG_F1_BAND");
     return e ? std::atoi(e) : 0;
   }();
   if (forced > 0) return forced;
-  const int ow = 64 - 2 * (K + 1);
-  const long strips = (nx + ow - 1) / ow;
-  int band = 256;
-  while (band > 16 && strips * ((ny + band - 1) / band) < 8192) band /= 2;
+  int band = 1;
+  while (band < 256 && ny / (2 * band) >= 128) band *= 2;
   return band;
 }
 
