@@ -150,6 +150,7 @@ class RieszMG {
   double *partials_ = nullptr, *scal_ = nullptr, *h_scal_ = nullptr;
   hipStream_t s_ = nullptr;
   bool neumann_ = false;
+  bool rows_ = false;               // stencil sweeps in the row kernels instead of the plane march
   int pre_ = 2, post_ = 2, coarse_sweeps_ = 64;
   double omega_ = 0.8;
 };

@@ -11,6 +11,8 @@
 //   * coarsest level: a fixed number of Jacobi sweeps from zero (a fixed symmetric polynomial).
 // With no sound-soft node S is singular (constant vectors); right-hand side, preconditioned
 // residuals and the solution are kept zero-sum (plain sum over nodes).
+#include <cstdlib>
+
 #include "f2_internal.h"
 #include "solver.h"
 
@@ -70,6 +72,68 @@ __global__ void jacobi_kernel(F2Geom g, const double *x, const double *b, double
     xo[o] = x[o] + omega * (b[o] - he * lap7(g, x, i, j, k)) / (6.0 * he);
   }
   F2_ROWS_END
+}
+
+// The same three stencil sweeps (Jacobi from a previous iterate, residual, y = R S x) as a
+// march through the planes: wavefront w of a block owns row j = 4 by + w, its lanes the columns
+// i = 64 bx + lane, and it walks the planes of chunk bz keeping x of its own column at k-1, k and
+// k+1 in registers.  Each node's operands and the order of their arithmetic are those of the row
+// kernels above, so the results are the same bit for bit; what changes is where the operands come
+// from.  In the row kernels the rows of planes k - 1 and k + 1 are loaded by workgroups on other
+// dies, so each plane of x crosses the memory system about three times.  Here those values are
+// already in registers, and the x and y neighbours are rows that this and the neighbouring
+// wavefronts load at the same plane.  Workgroups are ordered chunk-major and dealt to the eight
+// dies in contiguous ranges, so vertically adjacent rows share an L2.
+enum MGSweep : int { kMGJacobi = 0, kMGResidual = 1, kMGApply = 2 };
+constexpr int kMGChunk = 32;
+
+template <int MODE>
+__global__ __launch_bounds__(256) void mg_march_kernel(F2Geom g, const double *x, const double *b,
+                                                       double *out, double omega, int nbx,
+                                                       int nby) {
+  const int nb = (int)gridDim.x;
+  int t = (int)blockIdx.x;
+  if (nb % 8 == 0) t = (t % 8) * (nb / 8) + t / 8;
+  const int bx = t % nbx, by = (t / nbx) % nby, bz = t / (nbx * nby);
+  const int i = bx * 64 + (int)(threadIdx.x & 63), j = by * 4 + (int)(threadIdx.x >> 6);
+  if (i > g.nx || j > g.ny) return;          // no barriers below
+  const int k0 = bz * kMGChunk, k1 = min(k0 + kMGChunk, g.nz + 1);
+  const size_t col = (size_t)j * g.px + i;
+  const size_t oim = (size_t)j * g.px + mir(i - 1, g.nx), oip = (size_t)j * g.px + mir(i + 1, g.nx);
+  const size_t ojm = (size_t)mir(j - 1, g.ny) * g.px + i, ojp = (size_t)mir(j + 1, g.ny) * g.px + i;
+  // operands of plane k held in registers; those of plane k + 1 are loaded while plane k is
+  // computed (the plane after the last one is read at its mirror index, inside the field)
+  double xm = x[(size_t)mir(k0 - 1, g.nz) * g.plane + col];
+  double xc = x[(size_t)k0 * g.plane + col];
+  double xp = x[(size_t)mir(k0 + 1, g.nz) * g.plane + col];
+  size_t pk = (size_t)k0 * g.plane;
+  double nim = x[pk + oim], nip = x[pk + oip], njm = x[pk + ojm], njp = x[pk + ojp];
+  double bk = MODE == kMGApply ? 0.0 : b[pk + col];
+  for (int k = k0; k < k1; ++k) {
+    const size_t pn = (size_t)mir(k + 1, g.nz) * g.plane;
+    const double xpp = x[(size_t)mir(k + 2 > g.nz ? g.nz + 1 : k + 2, g.nz) * g.plane + col];
+    const double nim1 = x[pn + oim], nip1 = x[pn + oip], njm1 = x[pn + ojm], njp1 = x[pn + ojp];
+    const double bk1 = MODE == kMGApply ? 0.0 : b[pn + col];
+    const size_t o = pk + col;
+    double res = 0.0;
+    if (!msk(g, i, j, k)) {
+      const double he = g.h * eta3(g, i, j, k);
+      const double lap = 6.0 * xc - (nim + nip + njm + njp + xm + xp);
+      if (MODE == kMGJacobi) res = xc + omega * (bk - he * lap) / (6.0 * he);
+      else if (MODE == kMGResidual) res = bk - he * lap;
+      else res = he * lap;
+    }
+    out[o] = res;
+    xm = xc;
+    xc = xp;
+    xp = xpp;
+    nim = nim1;
+    nip = nip1;
+    njm = njm1;
+    njp = njp1;
+    bk = bk1;
+    pk = (size_t)(k + 1) * g.plane;
+  }
 }
 
 // bc = R_c P^T rf  (full weighting over the 27 fine neighbours of the coarse node's position)
@@ -185,6 +249,31 @@ int gridn(size_t n) {
   return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
 }
 
+// One stencil sweep of a level: the plane march, or the row kernels when `rows` is set.
+hipError_t mg_sweep(int mode, bool rows, const F2Geom &g, const double *x, const double *b,
+                    double *out, double omega, hipStream_t s) {
+  if (rows) {
+    if (mode == kMGJacobi)
+      hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(g)), dim3(256), 0, s, g, x, b, out, omega, 0);
+    else if (mode == kMGResidual)
+      hipLaunchKernelGGL(residual_kernel, dim3(rows_grid(g)), dim3(256), 0, s, g, x, b, out);
+    else
+      hipLaunchKernelGGL(s_apply_kernel, dim3(rows_grid(g)), dim3(256), 0, s, g, x, out);
+    return hipGetLastError();
+  }
+  const int nbx = (g.nx + 1 + 63) / 64, nby = (g.ny + 1 + 3) / 4;
+  const int nbz = (g.nz + 1 + kMGChunk - 1) / kMGChunk;
+  const dim3 grid((unsigned)(nbx * nby * nbz));
+  if (mode == kMGJacobi)
+    hipLaunchKernelGGL(mg_march_kernel<kMGJacobi>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx, nby);
+  else if (mode == kMGResidual)
+    hipLaunchKernelGGL(mg_march_kernel<kMGResidual>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
+                       nby);
+  else
+    hipLaunchKernelGGL(mg_march_kernel<kMGApply>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx, nby);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 RieszMG::~RieszMG() {
@@ -274,9 +363,13 @@ cmcg_status RieszMG::smooth(int l, int sweeps) {
   MGLevel &L = lv_[l];
   double *cur = L.x, *other = L.t;
   for (int k = 0; k < sweeps; ++k) {
-    hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, cur, L.b, other,
-                       omega_, k == 0 ? 1 : 0);
-    CMCG_HIP(hipGetLastError());
+    if (k == 0) {
+      hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, cur, L.b,
+                         other, omega_, 1);
+      CMCG_HIP(hipGetLastError());
+    } else {
+      CMCG_HIP(mg_sweep(kMGJacobi, rows_, L.g, cur, L.b, other, omega_, s_));
+    }
     std::swap(cur, other);
   }
   if (cur != L.x)
@@ -292,8 +385,7 @@ cmcg_status RieszMG::vcycle_level(int l) {
     return CMCG_OK;
   }
   CMCG_TRY(smooth(l, pre_));
-  hipLaunchKernelGGL(residual_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, L.x, L.b, L.r);
-  CMCG_HIP(hipGetLastError());
+  CMCG_HIP(mg_sweep(kMGResidual, rows_, L.g, L.x, L.b, L.r, 0.0, s_));
   MGLevel &C = lv_[l + 1];
   hipLaunchKernelGGL(restrict_kernel, dim3(rows_grid(C.g)), dim3(256), 0, s_, L.g, C.g, L.r, C.b);
   CMCG_HIP(hipGetLastError());
@@ -303,9 +395,7 @@ cmcg_status RieszMG::vcycle_level(int l) {
   // post-smoothing continues from the corrected x: x <- x + omega D^{-1}(b - S x), `post` times
   double *cur = L.x, *other = L.t;
   for (int k = 0; k < post_; ++k) {
-    hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, cur, L.b, other,
-                       omega_, 0);
-    CMCG_HIP(hipGetLastError());
+    CMCG_HIP(mg_sweep(kMGJacobi, rows_, L.g, cur, L.b, other, omega_, s_));
     std::swap(cur, other);
   }
   if (cur != L.x)
@@ -314,6 +404,10 @@ cmcg_status RieszMG::vcycle_level(int l) {
 }
 
 cmcg_status RieszMG::vcycle(const double *b, double *x) {
+  // CMCG_MG_ROWS=1 (environment) runs the stencil sweeps in the row kernels, so that tests can
+  // compare the plane march with them bit for bit
+  const char *e = std::getenv("CMCG_MG_ROWS");
+  rows_ = e && e[0] == '1';
   MGLevel &L = lv_[0];
   L.b = const_cast<double *>(b);
   L.x = x;
@@ -351,8 +445,11 @@ cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol,
   double rz = 0.0;
   CMCG_TRY(dot(pr_, pz_, n, &rz));
   for (int it = 1; it <= max_iter; ++it) {
-    hipLaunchKernelGGL(s_apply_kernel, dim3(rows_grid(g)), dim3(256), 0, s_, g, pp_, pq_);
-    CMCG_HIP(hipGetLastError());
+    {
+      const char *e = std::getenv("CMCG_MG_ROWS");
+      rows_ = e && e[0] == '1';
+    }
+    CMCG_HIP(mg_sweep(kMGApply, rows_, g, pp_, nullptr, pq_, 0.0, s_));
     double pq = 0.0;
     CMCG_TRY(dot(pp_, pq_, n, &pq));
     if (!(pq > 0.0)) return set_error("Riesz PCG breakdown"), CMCG_EBREAKDOWN;
