@@ -260,6 +260,27 @@ def test_full_size_period_sampled(cm, c2, prec, tol):
             assert abs(Pxo[cj0, ci0] - Pxs[cj0 - j0, ci0 - i0]) <= tol * sp
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2 * 164 * 6e-8)])
+def test_full_size_adjoint_identity(cm, c2, prec, tol):
+    """4096^2 in the default launch configuration of each precision (K = 8 in FP64, the
+    benchmark's K = 7 in FP32): <E z, y>_E = <z, E* y>_E for random device vectors, relative to
+    |E z|_E |y|_E.  The energy weights are read back from the library's own Riesz map
+    (M_E^{-1} applied to ones).  FP64 holds to rounding; FP32 periods round each of N = 164 steps
+    at eps_32, hence the bound 2 N eps_32 there."""
+    import torch
+    with cm.Solver(c2, prec) as s:
+        n = s.info["state_len"]
+        g = torch.Generator(device="cuda").manual_seed(22)
+        z = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        y = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        w = 1.0 / s.apply(cm.OP_RIESZ, torch.ones(n, dtype=torch.float64, device="cuda"))
+        Ez = s.apply(cm.OP_FORWARD, z)
+        Esy = s.apply(cm.OP_ADJOINT, y)
+        lhs, rhs = torch.dot(w * Ez, y).item(), torch.dot(w * z, Esy).item()
+        scale = math.sqrt(torch.dot(w * Ez, Ez).item() * torch.dot(w * y, y).item())
+    assert abs(lhs - rhs) <= tol * scale, (lhs, rhs, scale)
+
+
 def test_fp32_mixed_reliable_updates_match_fp64(cm):
     """FP32 periods alone stall above 1e-6 on a heterogeneous medium; with FP64 residual
     refreshes the FP32-mixed solve converges in about the FP64 iteration count and lands within
