@@ -151,6 +151,8 @@ class RieszMG {
   hipStream_t s_ = nullptr;
   bool neumann_ = false;
   bool rows_ = false;               // stencil sweeps in the row kernels instead of the plane march
+  int chunk_ = 0;                   // planes per march chunk (0: chosen per level)
+  void read_sweep_env();
   int pre_ = 2, post_ = 2, coarse_sweeps_ = 64;
   double omega_ = 0.8;
 };

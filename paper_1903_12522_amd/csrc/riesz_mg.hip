@@ -11,6 +11,7 @@
 //   * coarsest level: a fixed number of Jacobi sweeps from zero (a fixed symmetric polynomial).
 // With no sound-soft node S is singular (constant vectors); right-hand side, preconditioned
 // residuals and the solution are kept zero-sum (plain sum over nodes).
+#include <algorithm>
 #include <cstdlib>
 
 #include "f2_internal.h"
@@ -83,21 +84,22 @@ __global__ void jacobi_kernel(F2Geom g, const double *x, const double *b, double
 // dies, so each plane of x crosses the memory system about three times.  Here those values are
 // already in registers, and the x and y neighbours are rows that this and the neighbouring
 // wavefronts load at the same plane.  Workgroups are ordered chunk-major and dealt to the eight
-// dies in contiguous ranges, so vertically adjacent rows share an L2.
+// dies in contiguous ranges, so vertically adjacent rows share an L2.  A chunk spans `chunk`
+// planes (32 on large levels, fewer where that would leave the launch short of workgroups).
 enum MGSweep : int { kMGJacobi = 0, kMGResidual = 1, kMGApply = 2 };
 constexpr int kMGChunk = 32;
 
 template <int MODE>
 __global__ __launch_bounds__(256) void mg_march_kernel(F2Geom g, const double *x, const double *b,
                                                        double *out, double omega, int nbx,
-                                                       int nby) {
+                                                       int nby, int chunk) {
   const int nb = (int)gridDim.x;
   int t = (int)blockIdx.x;
   if (nb % 8 == 0) t = (t % 8) * (nb / 8) + t / 8;
   const int bx = t % nbx, by = (t / nbx) % nby, bz = t / (nbx * nby);
   const int i = bx * 64 + (int)(threadIdx.x & 63), j = by * 4 + (int)(threadIdx.x >> 6);
   if (i > g.nx || j > g.ny) return;          // no barriers below
-  const int k0 = bz * kMGChunk, k1 = min(k0 + kMGChunk, g.nz + 1);
+  const int k0 = bz * chunk, k1 = min(k0 + chunk, g.nz + 1);
   const size_t col = (size_t)j * g.px + i;
   const size_t oim = (size_t)j * g.px + mir(i - 1, g.nx), oip = (size_t)j * g.px + mir(i + 1, g.nx);
   const size_t ojm = (size_t)mir(j - 1, g.ny) * g.px + i, ojp = (size_t)mir(j + 1, g.ny) * g.px + i;
@@ -249,9 +251,11 @@ int gridn(size_t n) {
   return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
 }
 
-// One stencil sweep of a level: the plane march, or the row kernels when `rows` is set.
-hipError_t mg_sweep(int mode, bool rows, const F2Geom &g, const double *x, const double *b,
-                    double *out, double omega, hipStream_t s) {
+// One stencil sweep of a level: the plane march, or the row kernels when `rows` is set.  The
+// march's chunk length is halved from 32 planes until the launch has 8192 workgroups (one plane
+// at 129^3 nodes, 32 from 513^3 up); `chunk_req` > 0 fixes it instead.
+hipError_t mg_sweep(int mode, bool rows, int chunk_req, const F2Geom &g, const double *x,
+                    const double *b, double *out, double omega, hipStream_t s) {
   if (rows) {
     if (mode == kMGJacobi)
       hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(g)), dim3(256), 0, s, g, x, b, out, omega, 0);
@@ -262,15 +266,21 @@ hipError_t mg_sweep(int mode, bool rows, const F2Geom &g, const double *x, const
     return hipGetLastError();
   }
   const int nbx = (g.nx + 1 + 63) / 64, nby = (g.ny + 1 + 3) / 4;
-  const int nbz = (g.nz + 1 + kMGChunk - 1) / kMGChunk;
+  int chunk = kMGChunk;
+  if (chunk_req > 0) chunk = std::min(chunk_req, g.nz + 1);
+  else
+    while (chunk > 1 && (long)nbx * nby * ((g.nz + chunk) / chunk) < 8192) chunk /= 2;
+  const int nbz = (g.nz + chunk) / chunk;
   const dim3 grid((unsigned)(nbx * nby * nbz));
   if (mode == kMGJacobi)
-    hipLaunchKernelGGL(mg_march_kernel<kMGJacobi>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx, nby);
+    hipLaunchKernelGGL(mg_march_kernel<kMGJacobi>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
+                       nby, chunk);
   else if (mode == kMGResidual)
     hipLaunchKernelGGL(mg_march_kernel<kMGResidual>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
-                       nby);
+                       nby, chunk);
   else
-    hipLaunchKernelGGL(mg_march_kernel<kMGApply>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx, nby);
+    hipLaunchKernelGGL(mg_march_kernel<kMGApply>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
+                       nby, chunk);
   return hipGetLastError();
 }
 
@@ -368,7 +378,7 @@ cmcg_status RieszMG::smooth(int l, int sweeps) {
                          other, omega_, 1);
       CMCG_HIP(hipGetLastError());
     } else {
-      CMCG_HIP(mg_sweep(kMGJacobi, rows_, L.g, cur, L.b, other, omega_, s_));
+      CMCG_HIP(mg_sweep(kMGJacobi, rows_, chunk_, L.g, cur, L.b, other, omega_, s_));
     }
     std::swap(cur, other);
   }
@@ -385,7 +395,7 @@ cmcg_status RieszMG::vcycle_level(int l) {
     return CMCG_OK;
   }
   CMCG_TRY(smooth(l, pre_));
-  CMCG_HIP(mg_sweep(kMGResidual, rows_, L.g, L.x, L.b, L.r, 0.0, s_));
+  CMCG_HIP(mg_sweep(kMGResidual, rows_, chunk_, L.g, L.x, L.b, L.r, 0.0, s_));
   MGLevel &C = lv_[l + 1];
   hipLaunchKernelGGL(restrict_kernel, dim3(rows_grid(C.g)), dim3(256), 0, s_, L.g, C.g, L.r, C.b);
   CMCG_HIP(hipGetLastError());
@@ -395,7 +405,7 @@ cmcg_status RieszMG::vcycle_level(int l) {
   // post-smoothing continues from the corrected x: x <- x + omega D^{-1}(b - S x), `post` times
   double *cur = L.x, *other = L.t;
   for (int k = 0; k < post_; ++k) {
-    CMCG_HIP(mg_sweep(kMGJacobi, rows_, L.g, cur, L.b, other, omega_, s_));
+    CMCG_HIP(mg_sweep(kMGJacobi, rows_, chunk_, L.g, cur, L.b, other, omega_, s_));
     std::swap(cur, other);
   }
   if (cur != L.x)
@@ -403,11 +413,17 @@ cmcg_status RieszMG::vcycle_level(int l) {
   return CMCG_OK;
 }
 
-cmcg_status RieszMG::vcycle(const double *b, double *x) {
-  // CMCG_MG_ROWS=1 (environment) runs the stencil sweeps in the row kernels, so that tests can
-  // compare the plane march with them bit for bit
+// CMCG_MG_ROWS=1 (environment) runs the stencil sweeps in the row kernels and CMCG_MG_CHUNK=<n>
+// fixes the march's chunk length, so that tests can compare the forms bit for bit
+void RieszMG::read_sweep_env() {
   const char *e = std::getenv("CMCG_MG_ROWS");
   rows_ = e && e[0] == '1';
+  const char *c = std::getenv("CMCG_MG_CHUNK");
+  chunk_ = c ? std::atoi(c) : 0;
+}
+
+cmcg_status RieszMG::vcycle(const double *b, double *x) {
+  read_sweep_env();
   MGLevel &L = lv_[0];
   L.b = const_cast<double *>(b);
   L.x = x;
@@ -431,6 +447,7 @@ cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol,
   const F2Geom &g = lv_[0].g;
   const size_t n = g.fs;
   *iters = 0;
+  read_sweep_env();
   CMCG_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s_));
   if (b_is_float)
     CMCG_HIP(convert<double, float>(pr_, static_cast<const float *>(b), n, s_));
@@ -445,11 +462,7 @@ cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol,
   double rz = 0.0;
   CMCG_TRY(dot(pr_, pz_, n, &rz));
   for (int it = 1; it <= max_iter; ++it) {
-    {
-      const char *e = std::getenv("CMCG_MG_ROWS");
-      rows_ = e && e[0] == '1';
-    }
-    CMCG_HIP(mg_sweep(kMGApply, rows_, g, pp_, nullptr, pq_, 0.0, s_));
+    CMCG_HIP(mg_sweep(kMGApply, rows_, chunk_, g, pp_, nullptr, pq_, 0.0, s_));
     double pq = 0.0;
     CMCG_TRY(dot(pp_, pq_, n, &pq));
     if (!(pq > 0.0)) return set_error("Riesz PCG breakdown"), CMCG_EBREAKDOWN;

@@ -225,28 +225,33 @@ def test_vcycle_riesz_is_symmetric_positive(cm, masked):
 
 @pytest.mark.parametrize("masked", [True, False])
 def test_multigrid_plane_march_matches_row_kernels_bitwise(cm, masked, monkeypatch):
-    """The multigrid's stencil sweeps (Jacobi, residual, S x) run as a march through the planes;
-    CMCG_MG_ROWS=1 runs them in the row kernels instead.  Both forms do each node's arithmetic on
-    the same operands in the same order, so the V-cycle and the PCG Riesz solve give the same
-    bits.  The grid has several 64-wide x tiles, a ragged 4-row tail, three 32-plane chunks and
-    four levels."""
+    """The multigrid's stencil sweeps (Jacobi, residual, S x) run as a march through chunks of
+    planes; CMCG_MG_ROWS=1 runs them in the row kernels instead, and CMCG_MG_CHUNK fixes the
+    chunk length.  Every form does each node's arithmetic on the same operands in the same
+    order, so the V-cycle and the PCG Riesz solve give the same bits.  The grid has several
+    64-wide x tiles, a ragged 4-row tail and four levels; chunks of 32 and 5 planes leave ragged
+    last chunks (the automatic choice is one plane at this size)."""
     prob = _mixed3d(n=(96, 40, 72), seed=13, masked=masked)
     o = F2(prob)
     rng = np.random.default_rng(14)
     x = rng.standard_normal(o.size) * np.concatenate([o.free.ravel()] * 2)
     if not masked:
         x[: o.nn] -= x[: o.nn].mean()
+    forms = [("0", None), ("0", "32"), ("0", "5"), ("1", None)]
     for mode in ("vcycle", "solve"):
         out = []
-        for rows in (None, "1"):
-            if rows is None:
-                monkeypatch.delenv("CMCG_MG_ROWS", raising=False)
+        for rows, chunk in forms:
+            monkeypatch.setenv("CMCG_MG_ROWS", rows)
+            if chunk is None:
+                monkeypatch.delenv("CMCG_MG_CHUNK", raising=False)
             else:
-                monkeypatch.setenv("CMCG_MG_ROWS", rows)
+                monkeypatch.setenv("CMCG_MG_CHUNK", chunk)
             with cm.Solver(prob, "fp64", riesz_mode=mode) as s:
                 out.append(s.apply(cm.OP_RIESZ, x))
         monkeypatch.delenv("CMCG_MG_ROWS", raising=False)
-        assert np.array_equal(out[0], out[1]), (mode, np.max(np.abs(out[0] - out[1])))
+        monkeypatch.delenv("CMCG_MG_CHUNK", raising=False)
+        for f, a in zip(forms[1:], out[1:]):
+            assert np.array_equal(a, out[0]), (mode, f, np.max(np.abs(a - out[0])))
 
 
 @pytest.mark.parametrize("kind", ["inclusions", "sphere"])
