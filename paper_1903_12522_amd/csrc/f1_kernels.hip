@@ -282,7 +282,7 @@ __device__ __forceinline__ void buf_st(double x, __amdgpu_buffer_rsrc_t r, unsig
 
 // Resources and offsets of one fast-variant wavefront.
 struct FastIO {
-  __amdgpu_buffer_rsrc_t in, cc, out, sub;
+  __amdgpu_buffer_rsrc_t in, cc, out, sub, fre, fim;
   unsigned vo;        // this lane's column offset (bytes)
   unsigned vo_st;     // column offset for stores: vo, or out of range for a halo lane
   unsigned pitchb, fsb;
@@ -308,9 +308,13 @@ __device__ __forceinline__ void fast_store_rows(const FastIO &io, int j, int s0,
 // FIRST: the period's opening half kick at level 0 (forward p += dt/2 G v, backward
 // v -= dt/2 c^2 D p, on the raw input).  SUB: the stored values less the subtrahend (sub_a: Px,
 // sub_c: v of row j - K; sub_b: Py of row j - K - 1), loaded one row ahead with the inputs.
-template <typename T, int K, bool ADJ, bool FIRST, bool SUB>
+// FORCED (forward): level k adds the source of its row j - k at the step's time, read from the
+// forcing fields (rows that the previous levels read too, so mostly cache hits); `has_fim` is
+// wave-uniform.
+template <typename T, int K, bool ADJ, bool FIRST, bool SUB, bool FORCED>
 __device__ __forceinline__ void f1_fast_row(const FastIO &io, const F1Launch &L, const int j,
                                             const int s0, const int s1, const T dth, const T hdth,
+                                            const bool has_fim,
                                             T in_v, T in_px, const T in_py, const T in_cc,
                                             const T sub_a, const T sub_b, const T sub_c,
                                             const T (&Vp)[K + 1],
@@ -342,7 +346,19 @@ __device__ __forceinline__ void f1_fast_row(const FastIO &io, const F1Launch &L,
       const T kap = CCp[k - 1];
       const T kick_h = lastk ? hdth : dth;
       const T pl = lane_from_left(px);
-      const T vn = fma(kap, (px - pl) + (pyr - pyrm1), v);
+      T dsum = (px - pl) + (pyr - pyrm1);
+      if (FORCED) {
+        const unsigned so = (unsigned)(j - k) * io.pitchb;
+        T fr;
+        buf_ld(fr, io.fre, io.vo, so);
+        dsum = fma(fr, (T)L.cs[k - 1], dsum);
+        if (has_fim) {
+          T fi;
+          buf_ld(fi, io.fim, io.vo, so);
+          dsum = fma(fi, (T)L.sn[k - 1], dsum);
+        }
+      }
+      const T vn = fma(kap, dsum, v);
       const T vr = lane_from_right(vn);
       Vc[k] = vn;
       PXc[k] = fma(kick_h, vr - vn, px);
@@ -383,7 +399,7 @@ __device__ __forceinline__ void f1_fast_row(const FastIO &io, const F1Launch &L,
 // arithmetic per cell is identical to the general body's, so results do not depend on which
 // variant ran.  The row loop is unrolled by two with the previous/current register sets trading
 // roles (no register copies), and each row's loads are issued one row ahead of their use.
-template <typename T, int K, bool ADJ, bool FIRST, bool SUB>
+template <typename T, int K, bool ADJ, bool FIRST, bool SUB, bool FORCED>
 __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, const int i, const int lane,
                                                const int s0, const int s1) {
@@ -397,6 +413,9 @@ __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> 
   io.cc = buf_rsrc(p.cc, io.fsb);
   io.out = buf_rsrc(p.out, 3 * io.fsb);
   io.sub = buf_rsrc(SUB ? p.sub : p.in, 3 * io.fsb);
+  io.fre = buf_rsrc(FORCED ? p.fre : p.cc, io.fsb);
+  io.fim = buf_rsrc(FORCED && p.fim ? p.fim : p.cc, io.fsb);
+  const bool has_fim = FORCED && p.fim != nullptr;
   io.vo = (unsigned)i * (unsigned)sizeof(T);
   io.vo_st = (lane >= H && lane < 64 - H) ? io.vo : kBufDrop;
   T Va[K + 1], PXa[K + 1], PYa[K + 1], CCa[K + 1];
@@ -442,25 +461,26 @@ __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> 
     const RowIn x0 = A;
     load_row(j + 1, A);
     if (pinned) __builtin_amdgcn_sched_barrier(0);
-    f1_fast_row<T, K, ADJ, FIRST, SUB>(io, L, j, s0, s1, dth, hdth, x0.v, x0.px, x0.py, x0.cc,
-                                       x0.sa, x0.sb, x0.sc, Va, PXa, PYa, CCa, Vb, PXb, PYb, CCb,
-                                       HOLD);
+    f1_fast_row<T, K, ADJ, FIRST, SUB, FORCED>(io, L, j, s0, s1, dth, hdth, has_fim, x0.v, x0.px,
+                                               x0.py, x0.cc, x0.sa, x0.sb, x0.sc, Va, PXa, PYa,
+                                               CCa, Vb, PXb, PYb, CCb, HOLD);
     const RowIn x1 = A;
     if (pinned || j + 2 <= jend) load_row(j + 2, A);
     if (pinned) __builtin_amdgcn_sched_barrier(0);
-    f1_fast_row<T, K, ADJ, FIRST, SUB>(io, L, j + 1, s0, s1, dth, hdth, x1.v, x1.px, x1.py,
-                                       x1.cc, x1.sa, x1.sb, x1.sc, Vb, PXb, PYb, CCb, Va, PXa,
-                                       PYa, CCa, HOLD);
+    f1_fast_row<T, K, ADJ, FIRST, SUB, FORCED>(io, L, j + 1, s0, s1, dth, hdth, has_fim, x1.v,
+                                               x1.px, x1.py, x1.cc, x1.sa, x1.sb, x1.sc, Vb, PXb,
+                                               PYb, CCb, Va, PXa, PYa, CCa, HOLD);
   }
   if (j <= jend)
-    f1_fast_row<T, K, ADJ, FIRST, SUB>(io, L, j, s0, s1, dth, hdth, A.v, A.px, A.py, A.cc, A.sa,
-                                       A.sb, A.sc, Va, PXa, PYa, CCa, Vb, PXb, PYb, CCb, HOLD);
+    f1_fast_row<T, K, ADJ, FIRST, SUB, FORCED>(io, L, j, s0, s1, dth, hdth, has_fim, A.v, A.px,
+                                               A.py, A.cc, A.sa, A.sb, A.sc, Va, PXa, PYa, CCa, Vb,
+                                               PXb, PYb, CCb, HOLD);
 }
 
 // Which fast variants a kernel instance holds.  The first and last launches of a period run
 // their own instances, so that the register allocation of the instance every other launch runs
 // is not raised by variants it never takes.
-enum F1FastSet { kFastMiddle = 0, kFastEnds = 1, kFastAll = 2 };
+enum F1FastSet { kFastMiddle = 0, kFastEnds = 1, kFastAll = 2, kFastForced = 3 };
 
 // Tile (bx, by) of a launch: wavefront w of the workgroup owns column strip 4 bx + w of the
 // band of rows by.  Interior wavefronts (all 64 columns in 1..nx-2) of interior bands take the
@@ -490,15 +510,28 @@ __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> 
       return;
     }
   }
-  const bool fast = inner_cols && inner_rows && small && !L.forced && !L.accumulate &&
-                    !L.general && !(L.first && p.sub);
+  const bool fast = inner_cols && inner_rows && small && !L.accumulate && !L.general &&
+                    !(L.first && p.sub) && (!L.forced || (SET == kFastForced && !ADJ));
   const bool ends = L.first || p.sub;
+  if (SET == kFastForced) {
+    if (fast && L.first)
+      f1_stream_fast<T, K, ADJ, true, false, true>(g, p, L, i0 + lane, lane, s0, s1);
+    else if (fast && p.sub)
+      f1_stream_fast<T, K, ADJ, false, true, true>(g, p, L, i0 + lane, lane, s0, s1);
+    else if (fast)
+      f1_stream_fast<T, K, ADJ, false, false, true>(g, p, L, i0 + lane, lane, s0, s1);
+    else if (inner_cols)
+      f1_stream_body<T, K, ADJ, false, false>(g, p, L, i0 + lane, lane, s0, s1);
+    else
+      f1_stream_body<T, K, ADJ, true, false>(g, p, L, i0 + lane, lane, s0, s1);
+    return;
+  }
   if (SET != kFastMiddle && fast && L.first)
-    f1_stream_fast<T, K, ADJ, true, false>(g, p, L, i0 + lane, lane, s0, s1);
+    f1_stream_fast<T, K, ADJ, true, false, false>(g, p, L, i0 + lane, lane, s0, s1);
   else if (SET != kFastMiddle && fast && p.sub)
-    f1_stream_fast<T, K, ADJ, false, true>(g, p, L, i0 + lane, lane, s0, s1);
+    f1_stream_fast<T, K, ADJ, false, true, false>(g, p, L, i0 + lane, lane, s0, s1);
   else if (SET != kFastEnds && fast && !ends)
-    f1_stream_fast<T, K, ADJ, false, false>(g, p, L, i0 + lane, lane, s0, s1);
+    f1_stream_fast<T, K, ADJ, false, false, false>(g, p, L, i0 + lane, lane, s0, s1);
   else if (inner_cols)
     f1_stream_body<T, K, ADJ, false, false>(g, p, L, i0 + lane, lane, s0, s1);
   else
@@ -563,12 +596,23 @@ hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hi
 #define CMCG_F1_LAUNCH(MASK, SET)                                                              \
   hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ, MASK, SET>), grid, dim3(kThreads), 0, s, g, p, \
                      Lx, band)
-  if (g.mask) {
-    if (ends) CMCG_F1_LAUNCH(true, kFastEnds);
-    else CMCG_F1_LAUNCH(true, kFastMiddle);
-  } else {
-    if (ends) CMCG_F1_LAUNCH(false, kFastEnds);
-    else CMCG_F1_LAUNCH(false, kFastMiddle);
+  bool done = false;
+  if constexpr (!ADJ) {
+    // forced (forward) periods: every launch of the period runs the instance with the source
+    if (L.forced) {
+      if (g.mask) CMCG_F1_LAUNCH(true, kFastForced);
+      else CMCG_F1_LAUNCH(false, kFastForced);
+      done = true;
+    }
+  }
+  if (!done) {
+    if (g.mask) {
+      if (ends) CMCG_F1_LAUNCH(true, kFastEnds);
+      else CMCG_F1_LAUNCH(true, kFastMiddle);
+    } else {
+      if (ends) CMCG_F1_LAUNCH(false, kFastEnds);
+      else CMCG_F1_LAUNCH(false, kFastMiddle);
+    }
   }
 #undef CMCG_F1_LAUNCH
   return hipGetLastError();

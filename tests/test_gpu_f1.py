@@ -95,16 +95,17 @@ def test_temporal_blocking_is_bitwise_fp32(cm):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_fast_variants_match_general_body_bitwise(cm, prec, monkeypatch):
     """Interior tiles of the first launch of a period (opening half kick), of its last launch
-    (output less a subtrahend, as in each CG iteration's E d - d) and of the launches between
-    run register-streamed fast variants; CMCG_F1_GENERAL=1 sends every tile through the general
-    body instead.  Both must give the same bits for the periods and for CG iterates."""
+    (output less a subtrahend, as in each CG iteration's E d - d), of the launches between, and
+    of every launch of a forced period run register-streamed fast variants; CMCG_F1_GENERAL=1
+    sends every tile through the general body instead.  Both must give the same bits for the
+    periods and for CG iterates (whose initial gradient is a forced period less its input)."""
     prob = _mixed_problem(nx=420, ny=260, seed=8)
     z = np.random.default_rng(4).standard_normal(F1(prob).size)
 
     def run(k):
         with cm.Solver(prob, prec, tol=0.0, max_iter=50, steps_per_launch=k) as s:
             out = [s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z),
-                   s.apply(cm.OP_FORWARD, z, steps=k)]
+                   s.apply(cm.OP_FORWARD, z, steps=k), s.apply(cm.OP_FORCED, z)]
             s.begin()
             s.iterate(3)
             out.append(s.state(0))
