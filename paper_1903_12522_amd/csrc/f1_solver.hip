@@ -368,8 +368,11 @@ class F1Solver final : public Solver {
   int build_launch(const F1Set &b, bool forced, const T *in, T *out, const T *sub, int steps,
                    int n0, int K, bool filter, F1Ptrs<T> *pp, F1Launch *LL) const {
     T *S[2] = {tp<T>(b.S0), tp<T>(b.S1)};
-    const int l = n0 / K;
-    const int ns = std::min(K, steps - n0);
+    // a period of `steps` steps runs in launches of K steps; the remainder, if any, opens it, so
+    // that the last launch (which also reads the subtrahend) advances a full K steps
+    const int first_ns = (steps % K) ? steps % K : std::min(K, steps);
+    const int ns = (n0 == 0) ? first_ns : std::min(K, steps - n0);
+    const int l = (n0 == 0) ? 0 : 1 + (n0 - first_ns) / K;   // launch index (buffer ping-pong)
     const bool lastl = (n0 + ns == steps);
     F1Launch L{};
     L.nsteps = ns;
