@@ -118,6 +118,31 @@ def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10):
             "device_GB": round(gb, 1)}
 
 
+def nodal_cpu_baseline(which: str, steps: int = 2):
+    """The nodal oracle as it stands, on the full grid of a 3D workload: a forward and a
+    transposed run of `steps` leapfrog steps (the oracle built with N = steps: the same step,
+    start and end maps, a shorter period), timed on one host core and scaled to GLUP/s."""
+    import numpy as np
+    import cmcg_inputs as ci
+    from oracle.f2 import F2
+    # the sphere's 1024^3 grid would need about 200 GB of host memory in the oracle: its rate
+    # per node-step is sampled on the same problem at 512^3
+    prob = ci.inclusions_3d() if which == "inclusions" else ci.sound_soft_sphere_3d(n=512)
+    log(f"timing the nodal oracle on {which} {prob.n[0]}^3 ({steps} + {steps} steps)")
+    o = F2(prob, N=steps)
+    z = np.random.default_rng(0).standard_normal(o.size)
+    t0 = time.perf_counter()
+    o.period(z, False)
+    o.period_T(z)
+    dt = time.perf_counter() - t0
+    return {"value": round(2 * steps * o.nn / dt / 1e9, 4), "unit": "GLUP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} forward + {steps} transposed leapfrog steps of the NumPy FP64 "
+                      f"nodal oracle on a {prob.n[0]}^3 grid of this workload ({dt:.1f} s; "
+                      f"NumPy element-wise kernels run on one thread)",
+            "seconds": round(dt, 2)}
+
+
 def serving_run(count: int):
     import cmcg_inputs as ci
     from paper_1903_12522_amd import cmcg, serving
@@ -349,6 +374,8 @@ def main():
     ap.add_argument("--nodal", default="", help="comma list of inclusions,sphere: 3D solves")
     ap.add_argument("--nodal-max-iter", type=int, default=3000)
     ap.add_argument("--nodal-precisions", default="fp32", help="comma list of fp32,fp64")
+    ap.add_argument("--nodal-cpu", action="store_true",
+                    help="also time the nodal oracle on a bounded sample of each 3D workload")
     ap.add_argument("--serving", type=int, default=0, help="replay this many serving requests")
     ap.add_argument("--runup-study", action="store_true",
                     help="run-up and do-nothing long-time solve on the 4096^2 workload")
@@ -468,6 +495,20 @@ def main():
     for which in [w for w in args.nodal.split(",") if w]:
         out[f"nodal_{which}"] = {p: nodal_3d(which, p, args.nodal_max_iter)
                                  for p in args.nodal_precisions.split(",") if p}
+        if args.nodal_cpu:
+            cb = nodal_cpu_baseline(which)
+            runs = [r for r in out[f"nodal_{which}"].values() if r["converged"]]
+            if runs:
+                # the oracle's step rate carried over to each converged solve: two periods of
+                # N steps per CG iteration (Riesz solves and vector work not counted)
+                for r in runs:
+                    r["cpu_extrapolated_seconds"] = round(
+                        2 * r["steps_per_period"] * r["iterations"] * r["nodes"]
+                        / (cb["value"] * 1e9), 0)
+                cb["extrapolated_note"] = ("cpu_extrapolated_seconds in each solve: its CG "
+                                           "iterations x 2 periods x N steps at the sampled "
+                                           "oracle rate")
+            out[f"nodal_{which}"]["cpu_baseline"] = cb
     if args.serving > 0:
         out["serving"] = serving_run(args.serving)
     if args.runup_study:
