@@ -477,10 +477,10 @@ __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> 
                                                PXb, PYb, CCb, HOLD);
 }
 
-// Which fast variants a kernel instance holds.  The first and last launches of a period run
-// their own instances, so that the register allocation of the instance every other launch runs
-// is not raised by variants it never takes.
-enum F1FastSet { kFastMiddle = 0, kFastEnds = 1, kFastAll = 2, kFastForced = 3 };
+// Which fast variants a kernel instance holds.  The first and last launches of a period, and
+// the launches of a forced period, run their own instances, so that the register allocation of
+// the instance every other launch runs is not raised by variants it never takes.
+enum F1FastSet { kFastMiddle = 0, kFastEnds = 1, kFastForced = 3 };
 
 // Tile (bx, by) of a launch: wavefront w of the workgroup owns column strip 4 bx + w of the
 // band of rows by.  Interior wavefronts (all 64 columns in 1..nx-2) of interior bands take the
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void f1_stream_kernel(F1Geom g, F1Ptrs<T>
 // Several independent solves in one launch (continuous batching): workgroup b belongs to the
 // last slot whose first workgroup is <= b and runs that solve's tile exactly as a single-solve
 // launch would, so every solve's arithmetic is the same alone or batched.
-template <typename T, int K, bool ADJ>
+template <typename T, int K, bool ADJ, int SET>
 __global__ __launch_bounds__(kThreads) void f1_multi_kernel(const F1SlotLaunch<T> *slots,
                                                             int nslots) {
   int s = 0;
@@ -559,8 +559,8 @@ __global__ __launch_bounds__(kThreads) void f1_multi_kernel(const F1SlotLaunch<T
   const F1Ptrs<T> p = slots[s].p;
   const F1Launch L = slots[s].L;
   const int t = (int)blockIdx.x - slots[s].block0;
-  f1_stream_tile<T, K, ADJ, false, kFastAll>(g, p, L, slots[s].band, t % slots[s].nbx,
-                                             t / slots[s].nbx);
+  f1_stream_tile<T, K, ADJ, false, SET>(g, p, L, slots[s].band, t % slots[s].nbx,
+                                        t / slots[s].nbx);
 }
 
 // Rows per band.  Besides its band, each wavefront loads 2K + 3 rows to fill its pipeline, so
@@ -619,9 +619,21 @@ hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hi
 }
 
 template <typename T, int K, bool ADJ>
-hipError_t launch_multi_k(const F1SlotLaunch<T> *slots, int nslots, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((f1_multi_kernel<T, K, ADJ>), dim3(blocks), dim3(kThreads), 0, s, slots,
-                     nslots);
+hipError_t launch_multi_k(int set, const F1SlotLaunch<T> *slots, int nslots, int blocks,
+                          hipStream_t s) {
+  if (set == kFastMiddle)
+    hipLaunchKernelGGL((f1_multi_kernel<T, K, ADJ, kFastMiddle>), dim3(blocks), dim3(kThreads), 0,
+                       s, slots, nslots);
+  else if (set == kFastEnds)
+    hipLaunchKernelGGL((f1_multi_kernel<T, K, ADJ, kFastEnds>), dim3(blocks), dim3(kThreads), 0, s,
+                       slots, nslots);
+  else if constexpr (!ADJ) {
+    if (set != kFastForced) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((f1_multi_kernel<T, K, false, kFastForced>), dim3(blocks), dim3(kThreads), 0,
+                       s, slots, nslots);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -833,6 +845,11 @@ hipError_t f1_adjoint_launch(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch
   return launch_dispatch<T, true>(g, p, L, kmax, s);
 }
 
+int f1_fast_set(const F1Launch &L, bool has_sub) {
+  if (L.forced) return kFastForced;   // forward periods only: the backward one has no source
+  return (L.first || has_sub) ? kFastEnds : kFastMiddle;
+}
+
 void f1_launch_shape(int nx, int ny, int K, int *nbx, int *nby, int *band) {
   const int ow = 64 - 2 * (K + 1);
   const int strips = (nx + ow - 1) / ow;
@@ -842,12 +859,12 @@ void f1_launch_shape(int nx, int ny, int K, int *nbx, int *nby, int *band) {
 }
 
 template <typename T>
-hipError_t f1_multi_launch(int K, bool adjoint, const F1SlotLaunch<T> *slots, int nslots,
-                           int blocks, hipStream_t s) {
+hipError_t f1_multi_launch(int K, bool adjoint, int set, const F1SlotLaunch<T> *slots,
+                           int nslots, int blocks, hipStream_t s) {
 #define MK(k)                                                                        \
   case k:                                                                            \
-    return adjoint ? launch_multi_k<T, k, true>(slots, nslots, blocks, s)            \
-                   : launch_multi_k<T, k, false>(slots, nslots, blocks, s);
+    return adjoint ? launch_multi_k<T, k, true>(set, slots, nslots, blocks, s)       \
+                   : launch_multi_k<T, k, false>(set, slots, nslots, blocks, s);
   switch (K) {
     MK(1) MK(2) MK(3) MK(4) MK(5) MK(6) MK(7) MK(8)
     default: return hipErrorInvalidValue;
@@ -900,8 +917,8 @@ hipError_t f1_pack(const F1Geom &g, const T *dev, double *packed, size_t fs, hip
 }
 
 // explicit instantiations
-template hipError_t f1_multi_launch<float>(int, bool, const F1SlotLaunch<float> *, int, int, hipStream_t);
-template hipError_t f1_multi_launch<double>(int, bool, const F1SlotLaunch<double> *, int, int, hipStream_t);
+template hipError_t f1_multi_launch<float>(int, bool, int, const F1SlotLaunch<float> *, int, int, hipStream_t);
+template hipError_t f1_multi_launch<double>(int, bool, int, const F1SlotLaunch<double> *, int, int, hipStream_t);
 template hipError_t f1_forward_launch<float>(const F1Geom &, const F1Ptrs<float> &, const F1Launch &, int, hipStream_t);
 template hipError_t f1_forward_launch<double>(const F1Geom &, const F1Ptrs<double> &, const F1Launch &, int, hipStream_t);
 template hipError_t f1_adjoint_launch<float>(const F1Geom &, const F1Ptrs<float> &, const F1Launch &, int, hipStream_t);

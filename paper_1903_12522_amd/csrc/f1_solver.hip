@@ -14,6 +14,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <type_traits>
 
 #include "solver.h"
@@ -976,19 +977,20 @@ class F1Server final : public Server {
   // One batched launch planned for this tick: `count` descriptors at byte offset `off` of the
   // descriptor staging buffer, all of one precision, direction and step count.
   struct PlannedLaunch {
-    int prec, ns, adj, count, blocks;
+    int prec, ns, adj, set, count, blocks;
     size_t off;
   };
 
   // Append this round's launches of the solves in `sel` (all of precision T) to the plan: the
-  // solves are grouped by (direction, steps), each group one batched launch; every solve's step
-  // counter advances.  Returns false when the staging buffer cannot hold the round.
+  // solves are grouped by (direction, steps, fast-variant set), each group one batched launch;
+  // every solve's step counter advances.  Returns false when the staging buffer cannot hold the
+  // round.
   template <typename T>
   bool plan_round(const std::vector<ServeRequest *> &sel, size_t &off,
                   std::vector<PlannedLaunch> &plan, double &work) {
     if (sel.empty()) return true;
     if (off + sel.size() * sizeof(F1SlotLaunch<T>) + 2 * 256 > desc_cap) return false;
-    std::map<std::pair<int, int>, std::vector<F1SlotLaunch<T>>> groups;
+    std::map<std::tuple<int, int, int>, std::vector<F1SlotLaunch<T>>> groups;
     for (ServeRequest *R : sel) {
       F1Solver *S = R->S;
       const F1Set *b;
@@ -1005,7 +1007,7 @@ class F1Server final : public Server {
       int nby;
       f1_launch_shape(S->g.nx, S->g.ny, ns, &d.nbx, &nby, &d.band);
       d.nblocks = d.nbx * nby;
-      groups[{adj ? 1 : 0, ns}].push_back(d);
+      groups[{adj ? 1 : 0, ns, f1_fast_set(d.L, d.p.sub != nullptr)}].push_back(d);
       R->n0 += ns;
       const double u = (double)ns * S->g.nx * S->g.ny;
       S->updates += u;
@@ -1021,7 +1023,8 @@ class F1Server final : public Server {
       const size_t bytes = v.size() * sizeof(F1SlotLaunch<T>);
       std::memcpy(static_cast<char *>(h_desc) + off, v.data(), bytes);
       plan.push_back({std::is_same<T, double>::value ? CMCG_FP64 : CMCG_FP32_MIXED,
-                      kv.first.second, kv.first.first, (int)v.size(), blocks, off});
+                      std::get<1>(kv.first), std::get<0>(kv.first), std::get<2>(kv.first),
+                      (int)v.size(), blocks, off});
       off = (off + bytes + 255) / 256 * 256;
     }
     return true;
@@ -1030,7 +1033,7 @@ class F1Server final : public Server {
   template <typename T>
   cmcg_status launch_planned(const PlannedLaunch &L) {
     auto *dd = reinterpret_cast<const F1SlotLaunch<T> *>(static_cast<const char *>(d_desc) + L.off);
-    CMCG_HIP(f1_multi_launch<T>(L.ns, L.adj != 0, dd, L.count, L.blocks, s));
+    CMCG_HIP(f1_multi_launch<T>(L.ns, L.adj != 0, L.set, dd, L.count, L.blocks, s));
     return CMCG_OK;
   }
 
