@@ -110,7 +110,7 @@ typedef struct {
   int32_t device;              /* HIP device ordinal                                           */
   void *hip_stream;            /* hipStream_t to run on, or NULL                                */
   int32_t steps_per_launch;    /* leapfrog steps fused per kernel launch (temporal blocking):
-                                  F1 1..8 (default 7 in FP32-mixed, 8 in FP64); F2 1..4 for the
+                                  F1 1..8 (default 7); F2 1..4 for the
                                   homogeneous steps (default 3; 1 = one step per launch);
                                   0 = library default.  Results do not depend on it (bitwise)  */
   int32_t riesz_max_iter;      /* F2: cap on the Riesz (elliptic) PCG iterations; 0 = default  */

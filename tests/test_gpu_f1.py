@@ -263,8 +263,8 @@ def test_full_size_period_sampled(cm, c2, prec, tol):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2 * 164 * 6e-8)])
 def test_full_size_adjoint_identity(cm, c2, prec, tol):
-    """4096^2 in the default launch configuration of each precision (K = 8 in FP64, the
-    benchmark's K = 7 in FP32): <E z, y>_E = <z, E* y>_E for random device vectors, relative to
+    """4096^2 in the default launch configuration (K = 7, the benchmark's): <E z, y>_E =
+    <z, E* y>_E for random device vectors, relative to
     |E z|_E |y|_E.  The energy weights are read back from the library's own Riesz map
     (M_E^{-1} applied to ones).  FP64 holds to rounding; FP32 periods round each of N = 164 steps
     at eps_32, hence the bound 2 N eps_32 there."""
