@@ -440,8 +440,11 @@ __global__ __launch_bounds__(64 * kBlockRows) void f2_block_kernel(F2Geom g, con
   const int i0 = bx * OW - K, j0 = by * OH - K;
   const int i1 = i0 + 63, j1 = j0 + kBlockRows - 1;
   const bool faces = i0 < 1 || i1 > g.nx - 1 || j0 < 1 || j1 > g.ny - 1;
+  // the tile reads planes k0 - K .. k1 + K - 1 of its chunk: it meets a sound-soft node only if
+  // that slab meets the mask's bounding box too
+  const int k0 = bz * shape.chunk, k1 = min(k0 + shape.chunk, g.nz + 1);
   const bool mask = g.mask && i1 >= g.mlo[0] && i0 <= g.mhi[0] && j1 >= g.mlo[1] &&
-                    j0 <= g.mhi[1];
+                    j0 <= g.mhi[1] && k1 + K - 1 >= g.mlo[2] && k0 - K <= g.mhi[2];
   if (!faces && !mask)
     f2_block_tile<T, K, true>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz, shape.chunk);
   else

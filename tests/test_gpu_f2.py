@@ -67,6 +67,29 @@ def test_temporal_blocking_is_bitwise(cm, prec):
         assert _rel(outs[2][1], o.period_T(z)) < 1e-13
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_blocking_bitwise_around_a_sound_soft_ball(cm, prec):
+    """129^3 nodes, a sound-soft ball in the middle: interior tiles whose columns cross the
+    ball's bounding box but whose plane chunk lies above or below it take the unmasked inner
+    path, the others the masked one; blocked periods (K = 2, 3, 4) equal one step per launch bit
+    for bit, and the ball's nodes stay zero."""
+    import torch
+    prob = ci.sound_soft_sphere_3d(n=128, freq=6.0, radius=0.15)
+    mask = torch.as_tensor(np.concatenate([prob.sound_soft.ravel()] * 2) != 0).cuda()
+    with cm.Solver(prob, prec, steps_per_launch=1) as s:
+        n = s.info["state_len"]
+        g = torch.Generator(device="cuda").manual_seed(15)
+        z = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        z[mask] = 0.0
+        ref = (s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z))
+    assert torch.all(ref[0][mask] == 0) and torch.all(ref[1][mask] == 0)
+    for k in (2, 3, 4):
+        with cm.Solver(prob, prec, steps_per_launch=k) as s:
+            out = (s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z))
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), (k, (a - b).abs().max().item())
+
+
 @pytest.mark.parametrize("masked", [True, False])
 def test_periods_match_oracle_fp64(cm, masked):
     prob = _mixed3d(masked=masked)
