@@ -115,6 +115,7 @@ def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10):
             "seconds_riesz": round(rep["seconds_riesz"], 3),
             "riesz_iterations": rep["riesz_iterations"], "fp64_refreshes": rep["fp64_refreshes"],
             "glups_periods": round(rep["grid_updates"] / max(rep["seconds_fwd"] + rep["seconds_adj"], 1e-9) / 1e9, 1),
+            "stencil_dram_GB": round(rep["dram_bytes"] / 1e9, 1),
             "device_GB": round(gb, 1)}
 
 
@@ -482,7 +483,9 @@ def main():
                          "seconds_max": round(runs[-1][0], 3),
                          "iterations": rep["iterations"], "converged": rep["converged"],
                          "rel_residual": rep["rel_residual"],
-                         "glups": round(rep["grid_updates"] / rep["seconds"] / 1e9, 2)}
+                         "glups": round(rep["grid_updates"] / rep["seconds"] / 1e9, 2),
+                         "stencil_dram_GB": round(rep["dram_bytes"] / 1e9, 1),
+                         "stencil_dram_GB_per_s": round(rep["dram_bytes"] / rep["seconds"] / 1e9, 1)}
             log(f"TTS {prec}: median {sec:.3f} s of {len(runs)}, {rep['iterations']} iterations")
         err = float(torch.linalg.vector_norm(U["fp32"] - U["fp64"]) / torch.linalg.vector_norm(U["fp64"]))
         out["time_to_solution"] = {

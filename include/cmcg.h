@@ -158,6 +158,11 @@ typedef struct {
   int32_t fp64_refreshes;      /* FP32-mixed: number of FP64 true-gradient refreshes           */
   int32_t runup_periods;       /* periods of initial run-up done by the last cmcg_begin         */
   double seconds_runup;        /* device time of that run-up (part of seconds)                 */
+  double dram_bytes;           /* compulsory HBM traffic of the last solve's stencil launches:
+                                  each launch reads its input arrays (state, coefficients,
+                                  sources, subtrahend) once and writes its outputs once; the CG
+                                  vector operations, the Riesz map and the per-component
+                                  kernels of multi-frequency sources are not counted           */
 } cmcg_report;
 
 /* Create a solver for `problem`: validates it, sets T, N and dt, allocates the device state and

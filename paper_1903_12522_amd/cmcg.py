@@ -66,7 +66,8 @@ class _Report(ctypes.Structure):
                 ("seconds_adj", ctypes.c_double), ("seconds_riesz", ctypes.c_double),
                 ("seconds_other", ctypes.c_double), ("grid_updates", ctypes.c_double),
                 ("riesz_iterations", ctypes.c_int64), ("fp64_refreshes", ctypes.c_int32),
-                ("runup_periods", ctypes.c_int32), ("seconds_runup", ctypes.c_double)]
+                ("runup_periods", ctypes.c_int32), ("seconds_runup", ctypes.c_double),
+                ("dram_bytes", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):

@@ -226,6 +226,7 @@ class F1Solver final : public Solver {
   int iter = 0, refreshes = 0, last_refresh = 0, runup_done = 0;
   double rel = 1.0, delta_at_refresh = 0.0;
   double t_fwd = 0, t_adj = 0, t_other = 0, t_total = 0, t_runup = 0, updates = 0;
+  double dram = 0;   // compulsory HBM bytes of the stencil launches since cmcg_begin
   // source ramp of forced periods: absolute start time of the period and switch-on length
   // (t_tr = 0: no ramp)
   double t_offset = 0.0, t_tr = 0.0;
@@ -419,6 +420,15 @@ class F1Solver final : public Solver {
     return ns;
   }
 
+  // Compulsory HBM bytes of one launch: the input state (3 fields) and kap read, the output
+  // state (3 fields) written, plus the subtrahend, the source fields and the filter's FP64
+  // accumulators (read and written) when the launch uses them
+  template <typename T>
+  double launch_bytes(const F1Ptrs<T> &p, const F1Launch &L) const {
+    const double words = 7.0 + (p.sub ? 3.0 : 0.0) + (L.forced ? (p.fim ? 2.0 : 1.0) : 0.0);
+    return (words * sizeof(T) + (L.accumulate ? 32.0 : 0.0)) * g.nx * g.ny;
+  }
+
   // Weights of the components' Dirichlet data at t_n (ramped)
   ShotWeights dirichlet_weights(int n) const {
     ShotWeights w;
@@ -475,6 +485,7 @@ class F1Solver final : public Solver {
       F1Ptrs<T> p;
       F1Launch L;
       const int ns = build_launch<T>(b, forced, in, out, sub, steps, n0, K, filter, &p, &L);
+      dram += launch_bytes<T>(p, L);
       if (multi && forced) {
         hipLaunchKernelGGL((f1_combine_kernel<T>), dim3(grid_for(fs)), dim3(256), 0, s,
                            tpc<T>(b.Fre), tpc<T>(b.Fim), shot_weights(n0, true), tp<T>(b.Fk),
@@ -557,6 +568,7 @@ class F1Solver final : public Solver {
   cmcg_status begin() override {
     t_fwd = t_adj = t_other = t_total = t_runup = 0.0;
     updates = 0;
+    dram = 0;
     iter = refreshes = last_refresh = runup_done = 0;
     CMCG_HIP(hipEventRecord(ev[0], s));
     // Steps 1-4: z = 0, gradient, r = d = gradient (the Riesz map M_E^{-1} is built into E*)
@@ -772,6 +784,7 @@ class F1Solver final : public Solver {
     r->seconds_riesz = 0.0;
     r->seconds_other = t_other;
     r->grid_updates = updates;
+    r->dram_bytes = dram;
     r->riesz_iterations = 0;
     r->fp64_refreshes = refreshes;
     r->runup_periods = runup_done;
@@ -952,6 +965,7 @@ class F1Server final : public Server {
       F1Solver *S = R->S;
       S->iter = S->refreshes = 0;
       S->updates = 0;
+      S->dram = 0;
       S->rel = 1.0;
       CMCG_HIP(hipMemsetAsync(S->Z, 0, S->vecN * sizeof(double), s));
       used += S->arena.bytes();
@@ -1004,6 +1018,7 @@ class F1Server final : public Server {
       const int ns = S->build_launch<T>(*b, forced, static_cast<const T *>(in), static_cast<T *>(out),
                                         static_cast<const T *>(sub), S->cfg.N, R->n0, K, filter,
                                         &d.p, &d.L);
+      S->dram += S->launch_bytes<T>(d.p, d.L);
       int nby;
       f1_launch_shape(S->g.nx, S->g.ny, ns, &d.nbx, &nby, &d.band);
       d.nblocks = d.nbx * nby;

@@ -199,6 +199,7 @@ class F2Solver final : public Solver {
   double riesz_tol = 1e-10;
   int riesz_max = 500;
   double t_fwd = 0, t_adj = 0, t_riesz = 0, t_other = 0, t_total = 0, t_runup = 0, updates = 0;
+  double dram = 0;   // compulsory HBM bytes of the stencil launches since cmcg_begin
   int runup_done = 0;
   // source ramp of forced periods: absolute start time of the period and switch-on length
   // (t_tr = 0: no ramp)
@@ -398,6 +399,23 @@ class F2Solver final : public Solver {
   // `count` homogeneous steps from (cur, prev) = (u^n, u^{n-1}); on return they point to
   // u^{n+count} and u^{n+count-1}.  With the set's fourth buffer, kstep steps per blocked launch
   // (then the remainder one at a time); outputs always go to buffers that are not inputs.
+  // Compulsory HBM bytes of one sweep: each array its arguments name read (or written) once,
+  // the subtrahend as two fields, the filter's FP64 accumulators read and written
+  template <typename T>
+  double sweep_bytes(const F2Args<T> &p) const {
+    const double nn = (double)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    const int w = (p.st ? 1 : 0) + (p.aux ? 1 : 0) + (p.sub ? 2 : 0) + (p.lam ? 1 : 0) +
+                  (p.forced && p.fre ? 1 : 0) + (p.forced && p.fim ? 1 : 0) + (p.out ? 1 : 0) +
+                  (p.out2 ? 1 : 0);
+    return nn * (w * (double)sizeof(T) + (p.ure ? 32.0 : 0.0));
+  }
+  // a blocked launch reads u^n, u^{n-1} (and lambda) and writes u^{n+K}, u^{n+K-1}; the scaling
+  // into the adjoint variable reads a field (and lambda) and writes one
+  template <typename T>
+  double fields_bytes(int fields, const T *lam) const {
+    return (double)(g.nx + 1) * (g.ny + 1) * (g.nz + 1) * sizeof(T) * (fields + (lam ? 1 : 0));
+  }
+
   template <typename T>
   cmcg_status homogeneous_steps(const F2Set &b, const T *&cur, const T *&prev, int count,
                                 F2Args<T> p) {
@@ -414,6 +432,7 @@ class F2Solver final : public Solver {
         T *ok = pick(cur, prev, nullptr);
         T *okm1 = pick(cur, prev, ok);
         if (!ok || !okm1) return set_error("blocked march: no free buffer"), CMCG_EDEVICE;
+        dram += fields_bytes<T>(4, tpc<T>(b.lam));
         CMCG_HIP(f2_march_block<T>(g, cur, prev, tpc<T>(b.lam), ok, okm1, K, s));
         cur = ok;
         prev = okm1;
@@ -423,6 +442,7 @@ class F2Solver final : public Solver {
         p.st = cur;
         p.aux = prev;
         p.out = o;
+        dram += sweep_bytes<T>(p);
         CMCG_HIP(f2_march<T>(kF2FwdStep, g, p, s));
         prev = cur;
         cur = o;
@@ -516,6 +536,7 @@ class F2Solver final : public Solver {
       CMCG_TRY(combine<T>(b, load, dir, 0, 1, true));
       if (filter) CMCG_TRY(accumulate(reinterpret_cast<const double *>(zin), 0));
     }
+    dram += sweep_bytes<T>(p);
     CMCG_HIP(f2_march<T>(kF2FwdStart, g, p, s));
     const T *prev = zin;
     int cur = 0;
@@ -540,6 +561,7 @@ class F2Solver final : public Solver {
         CMCG_TRY(combine<T>(b, load, dir, n, n + 1, false));
         if (filter) CMCG_TRY(accumulate(reinterpret_cast<const double *>(buf[cur]), n));
       }
+      dram += sweep_bytes<T>(p);
       CMCG_HIP(f2_march<T>(kF2FwdStep, g, p, s));
       prev = buf[cur];
       cur = nxt;
@@ -555,6 +577,7 @@ class F2Solver final : public Solver {
     p.out = out;
     p.sub = sub;
     if (multi) CMCG_TRY(combine<T>(b, load, false, N, N, false));
+    dram += sweep_bytes<T>(p);
     CMCG_HIP(f2_march<T>(kF2FwdEnd, g, p, s));
     updates += (double)(N + 1) * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     return CMCG_OK;
@@ -567,6 +590,7 @@ class F2Solver final : public Solver {
     p.st = w;
     p.aux = w + g.fs;
     p.out = y;
+    dram += sweep_bytes<T>(p);
     CMCG_HIP(f2_march<T>(kF2Metric, g, p, s));
     return CMCG_OK;
   }
@@ -580,18 +604,21 @@ class F2Solver final : public Solver {
     p.lam = tpc<T>(b.lam);
     T *buf[3] = {tp<T>(b.A), tp<T>(b.B), tp<T>(b.C)};
     // g_y = psi y_v (C)
+    dram += fields_bytes<T>(2, p.lam);
     CMCG_HIP(f2_psi_scale<T>(g, y + g.fs, p.lam, buf[2], s));
     // transposed end map: g_0 (A), psi b_0 (B)
     p.st = buf[2];
     p.aux = y;
     p.out = buf[0];
     p.out2 = buf[1];
+    dram += sweep_bytes<T>(p);
     CMCG_HIP(f2_march<T>(kF2AdjInit, g, p, s));
     p.out2 = nullptr;
     // first transposed step: g_1 = K g_0 + psi b_0 -> C
     p.st = buf[0];
     p.aux = buf[1];
     p.out = buf[2];
+    dram += sweep_bytes<T>(p);
     CMCG_HIP(f2_march<T>(kF2AdjStepFirst, g, p, s));
     // interior transposed steps 1 .. N-2: forward homogeneous steps in g (temporally blocked)
     const T *curp = buf[2], *prevp = buf[0];
@@ -601,6 +628,7 @@ class F2Solver final : public Solver {
     p.aux = prevp;
     p.out = out;
     p.sub = sub;
+    dram += sweep_bytes<T>(p);
     CMCG_HIP(f2_march<T>(kF2AdjEnd, g, p, s));
     updates += (double)(N + 1) * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     return CMCG_OK;
@@ -693,6 +721,7 @@ class F2Solver final : public Solver {
   cmcg_status begin() override {
     t_fwd = t_adj = t_riesz = t_other = t_total = t_runup = 0.0;
     updates = 0;
+    dram = 0;
     iter = refreshes = runup_done = 0;
     riesz_iters = 0;
     CMCG_HIP(hipEventRecord(ev[0], s));
@@ -954,6 +983,7 @@ class F2Solver final : public Solver {
     r->seconds_riesz = t_riesz;
     r->seconds_other = t_other;
     r->grid_updates = updates;
+    r->dram_bytes = dram;
     r->riesz_iterations = riesz_iters;
     r->fp64_refreshes = refreshes;
     r->runup_periods = runup_done;

@@ -210,6 +210,18 @@ def test_solve_is_deterministic(cm):
     assert np.array_equal(U1, U2) and r1["iterations"] == r2["iterations"]
 
 
+def test_report_counts_compulsory_traffic(cm):
+    """cmcg_report.dram_bytes: each blocked launch moves its 7 FP64 words per cell once for
+    K = 7 steps (56 / 7 B per grid update), plus the subtrahend, the sources and the filter's
+    accumulators on the few launches that read them, so the total stays well under one pass per
+    step."""
+    prob = ci.random_medium_2d(n=256, freq=8.0, n_src=2, seed=19)
+    with cm.Solver(prob, "fp64", tol=1e-6, max_iter=500) as s:
+        _, rep = s.solve()
+    per = rep["dram_bytes"] / rep["grid_updates"]
+    assert 56 / 7 <= per < 56 / 3, per
+
+
 def test_notconv_returns_last_iterate(cm):
     prob = ci.single_source_2d(n=32, omega=2 * math.pi * 2)
     with cm.Solver(prob, "fp64", tol=1e-12, max_iter=1) as s:

@@ -90,6 +90,17 @@ def test_blocking_bitwise_around_a_sound_soft_ball(cm, prec):
             assert torch.equal(a, b), (k, (a - b).abs().max().item())
 
 
+def test_report_counts_compulsory_traffic(cm):
+    """cmcg_report.dram_bytes of a nodal solve: blocked interior steps (5 words per 3 steps)
+    and single-step start, end, metric and scaling sweeps, all in FP64: between the blocked rate
+    and a few single-step passes (4 words) per node-step."""
+    prob = ci.inclusions_3d(n=32, freq=1.5, n_incl=4, seed=9, width=0.12, r_range=(0.1, 0.25))
+    with cm.Solver(prob, "fp64", tol=1e-6, max_iter=2000) as s:
+        _, rep = s.solve()
+    per = rep["dram_bytes"] / rep["grid_updates"]
+    assert 5 * 8 / 3 <= per < 3 * 32, per
+
+
 @pytest.mark.parametrize("masked", [True, False])
 def test_periods_match_oracle_fp64(cm, masked):
     prob = _mixed3d(masked=masked)
