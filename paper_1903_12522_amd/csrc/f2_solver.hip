@@ -290,10 +290,11 @@ class F2Solver final : public Solver {
       has_d = has_d || sh.gD_re || sh.gD_im;
       has_dim = has_dim || sh.gD_im;
     }
-    // temporal blocking of the homogeneous steps: K steps per launch (1 = off); the CG periods'
-    // set gets the fourth state buffer it needs
+    // temporal blocking of the homogeneous steps: K steps per launch (1 = off); each set gets
+    // the fourth state buffer it needs (in FP32-mixed mode the FP64 set's backward periods, in
+    // the refreshes, then run blocked too)
     kstep = cfg.steps_request > 0 ? std::min(cfg.steps_request, 4) : kF2DefaultBlock;
-    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im, J, !mixed && kstep > 1));
+    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im, J, kstep > 1));
     if (mixed) CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, var_c, forced, has_im, J, kstep > 1));
     else lo = hi;
     CMCG_TRY(arena.alloc(2 * g.fs * (mixed ? sizeof(float) : sizeof(double)), &D, s));
