@@ -39,6 +39,41 @@ def test_binding_covers_header():
     assert set(cmcg.EXPORTED) == set(_declared())
 
 
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's field names, offsets and size: a C
+    program compiled against include/cmcg.h prints sizeof and offsetof for each ctypes field."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    from paper_1903_12522_amd import cmcg
+    pairs = [("cmcg_shot", cmcg._Shot), ("cmcg_problem", cmcg._Problem),
+             ("cmcg_options", cmcg._Options), ("cmcg_report", cmcg._Report),
+             ("cmcg_info", cmcg._Info), ("cmcg_server_options", cmcg._ServerOptions)]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cmcg.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            *key, val = line.split()
+            got[tuple(key)] = int(val)
+    for cname, cls in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
 def _problem(cm, **kw):
     p = cm._Problem()
     p.dim, p.formulation = kw.get("dim", 2), kw.get("formulation", 1)
