@@ -116,37 +116,42 @@ hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, h
 // rediscretised coarse operators, sound-soft mask injected to coarse nodes).  With no sound-soft
 // node S is singular (constants): right-hand side and iterates are kept zero-sum.
 // ---------------------------------------------------------------------------------------
-struct MGLevel {
+template <typename T>
+struct MGLevelT {
   F2Geom g;                         // geometry (mask pointer into `maskbuf`)
-  double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+  T *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
   uint8_t *maskbuf = nullptr;
   size_t nfree = 0;                 // number of free (non-sound-soft) real nodes
 };
 
 class DeviceArena;
 
-class RieszMG {
+// T: the storage and arithmetic type of the hierarchy.  FP64 serves the PCG solve and FP64
+// solves; FP32 serves the fixed V-cycle of FP32-mixed solves (apply_vcycle only).
+template <typename T>
+class RieszMGT {
  public:
-  ~RieszMG();
+  ~RieszMGT();
   cmcg_status build(const F2Geom &fine, DeviceArena &arena, hipStream_t s);
   // x = S^{-1} b (x: FP64 fine-level field; b: fine-level field in FP64, or FP32 if b_is_float;
-  // x may not alias b).  *iters receives the number of PCG iterations.
+  // x may not alias b).  *iters receives the number of PCG iterations.  FP64 hierarchy only.
   cmcg_status solve(const void *b, int b_is_float, double *x, double tol, int max_iter, int *iters);
-  // x = B b: one V-cycle (the preconditioner; b is overwritten only through the projection
-  // of a pure-Neumann problem's right-hand side, which the caller has already applied)
-  cmcg_status vcycle(const double *b, double *x);
   // x = Pi B Pi b for an FP64 or FP32 right-hand side (Pi: zero-sum projection when S is
-  // singular): the fixed symmetric V-cycle used in place of S^{-1}
+  // singular): the fixed symmetric V-cycle used in place of S^{-1}; x is FP64
   cmcg_status apply_vcycle(const void *b, int b_is_float, double *x);
   bool pure_neumann() const { return neumann_; }
 
  private:
+  // x = B b: one V-cycle on the fine level (b is not modified)
+  cmcg_status vcycle(const T *b, T *x);
   cmcg_status vcycle_level(int l);
   cmcg_status smooth(int l, int sweeps);
-  cmcg_status project(double *v, int l);
+  cmcg_status project(T *v, int l);
   cmcg_status dot(const double *a, const double *b, size_t n, double *out);
-  std::vector<MGLevel> lv_;
-  double *pr_ = nullptr, *pz_ = nullptr, *pp_ = nullptr, *pq_ = nullptr;   // fine PCG vectors
+  std::vector<MGLevelT<T>> lv_;
+  T *pr_ = nullptr;                 // the fine right-hand side (converted or copied)
+  T *pz_ = nullptr, *pp_ = nullptr, *pq_ = nullptr;   // fine PCG vectors (FP64 only)
+  T *xo_ = nullptr;                 // FP32: the V-cycle's result before its FP64 output
   double *partials_ = nullptr, *scal_ = nullptr, *h_scal_ = nullptr;
   hipStream_t s_ = nullptr;
   bool neumann_ = false;

@@ -191,7 +191,9 @@ class F2Solver final : public Solver {
   int kstep = 1;                           // homogeneous steps per blocked launch
   double *cpart = nullptr, *h_cpart = nullptr;   // compatibility sums: device partials, host copy
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
-  RieszMG mg;
+  RieszMGT<double> mg;     // FP64 hierarchy: the PCG solve, and FP64 solves' V-cycle
+  RieszMGT<float> mg32;    // FP32 hierarchy: the V-cycle of FP32-mixed solves
+  bool mg_f32 = false;
   bool started = false;
   int iter = 0, refreshes = 0;
   long long riesz_iters = 0;
@@ -364,7 +366,11 @@ class F2Solver final : public Solver {
       CMCG_TRY(arena.alloc_n((size_t)kCompatSums * kRedBlocks, &cpart, s));
       CMCG_HIP(hipHostMalloc((void **)&h_cpart, (size_t)kCompatSums * kRedBlocks * sizeof(double)));
     }
-    CMCG_TRY(mg.build(g, arena, s));
+    // the Riesz map of an FP32-mixed solve in V-cycle mode is one FP32 V-cycle, in the CG
+    // iterations and the FP64 refreshes alike (the same fixed operator throughout)
+    mg_f32 = mixed && cfg.riesz_mode == CMCG_RIESZ_VCYCLE;
+    if (mg_f32) CMCG_TRY(mg32.build(g, arena, s));
+    else CMCG_TRY(mg.build(g, arena, s));
     return CMCG_OK;
   }
 
@@ -662,7 +668,8 @@ class F2Solver final : public Solver {
     int it = 0;
     CMCG_HIP(hipEventRecord(ev[8], s));
     if (cfg.riesz_mode == CMCG_RIESZ_VCYCLE) {
-      CMCG_TRY(mg.apply_vcycle(qh_u, is_float, out));
+      CMCG_TRY(mg_f32 ? mg32.apply_vcycle(qh_u, is_float, out)
+                      : mg.apply_vcycle(qh_u, is_float, out));
       it = 1;
     } else {
       CMCG_TRY(mg.solve(qh_u, is_float, out, riesz_tol, riesz_max, &it));

@@ -13,6 +13,7 @@
 // residuals and the solution are kept zero-sum (plain sum over nodes).
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "f2_internal.h"
 #include "solver.h"
@@ -37,40 +38,45 @@ __device__ __forceinline__ bool msk(const F2Geom &g, int i, int j, int k) {
   return g.mask[g.idx(i, j, k)] != 0;
 }
 
-__device__ __forceinline__ double lap7(const F2Geom &g, const double *x, int i, int j, int k) {
-  const double c = x[g.idx(i, j, k)];
-  return 6.0 * c - (x[g.idx(mir(i - 1, g.nx), j, k)] + x[g.idx(mir(i + 1, g.nx), j, k)] +
+template <typename T>
+__device__ __forceinline__ T lap7(const F2Geom &g, const T *x, int i, int j, int k) {
+  const T c = x[g.idx(i, j, k)];
+  return T(6) * c - (x[g.idx(mir(i - 1, g.nx), j, k)] + x[g.idx(mir(i + 1, g.nx), j, k)] +
                     x[g.idx(i, mir(j - 1, g.ny), k)] + x[g.idx(i, mir(j + 1, g.ny), k)] +
                     x[g.idx(i, j, mir(k - 1, g.nz))] + x[g.idx(i, j, mir(k + 1, g.nz))]);
 }
 
 // y = R S x
-__global__ void s_apply_kernel(F2Geom g, const double *x, double *y) {
+template <typename T>
+__global__ void s_apply_kernel(F2Geom g, const T *x, T *y) {
   F2_ROWS(g)
-  y[o] = msk(g, i, j, k) ? 0.0 : g.h * eta3(g, i, j, k) * lap7(g, x, i, j, k);
+  y[o] = msk(g, i, j, k) ? T(0) : (T)(g.h * eta3(g, i, j, k)) * lap7(g, x, i, j, k);
   F2_ROWS_END
 }
 
 // r = R (b - S x)
-__global__ void residual_kernel(F2Geom g, const double *x, const double *b, double *r) {
+template <typename T>
+__global__ void residual_kernel(F2Geom g, const T *x, const T *b, T *r) {
   F2_ROWS(g)
-  r[o] = msk(g, i, j, k) ? 0.0 : b[o] - g.h * eta3(g, i, j, k) * lap7(g, x, i, j, k);
+  r[o] = msk(g, i, j, k) ? T(0) : b[o] - (T)(g.h * eta3(g, i, j, k)) * lap7(g, x, i, j, k);
   F2_ROWS_END
 }
 
 // damped Jacobi: xo = R (x + omega (b - S x) / (6 h eta))
-__global__ void jacobi_kernel(F2Geom g, const double *x, const double *b, double *xo, double omega,
+template <typename T>
+__global__ void jacobi_kernel(F2Geom g, const T *x, const T *b, T *xo, double omega,
                               int from_zero) {
+  const T om = (T)omega;
   F2_ROWS(g)
   if (msk(g, i, j, k)) {
-    xo[o] = 0.0;
+    xo[o] = T(0);
     continue;
   }
-  const double he = g.h * eta3(g, i, j, k);
+  const T he = (T)(g.h * eta3(g, i, j, k));
   if (from_zero) {
-    xo[o] = omega * b[o] / (6.0 * he);
+    xo[o] = om * b[o] / (T(6) * he);
   } else {
-    xo[o] = x[o] + omega * (b[o] - he * lap7(g, x, i, j, k)) / (6.0 * he);
+    xo[o] = x[o] + om * (b[o] - he * lap7(g, x, i, j, k)) / (T(6) * he);
   }
   F2_ROWS_END
 }
@@ -89,10 +95,11 @@ __global__ void jacobi_kernel(F2Geom g, const double *x, const double *b, double
 enum MGSweep : int { kMGJacobi = 0, kMGResidual = 1, kMGApply = 2 };
 constexpr int kMGChunk = 32;
 
-template <int MODE>
-__global__ __launch_bounds__(256) void mg_march_kernel(F2Geom g, const double *x, const double *b,
-                                                       double *out, double omega, int nbx,
-                                                       int nby, int chunk) {
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void mg_march_kernel(F2Geom g, const T *x, const T *b, T *out,
+                                                       double omega, int nbx, int nby,
+                                                       int chunk) {
+  const T om = (T)omega;
   const int nb = (int)gridDim.x;
   int t = (int)blockIdx.x;
   if (nb % 8 == 0) t = (t % 8) * (nb / 8) + t / 8;
@@ -105,23 +112,23 @@ __global__ __launch_bounds__(256) void mg_march_kernel(F2Geom g, const double *x
   const size_t ojm = (size_t)mir(j - 1, g.ny) * g.px + i, ojp = (size_t)mir(j + 1, g.ny) * g.px + i;
   // operands of plane k held in registers; those of plane k + 1 are loaded while plane k is
   // computed (the plane after the last one is read at its mirror index, inside the field)
-  double xm = x[(size_t)mir(k0 - 1, g.nz) * g.plane + col];
-  double xc = x[(size_t)k0 * g.plane + col];
-  double xp = x[(size_t)mir(k0 + 1, g.nz) * g.plane + col];
+  T xm = x[(size_t)mir(k0 - 1, g.nz) * g.plane + col];
+  T xc = x[(size_t)k0 * g.plane + col];
+  T xp = x[(size_t)mir(k0 + 1, g.nz) * g.plane + col];
   size_t pk = (size_t)k0 * g.plane;
-  double nim = x[pk + oim], nip = x[pk + oip], njm = x[pk + ojm], njp = x[pk + ojp];
-  double bk = MODE == kMGApply ? 0.0 : b[pk + col];
+  T nim = x[pk + oim], nip = x[pk + oip], njm = x[pk + ojm], njp = x[pk + ojp];
+  T bk = MODE == kMGApply ? T(0) : b[pk + col];
   for (int k = k0; k < k1; ++k) {
     const size_t pn = (size_t)mir(k + 1, g.nz) * g.plane;
-    const double xpp = x[(size_t)mir(k + 2 > g.nz ? g.nz + 1 : k + 2, g.nz) * g.plane + col];
-    const double nim1 = x[pn + oim], nip1 = x[pn + oip], njm1 = x[pn + ojm], njp1 = x[pn + ojp];
-    const double bk1 = MODE == kMGApply ? 0.0 : b[pn + col];
+    const T xpp = x[(size_t)mir(k + 2 > g.nz ? g.nz + 1 : k + 2, g.nz) * g.plane + col];
+    const T nim1 = x[pn + oim], nip1 = x[pn + oip], njm1 = x[pn + ojm], njp1 = x[pn + ojp];
+    const T bk1 = MODE == kMGApply ? T(0) : b[pn + col];
     const size_t o = pk + col;
-    double res = 0.0;
+    T res = T(0);
     if (!msk(g, i, j, k)) {
-      const double he = g.h * eta3(g, i, j, k);
-      const double lap = 6.0 * xc - (nim + nip + njm + njp + xm + xp);
-      if (MODE == kMGJacobi) res = xc + omega * (bk - he * lap) / (6.0 * he);
+      const T he = (T)(g.h * eta3(g, i, j, k));
+      const T lap = T(6) * xc - (nim + nip + njm + njp + xm + xp);
+      if (MODE == kMGJacobi) res = xc + om * (bk - he * lap) / (T(6) * he);
       else if (MODE == kMGResidual) res = bk - he * lap;
       else res = he * lap;
     }
@@ -139,13 +146,14 @@ __global__ __launch_bounds__(256) void mg_march_kernel(F2Geom g, const double *x
 }
 
 // bc = R_c P^T rf  (full weighting over the 27 fine neighbours of the coarse node's position)
-__global__ void restrict_kernel(F2Geom gf, F2Geom gc, const double *rf, double *bc) {
+template <typename T>
+__global__ void restrict_kernel(F2Geom gf, F2Geom gc, const T *rf, T *bc) {
   F2_ROWS(gc)
   if (msk(gc, i, j, k)) {
-    bc[o] = 0.0;
+    bc[o] = T(0);
     continue;
   }
-  double acc = 0.0;
+  T acc = T(0);
   for (int dk = -1; dk <= 1; ++dk) {
     const int fk = 2 * k + dk;
     if (fk < 0 || fk > gf.nz) continue;
@@ -155,7 +163,7 @@ __global__ void restrict_kernel(F2Geom gf, F2Geom gc, const double *rf, double *
       for (int di = -1; di <= 1; ++di) {
         const int fi = 2 * i + di;
         if (fi < 0 || fi > gf.nx) continue;
-        const double w = (di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0);
+        const T w = (T)((di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0));
         acc += w * rf[gf.idx(fi, fj, fk)];
       }
     }
@@ -165,17 +173,18 @@ __global__ void restrict_kernel(F2Geom gf, F2Geom gc, const double *rf, double *
 }
 
 // xf += R_f P xc  (trilinear interpolation)
-__global__ void prolong_add_kernel(F2Geom gf, F2Geom gc, const double *xc, double *xf) {
+template <typename T>
+__global__ void prolong_add_kernel(F2Geom gf, F2Geom gc, const T *xc, T *xf) {
   F2_ROWS(gf)
   if (msk(gf, i, j, k)) {
-    xf[o] = 0.0;
+    xf[o] = T(0);
     continue;
   }
   const int ci0 = i >> 1, ci1 = (i + 1) >> 1;
   const int cj0 = j >> 1, cj1 = (j + 1) >> 1;
   const int ck0 = k >> 1, ck1 = (k + 1) >> 1;
-  const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
-  double acc = 0.0;
+  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  T acc = T(0);
   const int is[2] = {ci0, ci1}, js[2] = {cj0, cj1}, ks[2] = {ck0, ck1};
   const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
   for (int c = 0; c < nk; ++c)
@@ -199,12 +208,12 @@ __device__ __forceinline__ double wsum(double x) {
 }
 
 // per-block partial sums of v over the real nodes (fixed order)
-__global__ __launch_bounds__(kRedThreads) void sum_kernel(F2Geom g, const double *v,
-                                                          double *partials) {
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void sum_kernel(F2Geom g, const T *v, double *partials) {
   __shared__ double part[kRedThreads / 64];
   double acc = 0.0;
   F2_ROWS(g)
-  acc += v[o];
+  acc += (double)v[o];
   F2_ROWS_END
   acc = wsum(acc);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
@@ -217,8 +226,9 @@ __global__ __launch_bounds__(kRedThreads) void sum_kernel(F2Geom g, const double
 }
 
 // v -= s[slot] / count on the real nodes (mean removal)
-__global__ void sub_mean_kernel(F2Geom g, double *v, const double *sc, int slot, double count) {
-  const double m = sc[slot] / count;
+template <typename T>
+__global__ void sub_mean_kernel(F2Geom g, T *v, const double *sc, int slot, double count) {
+  const T m = (T)(sc[slot] / count);
   F2_ROWS(g)
   v[o] -= m;
   F2_ROWS_END
@@ -254,15 +264,17 @@ int gridn(size_t n) {
 // One stencil sweep of a level: the plane march, or the row kernels when `rows` is set.  The
 // march's chunk length is halved from 32 planes until the launch has 8192 workgroups (one plane
 // at 129^3 nodes, 32 from 513^3 up); `chunk_req` > 0 fixes it instead.
-hipError_t mg_sweep(int mode, bool rows, int chunk_req, const F2Geom &g, const double *x,
-                    const double *b, double *out, double omega, hipStream_t s) {
+template <typename T>
+hipError_t mg_sweep(int mode, bool rows, int chunk_req, const F2Geom &g, const T *x, const T *b,
+                    T *out, double omega, hipStream_t s) {
   if (rows) {
     if (mode == kMGJacobi)
-      hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(g)), dim3(256), 0, s, g, x, b, out, omega, 0);
+      hipLaunchKernelGGL(jacobi_kernel<T>, dim3(rows_grid(g)), dim3(256), 0, s, g, x, b, out, omega,
+                         0);
     else if (mode == kMGResidual)
-      hipLaunchKernelGGL(residual_kernel, dim3(rows_grid(g)), dim3(256), 0, s, g, x, b, out);
+      hipLaunchKernelGGL(residual_kernel<T>, dim3(rows_grid(g)), dim3(256), 0, s, g, x, b, out);
     else
-      hipLaunchKernelGGL(s_apply_kernel, dim3(rows_grid(g)), dim3(256), 0, s, g, x, out);
+      hipLaunchKernelGGL(s_apply_kernel<T>, dim3(rows_grid(g)), dim3(256), 0, s, g, x, out);
     return hipGetLastError();
   }
   const int nbx = (g.nx + 1 + 63) / 64, nby = (g.ny + 1 + 3) / 4;
@@ -273,35 +285,37 @@ hipError_t mg_sweep(int mode, bool rows, int chunk_req, const F2Geom &g, const d
   const int nbz = (g.nz + chunk) / chunk;
   const dim3 grid((unsigned)(nbx * nby * nbz));
   if (mode == kMGJacobi)
-    hipLaunchKernelGGL(mg_march_kernel<kMGJacobi>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
+    hipLaunchKernelGGL((mg_march_kernel<T, kMGJacobi>), grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
                        nby, chunk);
   else if (mode == kMGResidual)
-    hipLaunchKernelGGL(mg_march_kernel<kMGResidual>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
+    hipLaunchKernelGGL((mg_march_kernel<T, kMGResidual>), grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
                        nby, chunk);
   else
-    hipLaunchKernelGGL(mg_march_kernel<kMGApply>, grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
+    hipLaunchKernelGGL((mg_march_kernel<T, kMGApply>), grid, dim3(256), 0, s, g, x, b, out, omega, nbx,
                        nby, chunk);
   return hipGetLastError();
 }
 
 }  // namespace
 
-RieszMG::~RieszMG() {
+template <typename T>
+RieszMGT<T>::~RieszMGT() {
   if (h_scal_) (void)hipHostFree(h_scal_);
 }
 
-cmcg_status RieszMG::build(const F2Geom &fine, DeviceArena &arena, hipStream_t s) {
+template <typename T>
+cmcg_status RieszMGT<T>::build(const F2Geom &fine, DeviceArena &arena, hipStream_t s) {
   s_ = s;
   lv_.clear();
   neumann_ = fine.mask == nullptr;
-  MGLevel L0;
+  MGLevelT<T> L0;
   L0.g = fine;
   lv_.push_back(L0);
   while (true) {
     const F2Geom &g = lv_.back().g;
     if (lv_.size() >= 12 || g.nx % 2 || g.ny % 2 || g.nz % 2 || g.nx < 4 || g.ny < 4 || g.nz < 4)
       break;
-    MGLevel L;
+    MGLevelT<T> L;
     L.g = g;
     L.g.nx = g.nx / 2;
     L.g.ny = g.ny / 2;
@@ -318,7 +332,7 @@ cmcg_status RieszMG::build(const F2Geom &fine, DeviceArena &arena, hipStream_t s
     lv_.push_back(L);
   }
   for (size_t l = 0; l < lv_.size(); ++l) {
-    MGLevel &L = lv_[l];
+    MGLevelT<T> &L = lv_[l];
     if (l > 0) {
       CMCG_TRY(arena.alloc_n(L.g.fs, &L.x, s));
       CMCG_TRY(arena.alloc_n(L.g.fs, &L.b, s));
@@ -336,10 +350,18 @@ cmcg_status RieszMG::build(const F2Geom &fine, DeviceArena &arena, hipStream_t s
   }
   const size_t n = fine.fs;
   CMCG_TRY(arena.alloc_n(n, &pr_, s));
-  CMCG_TRY(arena.alloc_n(n, &pz_, s));
-  CMCG_TRY(arena.alloc_n(n, &pp_, s));
-  CMCG_TRY(arena.alloc_n(n, &pq_, s));
-  lv_[0].r = pq_;   // S p is consumed before each V-cycle, so its buffer serves as the residual
+  if (std::is_same<T, double>::value) {
+    // the PCG vectors; S p is consumed before each V-cycle, so its buffer serves as the
+    // fine residual
+    CMCG_TRY(arena.alloc_n(n, &pz_, s));
+    CMCG_TRY(arena.alloc_n(n, &pp_, s));
+    CMCG_TRY(arena.alloc_n(n, &pq_, s));
+    lv_[0].r = pq_;
+  } else {
+    // V-cycle only: its own fine residual and the FP32 result before the FP64 output
+    CMCG_TRY(arena.alloc_n(n, &lv_[0].r, s));
+    CMCG_TRY(arena.alloc_n(n, &xo_, s));
+  }
   CMCG_TRY(arena.alloc_n(kRedBlocks, &partials_, s));
   CMCG_TRY(arena.alloc_n(kNumScalars, &scal_, s));
   if (!h_scal_) CMCG_HIP(hipHostMalloc((void **)&h_scal_, kNumScalars * sizeof(double)));
@@ -347,7 +369,8 @@ cmcg_status RieszMG::build(const F2Geom &fine, DeviceArena &arena, hipStream_t s
   return CMCG_OK;
 }
 
-cmcg_status RieszMG::dot(const double *a, const double *b, size_t n, double *out) {
+template <typename T>
+cmcg_status RieszMGT<T>::dot(const double *a, const double *b, size_t n, double *out) {
   CMCG_HIP(dot_plain<double, double>(a, b, n, partials_, s_));
   CMCG_HIP(finalize(partials_, kRedBlocks, scal_, kFinStore, 0, s_));
   CMCG_HIP(hipMemcpyAsync(h_scal_, scal_, sizeof(double), hipMemcpyDeviceToHost, s_));
@@ -356,94 +379,108 @@ cmcg_status RieszMG::dot(const double *a, const double *b, size_t n, double *out
   return CMCG_OK;
 }
 
-cmcg_status RieszMG::project(double *v, int l) {
+template <typename T>
+cmcg_status RieszMGT<T>::project(T *v, int l) {
   // v <- v - (sum v) / count over the real nodes (pure Neumann only)
   const F2Geom &g = lv_[l].g;
-  hipLaunchKernelGGL(sum_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, s_, g, v, partials_);
+  hipLaunchKernelGGL(sum_kernel<T>, dim3(kRedBlocks), dim3(kRedThreads), 0, s_, g, v, partials_);
   CMCG_HIP(hipGetLastError());
   CMCG_HIP(finalize(partials_, kRedBlocks, scal_, kFinStore, 1, s_));
-  hipLaunchKernelGGL(sub_mean_kernel, dim3(rows_grid(g)), dim3(256), 0, s_, g, v, scal_, 1,
+  hipLaunchKernelGGL(sub_mean_kernel<T>, dim3(rows_grid(g)), dim3(256), 0, s_, g, v, scal_, 1,
                      (double)lv_[l].nfree);
   CMCG_HIP(hipGetLastError());
   return CMCG_OK;
 }
 
-cmcg_status RieszMG::smooth(int l, int sweeps) {
+template <typename T>
+cmcg_status RieszMGT<T>::smooth(int l, int sweeps) {
   // `sweeps` damped Jacobi sweeps from x = 0, ping-pong between x and t, result left in x
-  MGLevel &L = lv_[l];
-  double *cur = L.x, *other = L.t;
+  MGLevelT<T> &L = lv_[l];
+  T *cur = L.x, *other = L.t;
   for (int k = 0; k < sweeps; ++k) {
     if (k == 0) {
-      hipLaunchKernelGGL(jacobi_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, cur, L.b,
+      hipLaunchKernelGGL(jacobi_kernel<T>, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, cur, L.b,
                          other, omega_, 1);
       CMCG_HIP(hipGetLastError());
     } else {
-      CMCG_HIP(mg_sweep(kMGJacobi, rows_, chunk_, L.g, cur, L.b, other, omega_, s_));
+      CMCG_HIP(mg_sweep<T>(kMGJacobi, rows_, chunk_, L.g, cur, L.b, other, omega_, s_));
     }
     std::swap(cur, other);
   }
   if (cur != L.x)
-    CMCG_HIP(hipMemcpyAsync(L.x, cur, L.g.fs * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    CMCG_HIP(hipMemcpyAsync(L.x, cur, L.g.fs * sizeof(T), hipMemcpyDeviceToDevice, s_));
   return CMCG_OK;
 }
 
-cmcg_status RieszMG::vcycle_level(int l) {
-  MGLevel &L = lv_[l];
+template <typename T>
+cmcg_status RieszMGT<T>::vcycle_level(int l) {
+  MGLevelT<T> &L = lv_[l];
   const int last = (int)lv_.size() - 1;
   if (l == last) {
     CMCG_TRY(smooth(l, coarse_sweeps_));
     return CMCG_OK;
   }
   CMCG_TRY(smooth(l, pre_));
-  CMCG_HIP(mg_sweep(kMGResidual, rows_, chunk_, L.g, L.x, L.b, L.r, 0.0, s_));
-  MGLevel &C = lv_[l + 1];
-  hipLaunchKernelGGL(restrict_kernel, dim3(rows_grid(C.g)), dim3(256), 0, s_, L.g, C.g, L.r, C.b);
+  CMCG_HIP(mg_sweep<T>(kMGResidual, rows_, chunk_, L.g, L.x, L.b, L.r, 0.0, s_));
+  MGLevelT<T> &C = lv_[l + 1];
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(rows_grid(C.g)), dim3(256), 0, s_, L.g, C.g, L.r, C.b);
   CMCG_HIP(hipGetLastError());
   CMCG_TRY(vcycle_level(l + 1));
-  hipLaunchKernelGGL(prolong_add_kernel, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, C.g, C.x, L.x);
+  hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(rows_grid(L.g)), dim3(256), 0, s_, L.g, C.g, C.x, L.x);
   CMCG_HIP(hipGetLastError());
   // post-smoothing continues from the corrected x: x <- x + omega D^{-1}(b - S x), `post` times
-  double *cur = L.x, *other = L.t;
+  T *cur = L.x, *other = L.t;
   for (int k = 0; k < post_; ++k) {
-    CMCG_HIP(mg_sweep(kMGJacobi, rows_, chunk_, L.g, cur, L.b, other, omega_, s_));
+    CMCG_HIP(mg_sweep<T>(kMGJacobi, rows_, chunk_, L.g, cur, L.b, other, omega_, s_));
     std::swap(cur, other);
   }
   if (cur != L.x)
-    CMCG_HIP(hipMemcpyAsync(L.x, cur, L.g.fs * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    CMCG_HIP(hipMemcpyAsync(L.x, cur, L.g.fs * sizeof(T), hipMemcpyDeviceToDevice, s_));
   return CMCG_OK;
 }
 
 // CMCG_MG_ROWS=1 (environment) runs the stencil sweeps in the row kernels and CMCG_MG_CHUNK=<n>
 // fixes the march's chunk length, so that tests can compare the forms bit for bit
-void RieszMG::read_sweep_env() {
+template <typename T>
+void RieszMGT<T>::read_sweep_env() {
   const char *e = std::getenv("CMCG_MG_ROWS");
   rows_ = e && e[0] == '1';
   const char *c = std::getenv("CMCG_MG_CHUNK");
   chunk_ = c ? std::atoi(c) : 0;
 }
 
-cmcg_status RieszMG::vcycle(const double *b, double *x) {
+template <typename T>
+cmcg_status RieszMGT<T>::vcycle(const T *b, T *x) {
   read_sweep_env();
-  MGLevel &L = lv_[0];
-  L.b = const_cast<double *>(b);
+  MGLevelT<T> &L = lv_[0];
+  L.b = const_cast<T *>(b);
   L.x = x;
   CMCG_TRY(vcycle_level(0));
   if (neumann_) CMCG_TRY(project(x, 0));
   return CMCG_OK;
 }
 
-cmcg_status RieszMG::apply_vcycle(const void *b, int b_is_float, double *x) {
+template <typename T>
+cmcg_status RieszMGT<T>::apply_vcycle(const void *b, int b_is_float, double *x) {
   const size_t n = lv_[0].g.fs;
   if (b_is_float)
-    CMCG_HIP(convert<double, float>(pr_, static_cast<const float *>(b), n, s_));
+    CMCG_HIP(convert<T, float>(pr_, static_cast<const float *>(b), n, s_));
   else
-    CMCG_HIP(hipMemcpyAsync(pr_, b, n * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    CMCG_HIP(convert<T, double>(pr_, static_cast<const double *>(b), n, s_));
   if (neumann_) CMCG_TRY(project(pr_, 0));
-  return vcycle(pr_, x);
+  if constexpr (std::is_same<T, double>::value) {
+    return vcycle(pr_, x);
+  } else {
+    CMCG_TRY(vcycle(pr_, xo_));
+    CMCG_HIP(convert<double, float>(x, xo_, n, s_));
+    return CMCG_OK;
+  }
 }
 
-cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol, int max_iter,
-                           int *iters) {
+template <typename T>
+cmcg_status RieszMGT<T>::solve(const void *b, int b_is_float, double *x, double tol, int max_iter,
+                               int *iters) {
+  static_assert(std::is_same<T, double>::value, "the PCG solve runs in FP64");
   const F2Geom &g = lv_[0].g;
   const size_t n = g.fs;
   *iters = 0;
@@ -462,7 +499,7 @@ cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol,
   double rz = 0.0;
   CMCG_TRY(dot(pr_, pz_, n, &rz));
   for (int it = 1; it <= max_iter; ++it) {
-    CMCG_HIP(mg_sweep(kMGApply, rows_, chunk_, g, pp_, nullptr, pq_, 0.0, s_));
+    CMCG_HIP(mg_sweep<T>(kMGApply, rows_, chunk_, g, pp_, nullptr, pq_, 0.0, s_));
     double pq = 0.0;
     CMCG_TRY(dot(pp_, pq_, n, &pq));
     if (!(pq > 0.0)) return set_error("Riesz PCG breakdown"), CMCG_EBREAKDOWN;
@@ -483,5 +520,11 @@ cmcg_status RieszMG::solve(const void *b, int b_is_float, double *x, double tol,
   if (neumann_) CMCG_TRY(project(x, 0));
   return CMCG_OK;
 }
+
+template class RieszMGT<double>;
+// the FP32 hierarchy serves the V-cycle only
+template RieszMGT<float>::~RieszMGT();
+template cmcg_status RieszMGT<float>::build(const F2Geom &, DeviceArena &, hipStream_t);
+template cmcg_status RieszMGT<float>::apply_vcycle(const void *, int, double *);
 
 }  // namespace cmcg

@@ -288,6 +288,30 @@ def test_multigrid_plane_march_matches_row_kernels_bitwise(cm, masked, monkeypat
             assert np.array_equal(a, out[0]), (mode, f, np.max(np.abs(a - out[0])))
 
 
+@pytest.mark.parametrize("masked", [True, False])
+def test_fp32_vcycle_is_the_fp64_vcycle_to_rounding(cm, masked):
+    """FP32-mixed solves apply the fixed V-cycle with FP32 storage and arithmetic: it equals
+    the FP64 V-cycle to FP32 rounding, and stays symmetric (to that rounding) and positive."""
+    prob = _mixed3d(n=(96, 40, 72), seed=16, masked=masked)
+    o = F2(prob)
+    rng = np.random.default_rng(17)
+    fr = np.concatenate([o.free.ravel()] * 2)
+    x = rng.standard_normal(o.size) * fr
+    y = rng.standard_normal(o.size) * fr
+    u = slice(0, o.nn)
+    if not masked:
+        x[u] -= x[u].mean()
+        y[u] -= y[u].mean()
+    with cm.Solver(prob, "fp64", riesz_mode="vcycle") as s:
+        P64x = s.apply(cm.OP_RIESZ, x)
+    with cm.Solver(prob, "fp32", riesz_mode="vcycle") as s:
+        Px = s.apply(cm.OP_RIESZ, x)
+        Py = s.apply(cm.OP_RIESZ, y)
+    assert _rel(Px[u], P64x[u]) < 1e-5
+    assert abs(Px[u] @ y[u] - x[u] @ Py[u]) <= 1e-5 * np.linalg.norm(Px[u]) * np.linalg.norm(y[u])
+    assert Px[u] @ x[u] > 0 and Py[u] @ y[u] > 0
+
+
 @pytest.mark.parametrize("kind", ["inclusions", "sphere"])
 def test_vcycle_riesz_reaches_the_same_solution(cm, kind):
     if kind == "inclusions":
