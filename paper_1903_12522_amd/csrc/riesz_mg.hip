@@ -11,6 +11,9 @@
 //   * coarsest level: a fixed number of Jacobi sweeps from zero (a fixed symmetric polynomial).
 // With no sound-soft node S is singular (constant vectors); right-hand side, preconditioned
 // residuals and the solution are kept zero-sum (plain sum over nodes).
+// The hierarchy is a template over its storage and arithmetic type: FP64 for the PCG solve and
+// FP64 solves, FP32 for the single fixed V-cycle that FP32-mixed solves use in place of S^{-1}
+// (the reductions of the zero-sum projection accumulate in FP64 either way).
 #include <algorithm>
 #include <cstdlib>
 #include <type_traits>
