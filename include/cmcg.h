@@ -124,7 +124,9 @@ typedef struct {
                                   riesz_tol (the exact map); CMCG_RIESZ_VCYCLE: one fixed
                                   symmetric multigrid V-cycle B ~ S^{-1} (an SPD stand-in: CG
                                   converges to the same minimiser, the stopping norm is the B
-                                  one); 0 = default: SOLVE for FP64, VCYCLE for FP32-mixed      */
+                                  one; FP32-mixed solves apply it in FP32 storage and
+                                  arithmetic); 0 = default: SOLVE for FP64, VCYCLE for
+                                  FP32-mixed                                                   */
   int32_t runup_periods;       /* initial run-up (Sec. 4.2.3): before the CG iteration, integrate
                                   the forced scheme from rest over this many periods with the
                                   source switched on by Mur's transient theta_tr (t_tr = the
