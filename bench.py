@@ -83,7 +83,7 @@ def single_source_tts():
             "converged": rep["converged"]}
 
 
-def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10):
+def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10, keep=None):
     """Time to solution (tol 1e-6) of a 3D second-order workload: begin, iterations in chunks of
     `chunk` (a progress line per chunk), finish, timed on the host around device-synchronised
     calls."""
@@ -103,10 +103,13 @@ def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10):
             done = rep["iterations"]
             log(f"{which} {precision}: iteration {done} rel {rep['rel_residual']:.3e} "
                 f"({time.perf_counter() - t0:.1f} s)")
-        _, rep = s.finish(device_output=True)
+        u, rep = s.finish(device_output=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         gb = s.info["device_bytes"] / 1e9
+        if keep is not None:
+            keep[precision] = torch.complex(u[0], u[1]).clone()
+        del u
     nodes = (prob.n[0] + 1) * (prob.n[1] + 1) * (prob.n[2] + 1)
     return {"workload": f"second-order {which} {prob.n[0]}^3, {precision}", "nodes": nodes,
             "seconds": round(wall, 3), "iterations": rep["iterations"], "converged": bool(conv),
@@ -496,8 +499,14 @@ def main():
 
     out["single_source_128"] = single_source_tts()
     for which in [w for w in args.nodal.split(",") if w]:
-        out[f"nodal_{which}"] = {p: nodal_3d(which, p, args.nodal_max_iter)
+        kept = {}
+        out[f"nodal_{which}"] = {p: nodal_3d(which, p, args.nodal_max_iter, keep=kept)
                                  for p in args.nodal_precisions.split(",") if p}
+        if "fp32" in kept and "fp64" in kept:
+            out[f"nodal_{which}"]["fp32_mixed_rel_l2_vs_fp64"] = float(
+                torch.linalg.vector_norm(kept["fp32"] - kept["fp64"])
+                / torch.linalg.vector_norm(kept["fp64"]))
+        del kept
         if args.nodal_cpu:
             cb = nodal_cpu_baseline(which)
             runs = [r for r in out[f"nodal_{which}"].values() if r["converged"]]
