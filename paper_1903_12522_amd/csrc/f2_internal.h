@@ -81,9 +81,10 @@ template <typename T>
 hipError_t f2_psi_scale(const F2Geom &g, const T *in, const T *lam, T *out, hipStream_t s);
 template <typename TA, typename TB>
 hipError_t dot_plain(const TA *a, const TB *b, size_t n, double *partials, hipStream_t s);
-template <typename T>
+// qu: the primal Riesz update q_u in FP64, or (FP32-mixed V-cycle) the FP32 V-cycle result
+template <typename T, typename TQ>
 hipError_t f2_cg_update(const F2Geom &g, double *z, double *ru, double *rh, const T *d,
-                        const double *qu, const T *qh, const T *lam, const double *sc,
+                        const TQ *qu, const T *qh, const T *lam, const double *sc,
                         double *partials, hipStream_t s);
 template <typename T>
 hipError_t f2_delta(const F2Geom &g, const double *ru, const double *rh, const T *lam,
@@ -139,6 +140,9 @@ class RieszMGT {
   // x = Pi B Pi b for an FP64 or FP32 right-hand side (Pi: zero-sum projection when S is
   // singular): the fixed symmetric V-cycle used in place of S^{-1}; x is FP64
   cmcg_status apply_vcycle(const void *b, int b_is_float, double *x);
+  // the same V-cycle, its result left in the hierarchy's own type: *x points at a buffer of
+  // the hierarchy, valid until its next call
+  cmcg_status apply_vcycle_native(const void *b, int b_is_float, const T **x);
   bool pure_neumann() const { return neumann_; }
 
  private:

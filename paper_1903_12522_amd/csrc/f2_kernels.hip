@@ -515,10 +515,10 @@ __device__ __forceinline__ double minv_at(const F2Geom &g, const T *lam, size_t 
 // Steps 5.4-5.5 with primal and dual residuals (the velocity block of the primal residual is
 // r_v = M^{-1} rh_v and is not stored):  z -= alpha d, r_u -= alpha q_u, rh -= alpha qh;
 // partial delta' = <rh, r> = rh_u . r_u + rh_v . M^{-1} rh_v
-template <typename T>
+template <typename T, typename TQ>
 __global__ __launch_bounds__(kRedThreads) void f2_cg_update_kernel(F2Geom g, double *z, double *ru,
                                                                    double *rh, const T *d,
-                                                                   const double *qu, const T *qh,
+                                                                   const TQ *qu, const T *qh,
                                                                    const T *lam, const double *sc,
                                                                    double *partials) {
   const double alpha = sc[kAlpha];
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(kRedThreads) void f2_cg_update_kernel(F2Geom g, dou
   F2_ROWS(g)
   z[o] -= alpha * (double)d[o];
   z[o + fs] -= alpha * (double)d[o + fs];
-  const double rn = ru[o] - alpha * qu[o];
+  const double rn = ru[o] - alpha * (double)qu[o];
   ru[o] = rn;
   const double rhu = rh[o] - alpha * (double)qh[o];
   const double rhv = rh[o + fs] - alpha * (double)qh[o + fs];
@@ -731,12 +731,12 @@ hipError_t dot_plain(const TA *a, const TB *b, size_t n, double *partials, hipSt
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename TQ>
 hipError_t f2_cg_update(const F2Geom &g, double *z, double *ru, double *rh, const T *d,
-                        const double *qu, const T *qh, const T *lam, const double *sc,
+                        const TQ *qu, const T *qh, const T *lam, const double *sc,
                         double *partials, hipStream_t s) {
-  hipLaunchKernelGGL((f2_cg_update_kernel<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, z, ru,
-                     rh, d, qu, qh, lam, sc, partials);
+  hipLaunchKernelGGL((f2_cg_update_kernel<T, TQ>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, z,
+                     ru, rh, d, qu, qh, lam, sc, partials);
   return hipGetLastError();
 }
 
@@ -800,9 +800,9 @@ hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, h
   template hipError_t f2_psi_scale<T>(const F2Geom &, const T *, const T *, T *, hipStream_t);   \
   template hipError_t f2_march_block<T>(const F2Geom &, const T *, const T *, const T *, T *,    \
                                         T *, int, hipStream_t);                                  \
-  template hipError_t f2_cg_update<T>(const F2Geom &, double *, double *, double *, const T *,   \
-                                      const double *, const T *, const T *, const double *,      \
-                                      double *, hipStream_t);                                    \
+  template hipError_t f2_cg_update<T, double>(const F2Geom &, double *, double *, double *,     \
+                                              const T *, const double *, const T *, const T *,   \
+                                              const double *, double *, hipStream_t);            \
   template hipError_t f2_delta<T>(const F2Geom &, const double *, const double *, const T *,     \
                                   double *, hipStream_t);                                        \
   template hipError_t f2_direction<T>(const F2Geom &, T *, const double *, const double *,       \
@@ -816,6 +816,10 @@ hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, h
   template hipError_t f2_pack<T>(const F2Geom &, const T *, double *, int, hipStream_t);
 INST(float)
 INST(double)
+template hipError_t f2_cg_update<float, float>(const F2Geom &, double *, double *, double *,
+                                               const float *, const float *, const float *,
+                                               const float *, const double *, double *,
+                                               hipStream_t);
 #undef INST
 template hipError_t dot_plain<double, double>(const double *, const double *, size_t, double *, hipStream_t);
 template hipError_t dot_plain<float, float>(const float *, const float *, size_t, double *, hipStream_t);

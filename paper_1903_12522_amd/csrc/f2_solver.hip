@@ -664,6 +664,18 @@ class F2Solver final : public Solver {
     return CMCG_OK;
   }
 
+  // FP32-mixed V-cycle: q_u left in the FP32 hierarchy's buffer (*out), read directly by the CG
+  // update (FP32 to FP64 is exact, so this equals converting it first)
+  cmcg_status riesz_u_f32(const void *qh_u, const float **out) {
+    CMCG_HIP(hipEventRecord(ev[8], s));
+    CMCG_TRY(mg32.apply_vcycle_native(qh_u, 1, out));
+    CMCG_HIP(hipEventRecord(ev[9], s));
+    CMCG_HIP(hipEventSynchronize(ev[9]));
+    t_riesz += PhaseEvents::seconds(ev[8], ev[9]);
+    riesz_iters += 1;
+    return CMCG_OK;
+  }
+
   cmcg_status riesz_u(const void *qh_u, int is_float, double *out) {
     int it = 0;
     CMCG_HIP(hipEventRecord(ev[8], s));
@@ -772,19 +784,28 @@ class F2Solver final : public Solver {
       CMCG_TRY(adj(lo, lo.Y, lo.W, lo.Y));
       CMCG_HIP(hipEventRecord(ev[4], s));
       // Step 5.2: q_u = S^{-1} qh_u (q_v = M^{-1} qh_v is applied on the fly)
-      CMCG_TRY(riesz_u(lo.W, mixed ? 1 : 0, QU));
+      const float *qu32 = nullptr;
+      if (mg_f32) CMCG_TRY(riesz_u_f32(lo.W, &qu32));
+      else CMCG_TRY(riesz_u(lo.W, mixed ? 1 : 0, QU));
       CMCG_HIP(hipEventRecord(ev[5], s));
       // Steps 5.3-5.6
       if (mixed) {
         CMCG_HIP(dot_plain<float, float>(tpc<float>(lo.W), tpc<float>(D), 2 * g.fs, partials, s));
         CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinAlpha, 0, s));
-        CMCG_HIP(f2_cg_update<float>(g, Z, RU, RH, tpc<float>(D), QU, tpc<float>(lo.W),
-                                     tpc<float>(lo.lam), scalars, partials, s));
+        if (qu32)
+          CMCG_HIP((f2_cg_update<float, float>(g, Z, RU, RH, tpc<float>(D), qu32,
+                                               tpc<float>(lo.W), tpc<float>(lo.lam), scalars,
+                                               partials, s)));
+        else
+          CMCG_HIP((f2_cg_update<float, double>(g, Z, RU, RH, tpc<float>(D), QU,
+                                                tpc<float>(lo.W), tpc<float>(lo.lam), scalars,
+                                                partials, s)));
       } else {
         CMCG_HIP(dot_plain<double, double>(tpc<double>(lo.W), tpc<double>(D), 2 * g.fs, partials, s));
         CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinAlpha, 0, s));
-        CMCG_HIP(f2_cg_update<double>(g, Z, RU, RH, tpc<double>(D), QU, tpc<double>(lo.W),
-                                      tpc<double>(lo.lam), scalars, partials, s));
+        CMCG_HIP((f2_cg_update<double, double>(g, Z, RU, RH, tpc<double>(D), QU,
+                                               tpc<double>(lo.W), tpc<double>(lo.lam), scalars,
+                                               partials, s)));
       }
       CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinBeta, 0, s));
       CMCG_HIP(hipEventRecord(ev[6], s));

@@ -481,6 +481,21 @@ cmcg_status RieszMGT<T>::apply_vcycle(const void *b, int b_is_float, double *x) 
 }
 
 template <typename T>
+cmcg_status RieszMGT<T>::apply_vcycle_native(const void *b, int b_is_float, const T **x) {
+  // the result buffer: FP32, the V-cycle's own; FP64, the PCG vector z (used by solve only)
+  T *dst = std::is_same<T, float>::value ? xo_ : pz_;
+  const size_t n = lv_[0].g.fs;
+  if (b_is_float)
+    CMCG_HIP(convert<T, float>(pr_, static_cast<const float *>(b), n, s_));
+  else
+    CMCG_HIP(convert<T, double>(pr_, static_cast<const double *>(b), n, s_));
+  if (neumann_) CMCG_TRY(project(pr_, 0));
+  CMCG_TRY(vcycle(pr_, dst));
+  *x = dst;
+  return CMCG_OK;
+}
+
+template <typename T>
 cmcg_status RieszMGT<T>::solve(const void *b, int b_is_float, double *x, double tol, int max_iter,
                                int *iters) {
   static_assert(std::is_same<T, double>::value, "the PCG solve runs in FP64");
@@ -529,5 +544,6 @@ template class RieszMGT<double>;
 template RieszMGT<float>::~RieszMGT();
 template cmcg_status RieszMGT<float>::build(const F2Geom &, DeviceArena &, hipStream_t);
 template cmcg_status RieszMGT<float>::apply_vcycle(const void *, int, double *);
+template cmcg_status RieszMGT<float>::apply_vcycle_native(const void *, int, const float **);
 
 }  // namespace cmcg
