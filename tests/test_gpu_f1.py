@@ -86,7 +86,11 @@ def test_temporal_blocking_is_bitwise_fp32(cm):
     outs = []
     for k in (1, 2, 3, 4, 5, 6, 7, 8):
         with cm.Solver(prob, "fp32", steps_per_launch=k) as s:
+            assert s.info["steps_per_launch"] == k
             outs.append((s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z)))
+    for prec in ("fp32", "fp64"):
+        with cm.Solver(prob, prec) as s:
+            assert s.info["steps_per_launch"] == 7   # the library default in both precisions
     for k, (a, b) in zip((2, 3, 4, 5, 6, 7, 8), outs[1:]):
         assert np.array_equal(a, outs[0][0]), (k, np.max(np.abs(a - outs[0][0])))
         assert np.array_equal(b, outs[0][1]), (k, np.max(np.abs(b - outs[0][1])))

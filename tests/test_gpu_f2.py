@@ -58,7 +58,10 @@ def test_temporal_blocking_is_bitwise(cm, prec):
     outs = []
     for k in (1, 2, 3, 4):
         with cm.Solver(prob, prec, steps_per_launch=k) as s:
+            assert s.info["steps_per_launch"] == k
             outs.append((s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z)))
+    with cm.Solver(prob, prec) as s:
+        assert s.info["steps_per_launch"] == 3       # the nodal default
     for k, (a, b) in zip((2, 3, 4), outs[1:]):
         assert np.array_equal(a, outs[0][0]), (k, np.max(np.abs(a - outs[0][0])))
         assert np.array_equal(b, outs[0][1]), (k, np.max(np.abs(b - outs[0][1])))
