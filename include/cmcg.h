@@ -165,6 +165,15 @@ typedef struct {
                                   sources, subtrahend) once and writes its outputs once; the CG
                                   vector operations, the Riesz map and the per-component
                                   kernels of multi-frequency sources are not counted           */
+  int32_t riesz_unconverged;   /* F2, CMCG_RIESZ_SOLVE: Riesz solves of the last solve (or
+                                  apply) that stopped at riesz_max_iter above riesz_tol.  CG then
+                                  ran with an inexact map, and cmcg_solve returns CMCG_ENOTCONV */
+  double seconds_bulk_fwd, seconds_bulk_adj;   /* device time of the bulk launches of the CG
+                                  iterations' forward / backward periods (HIP events around each
+                                  period's run of them): first order, the launches between a
+                                  period's first and last; second order, the blocked launches
+                                  of full depth.  Each direction's bulk runs one kernel instance */
+  int64_t bulk_launches_fwd, bulk_launches_adj;   /* the number of those launches              */
 } cmcg_report;
 
 /* Create a solver for `problem`: validates it, sets T, N and dt, allocates the device state and
@@ -290,7 +299,9 @@ cmcg_status cmcg_server_submit(cmcg_server *s, const cmcg_problem *p, const cmcg
 /* One tick: admit what fits, advance running solves, finish converged ones.  Optional counts. */
 cmcg_status cmcg_server_step(cmcg_server *s, int32_t *active, int32_t *queued);
 /* *state = CMCG_REQ_*; when DONE, copies the filtered solution (host arrays, layout of c) and
- * the report, and returns the solve's status (CMCG_OK or CMCG_ENOTCONV). */
+ * the report, and returns the solve's status (CMCG_OK or CMCG_ENOTCONV); when FAILED, returns
+ * the failure status.  The poll that reports DONE or FAILED releases the request: its id is
+ * unknown afterwards (CMCG_EINVAL). */
 cmcg_status cmcg_server_poll(cmcg_server *s, int64_t id, int32_t *state, double *u_re,
                              double *u_im, cmcg_report *rep);
 /* Device bytes held by resident solves, and the running / queued counts. */

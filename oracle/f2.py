@@ -401,3 +401,55 @@ class F2:
             z = z + np.concatenate([R * U.real, R * wh * U.imag])
             Us.append(U.reshape(self.shape))
         return (Us[0] if len(Us) == 1 else np.stack(Us)), z
+
+
+def window(prob, lo, hi):
+    """Sub-problem on the nodes lo[a] <= I_a <= hi[a] (axis a = x, y[, z]) of `prob`, for sampled
+    checks of large grids: sides that lie on the original boundary keep its condition and data,
+    cut sides become Neumann with zero data.  A period of N steps is N + 1 stencil sweeps (the
+    start map and N recurrence steps), each coupling a node only to its axis neighbours, and only
+    the nodes on a cut plane carry a changed stencil (half weights); so values at nodes more
+    than N + 2 from every cut plane equal those of the full problem."""
+    import copy
+    d = prob.dim
+    n = [int(m) for m in prob.n[:d]]
+    lo, hi = [int(a) for a in lo[:d]], [int(a) for a in hi[:d]]
+    shape = tuple(m + 1 for m in reversed(n))
+    nodes = tuple(slice(lo[a], hi[a] + 1) for a in reversed(range(d)))   # numpy order
+
+    def cut_field(x):
+        return None if x is None else np.asarray(x).reshape(shape)[nodes].copy()
+
+    keep = []
+    for a in range(d):
+        keep += [lo[a] == 0, hi[a] == n[a]]
+
+    def cut_faces(g):
+        if g is None:
+            return None
+        out = []
+        for a in range(d):
+            others = [b for b in range(d) if b != a]
+            fshape = tuple(n[b] + 1 for b in reversed(others))
+            sel = tuple(slice(lo[b], hi[b] + 1) for b in reversed(others))
+            for side in range(2):
+                arr = np.asarray(g[2 * a + side], dtype=complex).reshape(fshape)[sel]
+                out.append(arr.copy() if keep[2 * a + side] else np.zeros_like(arr))
+        return out
+
+    sub = copy.copy(prob)
+    sub.n = tuple(hi[a] - lo[a] for a in range(d))
+    sub.spacing = prob.h
+    if prob.c is not None:
+        sub.c = cut_field(prob.c)
+    sub.f = cut_field(prob.f)
+    sub.gS = cut_faces(prob.gS)
+    sub.sound_soft = cut_field(prob.sound_soft)
+    sub.gD = cut_field(prob.gD)
+    bc = list(prob.face_bc)[: 2 * d]
+    sub.face_bc = tuple(bc[k] if keep[k] else 1 for k in range(2 * d)) + tuple(prob.face_bc)[2 * d:]
+    if prob.shots:
+        sub.shots = [copy.copy(s) for s in prob.shots]
+        for s0, s in zip(prob.shots, sub.shots):
+            s.f, s.gS, s.gD = cut_field(s0.f), cut_faces(s0.gS), cut_field(s0.gD)
+    return sub

@@ -1,18 +1,32 @@
-"""Build libcmcg.so (all HIP sources, gfx950) in-tree with hipcc."""
+"""Build libcmcg.so (all HIP sources, gfx950) in-tree with hipcc.
+
+Each source is compiled to an object file in parallel (they share no device code), then the
+objects are linked into the shared library."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcmcg.so")
-SOURCES = ["cmcg_api.hip", "f1_kernels.hip", "f1_solver.hip", "f2_kernels.hip", "riesz_mg.hip",
-           "f2_solver.hip"]
+OBJ = os.path.join(HERE, "_build")
+# (source, object, extra flags): f1_kernels.hip builds as two objects, one per precision of its
+# stream-kernel instances
+UNITS = [
+    ("f1_kernels.hip", "f1_kernels_fp32.o", ["-DCMCG_F1_PART=1"]),
+    ("f1_kernels.hip", "f1_kernels_fp64.o", ["-DCMCG_F1_PART=2"]),
+    ("cmcg_api.hip", "cmcg_api.o", []),
+    ("f1_solver.hip", "f1_solver.o", []),
+    ("f2_kernels.hip", "f2_kernels.o", []),
+    ("riesz_mg.hip", "riesz_mg.o", []),
+    ("f2_solver.hip", "f2_solver.o", []),
+]
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # every multiply-add the kernels want is written as fma(); nothing else is contracted, so
@@ -29,10 +43,29 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def _jobs() -> int:
+    try:
+        return max(1, min(16, int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    except ValueError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
 def build(verbose: bool = True) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    os.makedirs(OBJ, exist_ok=True)
+
+    def compile_one(unit) -> str:
+        src, obj, extra = unit
+        obj = os.path.join(OBJ, obj)
+        cmd = [hipcc()] + FLAGS + extra + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        objs = list(ex.map(compile_one, UNITS))
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + srcs
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

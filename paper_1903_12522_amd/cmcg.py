@@ -67,7 +67,9 @@ class _Report(ctypes.Structure):
                 ("seconds_other", ctypes.c_double), ("grid_updates", ctypes.c_double),
                 ("riesz_iterations", ctypes.c_int64), ("fp64_refreshes", ctypes.c_int32),
                 ("runup_periods", ctypes.c_int32), ("seconds_runup", ctypes.c_double),
-                ("dram_bytes", ctypes.c_double)]
+                ("dram_bytes", ctypes.c_double), ("riesz_unconverged", ctypes.c_int32),
+                ("seconds_bulk_fwd", ctypes.c_double), ("seconds_bulk_adj", ctypes.c_double),
+                ("bulk_launches_fwd", ctypes.c_int64), ("bulk_launches_adj", ctypes.c_int64)]
 
 
 class _Info(ctypes.Structure):
@@ -248,18 +250,24 @@ class Solver:
         return self._out_value(keep, device_output), _report_dict(rep)
 
     # ------------------------------------------------------------------ stage calls
-    def apply(self, op: int, z, steps: int = 0):
+    def apply(self, op: int, z, steps: int = 0, out=None):
         """op(z) on a packed FP64 state; z may be a NumPy array or a torch device tensor.
-        Returns the same kind."""
+        Returns the same kind.  `out`: a device tensor to write into (it may be z itself)."""
         torch = self._torch
         as_np = isinstance(z, np.ndarray)
         zin = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64)).cuda() if as_np else z
         assert zin.dtype == torch.float64 and zin.is_cuda and zin.numel() == self.info["state_len"]
+        assert zin.is_contiguous() or out is None
         zin = zin.contiguous()
-        out = torch.empty_like(zin)
+        if out is None:
+            out = torch.empty_like(zin)
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == zin.numel()
         self._order()
-        _check(_lib.cmcg_apply(self._h, int(op), int(steps), ctypes.c_void_p(zin.data_ptr()),
-                               ctypes.c_void_p(out.data_ptr())), "cmcg_apply")
+        # CMCG_ENOTCONV: a Riesz solve stopped at its iteration cap (kept in last_status)
+        self.last_status = _check(
+            _lib.cmcg_apply(self._h, int(op), int(steps), ctypes.c_void_p(zin.data_ptr()),
+                            ctypes.c_void_p(out.data_ptr())), "cmcg_apply", allow_notconv=True)
         return out.cpu().numpy() if as_np else out
 
     def filter(self, z) -> np.ndarray:
@@ -453,9 +461,10 @@ class Server:
         self.close()
 
     def submit(self, problem, precision: str = "fp32", tol: float = 1e-6,
-               max_iter: int = 1000, runup_periods: int = 0) -> int:
+               max_iter: int = 1000, runup_periods: int = 0, fp64_refresh: float = 0.0) -> int:
         p, keep = marshal_problem(problem)
-        o = make_options(precision, tol, max_iter, runup_periods=runup_periods)
+        o = make_options(precision, tol, max_iter, runup_periods=runup_periods,
+                         fp64_refresh=fp64_refresh)
         rid = ctypes.c_int64(0)
         _check(_lib.cmcg_server_submit(self._h, ctypes.byref(p), ctypes.byref(o),
                                        ctypes.byref(rid)), "cmcg_server_submit")
@@ -477,6 +486,9 @@ class Server:
         st = _lib.cmcg_server_poll(self._h, int(rid), ctypes.byref(state),
                                    re.ctypes.data_as(ctypes.c_void_p),
                                    im.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rep))
+        if state.value in (REQ_DONE, REQ_FAILED):
+            # the library released the request with this poll
+            self._shapes.pop(rid, None)
         if state.value == REQ_DONE:
             return state.value, re + 1j * im, _report_dict(rep), st
         return state.value, None, None, st

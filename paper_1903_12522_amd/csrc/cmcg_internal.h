@@ -121,8 +121,9 @@ struct F1SlotLaunch {
 // Launch geometry of the streaming kernel for an nx x ny grid at K steps per launch.
 void f1_launch_shape(int nx, int ny, int K, int *nbx, int *nby, int *band);
 // Fast-variant set of a launch's kernel instance: 0 the launches between a period's first and
-// last, 1 those two, 3 every launch of a forced (forward) period.
-int f1_fast_set(const F1Launch &L, bool has_sub);
+// last (forward and backward alike: a backward middle launch is a forward homogeneous launch in
+// the backward period's variables), 1 those two, 3 every launch of a forced (forward) period.
+int f1_fast_set(const F1Launch &L, bool has_sub, bool adjoint);
 template <typename T>
 hipError_t f1_multi_launch(int K, bool adjoint, int set, const F1SlotLaunch<T> *slots, int nslots,
                            int blocks, hipStream_t s);

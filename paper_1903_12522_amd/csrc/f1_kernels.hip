@@ -12,7 +12,14 @@
 // The backward period applies E* = M_E^{-1} E^T M_E (M_E = diag(h^2 on faces, h^2/c^2 on cells),
 // eq. mix_cost_functional_J): per step the transposes of the three sub-maps in reverse order,
 //   v <- v - dt/2 c^2 D p;   p <- p - dt G (v / (1+gamma)),  v <- a v;   v <- v - dt/2 c^2 D p
-// with a = (1-gamma)/(1+gamma); its half kicks of v merge the same way.
+// with a = (1-gamma)/(1+gamma); its half kicks of v merge the same way.  In the variables
+// Q = -p, u = v / (1+gamma) a merged backward step reads
+//   Q <- Q + dt G u;   (1+gamma) u' = (1-gamma) u + dt c^2 D Q,
+// the forward's [velocity update, kick] pair shifted by half a step.  So a backward period is a
+// prologue (the opening half kick of v, the change of variables and the first Q kick), N - 1
+// forward homogeneous steps on (Q, u), and an epilogue (the closing half update straight back to
+// v = (1-gamma) u + dt/2 c^2 D Q, p = -Q).  Only the first and last launches of a backward period
+// differ from forward launches; the ones between run the forward kernel instance itself.
 //
 // Kernel design (register streaming with temporal blocking).  Each 64-lane wavefront owns a
 // strip of 64 consecutive columns (one column per lane, so every row access is one coalesced
@@ -27,6 +34,14 @@
 
 #include "cmcg_internal.h"
 #include "dpp.h"
+
+// The file is compiled twice so that the two precisions' stream-kernel instances build in
+// parallel: CMCG_F1_PART 1 holds the FP32 instances and everything else, 2 the FP64 instances.
+#ifndef CMCG_F1_PART
+#define CMCG_F1_PART 0
+#endif
+#define CMCG_F1_FP32 (CMCG_F1_PART != 2)
+#define CMCG_F1_FP64 (CMCG_F1_PART != 1)
 
 namespace cmcg {
 namespace {
@@ -63,6 +78,11 @@ __device__ __forceinline__ T f1_dirichlet(const F1Ptrs<T> &p, size_t o, double d
   return (T)v;
 }
 
+// Number of absorbing faces of cell (i, r): mx counts the x faces of column i.
+__device__ __forceinline__ int f1_abs_faces(const F1Geom &g, int mx, int r) {
+  return mx + (r == 0 ? g.abs_face[2] : 0) + (r == g.ny - 1 ? g.abs_face[3] : 0);
+}
+
 template <typename T, int K, bool ADJ, bool EDGE, bool MASK>
 __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, const int i, const int lane,
@@ -75,25 +95,23 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
   const bool colIn = EDGE ? ((i >= 0) && (i < nx)) : true;
   const bool pxCol = EDGE ? ((i >= 0) && (i <= nx - 2)) : true;
   const int mx = EDGE ? ((i == 0 ? g.abs_face[0] : 0) + (i == nx - 1 ? g.abs_face[1] : 0)) : 0;
-  const int af2 = g.abs_face[2], af3 = g.abs_face[3];
   const bool laneOut = colIn && lane >= H && lane < 64 - H;
 
   // per-level emissions of the previous (p) and current (c) row iteration:
   // level k emits v^k(r), Px^k(r) and Py^k(r-1) with r = j - k; CC is kap of row r.
   T Vp[K + 1], PXp[K + 1], PYp[K + 1], CCp[K + 1];
   T Vc[K + 1], PXc[K + 1], PYc[K + 1], CCc[K + 1];
-  T HOLD[K + 1];   // level 0: raw Py of the current row; adjoint level k: Py^k(r) one row ahead
+  T HOLD0 = T(0);   // level 0: raw Py of the current row
   T RMp[K + 1], RMc[K + 1];   // MASK: R of the emitted row (1 free, 0 Dirichlet)
   const bool dirichlet = MASK && !ADJ && L.forced && p.dre != nullptr;
 #pragma unroll
   for (int k = 0; k <= K; ++k) {
     Vp[k] = PXp[k] = PYp[k] = CCp[k] = T(0);
     Vc[k] = PXc[k] = PYc[k] = CCc[k] = T(0);
-    HOLD[k] = T(0);
     RMp[k] = RMc[k] = T(1);
   }
   const int jstart = s0 - K - 2, jend = s1 + K;
-  if (colIn && jstart - 1 >= 0 && jstart - 1 < ny) HOLD[0] = p.in[(size_t)(jstart - 1) * pitch + i + fs];
+  if (colIn && jstart - 1 >= 0 && jstart - 1 < ny) HOLD0 = p.in[(size_t)(jstart - 1) * pitch + i + fs];
 
   for (int j = jstart; j <= jend; ++j) {
     // ---- level 0: load row j
@@ -110,16 +128,17 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
     T rm0 = T(1);
     if (MASK) {
       if (in0 && g.mask[o0]) rm0 = T(0);
-      // a period starts from a state that is zero on the Dirichlet cells
-      if (L.first && rm0 == T(0)) v0 = dirichlet ? f1_dirichlet(p, o0, L.dc[0], L.ds[0]) : T(0);
+      // a forward period starts from a state that is zero on the Dirichlet cells
+      if (!ADJ && L.first && rm0 == T(0))
+        v0 = dirichlet ? f1_dirichlet(p, o0, L.dc[0], L.ds[0]) : T(0);
     }
     if (L.accumulate && laneOut && j >= s0 && j < s1) {
       const double vv = (double)v0;
       p.ure[o0] += vv * L.fcos;
       p.uim[o0] += vv * L.fsin;
     }
-    T pyprev = HOLD[0];   // raw Py(j-1)
-    HOLD[0] = py0;
+    T pyprev = HOLD0;   // raw Py(j-1)
+    HOLD0 = py0;
     if (L.first) {
       if (!ADJ) {
         // opening half kick  p <- p + dt/2 G v  (Px of row j, Py of row j-1)
@@ -127,9 +146,19 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
         if (in0 && pxCol) px0 = fma(hdth, vr - v0, px0);
         if (colIn && j - 1 >= 0 && j - 1 <= ny - 2) pyprev = fma(hdth, v0 - Vp[0], pyprev);
       } else {
-        // opening half kick  v <- v - dt/2 c^2 D p  (row j)
+        // backward prologue: the opening half kick v <- v - dt/2 c^2 D p (row j), then the
+        // change of variables Q = -p, u = R v / (1 + gamma), then the first kick
+        // Q <- Q + dt G u (Px of row j, Py of row j-1)
         const T pl = lane_from_left(px0);
         if (in0) v0 = fma(T(-0.5) * c0, (px0 - pl) + (py0 - pyprev), v0);
+        if (EDGE || j == 0 || j == ny - 1) {
+          const int m = in0 ? f1_abs_faces(g, mx, j) : 0;
+          if (m) v0 = v0 / (T(1) + T(0.5) * (T)m * sqrt(c0 * dth));
+        }
+        if (MASK && rm0 == T(0)) v0 = T(0);
+        const T vr = lane_from_right(v0);
+        if (in0 && pxCol) px0 = fma(dth, vr - v0, -px0);
+        if (colIn && j - 1 >= 0 && j - 1 <= ny - 2) pyprev = fma(dth, v0 - Vp[0], -pyprev);
       }
     }
     Vc[0] = v0;
@@ -138,85 +167,67 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
     CCc[0] = c0;
     RMc[0] = rm0;
 
-    // ---- levels 1..K
+    // ---- levels 1..K: [velocity update, flux kick] (forward: v and p; backward: u and Q)
 #pragma unroll
     for (int k = 1; k <= K; ++k) {
       const int r = j - k;
       const bool rIn = (r >= 0) && (r < ny);
       const bool cin = rIn && colIn;
       const bool lastk = L.last && k == K;
-      if (!ADJ) {
-        const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
-        const T kap = CCp[k - 1];
-        const T kick_h = lastk ? hdth : dth;
-        const T pl = lane_from_left(px);
-        T dsum = (px - pl) + (pyr - pyrm1);
-        if (L.forced && cin) {
-          const size_t o = (size_t)r * pitch + i;
-          dsum = fma(p.fre[o], (T)L.cs[k - 1], dsum);
-          if (p.fim) dsum = fma(p.fim[o], (T)L.sn[k - 1], dsum);
-        }
+      const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
+      const T kap = CCp[k - 1];
+      const T pl = lane_from_left(px);
+      T dsum = (px - pl) + (pyr - pyrm1);
+      if (!ADJ && L.forced && cin) {
+        const size_t o = (size_t)r * pitch + i;
+        dsum = fma(p.fre[o], (T)L.cs[k - 1], dsum);
+        if (p.fim) dsum = fma(p.fim[o], (T)L.sn[k - 1], dsum);
+      }
+      const bool rowB = (r == 0) || (r == ny - 1);
+      if (ADJ && lastk) {
+        // backward epilogue: the closing half update back in the original variables,
+        // v = (1 - gamma) u + dt/2 c^2 D Q, p = -Q
         T vn = T(0);
-        const bool rowB = (r == 0) || (r == ny - 1);
+        const T hk = T(0.5) * kap;
         if (!EDGE && !rowB) {
-          if (rIn) vn = fma(kap, dsum, v);
+          if (rIn) vn = fma(hk, dsum, v);
         } else if (cin) {
-          const int m = mx + (r == 0 ? af2 : 0) + (r == ny - 1 ? af3 : 0);
-          if (m == 0) {
-            vn = fma(kap, dsum, v);
-          } else {
-            const T gam = T(0.5) * (T)m * sqrt(kap * dth);
-            vn = fma(kap, dsum, (T(1) - gam) * v) / (T(1) + gam);
-          }
+          const int m = f1_abs_faces(g, mx, r);
+          if (m == 0) vn = fma(hk, dsum, v);
+          else vn = fma(hk, dsum, (T(1) - T(0.5) * (T)m * sqrt(kap * dth)) * v);
         }
-        if (MASK && cin && RMp[k - 1] == T(0))
-          vn = dirichlet ? f1_dirichlet(p, (size_t)r * pitch + i, L.dc[k], L.ds[k]) : T(0);
-        const T vr = lane_from_right(vn);
-        const T pxn = (cin && pxCol) ? fma(kick_h, vr - vn, px) : px;
         const bool pyv = colIn && (r - 1 >= 0) && (r - 1 <= ny - 2);
-        const T pyn = pyv ? fma(kick_h, vn - Vp[k], pyrm1) : pyrm1;
         Vc[k] = vn;
-        PXc[k] = pxn;
-        PYc[k] = pyn;
+        PXc[k] = (cin && pxCol) ? -px : px;
+        PYc[k] = pyv ? -pyrm1 : pyrm1;
         CCc[k] = kap;
         RMc[k] = RMp[k - 1];
-      } else {
-        // inputs: v^{k-1}(r+1) (current), v^{k-1}(r), Px^{k-1}(r) (previous), Py^{k-1}(r); the
-        // velocities enter as R v
-        const T vA = MASK ? Vc[k - 1] * RMc[k - 1] : Vc[k - 1];
-        const T vB = MASK ? Vp[k - 1] * RMp[k - 1] : Vp[k - 1];
-        const T pxB = PXp[k - 1], pyB = PYc[k - 1];
-        const T kA = CCc[k - 1], kB = CCp[k - 1];
-        const int rA = r + 1;
-        T wA = vA, wB = vB, aB = T(1);
-        const bool rowB = (r == 0) || (r == ny - 1) || (rA == 0) || (rA == ny - 1);
-        if (EDGE || rowB) {
-          const int mA = (colIn && rA >= 0 && rA < ny)
-                             ? mx + (rA == 0 ? af2 : 0) + (rA == ny - 1 ? af3 : 0) : 0;
-          const int mB = cin ? mx + (r == 0 ? af2 : 0) + (r == ny - 1 ? af3 : 0) : 0;
-          if (mA) wA = vA / (T(1) + T(0.5) * (T)mA * sqrt(kA * dth));
-          if (mB) {
-            const T gB = T(0.5) * (T)mB * sqrt(kB * dth);
-            wB = vB / (T(1) + gB);
-            aB = (T(1) - gB) / (T(1) + gB);
-          }
-        }
-        const T wBr = lane_from_right(wB);
-        // p <- p - dt G w
-        const T pxn = (cin && pxCol) ? fma(-dth, wBr - wB, pxB) : pxB;
-        const bool pyv = colIn && r >= 0 && r <= ny - 2;
-        const T pyn = pyv ? fma(-dth, wA - wB, pyB) : pyB;   // Py^k(r)
-        // v <- a v - kick c^2 D p = a v - (kick / dt) kap dsum
-        const T pl = lane_from_left(pxn);
-        T vn = T(0);
-        if (cin) vn = fma(lastk ? T(-0.5) * kB : -kB, (pxn - pl) + (pyn - HOLD[k]), aB * vB);
-        Vc[k] = vn;
-        PXc[k] = pxn;
-        PYc[k] = HOLD[k];
-        HOLD[k] = pyn;
-        CCc[k] = kB;
-        RMc[k] = RMp[k - 1];
+        continue;
       }
+      const T kick_h = (!ADJ && lastk) ? hdth : dth;
+      T vn = T(0);
+      if (!EDGE && !rowB) {
+        if (rIn) vn = fma(kap, dsum, v);
+      } else if (cin) {
+        const int m = f1_abs_faces(g, mx, r);
+        if (m == 0) {
+          vn = fma(kap, dsum, v);
+        } else {
+          const T gam = T(0.5) * (T)m * sqrt(kap * dth);
+          vn = fma(kap, dsum, (T(1) - gam) * v) / (T(1) + gam);
+        }
+      }
+      if (MASK && cin && RMp[k - 1] == T(0))
+        vn = dirichlet ? f1_dirichlet(p, (size_t)r * pitch + i, L.dc[k], L.ds[k]) : T(0);
+      const T vr = lane_from_right(vn);
+      const T pxn = (cin && pxCol) ? fma(kick_h, vr - vn, px) : px;
+      const bool pyv = colIn && (r - 1 >= 0) && (r - 1 <= ny - 2);
+      const T pyn = pyv ? fma(kick_h, vn - Vp[k], pyrm1) : pyrm1;
+      Vc[k] = vn;
+      PXc[k] = pxn;
+      PYc[k] = pyn;
+      CCc[k] = kap;
+      RMc[k] = RMp[k - 1];
     }
 
     // ---- write level K: v, Px of row j-K and Py of row j-K-1
@@ -305,9 +316,11 @@ __device__ __forceinline__ void fast_store_rows(const FastIO &io, int j, int s0,
 // the row; the face below is held from the previous iteration), level k advances row j - k from
 // level k-1 using the previous iteration's emissions (*p arrays) and writes this iteration's
 // (*c arrays); row j - K leaves the pipeline.
-// FIRST: the period's opening half kick at level 0 (forward p += dt/2 G v, backward
-// v -= dt/2 c^2 D p, on the raw input).  SUB: the stored values less the subtrahend (sub_a: Px,
-// sub_c: v of row j - K; sub_b: Py of row j - K - 1), loaded one row ahead with the inputs.
+// FIRST: the period's opening at level 0 (forward: the half kick p += dt/2 G v; backward: the
+// prologue, half kick v -= dt/2 c^2 D p, Q = -p, Q += dt G v).  Backward launches end their
+// period with the epilogue at level K when L.last (v = u + dt/2 c^2 D Q, p = -Q).  SUB: the
+// stored values less the subtrahend (sub_a: Px, sub_c: v of row j - K; sub_b: Py of row
+// j - K - 1), loaded one row ahead with the inputs.
 // FORCED (forward): level k adds the source of its row j - k at the step's time, read from the
 // forcing fields (rows that the previous levels read too, so mostly cache hits); `has_fim` is
 // wave-uniform.
@@ -321,8 +334,8 @@ __device__ __forceinline__ void f1_fast_row(const FastIO &io, const F1Launch &L,
                                             const T (&PXp)[K + 1], const T (&PYp)[K + 1],
                                             const T (&CCp)[K + 1], T (&Vc)[K + 1],
                                             T (&PXc)[K + 1], T (&PYc)[K + 1], T (&CCc)[K + 1],
-                                            T (&HOLD)[K + 1]) {
-  T pyprev = HOLD[0];        // Py(j-1)
+                                            T &HOLD0) {
+  T pyprev = HOLD0;        // Py(j-1)
   if (FIRST) {
     if (!ADJ) {
       const T vr = lane_from_right(in_v);
@@ -331,52 +344,48 @@ __device__ __forceinline__ void f1_fast_row(const FastIO &io, const F1Launch &L,
     } else {
       const T pl = lane_from_left(in_px);
       in_v = fma(T(-0.5) * in_cc, (in_px - pl) + (in_py - pyprev), in_v);
+      const T vr = lane_from_right(in_v);
+      in_px = fma(dth, vr - in_v, -in_px);
+      pyprev = fma(dth, in_v - Vp[0], -pyprev);
     }
   }
   Vc[0] = in_v;
   PXc[0] = in_px;
   PYc[0] = pyprev;
-  HOLD[0] = in_py;
+  HOLD0 = in_py;
   CCc[0] = in_cc;
 #pragma unroll
   for (int k = 1; k <= K; ++k) {
     const bool lastk = L.last && k == K;
-    if (!ADJ) {
-      const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
-      const T kap = CCp[k - 1];
-      const T kick_h = lastk ? hdth : dth;
-      const T pl = lane_from_left(px);
-      T dsum = (px - pl) + (pyr - pyrm1);
-      if (FORCED) {
-        const unsigned so = (unsigned)(j - k) * io.pitchb;
-        T fr;
-        buf_ld(fr, io.fre, io.vo, so);
-        dsum = fma(fr, (T)L.cs[k - 1], dsum);
-        if (has_fim) {
-          T fi;
-          buf_ld(fi, io.fim, io.vo, so);
-          dsum = fma(fi, (T)L.sn[k - 1], dsum);
-        }
+    const T v = Vp[k - 1], px = PXp[k - 1], pyr = PYc[k - 1], pyrm1 = PYp[k - 1];
+    const T kap = CCp[k - 1];
+    const T pl = lane_from_left(px);
+    T dsum = (px - pl) + (pyr - pyrm1);
+    if (!ADJ && FORCED) {
+      const unsigned so = (unsigned)(j - k) * io.pitchb;
+      T fr;
+      buf_ld(fr, io.fre, io.vo, so);
+      dsum = fma(fr, (T)L.cs[k - 1], dsum);
+      if (has_fim) {
+        T fi;
+        buf_ld(fi, io.fim, io.vo, so);
+        dsum = fma(fi, (T)L.sn[k - 1], dsum);
       }
-      const T vn = fma(kap, dsum, v);
-      const T vr = lane_from_right(vn);
-      Vc[k] = vn;
-      PXc[k] = fma(kick_h, vr - vn, px);
-      PYc[k] = fma(kick_h, vn - Vp[k], pyrm1);
-      CCc[k] = kap;
-    } else {
-      const T vA = Vc[k - 1], vB = Vp[k - 1], pxB = PXp[k - 1], pyB = PYc[k - 1];
-      const T kB = CCp[k - 1];
-      const T wBr = lane_from_right(vB);
-      const T pxn = fma(-dth, wBr - vB, pxB);
-      const T pyn = fma(-dth, vA - vB, pyB);
-      const T pl = lane_from_left(pxn);
-      Vc[k] = fma(lastk ? T(-0.5) * kB : -kB, (pxn - pl) + (pyn - HOLD[k]), vB);
-      PXc[k] = pxn;
-      PYc[k] = HOLD[k];
-      HOLD[k] = pyn;
-      CCc[k] = kB;
     }
+    if (ADJ && lastk) {
+      Vc[k] = fma(T(0.5) * kap, dsum, v);
+      PXc[k] = -px;
+      PYc[k] = -pyrm1;
+      CCc[k] = kap;
+      continue;
+    }
+    const T kick_h = (!ADJ && lastk) ? hdth : dth;
+    const T vn = fma(kap, dsum, v);
+    const T vr = lane_from_right(vn);
+    Vc[k] = vn;
+    PXc[k] = fma(kick_h, vr - vn, px);
+    PYc[k] = fma(kick_h, vn - Vp[k], pyrm1);
+    CCc[k] = kap;
   }
   // row ro = j - K: Px and v; row ro - 1: Py (its upper face is complete only now)
   unsigned voA, soA, voB, soB;
@@ -420,15 +429,14 @@ __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> 
   io.vo_st = (lane >= H && lane < 64 - H) ? io.vo : kBufDrop;
   T Va[K + 1], PXa[K + 1], PYa[K + 1], CCa[K + 1];
   T Vb[K + 1], PXb[K + 1], PYb[K + 1], CCb[K + 1];
-  T HOLD[K + 1];
+  T HOLD0 = T(0);
 #pragma unroll
   for (int k = 0; k <= K; ++k) {
     Va[k] = PXa[k] = PYa[k] = CCa[k] = T(0);
     Vb[k] = PXb[k] = PYb[k] = CCb[k] = T(0);
-    HOLD[k] = T(0);
   }
   const int jstart = s0 - K - 2, jend = s1 + K;
-  buf_ld(HOLD[0], io.in, io.vo, (unsigned)(jstart - 1) * io.pitchb + io.fsb);
+  buf_ld(HOLD0, io.in, io.vo, (unsigned)(jstart - 1) * io.pitchb + io.fsb);
   // level-0 inputs of a row iteration (and the subtrahend of the rows it stores), loaded one
   // iteration ahead of their use
   struct RowIn {
@@ -463,18 +471,18 @@ __device__ __forceinline__ void f1_stream_fast(const F1Geom &g, const F1Ptrs<T> 
     if (pinned) __builtin_amdgcn_sched_barrier(0);
     f1_fast_row<T, K, ADJ, FIRST, SUB, FORCED>(io, L, j, s0, s1, dth, hdth, has_fim, x0.v, x0.px,
                                                x0.py, x0.cc, x0.sa, x0.sb, x0.sc, Va, PXa, PYa,
-                                               CCa, Vb, PXb, PYb, CCb, HOLD);
+                                               CCa, Vb, PXb, PYb, CCb, HOLD0);
     const RowIn x1 = A;
     if (pinned || j + 2 <= jend) load_row(j + 2, A);
     if (pinned) __builtin_amdgcn_sched_barrier(0);
     f1_fast_row<T, K, ADJ, FIRST, SUB, FORCED>(io, L, j + 1, s0, s1, dth, hdth, has_fim, x1.v,
                                                x1.px, x1.py, x1.cc, x1.sa, x1.sb, x1.sc, Vb, PXb,
-                                               PYb, CCb, Va, PXa, PYa, CCa, HOLD);
+                                               PYb, CCb, Va, PXa, PYa, CCa, HOLD0);
   }
   if (j <= jend)
     f1_fast_row<T, K, ADJ, FIRST, SUB, FORCED>(io, L, j, s0, s1, dth, hdth, has_fim, A.v, A.px,
                                                A.py, A.cc, A.sa, A.sb, A.sc, Va, PXa, PYa, CCa, Vb,
-                                               PXb, PYb, CCb, HOLD);
+                                               PXb, PYb, CCb, HOLD0);
 }
 
 // Which fast variants a kernel instance holds.  The first and last launches of a period, and
@@ -592,27 +600,22 @@ hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hi
   const char *gen = std::getenv("CMCG_F1_GENERAL");
   F1Launch Lx = L;
   Lx.general = (gen && gen[0] == '1') ? 1 : 0;
-  const bool ends = L.first || p.sub;
-#define CMCG_F1_LAUNCH(MASK, SET)                                                              \
-  hipLaunchKernelGGL((f1_stream_kernel<T, K, ADJ, MASK, SET>), grid, dim3(kThreads), 0, s, g, p, \
+  // A backward launch between its period's first and last is a forward homogeneous launch in
+  // the variables (Q, u) = (-p, v / (1 + gamma)), so it runs the forward middle instance.
+  const bool ends = ADJ ? (L.first || L.last) : (L.first || p.sub);
+#define CMCG_F1_LAUNCH(DIR, MASK, SET)                                                         \
+  hipLaunchKernelGGL((f1_stream_kernel<T, K, DIR, MASK, SET>), grid, dim3(kThreads), 0, s, g, p, \
                      Lx, band)
-  bool done = false;
-  if constexpr (!ADJ) {
+  if (!ADJ && L.forced) {
     // forced (forward) periods: every launch of the period runs the instance with the source
-    if (L.forced) {
-      if (g.mask) CMCG_F1_LAUNCH(true, kFastForced);
-      else CMCG_F1_LAUNCH(false, kFastForced);
-      done = true;
-    }
-  }
-  if (!done) {
-    if (g.mask) {
-      if (ends) CMCG_F1_LAUNCH(true, kFastEnds);
-      else CMCG_F1_LAUNCH(true, kFastMiddle);
-    } else {
-      if (ends) CMCG_F1_LAUNCH(false, kFastEnds);
-      else CMCG_F1_LAUNCH(false, kFastMiddle);
-    }
+    if (g.mask) CMCG_F1_LAUNCH(false, true, kFastForced);
+    else CMCG_F1_LAUNCH(false, false, kFastForced);
+  } else if (ends) {
+    if (g.mask) CMCG_F1_LAUNCH(ADJ, true, kFastEnds);
+    else CMCG_F1_LAUNCH(ADJ, false, kFastEnds);
+  } else {
+    if (g.mask) CMCG_F1_LAUNCH(false, true, kFastMiddle);
+    else CMCG_F1_LAUNCH(false, false, kFastMiddle);
   }
 #undef CMCG_F1_LAUNCH
   return hipGetLastError();
@@ -621,8 +624,9 @@ hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hi
 template <typename T, int K, bool ADJ>
 hipError_t launch_multi_k(int set, const F1SlotLaunch<T> *slots, int nslots, int blocks,
                           hipStream_t s) {
+  // backward middle launches are forward homogeneous launches in (Q, u)
   if (set == kFastMiddle)
-    hipLaunchKernelGGL((f1_multi_kernel<T, K, ADJ, kFastMiddle>), dim3(blocks), dim3(kThreads), 0,
+    hipLaunchKernelGGL((f1_multi_kernel<T, K, false, kFastMiddle>), dim3(blocks), dim3(kThreads), 0,
                        s, slots, nslots);
   else if (set == kFastEnds)
     hipLaunchKernelGGL((f1_multi_kernel<T, K, ADJ, kFastEnds>), dim3(blocks), dim3(kThreads), 0, s,
@@ -827,12 +831,15 @@ inline int grid_for(size_t n, int threads = 256) {
 
 }  // namespace
 
+#if CMCG_F1_FP32
 hipError_t finalize(const double *partials, int n, double *scalars, int mode, int slot,
                     hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, n, scalars,
                      mode, slot);
   return hipGetLastError();
 }
+
+#endif
 
 template <typename T>
 hipError_t f1_forward_launch(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, int kmax,
@@ -845,9 +852,11 @@ hipError_t f1_adjoint_launch(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch
   return launch_dispatch<T, true>(g, p, L, kmax, s);
 }
 
-int f1_fast_set(const F1Launch &L, bool has_sub) {
+#if CMCG_F1_FP32
+int f1_fast_set(const F1Launch &L, bool has_sub, bool adjoint) {
   if (L.forced) return kFastForced;   // forward periods only: the backward one has no source
-  return (L.first || has_sub) ? kFastEnds : kFastMiddle;
+  const bool ends = adjoint ? (L.first || L.last) : (L.first || has_sub);
+  return ends ? kFastEnds : kFastMiddle;
 }
 
 void f1_launch_shape(int nx, int ny, int K, int *nbx, int *nby, int *band) {
@@ -857,6 +866,8 @@ void f1_launch_shape(int nx, int ny, int K, int *nbx, int *nby, int *band) {
   *nbx = (strips + 3) / 4;
   *nby = (ny + *band - 1) / *band;
 }
+
+#endif
 
 template <typename T>
 hipError_t f1_multi_launch(int K, bool adjoint, int set, const F1SlotLaunch<T> *slots,
@@ -917,12 +928,10 @@ hipError_t f1_pack(const F1Geom &g, const T *dev, double *packed, size_t fs, hip
 }
 
 // explicit instantiations
+#if CMCG_F1_FP32
 template hipError_t f1_multi_launch<float>(int, bool, int, const F1SlotLaunch<float> *, int, int, hipStream_t);
-template hipError_t f1_multi_launch<double>(int, bool, int, const F1SlotLaunch<double> *, int, int, hipStream_t);
 template hipError_t f1_forward_launch<float>(const F1Geom &, const F1Ptrs<float> &, const F1Launch &, int, hipStream_t);
-template hipError_t f1_forward_launch<double>(const F1Geom &, const F1Ptrs<double> &, const F1Launch &, int, hipStream_t);
 template hipError_t f1_adjoint_launch<float>(const F1Geom &, const F1Ptrs<float> &, const F1Launch &, int, hipStream_t);
-template hipError_t f1_adjoint_launch<double>(const F1Geom &, const F1Ptrs<double> &, const F1Launch &, int, hipStream_t);
 template hipError_t f1_dot<float, float>(const F1Geom &, const float *, const float *, const void *, int, size_t, double *, hipStream_t);
 template hipError_t f1_dot<double, double>(const F1Geom &, const double *, const double *, const void *, int, size_t, double *, hipStream_t);
 template hipError_t f1_dot<double, float>(const F1Geom &, const double *, const float *, const void *, int, size_t, double *, hipStream_t);
@@ -938,5 +947,11 @@ template hipError_t f1_unpack<float>(const F1Geom &, const double *, float *, si
 template hipError_t f1_unpack<double>(const F1Geom &, const double *, double *, size_t, hipStream_t);
 template hipError_t f1_pack<float>(const F1Geom &, const float *, double *, size_t, hipStream_t);
 template hipError_t f1_pack<double>(const F1Geom &, const double *, double *, size_t, hipStream_t);
+#endif
+#if CMCG_F1_FP64
+template hipError_t f1_multi_launch<double>(int, bool, int, const F1SlotLaunch<double> *, int, int, hipStream_t);
+template hipError_t f1_forward_launch<double>(const F1Geom &, const F1Ptrs<double> &, const F1Launch &, int, hipStream_t);
+template hipError_t f1_adjoint_launch<double>(const F1Geom &, const F1Ptrs<double> &, const F1Launch &, int, hipStream_t);
+#endif
 
 }  // namespace cmcg

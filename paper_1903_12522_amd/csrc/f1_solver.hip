@@ -211,6 +211,8 @@ class F1Solver final : public Solver {
   hipStream_t s = nullptr;
   DeviceArena arena;
   PhaseEvents ev;
+  BulkTimer bulk;
+  int bulk_dir = -1;     // >= 0: time the bulk launches of the next periods in this direction
   F1Set lo, hi;          // lo: precision of the CG periods; hi: FP64 (the same set in FP64 mode)
   bool mixed = false;
   void *D = nullptr;     // search direction, lo precision
@@ -255,6 +257,7 @@ class F1Solver final : public Solver {
     const int J = (int)shots.size();
     multi = J > 1;
     CMCG_TRY(ev.init(10));
+    CMCG_TRY(bulk.init());
     CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
     std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
     bool has_im = false;
@@ -481,11 +484,15 @@ class F1Solver final : public Solver {
     const int K = (filter || (multi && forced)) ? 1 : cfg.kblock;
     if (multi && filter && !std::is_same<T, double>::value)
       return set_error("the filter period runs in FP64"), CMCG_EINVAL;
+    long long mids = 0;
     for (int n0 = 0; n0 < steps;) {
       F1Ptrs<T> p;
       F1Launch L;
       const int ns = build_launch<T>(b, forced, in, out, sub, steps, n0, K, filter, &p, &L);
       dram += launch_bytes<T>(p, L);
+      // the bulk of a period: its launches between the first and the last, all of K steps
+      const bool mid = bulk_dir >= 0 && !L.first && !L.last;
+      if (mid && mids == 0) CMCG_TRY(bulk.begin(bulk_dir, s));
       if (multi && forced) {
         hipLaunchKernelGGL((f1_combine_kernel<T>), dim3(grid_for(fs)), dim3(256), 0, s,
                            tpc<T>(b.Fre), tpc<T>(b.Fim), shot_weights(n0, true), tp<T>(b.Fk),
@@ -501,6 +508,10 @@ class F1Solver final : public Solver {
         CMCG_HIP(hipGetLastError());
       }
       CMCG_HIP(adjoint ? f1_adjoint_launch<T>(g, p, L, K, s) : f1_forward_launch<T>(g, p, L, K, s));
+      if (mid) {
+        ++mids;
+        if (steps - (n0 + ns) <= K) CMCG_TRY(bulk.end(bulk_dir, mids, s));   // next is the last
+      }
       n0 += ns;
     }
     updates += (double)steps * g.nx * g.ny;
@@ -569,6 +580,7 @@ class F1Solver final : public Solver {
     t_fwd = t_adj = t_other = t_total = t_runup = 0.0;
     updates = 0;
     dram = 0;
+    bulk.reset();
     iter = refreshes = last_refresh = runup_done = 0;
     CMCG_HIP(hipEventRecord(ev[0], s));
     // Steps 1-4: z = 0, gradient, r = d = gradient (the Riesz map M_E^{-1} is built into E*)
@@ -606,9 +618,13 @@ class F1Solver final : public Solver {
     for (int it = 0; it < iters && !*converged; ++it) {
       CMCG_HIP(hipEventRecord(ev[2], s));
       // Step 5.1: w = E d - d (forward), q = E* w - w (backward)
-      CMCG_TRY(period(lo, false, false, D, lo.W, D, cfg.N, false));
+      bulk_dir = 0;
+      cmcg_status st = period(lo, false, false, D, lo.W, D, cfg.N, false);
       CMCG_HIP(hipEventRecord(ev[3], s));
-      CMCG_TRY(period(lo, true, false, lo.W, lo.Q, lo.W, cfg.N, false));
+      bulk_dir = 1;
+      if (st == CMCG_OK) st = period(lo, true, false, lo.W, lo.Q, lo.W, cfg.N, false);
+      bulk_dir = -1;
+      CMCG_TRY(st);
       CMCG_HIP(hipEventRecord(ev[4], s));
       // Step 5.3: alpha = delta / <q, d>_E
       CMCG_TRY(dot_to(lo, lo.Q, D, kFinAlpha));
@@ -622,6 +638,7 @@ class F1Solver final : public Solver {
       CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinBeta, 0, s));
       CMCG_HIP(hipEventRecord(ev[5], s));
       CMCG_TRY(read_scalars());
+      bulk.collect();
       t_fwd += PhaseEvents::seconds(ev[2], ev[3]);
       t_adj += PhaseEvents::seconds(ev[3], ev[4]);
       t_other += PhaseEvents::seconds(ev[4], ev[5]);
@@ -786,6 +803,11 @@ class F1Solver final : public Solver {
     r->grid_updates = updates;
     r->dram_bytes = dram;
     r->riesz_iterations = 0;
+    r->riesz_unconverged = 0;
+    r->seconds_bulk_fwd = bulk.seconds[0];
+    r->seconds_bulk_adj = bulk.seconds[1];
+    r->bulk_launches_fwd = bulk.launches[0];
+    r->bulk_launches_adj = bulk.launches[1];
     r->fp64_refreshes = refreshes;
     r->runup_periods = runup_done;
     r->seconds_runup = t_runup;
@@ -1022,7 +1044,9 @@ class F1Server final : public Server {
       int nby;
       f1_launch_shape(S->g.nx, S->g.ny, ns, &d.nbx, &nby, &d.band);
       d.nblocks = d.nbx * nby;
-      groups[{adj ? 1 : 0, ns, f1_fast_set(d.L, d.p.sub != nullptr)}].push_back(d);
+      const int set = f1_fast_set(d.L, d.p.sub != nullptr, adj);
+      // backward middle launches run the forward middle instance: one group with the forward
+      groups[{(adj && set != 0) ? 1 : 0, ns, set}].push_back(d);
       R->n0 += ns;
       const double u = (double)ns * S->g.nx * S->g.ny;
       S->updates += u;
@@ -1132,6 +1156,8 @@ class F1Server final : public Server {
         R->converged = true;
         return enter_filter(R);
       }
+      // a refresh may fall on the last allowed iteration, as in the single-solve loop
+      if (S->iter >= S->cfg.max_iter) return enter_filter(R);
       return direction(R);
     }
     if (pend == 2) {
@@ -1246,14 +1272,18 @@ class F1Server final : public Server {
     if (it == reqs.end()) return set_error("unknown request id"), CMCG_EINVAL;
     ServeRequest *R = it->second;
     *state = R->state;
+    if (R->state != 2 && R->state != -1) return CMCG_OK;
+    // a finished request is handed over once: its result, copied inputs and id are released
     if (R->state == 2) {
       if (u_re) std::memcpy(u_re, R->ure.data(), R->ure.size() * sizeof(double));
       if (u_im) std::memcpy(u_im, R->uim.data(), R->uim.size() * sizeof(double));
       if (rep) *rep = R->rep;
-      return R->status;
     }
-    if (R->state == -1) return R->status;
-    return CMCG_OK;
+    const cmcg_status st = R->status;
+    delete R->S;
+    delete R;
+    reqs.erase(it);
+    return st;
   }
 
   void stats(int64_t *used_bytes, int *n_active, int *n_queued) const override {

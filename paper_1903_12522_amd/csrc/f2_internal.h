@@ -136,6 +136,8 @@ class RieszMGT {
   cmcg_status build(const F2Geom &fine, DeviceArena &arena, hipStream_t s);
   // x = S^{-1} b (x: FP64 fine-level field; b: fine-level field in FP64, or FP32 if b_is_float;
   // x may not alias b).  *iters receives the number of PCG iterations.  FP64 hierarchy only.
+  // Returns CMCG_ENOTCONV when max_iter iterations did not reach the relative tolerance (x is
+  // then the last iterate).
   cmcg_status solve(const void *b, int b_is_float, double *x, double tol, int max_iter, int *iters);
   // x = Pi B Pi b for an FP64 or FP32 right-hand side (Pi: zero-sum projection when S is
   // singular): the fixed symmetric V-cycle used in place of S^{-1}; x is FP64

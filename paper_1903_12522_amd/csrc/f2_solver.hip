@@ -174,6 +174,8 @@ class F2Solver final : public Solver {
   hipStream_t s = nullptr;
   DeviceArena arena;
   PhaseEvents ev;
+  BulkTimer bulk;
+  int bulk_dir = -1;   // >= 0: time the full-depth blocked launches in this direction
   F2Set lo, hi;
   bool mixed = false;
   uint8_t *mask = nullptr;
@@ -197,6 +199,7 @@ class F2Solver final : public Solver {
   bool started = false;
   int iter = 0, refreshes = 0;
   long long riesz_iters = 0;
+  int riesz_unconverged = 0;   // Riesz PCG solves that stopped at riesz_max_iter above riesz_tol
   double rel = 1.0, delta_at_refresh = 0.0;
   double riesz_tol = 1e-10;
   int riesz_max = 500;
@@ -248,6 +251,7 @@ class F2Solver final : public Solver {
     riesz_tol = cfg.riesz_tol > 0 ? cfg.riesz_tol : 1e-10;
     riesz_max = cfg.riesz_max_iter > 0 ? cfg.riesz_max_iter : 500;
     CMCG_TRY(ev.init(12));
+    CMCG_TRY(bulk.init());
     CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
     std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
     const size_t nn = (size_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
@@ -433,6 +437,7 @@ class F2Solver final : public Solver {
         if (pool[k] != x && pool[k] != y && pool[k] != z) return pool[k];
       return nullptr;
     };
+    long long full = 0;   // blocked launches of full depth so far (the bulk of the period)
     while (count > 0) {
       const int K = (b.D && kstep > 1 && count >= 2) ? std::min(kstep, count) : 1;
       if (K >= 2) {
@@ -440,7 +445,13 @@ class F2Solver final : public Solver {
         T *okm1 = pick(cur, prev, ok);
         if (!ok || !okm1) return set_error("blocked march: no free buffer"), CMCG_EDEVICE;
         dram += fields_bytes<T>(4, tpc<T>(b.lam));
+        const bool timed = bulk_dir >= 0 && K == kstep;
+        if (timed && full == 0) CMCG_TRY(bulk.begin(bulk_dir, s));
         CMCG_HIP(f2_march_block<T>(g, cur, prev, tpc<T>(b.lam), ok, okm1, K, s));
+        if (timed) {
+          ++full;
+          if (count - K < kstep) CMCG_TRY(bulk.end(bulk_dir, full, s));   // the last full one
+        }
         cur = ok;
         prev = okm1;
       } else {
@@ -684,7 +695,9 @@ class F2Solver final : public Solver {
                       : mg.apply_vcycle(qh_u, is_float, out));
       it = 1;
     } else {
-      CMCG_TRY(mg.solve(qh_u, is_float, out, riesz_tol, riesz_max, &it));
+      const cmcg_status st = mg.solve(qh_u, is_float, out, riesz_tol, riesz_max, &it);
+      if (st < 0) return st;
+      if (st == CMCG_ENOTCONV) ++riesz_unconverged;
     }
     CMCG_HIP(hipEventRecord(ev[9], s));
     CMCG_HIP(hipEventSynchronize(ev[9]));
@@ -744,6 +757,8 @@ class F2Solver final : public Solver {
     dram = 0;
     iter = refreshes = runup_done = 0;
     riesz_iters = 0;
+    riesz_unconverged = 0;
+    bulk.reset();
     CMCG_HIP(hipEventRecord(ev[0], s));
     CMCG_HIP(hipMemsetAsync(Z, 0, 2 * g.fs * sizeof(double), s));
     CMCG_TRY(true_gradient(kFinStart));
@@ -778,10 +793,14 @@ class F2Solver final : public Solver {
     for (int it = 0; it < iters && !*converged; ++it) {
       CMCG_HIP(hipEventRecord(ev[2], s));
       // Step 5.1: w = E d - d, y = M_E w, qh = E^T y - y
-      CMCG_TRY(fwd(lo, false, D, lo.W, D, false));
-      CMCG_TRY(metric(lo, lo.W, lo.Y));
+      bulk_dir = 0;
+      cmcg_status st = fwd(lo, false, D, lo.W, D, false);
+      if (st == CMCG_OK) st = metric(lo, lo.W, lo.Y);
       CMCG_HIP(hipEventRecord(ev[3], s));
-      CMCG_TRY(adj(lo, lo.Y, lo.W, lo.Y));
+      bulk_dir = 1;
+      if (st == CMCG_OK) st = adj(lo, lo.Y, lo.W, lo.Y);
+      bulk_dir = -1;
+      CMCG_TRY(st);
       CMCG_HIP(hipEventRecord(ev[4], s));
       // Step 5.2: q_u = S^{-1} qh_u (q_v = M^{-1} qh_v is applied on the fly)
       const float *qu32 = nullptr;
@@ -810,6 +829,7 @@ class F2Solver final : public Solver {
       CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinBeta, 0, s));
       CMCG_HIP(hipEventRecord(ev[6], s));
       CMCG_TRY(read_scalars());
+      bulk.collect();
       t_fwd += PhaseEvents::seconds(ev[2], ev[3]);
       t_adj += PhaseEvents::seconds(ev[3], ev[4]);
       t_other += PhaseEvents::seconds(ev[5], ev[6]);
@@ -922,7 +942,8 @@ class F2Solver final : public Solver {
     CMCG_TRY(finish(u_re, u_im));
     t_other += PhaseEvents::seconds(ev[6], ev[7]);
     t_total = PhaseEvents::seconds(ev[0], ev[7]);
-    return conv ? CMCG_OK : CMCG_ENOTCONV;
+    // an inexact Riesz map changes the operator CG works with: not a converged solve
+    return (conv && riesz_unconverged == 0) ? CMCG_OK : CMCG_ENOTCONV;
   }
 
   // ------------------------------------------------------------------ stage calls
@@ -939,13 +960,14 @@ class F2Solver final : public Solver {
     } else {
       // P y = (S^{-1} y_u, M^{-1} y_v), FP64
       CMCG_HIP(f2_unpack<double>(g, in, tp<double>(hi.Y), 2, s));
+      const int unconv0 = riesz_unconverged;
       CMCG_TRY(riesz_u(hi.Y, 0, QU));
       CMCG_HIP(f2_mass_inverse<double>(g, tp<double>(hi.Y) + g.fs, tp<double>(hi.W) + g.fs,
                                        tpc<double>(hi.lam), s));
       CMCG_HIP(hipMemcpyAsync(hi.W, QU, g.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
       CMCG_HIP(f2_pack<double>(g, tp<double>(hi.W), out, 2, s));
       CMCG_HIP(hipStreamSynchronize(s));
-      return CMCG_OK;
+      return riesz_unconverged > unconv0 ? CMCG_ENOTCONV : CMCG_OK;
     }
     if (lo.prec == CMCG_FP64) CMCG_HIP(f2_pack<double>(g, tp<double>(lo.W), out, 2, s));
     else CMCG_HIP(f2_pack<float>(g, tp<float>(lo.W), out, 2, s));
@@ -1014,6 +1036,11 @@ class F2Solver final : public Solver {
     r->grid_updates = updates;
     r->dram_bytes = dram;
     r->riesz_iterations = riesz_iters;
+    r->riesz_unconverged = riesz_unconverged;
+    r->seconds_bulk_fwd = bulk.seconds[0];
+    r->seconds_bulk_adj = bulk.seconds[1];
+    r->bulk_launches_fwd = bulk.launches[0];
+    r->bulk_launches_adj = bulk.launches[1];
     r->fp64_refreshes = refreshes;
     r->runup_periods = runup_done;
     r->seconds_runup = t_runup;

@@ -516,6 +516,7 @@ cmcg_status RieszMGT<T>::solve(const void *b, int b_is_float, double *x, double 
   CMCG_HIP(hipMemcpyAsync(pp_, pz_, n * sizeof(double), hipMemcpyDeviceToDevice, s_));
   double rz = 0.0;
   CMCG_TRY(dot(pr_, pz_, n, &rz));
+  bool met = false;
   for (int it = 1; it <= max_iter; ++it) {
     CMCG_HIP(mg_sweep<T>(kMGApply, rows_, chunk_, g, pp_, nullptr, pq_, 0.0, s_));
     double pq = 0.0;
@@ -527,7 +528,10 @@ cmcg_status RieszMGT<T>::solve(const void *b, int b_is_float, double *x, double 
     *iters = it;
     double rr = 0.0;
     CMCG_TRY(dot(pr_, pr_, n, &rr));
-    if (rr <= tol * tol * bb) break;
+    if (rr <= tol * tol * bb) {
+      met = true;
+      break;
+    }
     CMCG_TRY(vcycle(pr_, pz_));
     double rz2 = 0.0;
     CMCG_TRY(dot(pr_, pz_, n, &rz2));
@@ -536,7 +540,7 @@ cmcg_status RieszMGT<T>::solve(const void *b, int b_is_float, double *x, double 
     rz = rz2;
   }
   if (neumann_) CMCG_TRY(project(x, 0));
-  return CMCG_OK;
+  return met ? CMCG_OK : CMCG_ENOTCONV;
 }
 
 template class RieszMGT<double>;

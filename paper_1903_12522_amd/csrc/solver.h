@@ -100,6 +100,56 @@ class PhaseEvents {
   std::vector<hipEvent_t> ev_;
 };
 
+// Device time of the bulk launches of the CG iterations' periods, per direction (0 forward,
+// 1 backward): one event before the first and one after the last of a period's consecutive run
+// of them, read once the stream has synchronised.  The bulk launches run one kernel instance
+// (first order: the launches between a period's first and last; second order: the blocked
+// launches of full depth), so their mean is that instance's own launch time.
+class BulkTimer {
+ public:
+  ~BulkTimer() {
+    for (auto &d : ev_)
+      for (auto &e : d)
+        if (e) (void)hipEventDestroy(e);
+  }
+  cmcg_status init() {
+    for (auto &d : ev_)
+      for (auto &e : d) CMCG_HIP(hipEventCreate(&e));
+    return CMCG_OK;
+  }
+  void reset() {
+    for (int d = 0; d < 2; ++d) {
+      seconds[d] = 0.0;
+      launches[d] = 0;
+      pending_[d] = 0;
+    }
+  }
+  cmcg_status begin(int dir, hipStream_t s) {
+    CMCG_HIP(hipEventRecord(ev_[dir][0], s));
+    return CMCG_OK;
+  }
+  cmcg_status end(int dir, long long n, hipStream_t s) {
+    CMCG_HIP(hipEventRecord(ev_[dir][1], s));
+    pending_[dir] = n;
+    return CMCG_OK;
+  }
+  // after the stream has synchronised
+  void collect() {
+    for (int d = 0; d < 2; ++d) {
+      if (!pending_[d]) continue;
+      seconds[d] += PhaseEvents::seconds(ev_[d][0], ev_[d][1]);
+      launches[d] += pending_[d];
+      pending_[d] = 0;
+    }
+  }
+  double seconds[2] = {0.0, 0.0};
+  long long launches[2] = {0, 0};
+
+ private:
+  hipEvent_t ev_[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  long long pending_[2] = {0, 0};
+};
+
 class Solver {
  public:
   virtual ~Solver() {}

@@ -35,7 +35,7 @@ def _mixed_problem(nx=70, ny=37, seed=3):
                    face_bc=(0, 0, 0, 1), courant=0.5, name="mixed")
 
 
-@pytest.mark.parametrize("kblock", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("kblock", [1, 2, 3, 4, 6, 7, 8])
 def test_periods_match_oracle_fp64(cm, kblock):
     prob = _mixed_problem()
     o = F1(prob)
@@ -275,6 +275,55 @@ def test_full_size_period_sampled(cm, c2, prec, tol):
         if ci0 < nx - 1:
             sp = np.max(np.abs(Pxs)) + 1e-300
             assert abs(Pxo[cj0, ci0] - Pxs[cj0 - j0, ci0 - i0]) <= tol * sp
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_full_size_homogeneous_periods_sampled(cm, c2, prec, tol):
+    """The homogeneous forward period E z and the backward period E* z = M_E^{-1} E^T M_E z on the
+    full 4096^2 grid, in the default launch configuration (K = 7, 32-row bands: every launch
+    between a period's first and last, forward or backward, runs the forward middle instance),
+    checked at sampled cells against the oracle on windows of radius N + 2 around each sample.
+    The samples include corners, edges, band and strip boundaries and the interior."""
+    prob = c2
+    n = prob.n[0]
+    ny = nx = n
+    sizes = [ny * (nx - 1), (ny - 1) * nx, ny * nx]
+    with cm.Solver(prob, prec) as s:
+        N = s.info["steps_per_period"]
+        assert N == 164 and s.info["steps_per_launch"] == 7
+        z = np.random.default_rng(23).standard_normal(sum(sizes))
+        outf = s.apply(cm.OP_FORWARD, z)
+        outa = s.apply(cm.OP_ADJOINT, z)
+
+    def fields(x):
+        return (x[: sizes[0]].reshape(ny, nx - 1),
+                x[sizes[0]: sizes[0] + sizes[1]].reshape(ny - 1, nx),
+                x[sizes[0] + sizes[1]:].reshape(ny, nx))
+
+    Px, Py, v = fields(z)
+    samples = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny // 2 + 13), (nx // 2, 0),
+               (2047, 2048), (48 * 40, 32 * 50 + 31), (48 * 61 - 1, 32 * 77), (1000, 3100)]
+    m = N + 2
+    for (ci0, cj0) in samples:
+        i0, i1 = max(0, ci0 - m), min(nx, ci0 + m + 1)
+        j0, j1 = max(0, cj0 - m), min(ny, cj0 + m + 1)
+        sub = F1(window(prob, i0, i1, j0, j1), N=N)
+        zs = sub.pack(Px[j0:j1, i0:i1 - 1], Py[j0:j1 - 1, i0:i1], v[j0:j1, i0:i1])
+        w = sub.weights()
+        refs = {"forward": (outf, sub.period(zs, False)),
+                "backward": (outa, sub.period_T(w * zs) / w)}
+        for name, (full, ref) in refs.items():
+            Pxo, Pyo, vo = fields(full)
+            Pxs, Pys, vs = sub.unpack(ref)
+            li, lj = ci0 - i0, cj0 - j0
+            sv = np.max(np.abs(vs)) + 1e-300
+            assert abs(vo[cj0, ci0] - vs[lj, li]) <= tol * sv, (name, ci0, cj0)
+            if ci0 < nx - 1:
+                sp = np.max(np.abs(Pxs)) + 1e-300
+                assert abs(Pxo[cj0, ci0] - Pxs[lj, li]) <= tol * sp, (name, ci0, cj0)
+            if cj0 < ny - 1:
+                sp = np.max(np.abs(Pys)) + 1e-300
+                assert abs(Pyo[cj0, ci0] - Pys[lj, li]) <= tol * sp, (name, ci0, cj0)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2 * 164 * 6e-8)])

@@ -125,6 +125,27 @@ def test_periods_match_oracle_fp64(cm, masked):
         assert _rel(s.apply(cm.OP_RIESZ, y), o.riesz(y)) < 1e-8
 
 
+def test_riesz_solve_at_its_iteration_cap_is_reported(cm):
+    """A Riesz PCG solve that stops at riesz_max_iter above riesz_tol is not passed off as
+    exact: cmcg_apply(OP_RIESZ) returns CMCG_ENOTCONV, the solve counts it in the report and
+    returns CMCG_ENOTCONV; with the default cap nothing is flagged."""
+    prob = ci.inclusions_3d(n=16, freq=1.5, n_incl=4, seed=9, width=0.12, r_range=(0.1, 0.25))
+    o = F2(prob)
+    y = np.random.default_rng(3).standard_normal(o.size)
+    y[: o.nn] -= y[: o.nn].mean()
+    with cm.Solver(prob, "fp64", tol=1e-6, max_iter=50, riesz_mode="solve", riesz_tol=1e-12,
+                   riesz_max_iter=1) as s:
+        s.apply(cm.OP_RIESZ, y)
+        assert s.last_status == cm.ENOTCONV
+        _, rep = s.solve()
+        assert rep["riesz_unconverged"] > 0 and not rep["converged"]
+    with cm.Solver(prob, "fp64", tol=1e-6, max_iter=2000, riesz_mode="solve") as s:
+        s.apply(cm.OP_RIESZ, y)
+        assert s.last_status == cm.OK
+        _, rep = s.solve()
+        assert rep["riesz_unconverged"] == 0 and rep["converged"]
+
+
 def test_periods_fp32_within_rounding(cm):
     prob = _mixed3d(n=(70, 9, 8), seed=4)
     o = F2(prob)

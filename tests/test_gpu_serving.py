@@ -122,3 +122,27 @@ def test_mini_workload_real_time(cm):
     assert summ["completed"] == 12 and summ["converged"] == 12
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
     assert summ["peak_active"] >= 2
+
+
+def test_served_solve_stops_at_max_iter_after_refresh(cm):
+    """A refresh on the last allowed iteration ends the served solve there (not converged), as it
+    ends the single solve: same iteration count, status and result bits."""
+    prob = _req(64, 4.0, 11)
+    max_iter = 6
+    with cm.Solver(prob, "fp32", tol=1e-12, max_iter=max_iter, fp64_refresh=0.999) as s:
+        Us, reps = s.solve()
+    assert not reps["converged"] and reps["iterations"] == max_iter
+    assert reps["fp64_refreshes"] >= max_iter - 1
+    with cm.Server(8 << 30, max_slots=4) as srv:
+        rid = srv.submit(prob, precision="fp32", tol=1e-12, max_iter=max_iter,
+                         fp64_refresh=0.999)
+        for _ in range(100000):
+            srv.step()
+            state, U, rep, st = srv.poll(rid)
+            if state in (cm.REQ_DONE, cm.REQ_FAILED):
+                break
+        assert state == cm.REQ_DONE and st == cm.ENOTCONV
+        assert rep["iterations"] == max_iter and rep["fp64_refreshes"] == reps["fp64_refreshes"]
+        assert np.array_equal(U, Us)
+        # the poll that reported DONE released the request
+        assert srv.stats() == (0, 0, 0)

@@ -242,3 +242,56 @@ def test_sound_soft_cavity_small():
     Ud, _ = s.direct()
     assert np.linalg.norm(U - Ud) / np.linalg.norm(Ud) < 1e-9
     assert np.max(np.abs(U[prob.sound_soft.astype(bool)])) == 0.0
+
+
+def test_window_reproduces_full_grid_away_from_cuts():
+    """Sampled checks at full size use node windows: a period of K steps is K + 1 sweeps, so a
+    window reaching K + 2 nodes past a sample (cut sides Neumann) reproduces the full grid's
+    forward, forced and transposed periods there.  The box has random c, a sound-soft ball,
+    a source, random data on every face and mixed face types, so a wrongly sliced field, face
+    or mask changes a sampled value."""
+    from oracle.f2 import window
+    n = (26, 22, 24)
+    prob = ci.sound_soft_sphere_3d(n=24, freq=1.5, radius=0.2)
+    rng = np.random.default_rng(17)
+    shape = tuple(m + 1 for m in reversed(n))
+    prob.n = n
+    prob.spacing = 1.0 / 24
+    prob.c = 1.0 + rng.uniform(size=shape)
+    prob.sound_soft = ci.sphere_mask(n, prob.spacing, (0.55, 0.45, 0.5), 0.2)
+    prob.f = np.zeros(shape, complex)
+    prob.f[3:9, 12:18, 2:7] = rng.standard_normal((6, 6, 5)) + 1j
+    gS = []
+    for a in range(3):
+        others = [b for b in range(3) if b != a]
+        fshape = tuple(n[b] + 1 for b in reversed(others))
+        gS += [rng.standard_normal(fshape) + 1j * rng.standard_normal(fshape) for _ in range(2)]
+    prob.gS = gS
+    prob.face_bc = (0, 1, 0, 0, 1, 0)
+    K = 5
+    full = F2(prob, N=K)
+    z = rng.standard_normal(full.size) * np.concatenate([full.free.ravel()] * 2)
+    outs = {"fwd": full.period(z, False), "forced": full.period(z, True),
+            "adj": full.period_T(z)}
+    zu = z[: full.nn].reshape(full.shape)
+    zv = z[full.nn:].reshape(full.shape)
+    # samples (x, y, z): corners, faces, next to the ball, interior
+    ball = (int(round(0.55 * 24 + 0.2 * 24)) + 1, int(round(0.45 * 24)), 12)
+    samples = [(0, 0, 0), (26, 22, 24), (26, 0, 11), (0, 11, 24), ball, (8, 15, 5)]
+    m = K + 2
+    for s in samples:
+        lo = [max(0, s[a] - m) for a in range(3)]
+        hi = [min(n[a], s[a] + m) for a in range(3)]
+        sub = F2(window(prob, lo, hi), N=K)
+        assert sub.dt == full.dt
+        sl = tuple(slice(lo[a], hi[a] + 1) for a in (2, 1, 0))
+        zs = np.concatenate([zu[sl].ravel(), zv[sl].ravel()])
+        subs = {"fwd": sub.period(zs, False), "forced": sub.period(zs, True),
+                "adj": sub.period_T(zs)}
+        li = (s[2] - lo[2], s[1] - lo[1], s[0] - lo[0])
+        gi = (s[2], s[1], s[0])
+        for key in outs:
+            for part in range(2):
+                a = outs[key][part * full.nn:(part + 1) * full.nn].reshape(full.shape)[gi]
+                b = subs[key][part * sub.nn:(part + 1) * sub.nn].reshape(sub.shape)[li]
+                assert abs(a - b) <= 1e-13 * (1 + abs(a)), (key, part, s, a, b)
