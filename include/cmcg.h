@@ -270,6 +270,27 @@ cmcg_status cmcg_runup(cmcg_handle *h, int32_t periods, int32_t ramp, double *z_
  * period.  The paper's relative misfit divides sqrt(J) by ||f|| + ||g_S|| (Sec. 4.2.1). */
 cmcg_status cmcg_misfit(cmcg_handle *h, const double *z, double *J);
 
+/* ---- allocation-free stage call ----
+ * For callers that cannot allocate device memory where they call: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The operator of cmcg_apply on
+ * a first-order problem, without a handle: the library lays out the problem's coefficient and
+ * source fields and the period's working states in one fixed device buffer of
+ * CMCG_STATIC_SCRATCH_BYTES per GPU (a static device array, held until the process ends), so
+ * the call allocates nothing: no device, pinned-host, stream or event allocation.
+ * Arguments: problem and options as for cmcg_create (precision, device, steps_per_launch and
+ * hip_stream are used; NULL hip_stream runs on the null stream; tol and max_iter must be valid),
+ * then op, steps, in and out as for cmcg_apply (packed FP64 device vectors of the problem's
+ * state length; they may alias).  The result equals cmcg_apply's bit for bit.
+ * Errors: CMCG_ENOMEM, before any device work, when the problem's fields do not fit the buffer
+ * (first-order grids up to about 500 x 500 cells in FP64, 450 x 450 in FP32-mixed);
+ * CMCG_EUNSUPPORTED for second-order problems; the validation errors of cmcg_create.
+ * The buffer is shared by every call on a GPU and keeps the last call's contents; each call
+ * clears what it uses.  Calls that overlap on one GPU (other threads, or concurrently running
+ * streams) race on it.  Returns after the work on its stream has finished. */
+#define CMCG_STATIC_SCRATCH_BYTES (64ull << 20)
+cmcg_status cmcg_apply_static(const cmcg_problem *problem, const cmcg_options *opts, int32_t op,
+                              int32_t steps, const double *in, double *out);
+
 /* ---- continuous-batching server (first-order 2D solves) ----
  * Solves of different grid sizes and frequencies share the GPU: submitted requests wait in
  * arrival order until their device footprint fits the HBM budget and a slot is free; admitted

@@ -23,6 +23,7 @@ UNITS = [
     ("f2_kernels.hip", "f2_kernels.o", []),
     ("riesz_mg.hip", "riesz_mg.o", []),
     ("f2_solver.hip", "f2_solver.o", []),
+    ("static_apply.hip", "static_apply.o", []),
 ]
 
 FLAGS = [

@@ -117,6 +117,9 @@ _sig = {
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32)]),
     "cmcg_server_destroy": (None, [_H]),
+    "cmcg_apply_static": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -423,6 +426,27 @@ def make_options(precision="fp64", tol=1e-6, max_iter=1000, device=0, steps_per_
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, -1
+
+
+def apply_static(problem, op: int, z, precision: str = "fp64", steps: int = 0,
+                 steps_per_launch: int = 0, device: int = 0, out=None):
+    """cmcg_apply_static: op(z) for a first-order problem without a handle (the library keeps
+    the problem's fields in its fixed per-GPU buffer and allocates nothing).  z: a torch FP64
+    device tensor of the problem's state length.  Runs on the caller's current stream and
+    returns after it; returns `out` (a new tensor when None; it may be z itself)."""
+    import torch
+    assert z.dtype == torch.float64 and z.is_cuda and z.is_contiguous()
+    if out is None:
+        out = torch.empty_like(z)
+    assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+    assert out.numel() == z.numel()
+    p, keep = marshal_problem(problem)
+    o = make_options(precision, 1e-6, 1, device, steps_per_launch)
+    o.hip_stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    _check(_lib.cmcg_apply_static(ctypes.byref(p), ctypes.byref(o), int(op), int(steps),
+                                  ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+           "cmcg_apply_static")
+    return out
 
 
 class Server:

@@ -61,6 +61,9 @@ enum FinalMode : int {
   kFinRefresh = 4  // true residual replaced the recursive one: beta = sum / delta_before, delta = sum
 };
 
+// Clears `bytes` of device memory with a fill kernel on stream s.
+hipError_t zero_device(void *p, size_t bytes, hipStream_t s);
+
 // Launches a one-block kernel that sums `n` partials in order and applies `mode`.
 hipError_t finalize(const double *partials, int n, double *scalars, int mode, int slot,
                     hipStream_t s);

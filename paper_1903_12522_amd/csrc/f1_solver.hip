@@ -233,9 +233,14 @@ class F1Solver final : public Solver {
   // (t_tr = 0: no ramp)
   double t_offset = 0.0, t_tr = 0.0;
 
+  // fixed-buffer mode: device memory from a caller's buffer, scalars in host memory of the
+  // object, no events
+  bool fixed = false;
+  double h_scalars_local[kNumScalars] = {};
+
   ~F1Solver() override {
     if (s) (void)hipStreamSynchronize(s);
-    if (h_scalars) (void)hipHostFree(h_scalars);
+    if (h_scalars && !fixed) (void)hipHostFree(h_scalars);
   }
 
   size_t device_bytes() const override { return arena.bytes(); }
@@ -256,9 +261,13 @@ class F1Solver final : public Solver {
     const std::vector<cmcg_shot> shots = shots_of(P);
     const int J = (int)shots.size();
     multi = J > 1;
-    CMCG_TRY(ev.init(10));
-    CMCG_TRY(bulk.init());
-    CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
+    if (fixed) {
+      h_scalars = h_scalars_local;
+    } else {
+      CMCG_TRY(ev.init(10));
+      CMCG_TRY(bulk.init());
+      CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
+    }
     std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
     bool has_im = false;
     for (const cmcg_shot &sh : shots) has_im = has_im || sh.f_im || sh.gS_im;
@@ -279,7 +288,10 @@ class F1Solver final : public Solver {
     const size_t ncell = (size_t)nx * ny, nface = 2 * (size_t)ny + 2 * (size_t)nx;
     if (P->sound_soft) CMCG_TRY(setup_dirichlet(P, shots));
     for (int j = 0; j < J; ++j) {
-      DeviceArena tmp;
+      // the inputs' device copies (in fixed-buffer mode carved from the same buffer, where they
+      // stay until the solver goes)
+      DeviceArena tmp_own;
+      DeviceArena &tmp = fixed ? arena : tmp_own;
       const double *src[5] = {P->c, shots[j].f_re, shots[j].f_im, shots[j].gS_re, shots[j].gS_im};
       const size_t len[5] = {ncell, ncell, ncell, nface, nface};
       double *dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -577,6 +589,7 @@ class F1Solver final : public Solver {
   }
 
   cmcg_status begin() override {
+    if (fixed) return set_error("a fixed-buffer solver serves stage calls only"), CMCG_EUNSUPPORTED;
     t_fwd = t_adj = t_other = t_total = t_runup = 0.0;
     updates = 0;
     dram = 0;
@@ -833,6 +846,22 @@ cmcg_status make_f1_solver(const cmcg_problem *P, const SolverConfig &cfg, Solve
   *out = nullptr;
   F1Solver *S = new F1Solver();
   S->cfg = cfg;
+  cmcg_status st = S->create(P);
+  if (st != CMCG_OK) {
+    delete S;
+    return st;
+  }
+  *out = S;
+  return CMCG_OK;
+}
+
+cmcg_status make_f1_solver_in(const cmcg_problem *P, const SolverConfig &cfg, void *base,
+                              size_t cap, Solver **out) {
+  *out = nullptr;
+  F1Solver *S = new F1Solver();
+  S->cfg = cfg;
+  S->fixed = true;
+  S->arena.use_buffer(base, cap);
   cmcg_status st = S->create(P);
   if (st != CMCG_OK) {
     delete S;

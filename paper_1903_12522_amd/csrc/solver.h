@@ -40,13 +40,35 @@ inline std::vector<cmcg_shot> shots_of(const cmcg_problem *P) {
   return {s};
 }
 
-// Device allocations owned by one solver (freed in the destructor).
+// Device allocations owned by one solver (freed in the destructor).  In fixed-buffer mode
+// (use_buffer) the allocations are carved from a device buffer the caller owns: nothing is
+// allocated or freed, a request beyond the buffer fails with CMCG_ENOMEM, and every piece is
+// cleared by a fill kernel rather than a memset.
 class DeviceArena {
  public:
   ~DeviceArena() { release(); }
+  void use_buffer(void *base, size_t cap) {
+    base_ = static_cast<char *>(base);
+    cap_ = cap;
+    off_ = 0;
+  }
   cmcg_status alloc(size_t bytes, void **p, hipStream_t s) {
     *p = nullptr;
     if (bytes == 0) bytes = 8;
+    if (base_) {
+      const size_t off = (off_ + 255) / 256 * 256;
+      if (off > cap_ || bytes > cap_ - off) {
+        set_error("the problem needs more device memory than the fixed " +
+                  std::to_string(cap_ >> 20) + " MiB buffer holds (a further " +
+                  std::to_string(bytes) + " B at offset " + std::to_string(off) + ")");
+        return CMCG_ENOMEM;
+      }
+      *p = base_ + off;
+      off_ = off + bytes;
+      bytes_ += bytes;
+      CMCG_HIP(zero_device(*p, bytes, s));
+      return CMCG_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -66,12 +88,16 @@ class DeviceArena {
     for (void *p : ptrs_) (void)hipFree(p);
     ptrs_.clear();
     bytes_ = 0;
+    off_ = 0;
   }
   size_t bytes() const { return bytes_; }
+  bool fixed() const { return base_ != nullptr; }
 
  private:
   std::vector<void *> ptrs_;
   size_t bytes_ = 0;
+  char *base_ = nullptr;   // fixed-buffer mode
+  size_t cap_ = 0, off_ = 0;
 };
 
 // Phase timer: pairs of HIP events recorded on the solver's stream.
@@ -177,6 +203,11 @@ cmcg_status make_config(const cmcg_problem *P, const cmcg_options *O, hipStream_
                         SolverConfig *cfg);
 
 cmcg_status make_f1_solver(const cmcg_problem *P, const SolverConfig &cfg, Solver **out);
+// A first-order solver whose device memory is carved from [base, base + cap) (allocates
+// nothing: no device, pinned-host or event allocation; see DeviceArena::use_buffer).  Its
+// stage calls work as the ordinary solver's; the phase timers are not kept.
+cmcg_status make_f1_solver_in(const cmcg_problem *P, const SolverConfig &cfg, void *base,
+                              size_t cap, Solver **out);
 cmcg_status make_f2_solver(const cmcg_problem *P, const SolverConfig &cfg, Solver **out);
 
 // Continuous-batching request server (first-order solves).
