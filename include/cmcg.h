@@ -294,10 +294,14 @@ cmcg_status cmcg_apply_static(const cmcg_problem *problem, const cmcg_options *o
 /* ---- continuous-batching server (first-order 2D solves) ----
  * Solves of different grid sizes and frequencies share the GPU: submitted requests wait in
  * arrival order until their device footprint fits the HBM budget and a slot is free; admitted
- * requests keep their CG state resident.  Each cmcg_server_step advances every running solve by
- * one launch of leapfrog steps, with ONE batched kernel launch per (precision, direction, steps)
- * group covering all those solves' tiles, then runs the CG updates of the solves whose period
- * ended.  A solve's result does not depend on what it was batched with.  Not thread-safe. */
+ * requests keep their CG state resident.  Each cmcg_server_step (a tick) is ONE launch of a
+ * persistent kernel on a co-resident grid: it advances every running solve through rounds of
+ * its CG algorithm (Sec. 2.3, with the FP64 refreshes of FP32-mixed solves), one operation per
+ * solve per round (a launch of a period's leapfrog steps, a CG vector pass, a reduction or a
+ * decision, all taken on the device), with a grid barrier between rounds, until its work budget
+ * is spent or the solves have finished; the host then hands out finished results and admits
+ * waiting requests.  A solve's result does not depend on what it shares the GPU with: it equals
+ * the single-solve path's bit for bit.  Not thread-safe. */
 typedef struct cmcg_server cmcg_server;
 
 typedef struct {
@@ -306,6 +310,9 @@ typedef struct {
   int32_t steps_per_launch;    /* leapfrog steps per launch (0 = library default)              */
   int32_t device;
   void *hip_stream;            /* stream for all server work, or NULL                          */
+  int64_t barrier_spin_limit;  /* polls a workgroup of the serving kernel makes at a grid barrier
+                                  before it gives up (0 = default, about 16 M); a tick whose
+                                  barrier gave up fails its running solves (CMCG_EDEVICE)      */
 } cmcg_server_options;
 
 enum { CMCG_REQ_QUEUED = 0, CMCG_REQ_RUNNING = 1, CMCG_REQ_DONE = 2, CMCG_REQ_FAILED = -1 };
@@ -317,7 +324,9 @@ cmcg_status cmcg_server_create(const cmcg_server_options *opts, cmcg_server **ou
  * run-up or shots). */
 cmcg_status cmcg_server_submit(cmcg_server *s, const cmcg_problem *p, const cmcg_options *opts,
                                int64_t *id);
-/* One tick: admit what fits, advance running solves, finish converged ones.  Optional counts. */
+/* One tick: admit what fits, advance the running solves, finish those that are done.  Optional
+ * counts: *active = the solves the tick advanced (resident during it, finished ones included),
+ * *queued = the requests still waiting for admission after it. */
 cmcg_status cmcg_server_step(cmcg_server *s, int32_t *active, int32_t *queued);
 /* *state = CMCG_REQ_*; when DONE, copies the filtered solution (host arrays, layout of c) and
  * the report, and returns the solve's status (CMCG_OK or CMCG_ENOTCONV); when FAILED, returns
@@ -328,6 +337,11 @@ cmcg_status cmcg_server_poll(cmcg_server *s, int64_t id, int32_t *state, double 
 /* Device bytes held by resident solves, and the running / queued counts. */
 cmcg_status cmcg_server_stats(const cmcg_server *s, int64_t *used_bytes, int32_t *active,
                               int32_t *queued);
+/* Ticks that advanced solves, the kernel launches those ticks made (the persistent serving
+ * kernel's; the field setup of admitted requests is not counted) and the rounds those launches
+ * ran (one operation of every resident solve each). */
+cmcg_status cmcg_server_launches(const cmcg_server *s, int64_t *ticks, int64_t *launches,
+                                 int64_t *rounds);
 void cmcg_server_destroy(cmcg_server *s);   /* NULL-safe */
 
 #ifdef __cplusplus

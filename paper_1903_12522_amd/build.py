@@ -24,6 +24,7 @@ UNITS = [
     ("riesz_mg.hip", "riesz_mg.o", []),
     ("f2_solver.hip", "f2_solver.o", []),
     ("static_apply.hip", "static_apply.o", []),
+    ("f1_serve.hip", "f1_serve.o", []),
 ]
 
 FLAGS = [

@@ -82,7 +82,7 @@ class _Info(ctypes.Structure):
 class _ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
                 ("steps_per_launch", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("hip_stream", ctypes.c_void_p)]
+                ("hip_stream", ctypes.c_void_p), ("barrier_spin_limit", ctypes.c_int64)]
 
 
 _H = ctypes.c_void_p
@@ -117,6 +117,9 @@ _sig = {
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32)]),
     "cmcg_server_destroy": (None, [_H]),
+    "cmcg_server_launches": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int64)]),
     "cmcg_apply_static": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.c_void_p]),
@@ -453,13 +456,14 @@ class Server:
     """Continuous-batching server for first-order 2D solves (cmcg_server_* in include/cmcg.h)."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 16, steps_per_launch: int = 0,
-                 device: int = 0, stream=None):
+                 device: int = 0, stream=None, barrier_spin_limit: int = 0):
         import torch
         o = _ServerOptions()
         o.hbm_budget_bytes = int(hbm_budget_bytes)
         o.max_slots = int(max_slots)
         o.steps_per_launch = int(steps_per_launch)
         o.device = int(device)
+        o.barrier_spin_limit = int(barrier_spin_limit)
         self.stream = _handle_stream(torch, stream, device)
         o.hip_stream = ctypes.c_void_p(self.stream.cuda_stream)
         h = _H()
@@ -516,6 +520,13 @@ class Server:
         if state.value == REQ_DONE:
             return state.value, re + 1j * im, _report_dict(rep), st
         return state.value, None, None, st
+
+    def launches(self):
+        """(ticks that advanced solves, kernel launches those ticks made, rounds they ran)."""
+        t, n, r = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(_lib.cmcg_server_launches(self._h, ctypes.byref(t), ctypes.byref(n),
+                                         ctypes.byref(r)), "cmcg_server_launches")
+        return t.value, n.value, r.value
 
     def stats(self):
         used = ctypes.c_int64(0)

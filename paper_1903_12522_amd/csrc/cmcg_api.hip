@@ -320,8 +320,9 @@ void cmcg_server_destroy(cmcg_server *S) {
 cmcg_status cmcg_server_create(const cmcg_server_options *o, cmcg_server **out) {
   if (!o || !out) return set_error("null argument"), CMCG_EINVAL;
   *out = nullptr;
-  if (o->hbm_budget_bytes <= 0 || o->max_slots < 0 || o->steps_per_launch < 0 ||
-      o->steps_per_launch > kMaxBlockSteps)
+  if (o->hbm_budget_bytes <= 0 || o->max_slots < 0 || o->max_slots > kServeMaxSlots ||
+      o->steps_per_launch < 0 || o->steps_per_launch > kMaxBlockSteps ||
+      o->barrier_spin_limit < 0)
     return set_error("bad server options"), CMCG_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
@@ -378,6 +379,13 @@ cmcg_status cmcg_server_stats(const cmcg_server *S, int64_t *used_bytes, int32_t
   S->impl->stats(used_bytes, &a, &q);
   *active = a;
   *queued = q;
+  return CMCG_OK;
+}
+
+cmcg_status cmcg_server_launches(const cmcg_server *S, int64_t *ticks, int64_t *launches,
+                                 int64_t *rounds) {
+  if (!S || !ticks || !launches || !rounds) return set_error("null argument"), CMCG_EINVAL;
+  S->impl->counters(ticks, launches, rounds);
   return CMCG_OK;
 }
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/cmcg.h"
+#include "serve_plan.h"
 
 namespace cmcg {
 
@@ -112,25 +113,8 @@ struct F1Ptrs {
   const double *dre, *dim;   // Dirichlet data of v on the masked cells (dim may be null)
 };
 
-// One solve's share of a batched (multi-solve) launch.
-template <typename T>
-struct F1SlotLaunch {
-  F1Geom g;
-  F1Ptrs<T> p;
-  F1Launch L;
-  int band, nbx, block0, nblocks;
-};
-
 // Launch geometry of the streaming kernel for an nx x ny grid at K steps per launch.
 void f1_launch_shape(int nx, int ny, int K, int *nbx, int *nby, int *band);
-// Fast-variant set of a launch's kernel instance: 0 the launches between a period's first and
-// last (forward and backward alike: a backward middle launch is a forward homogeneous launch in
-// the backward period's variables), 1 those two, 3 every launch of a forced (forward) period.
-int f1_fast_set(const F1Launch &L, bool has_sub, bool adjoint);
-template <typename T>
-hipError_t f1_multi_launch(int K, bool adjoint, int set, const F1SlotLaunch<T> *slots, int nslots,
-                           int blocks, hipStream_t s);
-
 template <typename T>
 hipError_t f1_forward_launch(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, int kmax,
                              hipStream_t s);
@@ -147,11 +131,53 @@ hipError_t f1_cg_update(const F1Geom &g, double *z, double *r, const T *d, const
                         const void *cc, size_t fs, const double *scalars, double *partials,
                         hipStream_t s);
 
+// ---------------------------------------------------------------------------------------
+// Persistent serving kernel (continuous batching of first-order solves): one launch per
+// server tick runs rounds of every resident solve's CG operations (serve_plan.h), a grid
+// barrier between rounds; decisions are taken on the device.
+// ---------------------------------------------------------------------------------------
+constexpr int kServeMaxSlots = 64;
+
+// One resident solve: geometry, constants and buffers (written by the host at admission).
+// lo: the CG periods' precision (FP32 in FP32-mixed mode); hi: FP64.  In FP64 mode they are
+// the same buffers.
+struct ServeSlot {
+  F1Geom g;
+  size_t fs, vecN;
+  int band;            // rows per band of the streaming tiles
+  int N, K_lo, K_hi, mixed, max_iter;
+  double tol, refresh;
+  double out_scale;    // 2 / (N omega)
+  void *lo_S0, *lo_S1, *lo_W, *lo_Q, *lo_cc, *lo_Fre, *lo_Fim;
+  double *hi_S0, *hi_S1, *hi_W, *hi_Q, *hi_cc, *hi_Fre, *hi_Fim;
+  void *D;
+  double *Z, *R, *Ure, *Uim, *partials, *scalars;
+  const double *tab;   // per step n < N: cos and sin of omega t_{n+1/2}, then of omega t_n
+};
+
+// Device control block of the serving kernel.
+struct ServeControl {
+  unsigned count;        // grid barrier: arrivals of the current round ...
+  unsigned pad0[31];
+  unsigned gen;          // ... and its generation, polled on a cache line of its own
+  unsigned pad1[31];
+  int failed;            // a barrier wait gave up (spin limit or the host's abort flag)
+  int rounds;            // rounds the last launch ran
+  double work;           // grid-point updates the last launch did
+};
+
 // Generic flat-array helpers.
 template <typename TD, typename TS>
 hipError_t convert(TD *dst, const TS *src, size_t n, hipStream_t s);
 template <typename T>
 hipError_t direction_update(T *d, const double *r, const double *scalars, size_t n, hipStream_t s);
+
+// The serving kernel: its co-resident grid on the current device, and one tick.
+hipError_t f1_serve_grid(int *blocks);
+hipError_t f1_serve_launch(const ServeSlot *slots, serve::State *states, int nslots,
+                           ServeControl *ctl, const int *abort_flag, int max_rounds,
+                           double work_budget, unsigned long long spin_limit, int blocks,
+                           hipStream_t s);
 
 // Pack / unpack between the packed user vector (FP64) and the device layout (T).
 template <typename T>

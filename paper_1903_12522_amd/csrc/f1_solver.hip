@@ -17,6 +17,7 @@
 #include <tuple>
 #include <type_traits>
 
+#include "f1_device.h"
 #include "solver.h"
 
 namespace cmcg {
@@ -64,11 +65,7 @@ __global__ void f1_setup_kernel(F1Geom g, const double *c, double c_const, const
 // u = i V / omega with V = (2/N) (Ure + i Uim)  (eq. TH_FILTERED_MIXED_SOLUTION, discrete)
 __global__ void f1_output_kernel(const double *ure, const double *uim, double scale, double *out_re,
                                  double *out_im, size_t fs) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < fs; o += stride) {
-    out_re[o] = -scale * uim[o];
-    out_im[o] = scale * ure[o];
-  }
+  f1_output_block(ure, uim, scale, out_re, out_im, fs, blockIdx.x, gridDim.x);
 }
 
 // Weights (c, s)_j of the components at one time: amp (cos, sin)(m_j omega t), amp the ramp.
@@ -877,18 +874,17 @@ cmcg_status make_f1_solver_in(const cmcg_problem *P, const SolverConfig &cfg, vo
 //
 // Requests are admitted in arrival order while the sum of their device footprints stays within
 // the HBM budget and the slot cap; each admitted solve keeps its whole CG state resident in its
-// own buffers.  One server tick advances every running solve by one launch's worth of leapfrog
-// steps: the launches of all solves that are in a period are grouped by (precision, direction,
-// steps) and each group is ONE kernel launch over the union of the solves' tiles
-// (f1_multi_kernel).  Solves whose period ended in this tick then run their CG reductions and
-// update (per-solve, deterministic), and the host reads their scalars after a single stream
-// synchronisation per tick.  A solve's arithmetic does not depend on what else is batched with it.
+// own buffers.  One server tick is ONE launch of the persistent serving kernel (f1_serve.hip):
+// it advances every running solve through rounds of its CG algorithm, one operation per solve
+// per round (a period launch, a vector pass, a reduction, a decision), the decisions taken on
+// the device from each solve's own scalars, until a work budget is spent or every solve has
+// finished.  The host then copies out finished results and admits queued requests.  A solve's
+// arithmetic does not depend on what else is resident: the kernel runs the standalone path's
+// tiles and vector passes on its buffers, with the same launch parameters.
 // =========================================================================================
 namespace {
 
-enum ServePhase { kPhGradFwd, kPhGradAdj, kPhFwd, kPhAdj, kPhFilter, kPhDone };
-
-size_t f1_footprint(int nx, int ny, int prec, bool has_im) {
+size_t f1_footprint(int nx, int ny, int prec, bool has_im, int N) {
   const size_t pitch = (size_t)(nx + 63) / 64 * 64, fs = (size_t)ny * pitch, vecN = 3 * fs;
   auto r8 = [](size_t b) { return b == 0 ? 8 : b; };
   size_t total = 0;
@@ -900,6 +896,7 @@ size_t f1_footprint(int nx, int ny, int prec, bool has_im) {
   total += r8(vecN * (prec == CMCG_FP32_MIXED ? 4 : 8));
   total += 2 * r8(vecN * 8) + 2 * r8(fs * 8);
   total += r8(kRedBlocks * 8) + r8(kNumScalars * 8);
+  total += r8((size_t)N * 4 * 8);    // the launch-parameter table of the serving kernel
   return total;
 }
 
@@ -911,26 +908,44 @@ struct ServeRequest {
   std::vector<double> c, fre, fim, gre, gim;
   size_t footprint = 0;
   F1Solver *S = nullptr;
-  int phase = kPhGradFwd, n0 = 0, grad_mode = kFinStart, pending = 0;
-  bool converged = false;
+  DeviceArena extra;             // the serving kernel's launch-parameter table
+  ServeSlot slot{};
+  serve::State st{};
   cmcg_status status = CMCG_OK;
   std::vector<double> ure, uim;
   cmcg_report rep{};
 };
 
+// Steps per launch of a served period: one of the serving kernel's launch sizes, at most the
+// requested K (FP32 7, 4, 2, 1; FP64 4, 2, 1).  Results do not depend on it.
+int served_K(int k, bool fp64) {
+  int K = k > 0 ? k : 7;
+  if (fp64 && K > 4) K = 4;
+  return K >= 7 ? 7 : K >= 4 ? 4 : K >= 2 ? 2 : 1;
+}
+
 class F1Server final : public Server {
  public:
   int64_t budget = 0;
   int max_slots = 16, kblock = 0, device = 0;
+  unsigned long long spin_limit = 1ull << 24;
   hipStream_t s = nullptr;
   std::map<int64_t, ServeRequest *> reqs;
   std::deque<int64_t> queue;
   std::vector<int64_t> active;
   size_t used = 0;
   int64_t next_id = 1;
-  // descriptor staging for the batched launches of one tick
-  void *h_desc = nullptr, *d_desc = nullptr;
-  size_t desc_cap = 0;
+  int64_t ticks = 0, launches = 0, rounds = 0;
+  int grid = 0;
+  // device slot table, states and control block of the serving kernel, their pinned staging
+  // buffers, and the host-settable abort flag the kernel's waits watch
+  ServeSlot *d_slots = nullptr, *h_slots = nullptr;
+  serve::State *d_states = nullptr, *h_states = nullptr;
+  ServeControl *d_ctl = nullptr, *h_ctl = nullptr;
+  int *h_abort = nullptr;
+  // per tick: rounds and grid-point updates of the last launch
+  static constexpr int kMaxRounds = 1 << 16;
+  static constexpr double kTickUpdates = 1.0e10;
 
   ~F1Server() override {
     if (s) (void)hipStreamSynchronize(s);
@@ -938,14 +953,27 @@ class F1Server final : public Server {
       delete kv.second->S;
       delete kv.second;
     }
-    if (h_desc) (void)hipHostFree(h_desc);
-    if (d_desc) (void)hipFree(d_desc);
+    if (d_slots) (void)hipFree(d_slots);
+    if (d_states) (void)hipFree(d_states);
+    if (d_ctl) (void)hipFree(d_ctl);
+    if (h_slots) (void)hipHostFree(h_slots);
+    if (h_states) (void)hipHostFree(h_states);
+    if (h_ctl) (void)hipHostFree(h_ctl);
+    if (h_abort) (void)hipHostFree(h_abort);
   }
 
   cmcg_status init() {
-    desc_cap = 1 << 20;
-    CMCG_HIP(hipHostMalloc(&h_desc, desc_cap));
-    CMCG_HIP(hipMalloc(&d_desc, desc_cap));
+    CMCG_HIP(hipSetDevice(device));
+    CMCG_HIP(hipMalloc((void **)&d_slots, kServeMaxSlots * sizeof(ServeSlot)));
+    CMCG_HIP(hipMalloc((void **)&d_states, kServeMaxSlots * sizeof(serve::State)));
+    CMCG_HIP(hipMalloc((void **)&d_ctl, sizeof(ServeControl)));
+    CMCG_HIP(hipHostMalloc((void **)&h_slots, kServeMaxSlots * sizeof(ServeSlot)));
+    CMCG_HIP(hipHostMalloc((void **)&h_states, kServeMaxSlots * sizeof(serve::State)));
+    CMCG_HIP(hipHostMalloc((void **)&h_ctl, sizeof(ServeControl)));
+    CMCG_HIP(hipHostMalloc((void **)&h_abort, sizeof(int)));
+    *h_abort = 0;
+    CMCG_HIP(f1_serve_grid(&grid));
+    if (max_slots > kServeMaxSlots) max_slots = kServeMaxSlots;
     return CMCG_OK;
   }
 
@@ -964,6 +992,8 @@ class F1Server final : public Server {
       return set_error("served solves return the filter output"), CMCG_EUNSUPPORTED;
     if (P->sound_soft)
       return set_error("served solves have no Dirichlet cells"), CMCG_EUNSUPPORTED;
+    SolverConfig cfg;
+    CMCG_TRY(make_config(P, O, s, &cfg));
     auto *R = new ServeRequest();
     R->id = next_id++;
     R->P = *P;
@@ -983,7 +1013,7 @@ class F1Server final : public Server {
     R->O.hip_stream = nullptr;
     R->O.steps_per_launch = O->steps_per_launch > 0 ? O->steps_per_launch : kblock;
     R->footprint = f1_footprint((int)P->n[0], (int)P->n[1], O->precision,
-                                P->f_im != nullptr || P->gS_im != nullptr);
+                                P->f_im != nullptr || P->gS_im != nullptr, cfg.N);
     if ((int64_t)R->footprint > budget) {
       delete R;
       return set_error("request larger than the server's HBM budget"), CMCG_ENOMEM;
@@ -991,6 +1021,71 @@ class F1Server final : public Server {
     reqs[R->id] = R;
     queue.push_back(R->id);
     *id = R->id;
+    return CMCG_OK;
+  }
+
+  // The serving kernel's view of an admitted solve, and its start state (Step 1: z = 0)
+  cmcg_status make_slot(ServeRequest *R) {
+    F1Solver *S = R->S;
+    const SolverConfig &cfg = S->cfg;
+    ServeSlot &sl = R->slot;
+    sl = ServeSlot{};
+    sl.g = S->g;
+    sl.fs = S->fs;
+    sl.vecN = S->vecN;
+    int nbx, nby, band;
+    f1_launch_shape(S->g.nx, S->g.ny, 1, &nbx, &nby, &band);
+    sl.band = band;
+    sl.N = cfg.N;
+    sl.mixed = S->mixed ? 1 : 0;
+    sl.K_lo = served_K(cfg.kblock, !S->mixed);
+    sl.K_hi = served_K(cfg.kblock, true);
+    sl.max_iter = cfg.max_iter;
+    sl.tol = cfg.tol;
+    sl.refresh = cfg.refresh;
+    sl.out_scale = 2.0 / (cfg.N * cfg.omega_of(0));
+    sl.lo_S0 = S->lo.S0;
+    sl.lo_S1 = S->lo.S1;
+    sl.lo_W = S->lo.W;
+    sl.lo_Q = S->lo.Q;
+    sl.lo_cc = S->lo.cc;
+    sl.lo_Fre = S->lo.Fre;
+    sl.lo_Fim = S->lo.Fim;
+    sl.hi_S0 = tp<double>(S->hi.S0);
+    sl.hi_S1 = tp<double>(S->hi.S1);
+    sl.hi_W = tp<double>(S->hi.W);
+    sl.hi_Q = tp<double>(S->hi.Q);
+    sl.hi_cc = tp<double>(S->hi.cc);
+    sl.hi_Fre = tp<double>(S->hi.Fre);
+    sl.hi_Fim = tp<double>(S->hi.Fim);
+    sl.D = S->D;
+    sl.Z = S->Z;
+    sl.R = S->R;
+    sl.Ure = S->Ure;
+    sl.Uim = S->Uim;
+    sl.partials = S->partials;
+    sl.scalars = S->scalars;
+    // the launch parameters the standalone period loop computes (no source ramp): the source
+    // weights at t_{n+1/2} and the filter weights at t_n
+    const int N = cfg.N;
+    const double w0 = cfg.omega_of(0);
+    std::vector<double> tab((size_t)4 * N);
+    for (int n = 0; n < N; ++n) {
+      const double t = (n + 0.5) * cfg.dt;
+      tab[4 * n] = std::cos(w0 * t);
+      tab[4 * n + 1] = std::sin(w0 * t);
+      tab[4 * n + 2] = std::cos(w0 * n * cfg.dt);
+      tab[4 * n + 3] = std::sin(w0 * n * cfg.dt);
+    }
+    double *dtab = nullptr;
+    CMCG_TRY(R->extra.alloc_n(tab.size(), &dtab, s));
+    CMCG_HIP(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    CMCG_HIP(hipStreamSynchronize(s));
+    sl.tab = dtab;
+    R->st = serve::State{};
+    R->st.active = 1;
+    R->st.phase = serve::kGradFwd;
+    R->st.grad_mode = serve::kModeStart;
     return CMCG_OK;
   }
 
@@ -1010,217 +1105,46 @@ class F1Server final : public Server {
       }
       R->S = static_cast<F1Solver *>(base);
       R->state = 1;
-      R->phase = kPhGradFwd;
-      R->grad_mode = kFinStart;
-      R->n0 = 0;
       F1Solver *S = R->S;
-      S->iter = S->refreshes = 0;
-      S->updates = 0;
-      S->dram = 0;
-      S->rel = 1.0;
       CMCG_HIP(hipMemsetAsync(S->Z, 0, S->vecN * sizeof(double), s));
-      used += S->arena.bytes();
+      st = make_slot(R);
+      if (st != CMCG_OK) {
+        fail(R, st);
+        continue;
+      }
+      used += S->arena.bytes() + R->extra.bytes();
       active.push_back(R->id);
     }
     return CMCG_OK;
   }
 
-  // the period job of a running solve
-  void job(ServeRequest *R, const F1Set **b, bool *adj, bool *forced, const void **in, void **out,
-           const void **sub, bool *filter) {
+  // result of a finished solve: the output field (in the FP64 W buffer) and the report
+  cmcg_status complete(ServeRequest *R) {
     F1Solver *S = R->S;
-    *filter = false;
-    switch (R->phase) {
-      case kPhGradFwd: *b = &S->hi; *adj = false; *forced = true; *in = S->Z; *out = S->hi.W; *sub = S->Z; break;
-      case kPhGradAdj: *b = &S->hi; *adj = true; *forced = false; *in = S->hi.W; *out = S->hi.Q; *sub = S->hi.W; break;
-      case kPhFwd: *b = &S->lo; *adj = false; *forced = false; *in = S->D; *out = S->lo.W; *sub = S->D; break;
-      case kPhAdj: *b = &S->lo; *adj = true; *forced = false; *in = S->lo.W; *out = S->lo.Q; *sub = S->lo.W; break;
-      default: *b = &S->hi; *adj = false; *forced = true; *in = S->Z; *out = S->hi.Q; *sub = nullptr; *filter = true; break;
-    }
-  }
-
-  // One batched launch planned for this tick: `count` descriptors at byte offset `off` of the
-  // descriptor staging buffer, all of one precision, direction and step count.
-  struct PlannedLaunch {
-    int prec, ns, adj, set, count, blocks;
-    size_t off;
-  };
-
-  // Append this round's launches of the solves in `sel` (all of precision T) to the plan: the
-  // solves are grouped by (direction, steps, fast-variant set), each group one batched launch;
-  // every solve's step counter advances.  Returns false when the staging buffer cannot hold the
-  // round.
-  template <typename T>
-  bool plan_round(const std::vector<ServeRequest *> &sel, size_t &off,
-                  std::vector<PlannedLaunch> &plan, double &work) {
-    if (sel.empty()) return true;
-    if (off + sel.size() * sizeof(F1SlotLaunch<T>) + 2 * 256 > desc_cap) return false;
-    std::map<std::tuple<int, int, int>, std::vector<F1SlotLaunch<T>>> groups;
-    for (ServeRequest *R : sel) {
-      F1Solver *S = R->S;
-      const F1Set *b;
-      bool adj, forced, filter;
-      const void *in, *sub;
-      void *out;
-      job(R, &b, &adj, &forced, &in, &out, &sub, &filter);
-      const int K = filter ? 1 : S->cfg.kblock;
-      F1SlotLaunch<T> d{};
-      d.g = S->g;
-      const int ns = S->build_launch<T>(*b, forced, static_cast<const T *>(in), static_cast<T *>(out),
-                                        static_cast<const T *>(sub), S->cfg.N, R->n0, K, filter,
-                                        &d.p, &d.L);
-      S->dram += S->launch_bytes<T>(d.p, d.L);
-      int nby;
-      f1_launch_shape(S->g.nx, S->g.ny, ns, &d.nbx, &nby, &d.band);
-      d.nblocks = d.nbx * nby;
-      const int set = f1_fast_set(d.L, d.p.sub != nullptr, adj);
-      // backward middle launches run the forward middle instance: one group with the forward
-      groups[{(adj && set != 0) ? 1 : 0, ns, set}].push_back(d);
-      R->n0 += ns;
-      const double u = (double)ns * S->g.nx * S->g.ny;
-      S->updates += u;
-      work += u;
-    }
-    for (auto &kv : groups) {
-      auto &v = kv.second;
-      int blocks = 0;
-      for (auto &d : v) {
-        d.block0 = blocks;
-        blocks += d.nblocks;
-      }
-      const size_t bytes = v.size() * sizeof(F1SlotLaunch<T>);
-      std::memcpy(static_cast<char *>(h_desc) + off, v.data(), bytes);
-      plan.push_back({std::is_same<T, double>::value ? CMCG_FP64 : CMCG_FP32_MIXED,
-                      std::get<1>(kv.first), std::get<0>(kv.first), std::get<2>(kv.first),
-                      (int)v.size(), blocks, off});
-      off = (off + bytes + 255) / 256 * 256;
-    }
-    return true;
-  }
-
-  template <typename T>
-  cmcg_status launch_planned(const PlannedLaunch &L) {
-    auto *dd = reinterpret_cast<const F1SlotLaunch<T> *>(static_cast<const char *>(d_desc) + L.off);
-    CMCG_HIP(f1_multi_launch<T>(L.ns, L.adj != 0, L.set, dd, L.count, L.blocks, s));
-    return CMCG_OK;
-  }
-
-  // reductions and CG update after a period ended (issued on the stream, read after the sync)
-  cmcg_status post_period(ServeRequest *R) {
-    F1Solver *S = R->S;
-    if (R->phase == kPhGradAdj) {
-      CMCG_HIP(hipMemcpyAsync(S->R, S->hi.Q, S->vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
-      CMCG_HIP(f1_dot<double, double>(S->g, S->R, S->R, S->hi.cc, 1, S->fs, S->partials, s));
-      CMCG_HIP(finalize(S->partials, kRedBlocks, S->scalars, R->grad_mode, 0, s));
-      CMCG_HIP(hipMemcpyAsync(S->h_scalars, S->scalars, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
-      R->pending = 1;
-    } else if (R->phase == kPhAdj) {
-      CMCG_TRY(S->dot_to(S->lo, S->lo.Q, S->D, kFinAlpha));
-      if (S->mixed)
-        CMCG_HIP(f1_cg_update<float>(S->g, S->Z, S->R, tpc<float>(S->D), tpc<float>(S->lo.Q), S->lo.cc,
-                                     S->fs, S->scalars, S->partials, s));
-      else
-        CMCG_HIP(f1_cg_update<double>(S->g, S->Z, S->R, tpc<double>(S->D), tpc<double>(S->lo.Q),
-                                      S->lo.cc, S->fs, S->scalars, S->partials, s));
-      CMCG_HIP(finalize(S->partials, kRedBlocks, S->scalars, kFinBeta, 0, s));
-      CMCG_HIP(hipMemcpyAsync(S->h_scalars, S->scalars, kNumScalars * sizeof(double), hipMemcpyDeviceToHost, s));
-      R->pending = 2;
-    } else if (R->phase == kPhFilter) {
-      double *ore = tp<double>(S->hi.W), *oim = tp<double>(S->hi.W) + S->fs;
-      hipLaunchKernelGGL(f1_output_kernel, dim3(grid_for(S->fs)), dim3(256), 0, s, S->Ure, S->Uim,
-                         2.0 / (S->cfg.N * S->cfg.omega), ore, oim, S->fs);
-      CMCG_HIP(hipGetLastError());
-      const size_t nxy = (size_t)S->g.nx * S->g.ny;
-      R->ure.resize(nxy);
-      R->uim.resize(nxy);
-      const size_t row = (size_t)S->g.nx * sizeof(double), pitchb = (size_t)S->g.pitch * sizeof(double);
-      CMCG_HIP(hipMemcpy2DAsync(R->ure.data(), row, ore, pitchb, row, S->g.ny, hipMemcpyDeviceToHost, s));
-      CMCG_HIP(hipMemcpy2DAsync(R->uim.data(), row, oim, pitchb, row, S->g.ny, hipMemcpyDeviceToHost, s));
-      R->pending = 3;
-    }
-    return CMCG_OK;
-  }
-
-  cmcg_status enter_filter(ServeRequest *R) {
-    F1Solver *S = R->S;
-    CMCG_HIP(hipMemsetAsync(S->Ure, 0, S->fs * sizeof(double), s));
-    CMCG_HIP(hipMemsetAsync(S->Uim, 0, S->fs * sizeof(double), s));
-    R->phase = kPhFilter;
-    R->n0 = 0;
-    return CMCG_OK;
-  }
-
-  cmcg_status direction(ServeRequest *R) {
-    F1Solver *S = R->S;
-    if (S->mixed) CMCG_HIP(direction_update<float>(tp<float>(S->D), S->R, S->scalars, S->vecN, s));
-    else CMCG_HIP(direction_update<double>(tp<double>(S->D), S->R, S->scalars, S->vecN, s));
-    R->phase = kPhFwd;
-    R->n0 = 0;
-    return CMCG_OK;
-  }
-
-  // host decisions after the tick's synchronisation (CG Steps 5.6-5.8, refresh, completion)
-  cmcg_status decide(ServeRequest *R) {
-    F1Solver *S = R->S;
-    const double *h = S->h_scalars;
-    const int pend = R->pending;
-    R->pending = 0;
-    if (pend == 1) {
-      if (h[kBreak] != 0.0) return fail(R, CMCG_EBREAKDOWN);
-      S->rel = h[kRel];
-      S->delta_at_refresh = h[kDelta];
-      if (R->grad_mode == kFinStart) {
-        if (S->mixed) CMCG_HIP(convert<float, double>(tp<float>(S->D), S->R, S->vecN, s));
-        else CMCG_HIP(hipMemcpyAsync(S->D, S->R, S->vecN * sizeof(double), hipMemcpyDeviceToDevice, s));
-        if (h[kDelta0] == 0.0) {
-          R->converged = true;
-          return enter_filter(R);
-        }
-        R->phase = kPhFwd;
-        R->n0 = 0;
-        return CMCG_OK;
-      }
-      ++S->refreshes;
-      if (S->rel <= S->cfg.tol) {
-        R->converged = true;
-        return enter_filter(R);
-      }
-      // a refresh may fall on the last allowed iteration, as in the single-solve loop
-      if (S->iter >= S->cfg.max_iter) return enter_filter(R);
-      return direction(R);
-    }
-    if (pend == 2) {
-      ++S->iter;
-      if (h[kBreak] != 0.0) return fail(R, CMCG_EBREAKDOWN);
-      S->rel = h[kRel];
-      if (S->mixed && S->cfg.refresh > 0.0 &&
-          (S->rel <= S->cfg.tol || h[kDelta] <= S->cfg.refresh * S->cfg.refresh * S->delta_at_refresh)) {
-        R->grad_mode = kFinRefresh;
-        R->phase = kPhGradFwd;
-        R->n0 = 0;
-        return CMCG_OK;
-      }
-      if (S->rel <= S->cfg.tol) {
-        R->converged = true;
-        return enter_filter(R);
-      }
-      if (S->iter >= S->cfg.max_iter) return enter_filter(R);
-      return direction(R);
-    }
-    if (pend == 3) {
-      S->report(&R->rep);
-      R->status = R->converged ? CMCG_OK : CMCG_ENOTCONV;
-      R->state = 2;
-      R->phase = kPhDone;
-      release(R);
-    }
+    const serve::State &st = R->st;
+    const double *ore = tp<double>(S->hi.W), *oim = tp<double>(S->hi.W) + S->fs;
+    const size_t nxy = (size_t)S->g.nx * S->g.ny;
+    R->ure.resize(nxy);
+    R->uim.resize(nxy);
+    const size_t row = (size_t)S->g.nx * sizeof(double), pitchb = (size_t)S->g.pitch * sizeof(double);
+    CMCG_HIP(hipMemcpy2DAsync(R->ure.data(), row, ore, pitchb, row, S->g.ny, hipMemcpyDeviceToHost, s));
+    CMCG_HIP(hipMemcpy2DAsync(R->uim.data(), row, oim, pitchb, row, S->g.ny, hipMemcpyDeviceToHost, s));
+    CMCG_TRY(S->read_scalars());
+    S->iter = st.iter;
+    S->refreshes = st.refreshes;
+    S->updates = st.updates;
+    S->dram = st.dram;
+    S->rel = S->h_scalars[kRel];
+    S->report(&R->rep);
+    R->status = st.converged ? CMCG_OK : CMCG_ENOTCONV;
+    R->state = 2;
+    release(R);
     return CMCG_OK;
   }
 
   cmcg_status fail(ServeRequest *R, cmcg_status st) {
     R->status = st;
     R->state = -1;
-    R->phase = kPhDone;
     release(R);
     return CMCG_OK;
   }
@@ -1228,72 +1152,57 @@ class F1Server final : public Server {
   void release(ServeRequest *R) {
     if (!R->S) return;
     (void)hipStreamSynchronize(s);
-    used -= R->S->arena.bytes();
+    used -= R->S->arena.bytes() + R->extra.bytes();
     delete R->S;
     R->S = nullptr;
+    R->extra.release();
     active.erase(std::remove(active.begin(), active.end(), R->id), active.end());
   }
-
-  // One tick.  Rounds of batched launches are planned on the host (each round advances every
-  // running solve by one launch) until the tick holds about kTickUpdates cell-updates or every
-  // solve waits for a host decision; a forward period that ends hands over to its backward period
-  // within the tick (no decision is needed there).  The descriptors of all rounds go to the
-  // device in one copy, the launches and the end-of-period reductions are queued, and the host
-  // synchronises once to take the CG decisions (Steps 5.6-5.8, refresh, completion).
-  static constexpr double kTickUpdates = 2.0e9;
-  static constexpr int kMaxRounds = 64;
 
   cmcg_status step(int *n_active, int *n_queued) override {
     CMCG_HIP(hipSetDevice(device));
     CMCG_TRY(admit());
-    std::vector<ServeRequest *> running;
+    std::vector<ServeRequest *> run;
     for (int64_t id : active) {
       ServeRequest *R = reqs[id];
-      if (R->phase != kPhDone && !R->pending) running.push_back(R);
+      if (R->S && R->st.active == 1) run.push_back(R);
     }
-    std::vector<PlannedLaunch> plan;
-    std::vector<ServeRequest *> ended;     // solves waiting for reductions and a decision
-    size_t off = 0;
-    double work = 0.0;
-    for (int round = 0; round < kMaxRounds && !running.empty() && work < kTickUpdates; ++round) {
-      std::vector<ServeRequest *> sel32, sel64;
-      for (ServeRequest *R : running) {
-        const F1Set *b;
-        bool adj, forced, filter;
-        const void *in, *sub;
-        void *out;
-        job(R, &b, &adj, &forced, &in, &out, &sub, &filter);
-        (b->prec == CMCG_FP64 ? sel64 : sel32).push_back(R);
+    cmcg_status result = CMCG_OK;
+    if (!run.empty()) {
+      const int n = (int)run.size();
+      for (int k = 0; k < n; ++k) {
+        h_slots[k] = run[k]->slot;
+        h_states[k] = run[k]->st;
       }
-      if (!plan_round<float>(sel32, off, plan, work)) break;
-      if (!plan_round<double>(sel64, off, plan, work)) break;
-      std::vector<ServeRequest *> still;
-      for (ServeRequest *R : running) {
-        if (R->n0 < R->S->cfg.N) {
-          still.push_back(R);
-        } else if (R->phase == kPhGradFwd || R->phase == kPhFwd) {
-          R->phase = R->phase == kPhGradFwd ? kPhGradAdj : kPhAdj;   // forward -> backward
-          R->n0 = 0;
-          still.push_back(R);
-        } else {
-          ended.push_back(R);
+      *h_ctl = ServeControl{};
+      CMCG_HIP(hipMemcpyAsync(d_slots, h_slots, n * sizeof(ServeSlot), hipMemcpyHostToDevice, s));
+      CMCG_HIP(hipMemcpyAsync(d_states, h_states, n * sizeof(serve::State), hipMemcpyHostToDevice, s));
+      CMCG_HIP(hipMemcpyAsync(d_ctl, h_ctl, sizeof(ServeControl), hipMemcpyHostToDevice, s));
+      CMCG_HIP(f1_serve_launch(d_slots, d_states, n, d_ctl, h_abort, kMaxRounds, kTickUpdates,
+                               spin_limit, grid, s));
+      ++launches;
+      ++ticks;
+      CMCG_HIP(hipMemcpyAsync(h_states, d_states, n * sizeof(serve::State), hipMemcpyDeviceToHost, s));
+      CMCG_HIP(hipMemcpyAsync(h_ctl, d_ctl, sizeof(ServeControl), hipMemcpyDeviceToHost, s));
+      CMCG_HIP(hipStreamSynchronize(s));
+      rounds += h_ctl->rounds;
+      if (h_ctl->failed) {
+        // a barrier wait gave up: the solves' states are not consistent any more
+        set_error("serving kernel: a grid barrier wait gave up (spin limit or abort)");
+        for (ServeRequest *R : run) fail(R, CMCG_EDEVICE);
+        result = CMCG_EDEVICE;
+      } else {
+        for (int k = 0; k < n; ++k) {
+          ServeRequest *R = run[k];
+          R->st = h_states[k];
+          if (R->st.active == 2) CMCG_TRY(complete(R));
+          else if (R->st.active == 3) fail(R, static_cast<cmcg_status>(R->st.status));
         }
       }
-      running.swap(still);
     }
-    if (off > 0)
-      CMCG_HIP(hipMemcpyAsync(d_desc, h_desc, off, hipMemcpyHostToDevice, s));
-    for (const PlannedLaunch &L : plan) {
-      if (L.prec == CMCG_FP64) CMCG_TRY(launch_planned<double>(L));
-      else CMCG_TRY(launch_planned<float>(L));
-    }
-    for (ServeRequest *R : ended) CMCG_TRY(post_period(R));
-    CMCG_HIP(hipStreamSynchronize(s));
-    for (ServeRequest *R : ended)
-      if (R->pending) CMCG_TRY(decide(R));
-    if (n_active) *n_active = (int)active.size();
+    if (n_active) *n_active = (int)run.size();
     if (n_queued) *n_queued = (int)queue.size();
-    return CMCG_OK;
+    return result;
   }
 
   cmcg_status poll(int64_t id, int *state, double *u_re, double *u_im, cmcg_report *rep) override {
@@ -1320,6 +1229,12 @@ class F1Server final : public Server {
     *n_active = (int)active.size();
     *n_queued = (int)queue.size();
   }
+
+  void counters(int64_t *n_ticks, int64_t *n_launches, int64_t *n_rounds) const override {
+    *n_ticks = ticks;
+    *n_launches = launches;
+    *n_rounds = rounds;
+  }
 };
 
 }  // namespace
@@ -1331,6 +1246,7 @@ cmcg_status make_f1_server(const cmcg_server_options *o, hipStream_t s, Server *
   S->max_slots = o->max_slots > 0 ? o->max_slots : 16;
   S->kblock = o->steps_per_launch > 0 ? o->steps_per_launch : 0;   // 0: per-solve default
   S->device = o->device;
+  if (o->barrier_spin_limit > 0) S->spin_limit = (unsigned long long)o->barrier_spin_limit;
   S->s = s;
   cmcg_status st = S->init();
   if (st != CMCG_OK) {

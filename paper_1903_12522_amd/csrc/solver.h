@@ -219,6 +219,7 @@ class Server {
   virtual cmcg_status poll(int64_t id, int *state, double *u_re, double *u_im,
                            cmcg_report *rep) = 0;
   virtual void stats(int64_t *used_bytes, int *n_active, int *n_queued) const = 0;
+  virtual void counters(int64_t *n_ticks, int64_t *n_launches, int64_t *n_rounds) const = 0;
 };
 cmcg_status make_f1_server(const cmcg_server_options *o, hipStream_t s, Server **out);
 

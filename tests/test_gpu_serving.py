@@ -146,3 +146,45 @@ def test_served_solve_stops_at_max_iter_after_refresh(cm):
         assert np.array_equal(U, Us)
         # the poll that reported DONE released the request
         assert srv.stats() == (0, 0, 0)
+
+
+def test_one_tick_is_one_kernel_launch(cm):
+    """Each server tick advances every resident solve through many rounds (period launches,
+    reductions and CG decisions) inside one launch of the persistent serving kernel."""
+    probs = [_req(64, 4.0, 21), _req(96, 6.0, 22, pos=(0.4, 0.6)), _req(80, 5.0, 23)]
+    with cm.Server(8 << 30, max_slots=8) as srv:
+        ids = [srv.submit(p, precision="fp32", tol=1e-5, max_iter=2000) for p in probs]
+        done = {}
+        for _ in range(10000):
+            srv.step()
+            for rid in ids:
+                if rid in done:
+                    continue
+                state, U, rep, st = srv.poll(rid)
+                if state == cm.REQ_DONE:
+                    done[rid] = rep
+            if len(done) == len(ids):
+                break
+        ticks, launches, rounds = srv.launches()
+    assert len(done) == len(ids)
+    assert ticks >= 1 and launches == ticks and rounds > ticks
+    # a solve takes thousands of period launches; the ticks are far fewer
+    iters = sum(r["iterations"] for r in done.values())
+    assert ticks < iters
+
+
+def test_barrier_that_gives_up_fails_the_tick(cm):
+    """A grid barrier whose wait runs out (a spin limit of one poll, forced from the host)
+    ends the serving kernel: the tick reports CMCG_EDEVICE and fails the resident solves;
+    a server with the default limit then serves the same request normally."""
+    prob = _req(64, 4.0, 31)
+    with cm.Server(8 << 30, max_slots=4, barrier_spin_limit=1) as srv:
+        rid = srv.submit(prob, precision="fp32", tol=1e-5, max_iter=2000)
+        with pytest.raises(cm.CMCGError) as e:
+            srv.step()
+        assert e.value.status == cm.EDEVICE
+        state, U, rep, st = srv.poll(rid)
+        assert state == cm.REQ_FAILED and st == cm.EDEVICE
+        assert srv.stats() == (0, 0, 0)
+    (U, rep, st), = _serve(cm, [prob], precision="fp32", tol=1e-5)
+    assert st == 0 and rep["iterations"] > 0
