@@ -81,17 +81,27 @@ template <typename T>
 hipError_t f2_psi_scale(const F2Geom &g, const T *in, const T *lam, T *out, hipStream_t s);
 template <typename TA, typename TB>
 hipError_t dot_plain(const TA *a, const TB *b, size_t n, double *partials, hipStream_t s);
-// qu: the primal Riesz update q_u in FP64, or (FP32-mixed V-cycle) the FP32 V-cycle result
-template <typename T, typename TQ>
-hipError_t f2_cg_update(const F2Geom &g, double *z, double *ru, double *rh, const T *d,
-                        const TQ *qu, const T *qh, const T *lam, const double *sc,
-                        double *partials, hipStream_t s);
-template <typename T>
-hipError_t f2_delta(const F2Geom &g, const double *ru, const double *rh, const T *lam,
-                    double *partials, hipStream_t s);
-template <typename T>
-hipError_t f2_direction(const F2Geom &g, T *d, const double *ru, const double *rh, const T *lam,
+// Steps 5.4-5.5 (FP64 arithmetic): z -= alpha d, r_u -= alpha q_u, rh -= alpha qh, partials of
+// delta.  qu: the primal Riesz update q_u in FP64, or (FP32-mixed V-cycle) the FP32 V-cycle
+// result; TR: residual storage; TZ: the iterate (FP64), or its FP32 correction dz (FP32-mixed)
+template <typename T, typename TQ, typename TR, typename TZ>
+hipError_t f2_cg_update(const F2Geom &g, TZ *z, TR *ru, TR *rh, const T *d, const TQ *qu,
+                        const T *qh, const T *lam, const double *sc, double *partials,
+                        hipStream_t s);
+// partials of delta = <rh, r> from FP64 residuals; rus, rhs (may be null): their stored copies
+template <typename T, typename TR>
+hipError_t f2_delta(const F2Geom &g, const double *ru, const double *rh, const T *lam, TR *rus,
+                    TR *rhs, double *partials, hipStream_t s);
+template <typename T, typename TR>
+hipError_t f2_direction(const F2Geom &g, T *d, const TR *ru, const TR *rh, const T *lam,
                         const double *sc, int first, hipStream_t s);
+// out = z + dz (two fields); `clear`: dz = 0 (with out == z: z += dz, dz = 0)
+hipError_t f2_iterate(const F2Geom &g, const double *z, float *dz, double *out, int clear,
+                      hipStream_t s);
+// out = (r_u, M^{-1} rh_v) in FP64 (the primal residual)
+template <typename TR, typename T>
+hipError_t f2_primal(const F2Geom &g, const TR *ru, const TR *rh, const T *lam, double *out,
+                     hipStream_t s);
 template <typename T>
 hipError_t f2_mass_inverse(const F2Geom &g, const T *qh_v, double *q_v, const T *lam, hipStream_t s);
 // Partial sums (kCompatSums x kRedBlocks, sum-major) of the compatibility condition: sum M,

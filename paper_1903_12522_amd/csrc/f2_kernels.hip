@@ -278,27 +278,36 @@ __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
 
 // Temporal blocking of the homogeneous step u^{n+1} = R (2 u^n - (1-beta) u^{n-1} - lambda L u^n)
 // / (1 + beta) (every step of a forward period but its start and end, and every interior step of
-// the backward period in the scaled variable).  A workgroup of kBlockRows wavefronts owns a
-// (64 x kBlockRows) column tile and marches a chunk of kBlockChunk planes; the K steps of a
-// launch are K pipeline levels: at plane iteration p, level 0 loads plane p of u^n and u^{n-1},
-// and level s computes plane p - s of u^{n+s} from level s-1's planes p-s-1 .. p-s+1 (a register
-// window), level s-2's plane p-s (the older state) and the neighbours: x through lane shifts, y
-// through a double-buffered LDS plane per level (one barrier per plane iteration).  Each level
-// loses one lane, one row and one plane of validity at the tile's edges, so the tile writes its
-// inner (64 - 2K) x (kBlockRows - 2K) columns and the chunk's planes, preceded by K lead-in
-// planes; it writes u^{n+K} and u^{n+K-1}.  On the box faces a real node takes its mirrored
-// neighbour from the true node, as the single-step kernel does, so every real node sees the
-// same operands in the same order: blocked and single-step periods agree bit for bit.  Halo
-// lanes, rows and planes outside the box read clamped addresses and are never stored.
-constexpr int kBlockRows = 16;
+// the backward period in the scaled variable).  A workgroup of kBlockWaves wavefronts owns a
+// (64 x TY) column tile, TY = kBlockWaves RPW (each wavefront RPW consecutive rows, one column per
+// lane), and marches a chunk of planes; the K steps of a launch are K pipeline levels: at plane
+// iteration p, level 0 loads plane p of u^n and u^{n-1}, and level s computes plane p - s of
+// u^{n+s} from level s-1's planes p-s-1 .. p-s+1 (a register window), level s-2's plane p-s (the
+// older state) and the neighbours: x through lane shifts, y from the wavefront's own other row
+// or, across wavefronts, through a double-buffered LDS plane per level (one barrier per plane
+// iteration).  Each level loses one lane, one row and one plane of validity at the tile's edges,
+// so the tile writes its inner (64 - 2K) x (TY - 2K) columns and the chunk's planes, preceded by
+// K lead-in planes; it writes u^{n+K} and u^{n+K-1}.  Taller tiles re-read fewer halo rows
+// (64 x 32 tiles write 58 x 26 columns at K = 3, against 58 x 10 of 64 x 16).  On the box faces a
+// real node takes its mirrored neighbour from the true node, as the single-step kernel does, so
+// every real node sees the same operands in the same order: blocked and single-step periods
+// agree bit for bit.  Halo lanes, rows and planes outside the box read clamped addresses and are
+// never stored.
+constexpr int kBlockWaves = 16;
 constexpr int kBlockChunk = 32;
 
-// Launch shape of the blocked sweep: planes per workgroup and whether workgroups are dealt to
-// the 8 XCDs in contiguous runs (so that neighbouring tiles, whose halos overlap, share an L2).
+// Launch shape of the blocked sweep: planes per workgroup and whether workgroups are dealt to the
+// 8 XCDs in contiguous runs (so that neighbouring tiles, whose halos overlap, share an L2).
 struct F2BlockShape {
   int chunk = kBlockChunk;
   int xcd = 0;
 };
+
+// rows per wavefront by default: one.  Two rows (64 x 32 tiles) read 23% fewer halo nodes but
+// raise the FP32 K = 3 instance from 52 to 84 VGPRs, one 16-wave workgroup per CU instead of two,
+// and measured slower on the 512^3 inclusions (983 against 884 us per launch)
+template <typename T>
+constexpr int default_rpw() { return 1; }
 
 // Tile (bx, by, bz) of workgroup blockIdx: in launch order, or XCD-aware (consecutive workgroup
 // ids go round-robin over the XCDs; the remap gives each XCD a contiguous run of tiles).
@@ -314,98 +323,131 @@ __device__ __forceinline__ void block_tile(int xcd, int &bx, int &by, int &bz) {
 // INNER: the tile's columns and rows (halo included) hold no node on an x or y box face and no
 // sound-soft node, so the x/y mirror substitutions, the mask and the x/y absorbing faces drop
 // out; only the z face planes (plane-uniform) keep their mirror and absorption.
-template <typename T, int K, bool INNER>
+template <typename T, int K, int RPW, bool INNER>
 __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, const T *prev,
                                               const T *lam, T *out_k, T *out_km1,
-                                              T (&lds)[K][2][kBlockRows][64], int bx, int by,
-                                              int bz, int chunk) {
-  constexpr int TY = kBlockRows, OW = 64 - 2 * K, OH = TY - 2 * K;
+                                              T (&lds)[K][2][kBlockWaves * RPW][64], int bx,
+                                              int by, int bz, int chunk) {
+  constexpr int TY = kBlockWaves * RPW, OW = 64 - 2 * K, OH = TY - 2 * K;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = bx * OW - K + lane;
-  const int j = by * OH - K + w;
   const int k0 = bz * chunk, k1 = min(k0 + chunk, g.nz + 1);
-  const int ic = INNER ? i : min(max(i, 0), g.nx), jc = INNER ? j : min(max(j, 0), g.ny);
-  const bool store = lane >= K && lane < 64 - K && w >= K && w < TY - K && i <= g.nx && j <= g.ny;
-  const int wm = w > 0 ? w - 1 : w, wp = w < TY - 1 ? w + 1 : w;
-  const size_t col = (size_t)jc * g.px + ic;
-  // absorbing faces at this column from the x and y faces (zero for INNER tiles)
-  const int mxy = INNER ? 0
-                        : (ic == 0 ? g.abs_face[0] : 0) + (ic == g.nx ? g.abs_face[1] : 0) +
-                              (jc == 0 ? g.abs_face[2] : 0) + (jc == g.ny ? g.abs_face[3] : 0);
-  T W[K][3];            // level s: its values at the three latest planes
-  T Ld[K + 1], Rd[K + 1];   // lambda and R at planes p, p-1, ..., p-K
-  T b1 = T(0);          // u^{n-1} at plane p-1 (the older state of level 1)
+  const int ic = INNER ? i : min(max(i, 0), g.nx);
+  // per row t of this wavefront: tile row R = RPW w + t, box row j
+  int jr[RPW], jcr[RPW], mxy[RPW];
+  size_t col[RPW];
+  bool store[RPW];
 #pragma unroll
-  for (int s = 0; s < K; ++s) W[s][0] = W[s][1] = W[s][2] = T(0);
+  for (int t = 0; t < RPW; ++t) {
+    const int R = RPW * w + t;
+    const int j = by * OH - K + R;
+    jr[t] = j;
+    jcr[t] = INNER ? j : min(max(j, 0), g.ny);
+    col[t] = (size_t)jcr[t] * g.px + ic;
+    store[t] = lane >= K && lane < 64 - K && R >= K && R < TY - K && i <= g.nx && j <= g.ny;
+    // absorbing faces at this column from the x and y faces (zero for INNER tiles)
+    mxy[t] = INNER ? 0
+                   : (ic == 0 ? g.abs_face[0] : 0) + (ic == g.nx ? g.abs_face[1] : 0) +
+                         (jcr[t] == 0 ? g.abs_face[2] : 0) + (jcr[t] == g.ny ? g.abs_face[3] : 0);
+  }
+  // the rows just outside this wavefront's rows (clamped to the tile), read from LDS
+  const int Rlo = RPW * w > 0 ? RPW * w - 1 : 0;
+  const int Rhi = RPW * w + RPW < TY ? RPW * w + RPW : TY - 1;
+  T W[RPW][K][3];             // level s: its values at the three latest planes
+  T Ld[RPW][K + 1], Rd[RPW][K + 1];   // lambda and R at planes p, p-1, ..., p-K
+  T b1[RPW];                  // u^{n-1} at plane p-1 (the older state of level 1)
 #pragma unroll
-  for (int d = 0; d <= K; ++d) Ld[d] = Rd[d] = T(1);
+  for (int t = 0; t < RPW; ++t) {
+    b1[t] = T(0);
+#pragma unroll
+    for (int s = 0; s < K; ++s) W[t][s][0] = W[t][s][1] = W[t][s][2] = T(0);
+#pragma unroll
+    for (int d = 0; d <= K; ++d) Ld[t][d] = Rd[t][d] = T(1);
+  }
   // The loads of plane p + 1 are issued before plane p is computed, into the other of two
   // register sets (the loop is unrolled by two so that the sets trade roles without copies),
   // and the barrier waits for LDS only: the loads stay in flight across it.  (Loads two planes
   // ahead, with three register sets, measured slower.)
   struct Plane {
-    T a, b, l, r;
+    T a[RPW], b[RPW], l[RPW], r[RPW];
   };
   auto load_plane = [&](int p, Plane &x) {
     const int pc = min(max(p, 0), g.nz);
-    const size_t o = (size_t)pc * g.plane + col;
-    x.a = cur[o];
-    x.b = prev[o];
-    x.l = lam_at(g, lam, o);
-    x.r = INNER ? T(1) : (masked(g, ic, jc, pc) ? T(0) : T(1));
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const size_t o = (size_t)pc * g.plane + col[t];
+      x.a[t] = cur[o];
+      x.b[t] = prev[o];
+      x.l[t] = lam_at(g, lam, o);
+      x.r[t] = INNER ? T(1) : (masked(g, ic, jcr[t], pc) ? T(0) : T(1));
+    }
   };
   auto plane_iteration = [&](int p, const Plane &x) {
 #pragma unroll
-    for (int d = K; d > 0; --d) {
-      Ld[d] = Ld[d - 1];
-      if (!INNER) Rd[d] = Rd[d - 1];
+    for (int t = 0; t < RPW; ++t) {
+#pragma unroll
+      for (int d = K; d > 0; --d) {
+        Ld[t][d] = Ld[t][d - 1];
+        if (!INNER) Rd[t][d] = Rd[t][d - 1];
+      }
+      Ld[t][0] = x.l[t];
+      if (!INNER) Rd[t][0] = x.r[t];
+      W[t][0][0] = W[t][0][1];
+      W[t][0][1] = W[t][0][2];
+      W[t][0][2] = x.a[t];
+      lds[0][p & 1][RPW * w + t][lane] = x.a[t];
     }
-    Ld[0] = x.l;
-    if (!INNER) Rd[0] = x.r;
-    W[0][0] = W[0][1];
-    W[0][1] = W[0][2];
-    W[0][2] = x.a;
-    lds[0][p & 1][w][lane] = x.a;
 #pragma unroll
     for (int s = 1; s <= K; ++s) {
       const int q = p - s;
-      T zm = W[s - 1][0];
-      const T zc = W[s - 1][1];
-      T zp = W[s - 1][2];
-      T xl = lane_from_left(zc), xr = lane_from_right(zc);
-      T ym = lds[s - 1][(p - 1) & 1][wm][lane], yp = lds[s - 1][(p - 1) & 1][wp][lane];
-      if (!INNER) {
-        if (i == 0) xl = xr;
-        if (i == g.nx) xr = xl;
-        if (j == 0) ym = yp;
-        if (j == g.ny) yp = ym;
+      // the wavefront's neighbour rows of level s-1 at plane q (written one iteration ago)
+      const T yl = lds[s - 1][(p - 1) & 1][Rlo][lane];
+      const T yh = lds[s - 1][(p - 1) & 1][Rhi][lane];
+      T un[RPW];
+#pragma unroll
+      for (int t = 0; t < RPW; ++t) {
+        T zm = W[t][s - 1][0];
+        const T zc = W[t][s - 1][1];
+        T zp = W[t][s - 1][2];
+        T xl = lane_from_left(zc), xr = lane_from_right(zc);
+        T ym = t > 0 ? W[t - 1][s - 1][1] : (RPW * w > 0 ? yl : zc);
+        T yp = t < RPW - 1 ? W[t + 1][s - 1][1] : (RPW * w + RPW < TY ? yh : zc);
+        if (!INNER) {
+          if (i == 0) xl = xr;
+          if (i == g.nx) xr = xl;
+          if (jr[t] == 0) ym = yp;
+          if (jr[t] == g.ny) yp = ym;
+        }
+        if (q == 0) zm = zp;
+        if (q == g.nz) zp = zm;
+        const T lap = T(6) * zc - (zm + zp + xl + xr + ym + yp);
+        const T l = Ld[t][s];
+        const T aux = s == 1 ? b1[t] : W[t][s >= 2 ? s - 2 : 0][0];
+        const int m = mxy[t] + (q == 0 ? g.abs_face[4] : 0) + (q == g.nz ? g.abs_face[5] : 0);
+        if (m == 0) {
+          un[t] = fma(-l, lap, T(2) * zc - aux);
+        } else {
+          const T beta = (T)m * sqrt(l);
+          un[t] = (T(2) * zc - (T(1) - beta) * aux - l * lap) / (T(1) + beta);
+        }
+        if (!INNER) un[t] = Rd[t][s] != T(0) ? un[t] : T(0);
       }
-      if (q == 0) zm = zp;
-      if (q == g.nz) zp = zm;
-      const T lap = T(6) * zc - (zm + zp + xl + xr + ym + yp);
-      const T l = Ld[s];
-      const T aux = s == 1 ? b1 : W[s >= 2 ? s - 2 : 0][0];
-      const int m = mxy + (q == 0 ? g.abs_face[4] : 0) + (q == g.nz ? g.abs_face[5] : 0);
-      T un;
-      if (m == 0) {
-        un = fma(-l, lap, T(2) * zc - aux);
-      } else {
-        const T beta = (T)m * sqrt(l);
-        un = (T(2) * zc - (T(1) - beta) * aux - l * lap) / (T(1) + beta);
-      }
-      if (!INNER) un = Rd[s] != T(0) ? un : T(0);
-      if (s < K) {
-        W[s][0] = W[s][1];
-        W[s][1] = W[s][2];
-        W[s][2] = un;
-        lds[s][p & 1][w][lane] = un;
-      }
-      if (store && q >= k0 && q < k1) {
-        if (s == K) out_k[(size_t)q * g.plane + col] = un;
-        if (s == K - 1) out_km1[(size_t)q * g.plane + col] = un;
+#pragma unroll
+      for (int t = 0; t < RPW; ++t) {
+        if (s < K) {
+          W[t][s][0] = W[t][s][1];
+          W[t][s][1] = W[t][s][2];
+          W[t][s][2] = un[t];
+          lds[s][p & 1][RPW * w + t][lane] = un[t];
+        }
+        if (store[t] && q >= k0 && q < k1) {
+          if (s == K) out_k[(size_t)q * g.plane + col[t]] = un[t];
+          if (s == K - 1) out_km1[(size_t)q * g.plane + col[t]] = un[t];
+        }
       }
     }
-    b1 = x.b;
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) b1[t] = x.b[t];
     // LDS-only barrier: this plane's LDS writes are visible to the next iteration's reads,
     // and the next iteration's writes (the other parity) follow this iteration's reads
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -428,17 +470,17 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
   }
 }
 
-template <typename T, int K>
-__global__ __launch_bounds__(64 * kBlockRows) void f2_block_kernel(F2Geom g, const T *cur,
-                                                                    const T *prev, const T *lam,
-                                                                    T *out_k, T *out_km1,
-                                                                    F2BlockShape shape) {
-  constexpr int OW = 64 - 2 * K, OH = kBlockRows - 2 * K;
-  __shared__ T lds[K][2][kBlockRows][64];
+template <typename T, int K, int RPW>
+__global__ __launch_bounds__(64 * kBlockWaves) void f2_block_kernel(F2Geom g, const T *cur,
+                                                                     const T *prev, const T *lam,
+                                                                     T *out_k, T *out_km1,
+                                                                     F2BlockShape shape) {
+  constexpr int TY = kBlockWaves * RPW, OW = 64 - 2 * K, OH = TY - 2 * K;
+  __shared__ T lds[K][2][TY][64];
   int bx, by, bz;
   block_tile(shape.xcd, bx, by, bz);
   const int i0 = bx * OW - K, j0 = by * OH - K;
-  const int i1 = i0 + 63, j1 = j0 + kBlockRows - 1;
+  const int i1 = i0 + 63, j1 = j0 + TY - 1;
   const bool faces = i0 < 1 || i1 > g.nx - 1 || j0 < 1 || j1 > g.ny - 1;
   // the tile reads planes k0 - K .. k1 + K - 1 of its chunk: it meets a sound-soft node only if
   // that slab meets the mask's bounding box too
@@ -446,9 +488,11 @@ __global__ __launch_bounds__(64 * kBlockRows) void f2_block_kernel(F2Geom g, con
   const bool mask = g.mask && i1 >= g.mlo[0] && i0 <= g.mhi[0] && j1 >= g.mlo[1] &&
                     j0 <= g.mhi[1] && k1 + K - 1 >= g.mlo[2] && k0 - K <= g.mhi[2];
   if (!faces && !mask)
-    f2_block_tile<T, K, true>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz, shape.chunk);
+    f2_block_tile<T, K, RPW, true>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,
+                                   shape.chunk);
   else
-    f2_block_tile<T, K, false>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz, shape.chunk);
+    f2_block_tile<T, K, RPW, false>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,
+                                    shape.chunk);
 }
 
 // out = psi in, psi = lambda R / ((1 + beta) eta)
@@ -514,10 +558,13 @@ __device__ __forceinline__ double minv_at(const F2Geom &g, const T *lam, size_t 
 
 // Steps 5.4-5.5 with primal and dual residuals (the velocity block of the primal residual is
 // r_v = M^{-1} rh_v and is not stored):  z -= alpha d, r_u -= alpha q_u, rh -= alpha qh;
-// partial delta' = <rh, r> = rh_u . r_u + rh_v . M^{-1} rh_v
-template <typename T, typename TQ>
-__global__ __launch_bounds__(kRedThreads) void f2_cg_update_kernel(F2Geom g, double *z, double *ru,
-                                                                   double *rh, const T *d,
+// partial delta' = <rh, r> = rh_u . r_u + rh_v . M^{-1} rh_v.  The arithmetic is FP64; TR is the
+// residuals' storage type, and TZ the iterate's: FP64 z, or (FP32-mixed) the FP32 correction
+// dz accumulated since the iterate was last brought up to date (z -= alpha d becomes
+// dz -= alpha d, and z += dz, dz = 0 at every reliable update).
+template <typename T, typename TQ, typename TR, typename TZ>
+__global__ __launch_bounds__(kRedThreads) void f2_cg_update_kernel(F2Geom g, TZ *z, TR *ru,
+                                                                   TR *rh, const T *d,
                                                                    const TQ *qu, const T *qh,
                                                                    const T *lam, const double *sc,
                                                                    double *partials) {
@@ -525,29 +572,36 @@ __global__ __launch_bounds__(kRedThreads) void f2_cg_update_kernel(F2Geom g, dou
   const size_t fs = g.fs;
   double acc = 0.0;
   F2_ROWS(g)
-  z[o] -= alpha * (double)d[o];
-  z[o + fs] -= alpha * (double)d[o + fs];
-  const double rn = ru[o] - alpha * (double)qu[o];
+  z[o] = (TZ)((double)z[o] - alpha * (double)d[o]);
+  z[o + fs] = (TZ)((double)z[o + fs] - alpha * (double)d[o + fs]);
+  const TR rn = (TR)((double)ru[o] - alpha * (double)qu[o]);
   ru[o] = rn;
-  const double rhu = rh[o] - alpha * (double)qh[o];
-  const double rhv = rh[o + fs] - alpha * (double)qh[o + fs];
+  const TR rhu = (TR)((double)rh[o] - alpha * (double)qh[o]);
+  const TR rhv = (TR)((double)rh[o + fs] - alpha * (double)qh[o + fs]);
   rh[o] = rhu;
   rh[o + fs] = rhv;
-  acc += rhu * rn + rhv * rhv * minv_at(g, lam, o, i, j, k);
+  acc += (double)rhu * (double)rn + (double)rhv * (double)rhv * minv_at(g, lam, o, i, j, k);
   F2_ROWS_END
   const double t = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// delta = <rh, r> with r_v = M^{-1} rh_v
-template <typename T>
+// delta = <rh, r> with r_v = M^{-1} rh_v; with `rus`, `rhs` non-null the residuals (FP64) are
+// also stored there in their storage type
+template <typename T, typename TR>
 __global__ __launch_bounds__(kRedThreads) void f2_delta_kernel(F2Geom g, const double *ru,
                                                                const double *rh, const T *lam,
+                                                               TR *rus, TR *rhs,
                                                                double *partials) {
   const size_t fs = g.fs;
   double acc = 0.0;
   F2_ROWS(g)
   acc += rh[o] * ru[o] + rh[o + fs] * rh[o + fs] * minv_at(g, lam, o, i, j, k);
+  if (rus) {
+    rus[o] = (TR)ru[o];
+    rhs[o] = (TR)rh[o];
+    rhs[o + fs] = (TR)rh[o + fs];
+  }
   F2_ROWS_END
   const double t = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -555,14 +609,39 @@ __global__ __launch_bounds__(kRedThreads) void f2_delta_kernel(F2Geom g, const d
 
 // Step 5.7: d = r + beta d  (d_u = r_u + beta d_u, d_v = M^{-1} rh_v + beta d_v); beta from sc,
 // or 0 when `first` (d = r)
-template <typename T>
-__global__ void f2_direction_kernel(F2Geom g, T *d, const double *ru, const double *rh,
-                                    const T *lam, const double *sc, int first) {
+template <typename T, typename TR>
+__global__ void f2_direction_kernel(F2Geom g, T *d, const TR *ru, const TR *rh, const T *lam,
+                                    const double *sc, int first) {
   const size_t fs = g.fs;
   const double beta = first ? 0.0 : sc[kBeta];
   F2_ROWS(g)
-  d[o] = (T)(ru[o] + beta * (double)d[o]);
-  d[o + fs] = (T)(minv_at(g, lam, o, i, j, k) * rh[o + fs] + beta * (double)d[o + fs]);
+  d[o] = (T)((double)ru[o] + beta * (double)d[o]);
+  d[o + fs] = (T)(minv_at(g, lam, o, i, j, k) * (double)rh[o + fs] + beta * (double)d[o + fs]);
+  F2_ROWS_END
+}
+
+// out = z + dz (two fields), the iterate with its FP32 correction; `clear`: dz = 0 (out == z
+// brings the iterate up to date in place)
+__global__ void f2_iterate_kernel(F2Geom g, const double *z, float *dz, double *out, int clear) {
+  const size_t fs = g.fs;
+  F2_ROWS(g)
+  const double a = z[o] + (double)dz[o], b = z[o + fs] + (double)dz[o + fs];
+  out[o] = a;
+  out[o + fs] = b;
+  if (clear) {
+    dz[o] = 0.0f;
+    dz[o + fs] = 0.0f;
+  }
+  F2_ROWS_END
+}
+
+// out = in (two fields: u, and the velocity block through M^{-1}), widened to FP64
+template <typename TR, typename T>
+__global__ void f2_primal_kernel(F2Geom g, const TR *ru, const TR *rh, const T *lam, double *out) {
+  const size_t fs = g.fs;
+  F2_ROWS(g)
+  out[o] = (double)ru[o];
+  out[o + fs] = minv_at(g, lam, o, i, j, k) * (double)rh[o + fs];
   F2_ROWS_END
 }
 
@@ -703,18 +782,30 @@ hipError_t f2_march_block(const F2Geom &g, const T *cur, const T *prev, const T 
     if (const char *e = std::getenv("CMCG_F2_XCD")) sh.xcd = std::atoi(e);
     return sh;
   }();
-  dim3 block(64 * kBlockRows);
+  // CMCG_F2_RPW (environment, read per launch): rows per wavefront, 1 or 2
+  const char *re = std::getenv("CMCG_F2_RPW");
+  const int want = re ? std::atoi(re) : 0;
+  const int rpw = (want == 1 || want == 2) ? want : default_rpw<T>();
+  dim3 block(64 * kBlockWaves);
   auto grid = [&](int k) {
+    const int ty = kBlockWaves * rpw;
     return dim3((g.nx + 1 + 64 - 2 * k - 1) / (64 - 2 * k),
-                (g.ny + 1 + kBlockRows - 2 * k - 1) / (kBlockRows - 2 * k),
+                (g.ny + 1 + ty - 2 * k - 1) / (ty - 2 * k),
                 (g.nz + 1 + shape.chunk - 1) / shape.chunk);
   };
-  switch (K) {
-    case 2: hipLaunchKernelGGL((f2_block_kernel<T, 2>), grid(2), block, 0, s, g, cur, prev, lam, out_k, out_km1, shape); break;
-    case 3: hipLaunchKernelGGL((f2_block_kernel<T, 3>), grid(3), block, 0, s, g, cur, prev, lam, out_k, out_km1, shape); break;
-    case 4: hipLaunchKernelGGL((f2_block_kernel<T, 4>), grid(4), block, 0, s, g, cur, prev, lam, out_k, out_km1, shape); break;
+#define CMCG_F2_BLOCK(KK, RR)                                                                  \
+  hipLaunchKernelGGL((f2_block_kernel<T, KK, RR>), grid(KK), block, 0, s, g, cur, prev, lam,   \
+                     out_k, out_km1, shape)
+  switch (K * 4 + rpw) {
+    case 2 * 4 + 1: CMCG_F2_BLOCK(2, 1); break;
+    case 3 * 4 + 1: CMCG_F2_BLOCK(3, 1); break;
+    case 4 * 4 + 1: CMCG_F2_BLOCK(4, 1); break;
+    case 2 * 4 + 2: CMCG_F2_BLOCK(2, 2); break;
+    case 3 * 4 + 2: CMCG_F2_BLOCK(3, 2); break;
+    case 4 * 4 + 2: CMCG_F2_BLOCK(4, 2); break;
     default: return hipErrorInvalidValue;
   }
+#undef CMCG_F2_BLOCK
   return hipGetLastError();
 }
 
@@ -731,28 +822,42 @@ hipError_t dot_plain(const TA *a, const TB *b, size_t n, double *partials, hipSt
   return hipGetLastError();
 }
 
-template <typename T, typename TQ>
-hipError_t f2_cg_update(const F2Geom &g, double *z, double *ru, double *rh, const T *d,
-                        const TQ *qu, const T *qh, const T *lam, const double *sc,
-                        double *partials, hipStream_t s) {
-  hipLaunchKernelGGL((f2_cg_update_kernel<T, TQ>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, z,
-                     ru, rh, d, qu, qh, lam, sc, partials);
+template <typename T, typename TQ, typename TR, typename TZ>
+hipError_t f2_cg_update(const F2Geom &g, TZ *z, TR *ru, TR *rh, const T *d, const TQ *qu,
+                        const T *qh, const T *lam, const double *sc, double *partials,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((f2_cg_update_kernel<T, TQ, TR, TZ>), dim3(kRedBlocks), dim3(kRedThreads), 0,
+                     s, g, z, ru, rh, d, qu, qh, lam, sc, partials);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t f2_delta(const F2Geom &g, const double *ru, const double *rh, const T *lam,
-                    double *partials, hipStream_t s) {
-  hipLaunchKernelGGL((f2_delta_kernel<T>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, ru, rh,
-                     lam, partials);
+template <typename T, typename TR>
+hipError_t f2_delta(const F2Geom &g, const double *ru, const double *rh, const T *lam, TR *rus,
+                    TR *rhs, double *partials, hipStream_t s) {
+  hipLaunchKernelGGL((f2_delta_kernel<T, TR>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, g, ru,
+                     rh, lam, rus, rhs, partials);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t f2_direction(const F2Geom &g, T *d, const double *ru, const double *rh, const T *lam,
+template <typename T, typename TR>
+hipError_t f2_direction(const F2Geom &g, T *d, const TR *ru, const TR *rh, const T *lam,
                         const double *sc, int first, hipStream_t s) {
-  hipLaunchKernelGGL((f2_direction_kernel<T>), dim3(rows_grid(g)), dim3(256), 0, s, g, d, ru, rh,
-                     lam, sc, first);
+  hipLaunchKernelGGL((f2_direction_kernel<T, TR>), dim3(rows_grid(g)), dim3(256), 0, s, g, d, ru,
+                     rh, lam, sc, first);
+  return hipGetLastError();
+}
+
+hipError_t f2_iterate(const F2Geom &g, const double *z, float *dz, double *out, int clear,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(f2_iterate_kernel, dim3(rows_grid(g)), dim3(256), 0, s, g, z, dz, out, clear);
+  return hipGetLastError();
+}
+
+template <typename TR, typename T>
+hipError_t f2_primal(const F2Geom &g, const TR *ru, const TR *rh, const T *lam, double *out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL((f2_primal_kernel<TR, T>), dim3(rows_grid(g)), dim3(256), 0, s, g, ru, rh,
+                     lam, out);
   return hipGetLastError();
 }
 
@@ -800,13 +905,6 @@ hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, h
   template hipError_t f2_psi_scale<T>(const F2Geom &, const T *, const T *, T *, hipStream_t);   \
   template hipError_t f2_march_block<T>(const F2Geom &, const T *, const T *, const T *, T *,    \
                                         T *, int, hipStream_t);                                  \
-  template hipError_t f2_cg_update<T, double>(const F2Geom &, double *, double *, double *,     \
-                                              const T *, const double *, const T *, const T *,   \
-                                              const double *, double *, hipStream_t);            \
-  template hipError_t f2_delta<T>(const F2Geom &, const double *, const double *, const T *,     \
-                                  double *, hipStream_t);                                        \
-  template hipError_t f2_direction<T>(const F2Geom &, T *, const double *, const double *,       \
-                                      const T *, const double *, int, hipStream_t);              \
   template hipError_t f2_mass_inverse<T>(const F2Geom &, const T *, double *, const T *,         \
                                          hipStream_t);                                            \
   template hipError_t f2_setup<T>(const F2Geom &, const double *, double, const double *,        \
@@ -816,10 +914,33 @@ hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, h
   template hipError_t f2_pack<T>(const F2Geom &, const T *, double *, int, hipStream_t);
 INST(float)
 INST(double)
-template hipError_t f2_cg_update<float, float>(const F2Geom &, double *, double *, double *,
-                                               const float *, const float *, const float *,
-                                               const float *, const double *, double *,
+// CG vector passes: FP64 solves (FP64 everything), FP32-mixed solves (FP32 d, q, residuals and
+// iterate correction; q_u in FP64 from a PCG Riesz solve or FP32 from a V-cycle)
+template hipError_t f2_cg_update<double, double, double, double>(
+    const F2Geom &, double *, double *, double *, const double *, const double *, const double *,
+    const double *, const double *, double *, hipStream_t);
+template hipError_t f2_cg_update<float, double, float, float>(
+    const F2Geom &, float *, float *, float *, const float *, const double *, const float *,
+    const float *, const double *, double *, hipStream_t);
+template hipError_t f2_cg_update<float, float, float, float>(
+    const F2Geom &, float *, float *, float *, const float *, const float *, const float *,
+    const float *, const double *, double *, hipStream_t);
+template hipError_t f2_delta<double, double>(const F2Geom &, const double *, const double *,
+                                             const double *, double *, double *, double *,
+                                             hipStream_t);
+template hipError_t f2_delta<double, float>(const F2Geom &, const double *, const double *,
+                                            const double *, float *, float *, double *,
+                                            hipStream_t);
+template hipError_t f2_direction<double, double>(const F2Geom &, double *, const double *,
+                                                 const double *, const double *, const double *,
+                                                 int, hipStream_t);
+template hipError_t f2_direction<float, float>(const F2Geom &, float *, const float *,
+                                               const float *, const float *, const double *, int,
                                                hipStream_t);
+template hipError_t f2_primal<double, double>(const F2Geom &, const double *, const double *,
+                                              const double *, double *, hipStream_t);
+template hipError_t f2_primal<float, double>(const F2Geom &, const float *, const float *,
+                                             const double *, double *, hipStream_t);
 #undef INST
 template hipError_t dot_plain<double, double>(const double *, const double *, size_t, double *, hipStream_t);
 template hipError_t dot_plain<float, float>(const float *, const float *, size_t, double *, hipStream_t);

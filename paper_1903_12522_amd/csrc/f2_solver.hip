@@ -181,8 +181,10 @@ class F2Solver final : public Solver {
   uint8_t *mask = nullptr;
   void *D = nullptr;                 // direction (lo, two fields)
   double *Z = nullptr;               // iterate (two fields)
-  double *RU = nullptr;              // primal residual, u block
-  double *RH = nullptr;              // dual residual (two fields)
+  float *DZ = nullptr;               // FP32-mixed: the iterate's FP32 correction since the last
+                                     // reliable update (the iterate is Z + DZ)
+  void *RU = nullptr;                // primal residual, u block (FP64; FP32 in FP32-mixed mode)
+  void *RH = nullptr;                // dual residual (two fields, like RU)
   double *QU = nullptr;              // Riesz output, u block
   double *Ure = nullptr, *Uim = nullptr;   // filter sums, one field per component
   double *Dre = nullptr, *Dim = nullptr;   // Dirichlet data on the sound-soft nodes (one field per
@@ -305,8 +307,10 @@ class F2Solver final : public Solver {
     else lo = hi;
     CMCG_TRY(arena.alloc(2 * g.fs * (mixed ? sizeof(float) : sizeof(double)), &D, s));
     CMCG_TRY(arena.alloc_n(2 * g.fs, &Z, s));
-    CMCG_TRY(arena.alloc_n(g.fs, &RU, s));
-    CMCG_TRY(arena.alloc_n(2 * g.fs, &RH, s));
+    if (mixed) CMCG_TRY(arena.alloc_n(2 * g.fs, &DZ, s));
+    const size_t rsz = mixed ? sizeof(float) : sizeof(double);
+    CMCG_TRY(arena.alloc(g.fs * rsz, &RU, s));
+    CMCG_TRY(arena.alloc(2 * g.fs * rsz, &RH, s));
     CMCG_TRY(arena.alloc_n(g.fs, &QU, s));
     CMCG_TRY(arena.alloc_n(J * g.fs, &Ure, s));
     CMCG_TRY(arena.alloc_n(J * g.fs, &Uim, s));
@@ -713,19 +717,43 @@ class F2Solver final : public Solver {
     return CMCG_OK;
   }
 
-  // true gradient at the FP64 iterate: RH = qh (dual), RU = S^{-1} qh_u; delta via `mode`
+  // true gradient at the FP64 iterate: RH = qh (dual), RU = S^{-1} qh_u; delta via `mode`.
+  // FP32-mixed: the iterate is first brought up to date (Z += DZ, DZ = 0: the reliable update),
+  // delta is formed from the FP64 residuals, which are then stored in FP32.
   cmcg_status true_gradient(int mode) {
+    if (mixed) CMCG_HIP(f2_iterate(g, Z, DZ, Z, 1, s));
     CMCG_TRY(gradient_dual(hi, true, Z));
-    CMCG_HIP(hipMemcpyAsync(RH, hi.W, 2 * g.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
-    CMCG_TRY(riesz_u(RH, 0, RU));
-    CMCG_HIP(f2_delta<double>(g, RU, RH, tpc<double>(hi.lam), partials, s));
+    if (mixed) {
+      CMCG_TRY(riesz_u(hi.W, 0, QU));
+      CMCG_HIP((f2_delta<double, float>(g, QU, tpc<double>(hi.W), tpc<double>(hi.lam),
+                                        tp<float>(RU), tp<float>(RH), partials, s)));
+    } else {
+      CMCG_HIP(hipMemcpyAsync(RH, hi.W, 2 * g.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+      CMCG_TRY(riesz_u(RH, 0, tp<double>(RU)));
+      CMCG_HIP((f2_delta<double, double>(g, tpc<double>(RU), tpc<double>(RH),
+                                         tpc<double>(hi.lam), nullptr, nullptr, partials, s)));
+    }
     CMCG_HIP(finalize(partials, kRedBlocks, scalars, mode, 0, s));
     return CMCG_OK;
   }
 
   cmcg_status direction(int first) {
-    if (mixed) CMCG_HIP(f2_direction<float>(g, tp<float>(D), RU, RH, tpc<float>(lo.lam), scalars, first, s));
-    else CMCG_HIP(f2_direction<double>(g, tp<double>(D), RU, RH, tpc<double>(lo.lam), scalars, first, s));
+    if (mixed)
+      CMCG_HIP((f2_direction<float, float>(g, tp<float>(D), tpc<float>(RU), tpc<float>(RH),
+                                           tpc<float>(lo.lam), scalars, first, s)));
+    else
+      CMCG_HIP((f2_direction<double, double>(g, tp<double>(D), tpc<double>(RU), tpc<double>(RH),
+                                             tpc<double>(lo.lam), scalars, first, s)));
+    return CMCG_OK;
+  }
+
+  // The current iterate as an FP64 device field: Z, or (FP32-mixed) Z + DZ staged in `stage`
+  // (the state itself is left as it is, so that reading it changes no later rounding)
+  cmcg_status current_iterate(double *stage, const double **z) {
+    *z = Z;
+    if (!mixed) return CMCG_OK;
+    CMCG_HIP(f2_iterate(g, Z, DZ, stage, 0, s));
+    *z = stage;
     return CMCG_OK;
   }
 
@@ -761,6 +789,7 @@ class F2Solver final : public Solver {
     bulk.reset();
     CMCG_HIP(hipEventRecord(ev[0], s));
     CMCG_HIP(hipMemsetAsync(Z, 0, 2 * g.fs * sizeof(double), s));
+    if (mixed) CMCG_HIP(hipMemsetAsync(DZ, 0, 2 * g.fs * sizeof(float), s));
     CMCG_TRY(true_gradient(kFinStart));
     if (cfg.runup > 0) {
       // start from the run-up state; delta0 stays the residual at rest (stopping reference)
@@ -812,19 +841,19 @@ class F2Solver final : public Solver {
         CMCG_HIP(dot_plain<float, float>(tpc<float>(lo.W), tpc<float>(D), 2 * g.fs, partials, s));
         CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinAlpha, 0, s));
         if (qu32)
-          CMCG_HIP((f2_cg_update<float, float>(g, Z, RU, RH, tpc<float>(D), qu32,
-                                               tpc<float>(lo.W), tpc<float>(lo.lam), scalars,
-                                               partials, s)));
+          CMCG_HIP((f2_cg_update<float, float, float, float>(
+              g, DZ, tp<float>(RU), tp<float>(RH), tpc<float>(D), qu32, tpc<float>(lo.W),
+              tpc<float>(lo.lam), scalars, partials, s)));
         else
-          CMCG_HIP((f2_cg_update<float, double>(g, Z, RU, RH, tpc<float>(D), QU,
-                                                tpc<float>(lo.W), tpc<float>(lo.lam), scalars,
-                                                partials, s)));
+          CMCG_HIP((f2_cg_update<float, double, float, float>(
+              g, DZ, tp<float>(RU), tp<float>(RH), tpc<float>(D), QU, tpc<float>(lo.W),
+              tpc<float>(lo.lam), scalars, partials, s)));
       } else {
         CMCG_HIP(dot_plain<double, double>(tpc<double>(lo.W), tpc<double>(D), 2 * g.fs, partials, s));
         CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinAlpha, 0, s));
-        CMCG_HIP((f2_cg_update<double, double>(g, Z, RU, RH, tpc<double>(D), QU,
-                                               tpc<double>(lo.W), tpc<double>(lo.lam), scalars,
-                                               partials, s)));
+        CMCG_HIP((f2_cg_update<double, double, double, double>(
+            g, Z, tp<double>(RU), tp<double>(RH), tpc<double>(D), QU, tpc<double>(lo.W),
+            tpc<double>(lo.lam), scalars, partials, s)));
       }
       CMCG_HIP(finalize(partials, kRedBlocks, scalars, kFinBeta, 0, s));
       CMCG_HIP(hipEventRecord(ev[6], s));
@@ -893,12 +922,17 @@ class F2Solver final : public Solver {
 
   cmcg_status finish(double *u_re, double *u_im) override {
     if (!started) return set_error("cmcg_begin first"), CMCG_EINVAL;
+    const double *z = Z;
     if (cfg.output == CMCG_OUTPUT_STEP6) {
-      CMCG_TRY(step6_from(Z, u_re, u_im));
+      // (step6_from stages its output in hi.Y)
+      CMCG_TRY(current_iterate(tp<double>(hi.W), &z));
+      CMCG_TRY(step6_from(z, u_re, u_im));
       CMCG_HIP(hipEventRecord(ev[7], s));
       return CMCG_OK;
     }
-    return output(Z, u_re, u_im, true);
+    // (the forced period reads its input from hi.Y and writes hi.W)
+    CMCG_TRY(current_iterate(tp<double>(hi.Y), &z));
+    return output(z, u_re, u_im, true);
   }
 
   // Step 6 read off a device-layout FP64 state (u_0 + i v_1 / wh, Dirichlet data on the
@@ -988,11 +1022,17 @@ class F2Solver final : public Solver {
 
   cmcg_status get_state(int which, double *out) override {
     if (which == 0) {
-      CMCG_HIP(f2_pack<double>(g, Z, out, 2, s));
+      const double *z = Z;
+      CMCG_TRY(current_iterate(tp<double>(hi.W), &z));
+      CMCG_HIP(f2_pack<double>(g, z, out, 2, s));
     } else if (which == 1) {
       // primal residual (r_u, M^{-1} rh_v)
-      CMCG_HIP(hipMemcpyAsync(hi.W, RU, g.fs * sizeof(double), hipMemcpyDeviceToDevice, s));
-      CMCG_HIP(f2_mass_inverse<double>(g, RH + g.fs, tp<double>(hi.W) + g.fs, tpc<double>(hi.lam), s));
+      if (mixed)
+        CMCG_HIP((f2_primal<float, double>(g, tpc<float>(RU), tpc<float>(RH),
+                                           tpc<double>(hi.lam), tp<double>(hi.W), s)));
+      else
+        CMCG_HIP((f2_primal<double, double>(g, tpc<double>(RU), tpc<double>(RH),
+                                            tpc<double>(hi.lam), tp<double>(hi.W), s)));
       CMCG_HIP(f2_pack<double>(g, tp<double>(hi.W), out, 2, s));
     } else if (mixed) {
       CMCG_HIP(f2_pack<float>(g, tp<float>(D), out, 2, s));

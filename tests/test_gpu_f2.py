@@ -70,6 +70,23 @@ def test_temporal_blocking_is_bitwise(cm, prec):
         assert _rel(outs[2][1], o.period_T(z)) < 1e-13
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_blocked_tile_height_is_bitwise(cm, prec, monkeypatch):
+    """Tiles of one row per wavefront (64 x 16) and of two (64 x 32, CMCG_F2_RPW=2) give the same
+    periods bit for bit on a ragged box with a sound-soft block and mixed faces, where tile
+    edges fall at different rows."""
+    prob = _mixed3d(n=(70, 45, 40), seed=12)
+    o = F2(prob)
+    z = np.random.default_rng(13).standard_normal(o.size) * np.concatenate([o.free.ravel()] * 2)
+    outs = []
+    for rpw in ("1", "2"):
+        monkeypatch.setenv("CMCG_F2_RPW", rpw)
+        with cm.Solver(prob, prec, steps_per_launch=3) as s:
+            outs.append((s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z)))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_blocking_bitwise_around_a_sound_soft_ball(cm, prec):
     """129^3 nodes, a sound-soft ball in the middle: interior tiles whose columns cross the
@@ -219,6 +236,23 @@ def test_fp32_mixed_matches_fp64(cm):
     assert r64["converged"] and r32["converged"]
     assert _rel(U32, U64) < 1e-4
     assert r32["iterations"] <= 1.2 * r64["iterations"] + 5
+
+
+@pytest.mark.parametrize("riesz", ["solve", "vcycle"])
+@pytest.mark.parametrize("n,freq,width", [(32, 3.0, 0.05), (128, 8.0, 0.02)])
+def test_fp32_mixed_storage_tracks_fp64(cm, n, freq, width, riesz):
+    """FP32-mixed CG stores its residuals and the iterate's correction since the last reliable
+    update in FP32 (FP64 arithmetic; the FP64 iterate is brought up to date at every refresh):
+    the solution stays within 1e-4 of the FP64 solve's, in as many iterations within 5%."""
+    prob = ci.inclusions_3d(n=n, freq=freq, n_incl=10, seed=4, width=width)
+    with cm.Solver(prob, "fp64", tol=1e-6, max_iter=4000, riesz_mode=riesz) as s:
+        U64, r64 = s.solve()
+    with cm.Solver(prob, "fp32", tol=1e-6, max_iter=4000, riesz_mode=riesz) as s:
+        U32, r32 = s.solve()
+    assert r64["converged"] and r32["converged"]
+    assert _rel(U32, U64) < 1e-4
+    assert abs(r32["iterations"] - r64["iterations"]) <= 0.05 * r64["iterations"] + 1, \
+        (r32["iterations"], r64["iterations"])
 
 
 def test_sound_soft_field_vanishes_on_obstacle(cm):
