@@ -8,11 +8,14 @@ period, the adjoint (backward) period, the energy inner products and the CG upda
 timed steps, inputs resident in HBM.
 
 Also reported: time-to-solution at relative residual 1e-6 in FP32-mixed and FP64 (full solves
-from z = 0 including the filter), their ratio and the FP32-mixed error against FP64, the
-roofline of the dominant kernel from the library's HIP events, and the CPU oracle timed on a
-bounded sample of the same workload.
+from z = 0 including the filter) on the 4096^2 problem and on the 512^3 second-order inclusions
+problem (both precisions with the same Riesz map, one fixed V-cycle, so that their ratio is the
+precision's alone), their ratios and the FP32-mixed errors against FP64; the roofline of each
+workload's dominant kernel from the library's HIP events around that kernel's own launches;
+and the CPU oracle timed on a bounded sample of the 4096^2 workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-tts] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-tts] [--no-cpu] [--no-c3]
+       python bench.py --c3-iters K   (K FP32-mixed CG iterations of the 512^3 problem only)
        python bench.py --calibrate-copy   (one 1 GiB device copy, for counter calibration)
 """
 from __future__ import annotations
@@ -48,20 +51,57 @@ def calibrate_copy():
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter record (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain-copy calibration), or None when the record is for another
-    version of the kernel source."""
+    WRITE_SIZE, scaled by a plain-copy calibration), or None when the record was taken on
+    another version of the kernel's source file."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
-    src = os.path.join(ROOT, "paper_1903_12522_amd", "csrc", "f1_kernels.hip")
     try:
         rec = json.load(open(rec_path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
     e = rec.get("kernels", {}).get(kernel)
-    if not e or rec.get("f1_kernels_sha256") != sha:
+    if not e or "source" not in e:
+        return None
+    src = os.path.join(ROOT, "paper_1903_12522_amd", "csrc", e["source"])
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("sources", {}).get(e["source"]) != sha:
         return None
     return int(e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"])
+
+
+def roofline_entry(kernel: str, launch_s: float, alg_bytes: float, one_pass_bytes: float,
+                   launches: int, **extra):
+    """The roofline of one kernel instance from its own average launch time.
+
+    * achieved / frac: the scope's convention for the leapfrog sweep, single-step compulsory
+      bytes per grid-point update times the updates of one launch (K steps of every point),
+      divided by the launch time.  With temporal blocking one HBM pass serves K steps, so frac
+      can exceed 1: it measures the sweep's rate, not the position under the HBM roof.
+    * one_pass_bytes / frac_one_pass: the launch's own compulsory traffic (its inputs read once,
+      its outputs written once) at the 8 TB/s peak, against its launch time: where the kernel
+      sits under the roof.
+    * traffic / measured_GBps / frac_measured: the HBM bytes the counters saw per launch
+      (null once the kernel's source has changed since they were taken)."""
+    traffic = measured_traffic(kernel)
+    achieved = alg_bytes / launch_s / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 3),
+           "frac_convention": "single-step compulsory bytes x K steps per launch / launch time "
+                              "(temporally blocked: can exceed 1)",
+           "traffic": traffic,
+           "kernel": kernel, "avg_launch_us": round(launch_s * 1e6, 2), "launches": launches,
+           "algorithmic_bytes_per_launch": int(alg_bytes),
+           "one_pass_bytes": int(one_pass_bytes),
+           "one_pass_time_us": round(one_pass_bytes / (HBM_PEAK_GBS * 1e9) * 1e6, 2),
+           "frac_one_pass": round(one_pass_bytes / launch_s / 1e9 / HBM_PEAK_GBS, 3)}
+    if traffic is not None:
+        out["measured_GBps"] = round(traffic / launch_s / 1e9, 1)
+        out["frac_measured"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 3)
+    out.update(extra)
+    return out
 
 
 def single_source_tts():
@@ -83,16 +123,17 @@ def single_source_tts():
             "converged": rep["converged"]}
 
 
-def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10, keep=None):
-    """Time to solution (tol 1e-6) of a 3D second-order workload: begin, iterations in chunks of
-    `chunk` (a progress line per chunk), finish, timed on the host around device-synchronised
-    calls."""
+def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10, keep=None,
+             riesz_mode: str = "default", tol: float = 1e-6):
+    """Time to solution of a 3D second-order workload: begin, iterations in chunks of `chunk`
+    (a progress line per chunk), finish, timed on the host around device-synchronised calls;
+    with the roofline of the blocked kernel from the library's events around its launches."""
     import torch
     import cmcg_inputs as ci
     from paper_1903_12522_amd import cmcg
     prob = ci.inclusions_3d() if which == "inclusions" else ci.sound_soft_sphere_3d()
     torch.cuda.empty_cache()
-    with cmcg.Solver(prob, precision, tol=1e-6, max_iter=max_iter) as s:
+    with cmcg.Solver(prob, precision, tol=tol, max_iter=max_iter, riesz_mode=riesz_mode) as s:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.begin()
@@ -107,19 +148,36 @@ def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10, keep=No
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         gb = s.info["device_bytes"] / 1e9
+        kb = s.info["steps_per_launch"]
         if keep is not None:
             keep[precision] = torch.complex(u[0], u[1]).clone()
         del u
     nodes = (prob.n[0] + 1) * (prob.n[1] + 1) * (prob.n[2] + 1)
-    return {"workload": f"second-order {which} {prob.n[0]}^3, {precision}", "nodes": nodes,
-            "seconds": round(wall, 3), "iterations": rep["iterations"], "converged": bool(conv),
-            "rel_residual": rep["rel_residual"], "steps_per_period": rep["steps_per_period"],
-            "seconds_fwd": round(rep["seconds_fwd"], 3), "seconds_adj": round(rep["seconds_adj"], 3),
-            "seconds_riesz": round(rep["seconds_riesz"], 3),
-            "riesz_iterations": rep["riesz_iterations"], "fp64_refreshes": rep["fp64_refreshes"],
-            "glups_periods": round(rep["grid_updates"] / max(rep["seconds_fwd"] + rep["seconds_adj"], 1e-9) / 1e9, 1),
-            "stencil_dram_GB": round(rep["dram_bytes"] / 1e9, 1),
-            "device_GB": round(gb, 1)}
+    out = {"workload": f"second-order {which} {prob.n[0]}^3, {precision}", "nodes": nodes,
+           "riesz_mode": riesz_mode,
+           "seconds": round(wall, 3), "iterations": rep["iterations"], "converged": bool(conv),
+           "rel_residual": rep["rel_residual"], "steps_per_period": rep["steps_per_period"],
+           "seconds_fwd": round(rep["seconds_fwd"], 3), "seconds_adj": round(rep["seconds_adj"], 3),
+           "seconds_riesz": round(rep["seconds_riesz"], 3),
+           "seconds_other": round(rep["seconds_other"], 3),
+           "riesz_iterations": rep["riesz_iterations"], "fp64_refreshes": rep["fp64_refreshes"],
+           "glups_periods": round(rep["grid_updates"] / max(rep["seconds_fwd"] + rep["seconds_adj"], 1e-9) / 1e9, 1),
+           "stencil_dram_GB": round(rep["dram_bytes"] / 1e9, 1),
+           "device_GB": round(gb, 1)}
+    nl = rep["bulk_launches_fwd"] + rep["bulk_launches_adj"]
+    if nl > 0:
+        t = (rep["seconds_bulk_fwd"] + rep["seconds_bulk_adj"]) / nl
+        esz = 4 if precision == "fp32" else 8
+        lam = prob.c is not None           # the per-node coefficient is read when c varies
+        step_words = 4 if lam else 3       # one step: read u^n, u^(n-1) (, lambda), write u^(n+1)
+        launch_words = 5 if lam else 4     # a blocked launch also writes u^(n+K-1)
+        tname = "float" if precision == "fp32" else "double"
+        out["roofline"] = roofline_entry(
+            f"f2_block_kernel<{tname}, {kb}>", t, step_words * esz * nodes * kb,
+            launch_words * esz * nodes, nl,
+            fwd_avg_launch_us=round(rep["seconds_bulk_fwd"] / max(1, rep["bulk_launches_fwd"]) * 1e6, 2),
+            adj_avg_launch_us=round(rep["seconds_bulk_adj"] / max(1, rep["bulk_launches_adj"]) * 1e6, 2))
+    return out
 
 
 def nodal_cpu_baseline(which: str, steps: int = 2):
@@ -370,11 +428,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--steps-per-launch", type=int, default=0)
     ap.add_argument("--no-tts", action="store_true")
-    ap.add_argument("--tts-runs", type=int, default=5,
+    ap.add_argument("--tts-runs", type=int, default=3,
                     help="timed solves per precision after one warm-up (the median is reported)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 512^3 second-order inclusions solves (FP32-mixed and FP64)")
+    ap.add_argument("--c3-iters", type=int, default=0,
+                    help="only K FP32-mixed CG iterations of the 512^3 problem (for profiling)")
     ap.add_argument("--nodal", default="", help="comma list of inclusions,sphere: 3D solves")
     ap.add_argument("--nodal-max-iter", type=int, default=3000)
     ap.add_argument("--nodal-precisions", default="fp32", help="comma list of fp32,fp64")
@@ -434,23 +496,21 @@ def main():
     glups = updates / elapsed / 1e9
     log(f"{args.steps} iterations in {elapsed:.3f} s: {ms_per_step:.2f} ms/iteration, {glups:.1f} GLUP/s")
 
-    # roofline of the dominant kernel: phase times from the library's HIP events on its stream
-    launches = math.ceil(N / kb)
-    fwd = (rep1["seconds_fwd"] - rep0["seconds_fwd"]) / args.steps / launches
-    adj = (rep1["seconds_adj"] - rep0["seconds_adj"]) / args.steps / launches
-    bytes_per_update = 28            # FP32: read Px, Py, v, c^2; write Px, Py, v
-    alg_bytes = bytes_per_update * cells * kb       # per launch: kb leapfrog steps of every cell
-    dom, dom_t, other_t = ("adjoint", adj, fwd) if adj >= fwd else ("forward", fwd, adj)
-    achieved = alg_bytes / dom_t / 1e9
-    # the instance the launches between a period's first and last run (no mask, middle set)
-    kname = f"f1_stream_kernel<float, {kb}, {'true' if dom == 'adjoint' else 'false'}, false, 0>"
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 3),
-                "traffic": measured_traffic(kname),
-                "kernel": kname,
-                "avg_launch_us": round(dom_t * 1e6, 2),
-                "algorithmic_bytes_per_launch": alg_bytes,
-                "other_direction_avg_launch_us": round(other_t * 1e6, 2)}
+    # roofline of the dominant kernel: the launches between each period's first and last, in
+    # both directions the forward middle instance, timed by the library's HIP events around them
+    nl = (rep1["bulk_launches_fwd"] - rep0["bulk_launches_fwd"]
+          + rep1["bulk_launches_adj"] - rep0["bulk_launches_adj"])
+    tb = (rep1["seconds_bulk_fwd"] - rep0["seconds_bulk_fwd"]
+          + rep1["seconds_bulk_adj"] - rep0["seconds_bulk_adj"])
+    fwd_us = 1e6 * (rep1["seconds_bulk_fwd"] - rep0["seconds_bulk_fwd"]) / max(
+        1, rep1["bulk_launches_fwd"] - rep0["bulk_launches_fwd"])
+    adj_us = 1e6 * (rep1["seconds_bulk_adj"] - rep0["seconds_bulk_adj"]) / max(
+        1, rep1["bulk_launches_adj"] - rep0["bulk_launches_adj"])
+    bytes_per_update = 28            # FP32: read Px, Py, v, kap; write Px, Py, v
+    kname = f"f1_stream_kernel<float, {kb}, false, false, 0>"
+    roofline = roofline_entry(kname, tb / nl, bytes_per_update * cells * kb,
+                              bytes_per_update * cells, nl,
+                              fwd_avg_launch_us=round(fwd_us, 2), adj_avg_launch_us=round(adj_us, 2))
 
     out = {"metric": METRIC, "value": round(glups, 2), "unit": "GLUP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -498,6 +558,22 @@ def main():
         del U
 
     out["single_source_128"] = single_source_tts()
+
+    # ---------------------------------------------------------------- 512^3 second order
+    if args.c3_iters > 0:
+        out["c3_iterations"] = nodal_3d("inclusions", "fp32", args.c3_iters, tol=0.0)
+    elif not args.no_c3 and not args.no_tts:
+        # both precisions with the same Riesz map (one fixed V-cycle per iteration), so the
+        # time ratio is the precision's alone; one solve each (about a minute apiece)
+        kept = {}
+        c3 = {p: nodal_3d("inclusions", p, 3000, keep=kept, riesz_mode="vcycle")
+              for p in ("fp32", "fp64")}
+        c3["fp64_over_fp32_mixed"] = round(c3["fp64"]["seconds"] / c3["fp32"]["seconds"], 3)
+        c3["fp32_mixed_rel_l2_vs_fp64"] = float(
+            torch.linalg.vector_norm(kept["fp32"] - kept["fp64"])
+            / torch.linalg.vector_norm(kept["fp64"]))
+        del kept
+        out["time_to_solution_c3"] = c3
     for which in [w for w in args.nodal.split(",") if w]:
         kept = {}
         out[f"nodal_{which}"] = {p: nodal_3d(which, p, args.nodal_max_iter, keep=kept)
