@@ -62,13 +62,15 @@ def measured_traffic(kernel: str):
     e = rec.get("kernels", {}).get(kernel)
     if not e or "source" not in e:
         return None
-    src = os.path.join(ROOT, "paper_1903_12522_amd", "csrc", e["source"])
-    try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    if rec.get("sources", {}).get(e["source"]) != sha:
-        return None
+    names = [e["source"]] if isinstance(e["source"], str) else list(e["source"])
+    for name in names:
+        src = os.path.join(ROOT, "paper_1903_12522_amd", "csrc", name)
+        try:
+            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        except OSError:
+            return None
+        if rec.get("sources", {}).get(name) != sha:
+            return None
     return int(e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"])
 
 
@@ -172,8 +174,12 @@ def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10, keep=No
         step_words = 4 if lam else 3       # one step: read u^n, u^(n-1) (, lambda), write u^(n+1)
         launch_words = 5 if lam else 4     # a blocked launch also writes u^(n+K-1)
         tname = "float" if precision == "fp32" else "double"
+        # the library's tile shape: rows per wavefront and wavefronts per workgroup
+        env_r, env_w = os.environ.get("CMCG_F2_RPW", ""), os.environ.get("CMCG_F2_WAVES", "")
+        rpw = int(env_r) if env_r in ("1", "2") else (2 if precision == "fp32" else 1)
+        wv = 16 if rpw == 1 else (int(env_w) if env_w in ("12", "16") else (12 if lam else 16))
         out["roofline"] = roofline_entry(
-            f"f2_block_kernel<{tname}, {kb}>", t, step_words * esz * nodes * kb,
+            f"f2_block_kernel<{tname}, {kb}, {rpw}, {wv}>", t, step_words * esz * nodes * kb,
             launch_words * esz * nodes, nl,
             fwd_avg_launch_us=round(rep["seconds_bulk_fwd"] / max(1, rep["bulk_launches_fwd"]) * 1e6, 2),
             adj_avg_launch_us=round(rep["seconds_bulk_adj"] / max(1, rep["bulk_launches_adj"]) * 1e6, 2))

@@ -278,9 +278,9 @@ __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
 
 // Temporal blocking of the homogeneous step u^{n+1} = R (2 u^n - (1-beta) u^{n-1} - lambda L u^n)
 // / (1 + beta) (every step of a forward period but its start and end, and every interior step of
-// the backward period in the scaled variable).  A workgroup of kBlockWaves wavefronts owns a
-// (64 x TY) column tile, TY = kBlockWaves RPW (each wavefront RPW consecutive rows, one column per
-// lane), and marches a chunk of planes; the K steps of a launch are K pipeline levels: at plane
+// the backward period in the scaled variable).  A workgroup of WV wavefronts owns a (64 x TY)
+// column tile, TY = WV RPW (each wavefront RPW consecutive rows, one column per lane), and
+// marches a chunk of planes; the K steps of a launch are K pipeline levels: at plane
 // iteration p, level 0 loads plane p of u^n and u^{n-1}, and level s computes plane p - s of
 // u^{n+s} from level s-1's planes p-s-1 .. p-s+1 (a register window), level s-2's plane p-s (the
 // older state) and the neighbours: x through lane shifts, y from the wavefront's own other row
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
 // every real node sees the same operands in the same order: blocked and single-step periods
 // agree bit for bit.  Halo lanes, rows and planes outside the box read clamped addresses and are
 // never stored.
-constexpr int kBlockWaves = 16;
+constexpr int kBlockWaves = 16;   // wavefronts per workgroup unless the shape says otherwise
 constexpr int kBlockChunk = 32;
 
 // Launch shape of the blocked sweep: planes per workgroup and whether workgroups are dealt to the
@@ -303,11 +303,20 @@ struct F2BlockShape {
   int xcd = 0;
 };
 
-// rows per wavefront by default: one.  Two rows (64 x 32 tiles) read 23% fewer halo nodes but
-// raise the FP32 K = 3 instance from 52 to 84 VGPRs, one 16-wave workgroup per CU instead of two,
-// and measured slower on the 512^3 inclusions (983 against 884 us per launch)
+// Default tile shapes, from a sweep of FP32 K = 3 launches (us per launch, 32-plane chunks):
+//   rows x waves      64x16 (1x16)   64x32 (2x16)   64x24 (2x12)   64x20 (2x10)
+//   512^3 inclusions      894            984            875           1414
+//   1025^3 ball          6028           5509           5840           7128
+// Two rows per wavefront halve the barriers per node and re-read fewer halo rows, but take the
+// FP32 instance from 52 to 84 VGPRs: a 16-wave workgroup then runs alone on its CU.  With a
+// per-node lambda (one more load per node) 12-wave workgroups held to 80 VGPRs, two per CU, do
+// best; with a constant lambda the 64 x 32 tile does.  64-plane chunks and K = 2 or 4 were
+// slower on both.  FP64 keeps one row (two rows spill in FP64).
 template <typename T>
-constexpr int default_rpw() { return 1; }
+constexpr int default_rpw() { return sizeof(T) == 4 ? 2 : 1; }
+inline int default_waves(int rpw, const void *lam) {
+  return (rpw == 2 && lam != nullptr) ? 12 : kBlockWaves;
+}
 
 // Tile (bx, by, bz) of workgroup blockIdx: in launch order, or XCD-aware (consecutive workgroup
 // ids go round-robin over the XCDs; the remap gives each XCD a contiguous run of tiles).
@@ -323,12 +332,12 @@ __device__ __forceinline__ void block_tile(int xcd, int &bx, int &by, int &bz) {
 // INNER: the tile's columns and rows (halo included) hold no node on an x or y box face and no
 // sound-soft node, so the x/y mirror substitutions, the mask and the x/y absorbing faces drop
 // out; only the z face planes (plane-uniform) keep their mirror and absorption.
-template <typename T, int K, int RPW, bool INNER>
+template <typename T, int K, int RPW, int WV, bool INNER>
 __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, const T *prev,
                                               const T *lam, T *out_k, T *out_km1,
-                                              T (&lds)[K][2][kBlockWaves * RPW][64], int bx,
-                                              int by, int bz, int chunk) {
-  constexpr int TY = kBlockWaves * RPW, OW = 64 - 2 * K, OH = TY - 2 * K;
+                                              T (&lds)[K][2][WV * RPW][64], int bx, int by,
+                                              int bz, int chunk) {
+  constexpr int TY = WV * RPW, OW = 64 - 2 * K, OH = TY - 2 * K;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = bx * OW - K + lane;
   const int k0 = bz * chunk, k1 = min(k0 + chunk, g.nz + 1);
@@ -470,12 +479,19 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
   }
 }
 
-template <typename T, int K, int RPW>
-__global__ __launch_bounds__(64 * kBlockWaves) void f2_block_kernel(F2Geom g, const T *cur,
-                                                                     const T *prev, const T *lam,
-                                                                     T *out_k, T *out_km1,
-                                                                     F2BlockShape shape) {
-  constexpr int TY = kBlockWaves * RPW, OW = 64 - 2 * K, OH = TY - 2 * K;
+// waves per SIMD a workgroup shape is compiled for (1: the compiler's choice); 12-wave
+// workgroups are held to 6 waves per SIMD, two workgroups per CU
+template <int WV>
+struct F2BlockOccupancy {
+  static constexpr int value = WV == 12 ? 6 : 1;
+};
+
+template <typename T, int K, int RPW, int WV>
+__global__ __launch_bounds__(64 * WV)
+__attribute__((amdgpu_waves_per_eu(F2BlockOccupancy<WV>::value))) void f2_block_kernel(
+    F2Geom g, const T *cur, const T *prev, const T *lam, T *out_k, T *out_km1,
+    F2BlockShape shape) {
+  constexpr int TY = WV * RPW, OW = 64 - 2 * K, OH = TY - 2 * K;
   __shared__ T lds[K][2][TY][64];
   int bx, by, bz;
   block_tile(shape.xcd, bx, by, bz);
@@ -488,11 +504,11 @@ __global__ __launch_bounds__(64 * kBlockWaves) void f2_block_kernel(F2Geom g, co
   const bool mask = g.mask && i1 >= g.mlo[0] && i0 <= g.mhi[0] && j1 >= g.mlo[1] &&
                     j0 <= g.mhi[1] && k1 + K - 1 >= g.mlo[2] && k0 - K <= g.mhi[2];
   if (!faces && !mask)
-    f2_block_tile<T, K, RPW, true>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,
-                                   shape.chunk);
+    f2_block_tile<T, K, RPW, WV, true>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,
+                                       shape.chunk);
   else
-    f2_block_tile<T, K, RPW, false>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,
-                                    shape.chunk);
+    f2_block_tile<T, K, RPW, WV, false>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,
+                                        shape.chunk);
 }
 
 // out = psi in, psi = lambda R / ((1 + beta) eta)
@@ -782,27 +798,34 @@ hipError_t f2_march_block(const F2Geom &g, const T *cur, const T *prev, const T 
     if (const char *e = std::getenv("CMCG_F2_XCD")) sh.xcd = std::atoi(e);
     return sh;
   }();
-  // CMCG_F2_RPW (environment, read per launch): rows per wavefront, 1 or 2
+  // CMCG_F2_RPW and CMCG_F2_WAVES (environment, read per launch): rows per wavefront (1 or 2)
+  // and wavefronts per workgroup (16, or 12 with two rows)
   const char *re = std::getenv("CMCG_F2_RPW");
+  const char *we = std::getenv("CMCG_F2_WAVES");
   const int want = re ? std::atoi(re) : 0;
   const int rpw = (want == 1 || want == 2) ? want : default_rpw<T>();
-  dim3 block(64 * kBlockWaves);
+  const int wq = we ? std::atoi(we) : 0;
+  const int wv = rpw == 1 ? kBlockWaves : (wq == 12 || wq == 16) ? wq : default_waves(rpw, lam);
+  dim3 block(64 * wv);
   auto grid = [&](int k) {
-    const int ty = kBlockWaves * rpw;
+    const int ty = wv * rpw;
     return dim3((g.nx + 1 + 64 - 2 * k - 1) / (64 - 2 * k),
                 (g.ny + 1 + ty - 2 * k - 1) / (ty - 2 * k),
                 (g.nz + 1 + shape.chunk - 1) / shape.chunk);
   };
-#define CMCG_F2_BLOCK(KK, RR)                                                                  \
-  hipLaunchKernelGGL((f2_block_kernel<T, KK, RR>), grid(KK), block, 0, s, g, cur, prev, lam,   \
-                     out_k, out_km1, shape)
-  switch (K * 4 + rpw) {
-    case 2 * 4 + 1: CMCG_F2_BLOCK(2, 1); break;
-    case 3 * 4 + 1: CMCG_F2_BLOCK(3, 1); break;
-    case 4 * 4 + 1: CMCG_F2_BLOCK(4, 1); break;
-    case 2 * 4 + 2: CMCG_F2_BLOCK(2, 2); break;
-    case 3 * 4 + 2: CMCG_F2_BLOCK(3, 2); break;
-    case 4 * 4 + 2: CMCG_F2_BLOCK(4, 2); break;
+#define CMCG_F2_BLOCK(KK, RR, WW)                                                              \
+  hipLaunchKernelGGL((f2_block_kernel<T, KK, RR, WW>), grid(KK), block, 0, s, g, cur, prev,    \
+                     lam, out_k, out_km1, shape)
+  switch ((K * 4 + rpw) * 32 + wv) {
+    case (2 * 4 + 1) * 32 + 16: CMCG_F2_BLOCK(2, 1, 16); break;
+    case (3 * 4 + 1) * 32 + 16: CMCG_F2_BLOCK(3, 1, 16); break;
+    case (4 * 4 + 1) * 32 + 16: CMCG_F2_BLOCK(4, 1, 16); break;
+    case (2 * 4 + 2) * 32 + 16: CMCG_F2_BLOCK(2, 2, 16); break;
+    case (3 * 4 + 2) * 32 + 16: CMCG_F2_BLOCK(3, 2, 16); break;
+    case (4 * 4 + 2) * 32 + 16: CMCG_F2_BLOCK(4, 2, 16); break;
+    case (2 * 4 + 2) * 32 + 12: CMCG_F2_BLOCK(2, 2, 12); break;
+    case (3 * 4 + 2) * 32 + 12: CMCG_F2_BLOCK(3, 2, 12); break;
+    case (4 * 4 + 2) * 32 + 12: CMCG_F2_BLOCK(4, 2, 12); break;
     default: return hipErrorInvalidValue;
   }
 #undef CMCG_F2_BLOCK

@@ -29,3 +29,32 @@ def test_roofline_entry_fractions():
     assert abs(r["frac_one_pass"] - 28 * cells / t / 8e12) < 1e-3
     assert abs(r["one_pass_time_us"] - 28 * cells / 8e12 * 1e6) < 0.01
     assert r["frac_one_pass"] < 1.0 < r["frac"]
+
+
+def test_measured_traffic_needs_every_named_source_unchanged(tmp_path, monkeypatch):
+    """Counter traffic is used only while each source the record names hashes as it did when
+    the counters were taken."""
+    import hashlib
+    import json
+    sys.path.insert(0, ROOT)
+    import bench
+    csrc = tmp_path / "paper_1903_12522_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    (csrc / "a.hip").write_text("kernel a")
+    (csrc / "b.h").write_text("header b")
+    sha = {n: hashlib.sha256((csrc / n).read_bytes()).hexdigest() for n in ("a.hip", "b.h")}
+    rec = {"sources": sha, "kernels": {
+        "k1": {"source": ["a.hip", "b.h"], "fetch_bytes_per_launch": 300,
+               "write_bytes_per_launch": 100},
+        "k2": {"source": "a.hip", "fetch_bytes_per_launch": 10, "write_bytes_per_launch": 5},
+        "k3": {"fetch_bytes_per_launch": 1, "write_bytes_per_launch": 1}}}
+    (tmp_path / "profiles" / "hbm_traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("k1") == 400
+    assert bench.measured_traffic("k2") == 15
+    assert bench.measured_traffic("k3") is None       # no source recorded
+    assert bench.measured_traffic("k4") is None       # no record
+    (csrc / "b.h").write_text("header b, edited")
+    assert bench.measured_traffic("k1") is None       # one of its sources changed
+    assert bench.measured_traffic("k2") == 15
