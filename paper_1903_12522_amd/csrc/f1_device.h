@@ -15,7 +15,8 @@ constexpr int kThreads = 256;   // 4 wavefronts per workgroup, each an independe
 
 // XCD-aware workgroup order: consecutive workgroup ids are dispatched round-robin over the 8
 // XCDs; remap so each XCD walks a contiguous band of (column group, row band) tiles, whose
-// overlapping halo rows and columns then meet in that XCD's L2.
+// overlapping halo rows and columns then meet in that XCD's L2 (without the remap the FP32
+// middle launch on a 4096^2 grid takes 189 instead of 178 us).
 __device__ __forceinline__ void tile_of_block(int &bx, int &by) {
   const int nbx = gridDim.x, nby = gridDim.y;
   const int nb = nbx * nby;
@@ -249,11 +250,17 @@ __device__ __forceinline__ void buf_ld(float &x, __amdgpu_buffer_rsrc_t r, unsig
 __device__ __forceinline__ void buf_ld(double &x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
   x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
 }
+// The state a launch writes is read again only by the next launch, after every tile has streamed
+// through L2, so the stores are non-temporal (cache-policy bit nt) and do not evict the rows
+// that neighbouring tiles are about to re-read: 172.7 against 177.8 us per FP32 middle launch on
+// a 4096^2 grid.
+constexpr int kStorePolicy = 2;
 __device__ __forceinline__ void buf_st(float x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(x), r, (int)vo, (int)so, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(x), r, (int)vo, (int)so, kStorePolicy);
 }
 __device__ __forceinline__ void buf_st(double x, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i32x2, x), r, (int)vo, (int)so, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i32x2, x), r, (int)vo, (int)so,
+                                        kStorePolicy);
 }
 
 // Resources and offsets of one fast-variant wavefront.
