@@ -438,6 +438,8 @@ def main():
                     help="timed solves per precision after one warm-up (the median is reported)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--fp64-step", action="store_true",
+                    help="time FP64 CG iterations instead (the FP64 path's rate and roofline)")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 512^3 second-order inclusions solves (FP32-mixed and FP64)")
@@ -479,7 +481,8 @@ def main():
     spl = args.steps_per_launch
 
     # ---------------------------------------------------------------- timed CG iterations
-    with cmcg.Solver(prob, "fp32", tol=0.0, max_iter=1 << 30, steps_per_launch=spl) as s:
+    step_prec = "fp64" if args.fp64_step else "fp32"
+    with cmcg.Solver(prob, step_prec, tol=0.0, max_iter=1 << 30, steps_per_launch=spl) as s:
         N = s.info["steps_per_period"]
         s.begin()
         log(f"N = {N} steps per period; {args.warmup} warm-up iterations")
@@ -512,18 +515,20 @@ def main():
         1, rep1["bulk_launches_fwd"] - rep0["bulk_launches_fwd"])
     adj_us = 1e6 * (rep1["seconds_bulk_adj"] - rep0["seconds_bulk_adj"]) / max(
         1, rep1["bulk_launches_adj"] - rep0["bulk_launches_adj"])
-    bytes_per_update = 28            # FP32: read Px, Py, v, kap; write Px, Py, v
-    kname = f"f1_stream_kernel<float, {kb}, false, false, 0>"
+    # read Px, Py, v, kap; write Px, Py, v
+    bytes_per_update = 56 if args.fp64_step else 28
+    kname = f"f1_stream_kernel<{'double' if args.fp64_step else 'float'}, {kb}, false, false, 0>"
     roofline = roofline_entry(kname, tb / nl, bytes_per_update * cells * kb,
                               bytes_per_update * cells, nl,
                               fwd_avg_launch_us=round(fwd_us, 2), adj_avg_launch_us=round(adj_us, 2))
 
     out = {"metric": METRIC, "value": round(glups, 2), "unit": "GLUP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.fp64_step else "f32", "data": "synthetic",
            "config": {"workload": f"first-order random medium {prob.n[0]}x{prob.n[1]}, "
-                                  f"omega=2pi*100, 8 sources, FP32-mixed CG iteration",
+                                  f"omega=2pi*100, 8 sources, "
+                                  f"{'FP64' if args.fp64_step else 'FP32-mixed'} CG iteration",
                       "cells": cells, "steps_per_period": N, "steps_per_launch": kb,
                       "grid_updates_per_step": 2 * N * cells, "device_bytes": dev_bytes},
            "roofline": roofline}
