@@ -148,52 +148,87 @@ __global__ __launch_bounds__(256) void mg_march_kernel(F2Geom g, const T *x, con
   }
 }
 
-// bc = R_c P^T rf  (full weighting over the 27 fine neighbours of the coarse node's position)
+// bc = R_c P^T rf  (full weighting over the 27 fine neighbours of the coarse node's position).
+// All 27 loads are issued before the sum (neighbours outside the fine box read a clamped node);
+// the terms are then added in the fixed (k, j, i) order, each only where its neighbour exists,
+// so the sum is the plain loop's, operation for operation.
 template <typename T>
 __global__ void restrict_kernel(F2Geom gf, F2Geom gc, const T *rf, T *bc) {
   F2_ROWS(gc)
-  if (msk(gc, i, j, k)) {
-    bc[o] = T(0);
-    continue;
-  }
-  T acc = T(0);
+  const bool m = msk(gc, i, j, k);
+  T x[3][3][3];
+#pragma unroll
   for (int dk = -1; dk <= 1; ++dk) {
-    const int fk = 2 * k + dk;
-    if (fk < 0 || fk > gf.nz) continue;
+    const int fk = min(max(2 * k + dk, 0), gf.nz);
+#pragma unroll
     for (int dj = -1; dj <= 1; ++dj) {
-      const int fj = 2 * j + dj;
-      if (fj < 0 || fj > gf.ny) continue;
+      const int fj = min(max(2 * j + dj, 0), gf.ny);
+      const size_t row = gf.idx(0, fj, fk);
+#pragma unroll
       for (int di = -1; di <= 1; ++di) {
-        const int fi = 2 * i + di;
-        if (fi < 0 || fi > gf.nx) continue;
-        const T w = (T)((di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0));
-        acc += w * rf[gf.idx(fi, fj, fk)];
+        const int fi = min(max(2 * i + di, 0), gf.nx);
+        x[dk + 1][dj + 1][di + 1] = rf[row + fi];
       }
     }
   }
-  bc[o] = acc;
+  T acc = T(0);
+#pragma unroll
+  for (int dk = -1; dk <= 1; ++dk) {
+    const int fk = 2 * k + dk;
+    const bool vk = fk >= 0 && fk <= gf.nz;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int fj = 2 * j + dj;
+      const bool vj = vk && fj >= 0 && fj <= gf.ny;
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int fi = 2 * i + di;
+        const bool v = vj && fi >= 0 && fi <= gf.nx;
+        const T w = (T)((di ? 0.5 : 1.0) * (dj ? 0.5 : 1.0) * (dk ? 0.5 : 1.0));
+        const T t = acc + w * x[dk + 1][dj + 1][di + 1];
+        acc = v ? t : acc;
+      }
+    }
+  }
+  bc[o] = m ? T(0) : acc;
   F2_ROWS_END
 }
 
-// xf += R_f P xc  (trilinear interpolation)
+// xf += R_f P xc  (trilinear interpolation).  The up to 8 coarse neighbours (ci0, ci1) x (cj0,
+// cj1) x (ck0, ck1), equal pairs where a fine index is even, are all loaded before the sum;
+// the terms are then added in the fixed (k, j, i) order, the second of an equal pair skipped,
+// so the sum is the plain loop's, operation for operation.
 template <typename T>
 __global__ void prolong_add_kernel(F2Geom gf, F2Geom gc, const T *xc, T *xf) {
   F2_ROWS(gf)
-  if (msk(gf, i, j, k)) {
-    xf[o] = T(0);
-    continue;
-  }
-  const int ci0 = i >> 1, ci1 = (i + 1) >> 1;
-  const int cj0 = j >> 1, cj1 = (j + 1) >> 1;
-  const int ck0 = k >> 1, ck1 = (k + 1) >> 1;
-  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  const bool m = msk(gf, i, j, k);
+  const int ci[2] = {i >> 1, (i + 1) >> 1};
+  const int cj[2] = {j >> 1, (j + 1) >> 1};
+  const int ck[2] = {k >> 1, (k + 1) >> 1};
+  const bool oi = i & 1, oj = j & 1, ok = k & 1;
+  const T wi = oi ? T(0.5) : T(1), wj = oj ? T(0.5) : T(1), wk = ok ? T(0.5) : T(1);
+  T x[2][2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const size_t row = gc.idx(0, cj[b], ck[c]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) x[c][b][a] = xc[row + ci[a]];
+    }
+  const T f = xf[o];
   T acc = T(0);
-  const int is[2] = {ci0, ci1}, js[2] = {cj0, cj1}, ks[2] = {ck0, ck1};
-  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-  for (int c = 0; c < nk; ++c)
-    for (int b = 0; b < nj; ++b)
-      for (int a = 0; a < ni; ++a) acc += wi * wj * wk * xc[gc.idx(is[a], js[b], ks[c])];
-  xf[o] += acc;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const bool v = (c == 0 || ok) && (b == 0 || oj) && (a == 0 || oi);
+        const T t = acc + wi * wj * wk * x[c][b][a];
+        acc = v ? t : acc;
+      }
+  xf[o] = m ? T(0) : f + acc;
   F2_ROWS_END
 }
 
