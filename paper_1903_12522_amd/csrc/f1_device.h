@@ -49,7 +49,10 @@ __device__ __forceinline__ int f1_abs_faces(const F1Geom &g, int mx, int r) {
   return mx + (r == 0 ? g.abs_face[2] : 0) + (r == g.ny - 1 ? g.abs_face[3] : 0);
 }
 
-template <typename T, int K, bool ADJ, bool EDGE, bool MASK>
+// MID: the launch is one between a period's first and last (no opening kick, no subtrahend, no
+// source, no filter sums): those paths are compiled out, which keeps the register count of the
+// instance these launches run at that of its fast variant.
+template <typename T, int K, bool ADJ, bool EDGE, bool MASK, bool MID = false>
 __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> &p,
                                                const F1Launch &L, const int i, const int lane,
                                                const int s0, const int s1) {
@@ -69,7 +72,7 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
   T Vc[K + 1], PXc[K + 1], PYc[K + 1], CCc[K + 1];
   T HOLD0 = T(0);   // level 0: raw Py of the current row
   T RMp[K + 1], RMc[K + 1];   // MASK: R of the emitted row (1 free, 0 Dirichlet)
-  const bool dirichlet = MASK && !ADJ && L.forced && p.dre != nullptr;
+  const bool dirichlet = MASK && !ADJ && !MID && L.forced && p.dre != nullptr;
 #pragma unroll
   for (int k = 0; k <= K; ++k) {
     Vp[k] = PXp[k] = PYp[k] = CCp[k] = T(0);
@@ -95,17 +98,17 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
     if (MASK) {
       if (in0 && g.mask[o0]) rm0 = T(0);
       // a forward period starts from a state that is zero on the Dirichlet cells
-      if (!ADJ && L.first && rm0 == T(0))
+      if (!ADJ && !MID && L.first && rm0 == T(0))
         v0 = dirichlet ? f1_dirichlet(p, o0, L.dc[0], L.ds[0]) : T(0);
     }
-    if (L.accumulate && laneOut && j >= s0 && j < s1) {
+    if (!MID && L.accumulate && laneOut && j >= s0 && j < s1) {
       const double vv = (double)v0;
       p.ure[o0] += vv * L.fcos;
       p.uim[o0] += vv * L.fsin;
     }
     T pyprev = HOLD0;   // raw Py(j-1)
     HOLD0 = py0;
-    if (L.first) {
+    if (!MID && L.first) {
       if (!ADJ) {
         // opening half kick  p <- p + dt/2 G v  (Px of row j, Py of row j-1)
         const T vr = lane_from_right(v0);
@@ -144,7 +147,7 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
       const T kap = CCp[k - 1];
       const T pl = lane_from_left(px);
       T dsum = (px - pl) + (pyr - pyrm1);
-      if (!ADJ && L.forced && cin) {
+      if (!ADJ && !MID && L.forced && cin) {
         const size_t o = (size_t)r * pitch + i;
         dsum = fma(p.fre[o], (T)L.cs[k - 1], dsum);
         if (p.fim) dsum = fma(p.fim[o], (T)L.sn[k - 1], dsum);
@@ -203,7 +206,7 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
         const size_t o = (size_t)ro * pitch + i;
         T a = PXc[K], c = Vc[K];
         if (MASK && L.last && RMc[K] == T(0)) c = T(0);   // the state is zero there
-        if (p.sub) {
+        if (!MID && p.sub) {
           a -= p.sub[o];
           c -= p.sub[o + 2 * fs];
         }
@@ -213,7 +216,7 @@ __device__ __forceinline__ void f1_stream_body(const F1Geom &g, const F1Ptrs<T> 
       if (ro - 1 >= s0 && ro - 1 < s1) {
         const size_t o = (size_t)(ro - 1) * pitch + i;
         T b = PYc[K];
-        if (p.sub) b -= p.sub[o + fs];
+        if (!MID && p.sub) b -= p.sub[o + fs];
         p.out[o + fs] = b;
       }
     }
@@ -479,14 +482,17 @@ __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> 
   const bool inner_cols = i0 >= 1 && i0 + 63 <= g.nx - 2;
   const bool inner_rows = s0 >= 2 * K + 3 && s1 + K <= g.ny - 2;
   const bool small = 3ull * p.fs * sizeof(T) <= kBufMax;
+  constexpr bool MID = SET == kFastMiddle;
   if (MASK) {
     // wavefronts whose columns and pipeline rows (s0 - K - 3 .. s1 + K) meet the box of the
     // Dirichlet cells take the masked body; the others never touch a masked cell
     const bool meets = i0 + 63 >= g.mlo[0] && i0 <= g.mhi[0] && s1 + K >= g.mlo[1] &&
                        s0 - K - 3 <= g.mhi[1];
     if (meets) {
-      if (inner_cols) f1_stream_body<T, K, ADJ, false, true>(g, p, L, i0 + lane, lane, s0, s1);
-      else f1_stream_body<T, K, ADJ, true, true>(g, p, L, i0 + lane, lane, s0, s1);
+      if (inner_cols)
+        f1_stream_body<T, K, ADJ, false, true, MID>(g, p, L, i0 + lane, lane, s0, s1);
+      else
+        f1_stream_body<T, K, ADJ, true, true, MID>(g, p, L, i0 + lane, lane, s0, s1);
       return;
     }
   }
@@ -513,9 +519,9 @@ __device__ __forceinline__ void f1_stream_tile(const F1Geom &g, const F1Ptrs<T> 
   else if (SET != kFastEnds && fast && !ends)
     f1_stream_fast<T, K, ADJ, false, false, false>(g, p, L, i0 + lane, lane, s0, s1);
   else if (inner_cols)
-    f1_stream_body<T, K, ADJ, false, false>(g, p, L, i0 + lane, lane, s0, s1);
+    f1_stream_body<T, K, ADJ, false, false, MID>(g, p, L, i0 + lane, lane, s0, s1);
   else
-    f1_stream_body<T, K, ADJ, true, false>(g, p, L, i0 + lane, lane, s0, s1);
+    f1_stream_body<T, K, ADJ, true, false, MID>(g, p, L, i0 + lane, lane, s0, s1);
 }
 
 __device__ __forceinline__ double wave_sum(double x) {

@@ -88,8 +88,9 @@ hipError_t launch_one(const F1Geom &g, const F1Ptrs<T> &p, const F1Launch &L, hi
 #define CMCG_F1_LAUNCH(DIR, MASK, SET)                                                         \
   hipLaunchKernelGGL((f1_stream_kernel<T, K, DIR, MASK, SET>), grid, dim3(kThreads), 0, s, g, p, \
                      Lx, band)
-  if (!ADJ && L.forced) {
+  if (!ADJ && (L.forced || L.accumulate)) {
     // forced (forward) periods: every launch of the period runs the instance with the source
+    // (and the filter sums, which only forced periods take)
     if (g.mask) CMCG_F1_LAUNCH(false, true, kFastForced);
     else CMCG_F1_LAUNCH(false, false, kFastForced);
   } else if (ends) {
