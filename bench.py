@@ -465,7 +465,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU slab decomposition is a design, not part of this build",
+              "the multi-GPU slab decomposition is described, not implemented",
               file=sys.stderr)
         return 2
 
