@@ -261,7 +261,7 @@ class F1Solver final : public Solver {
     if (fixed) {
       h_scalars = h_scalars_local;
     } else {
-      CMCG_TRY(ev.init(11));
+      CMCG_TRY(ev.init(10));
       CMCG_TRY(bulk.init());
       CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
     }
@@ -549,7 +549,7 @@ class F1Solver final : public Solver {
   cmcg_status read_scalars() {
     CMCG_HIP(hipMemcpyAsync(h_scalars, scalars, kNumScalars * sizeof(double),
                             hipMemcpyDeviceToHost, s));
-    CMCG_TRY(ev.spin_wait(10, s));   // (event 10: the polling wait, no phase)
+    CMCG_HIP(hipStreamSynchronize(s));
     return CMCG_OK;
   }
 

@@ -252,7 +252,7 @@ class F2Solver final : public Solver {
     mixed = cfg.prec == CMCG_FP32_MIXED;
     riesz_tol = cfg.riesz_tol > 0 ? cfg.riesz_tol : 1e-10;
     riesz_max = cfg.riesz_max_iter > 0 ? cfg.riesz_max_iter : 500;
-    CMCG_TRY(ev.init(13));
+    CMCG_TRY(ev.init(12));
     CMCG_TRY(bulk.init());
     CMCG_HIP(hipHostMalloc((void **)&h_scalars, kNumScalars * sizeof(double)));
     std::fill(h_scalars, h_scalars + kNumScalars, 0.0);
@@ -713,7 +713,7 @@ class F2Solver final : public Solver {
   cmcg_status read_scalars() {
     CMCG_HIP(hipMemcpyAsync(h_scalars, scalars, kNumScalars * sizeof(double),
                             hipMemcpyDeviceToHost, s));
-    CMCG_TRY(ev.spin_wait(12, s));   // (event 12: the polling wait, no phase)
+    CMCG_HIP(hipStreamSynchronize(s));
     return CMCG_OK;
   }
 

@@ -113,17 +113,6 @@ class PhaseEvents {
     return CMCG_OK;
   }
   hipEvent_t operator[](int k) const { return ev_[k]; }
-  // Wait for the work queued on `s` so far by polling an event recorded after it: the CG loop
-  // waits once per iteration for a few scalars, and a sleeping stream synchronisation sometimes
-  // woke about a millisecond late (an 8.6 ms iteration measured 9.6 ms in some runs).
-  cmcg_status spin_wait(int k, hipStream_t s) const {
-    CMCG_HIP(hipEventRecord(ev_[k], s));
-    hipError_t e;
-    while ((e = hipEventQuery(ev_[k])) == hipErrorNotReady) {
-    }
-    CMCG_HIP(e);
-    return CMCG_OK;
-  }
   static double seconds(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
