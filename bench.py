@@ -490,8 +490,7 @@ def main():
         if rep0 is None:
             _, rep0 = s.iterate(0)
         # the K timed iterations run in one cmcg_iterate call: the library's own iteration loop,
-        # as in cmcg_solve (one Python call per iteration added about 1 ms per iteration in
-        # some runs: 9.56 against 8.59 ms)
+        # as in cmcg_solve
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.iterate(args.steps)
