@@ -151,6 +151,7 @@ def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10, keep=No
         wall = time.perf_counter() - t0
         gb = s.info["device_bytes"] / 1e9
         kb = s.info["steps_per_launch"]
+        rpw, wv = s.info["block_rows"], s.info["block_waves"]
         if keep is not None:
             keep[precision] = torch.complex(u[0], u[1]).clone()
         del u
@@ -174,10 +175,7 @@ def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10, keep=No
         step_words = 4 if lam else 3       # one step: read u^n, u^(n-1) (, lambda), write u^(n+1)
         launch_words = 5 if lam else 4     # a blocked launch also writes u^(n+K-1)
         tname = "float" if precision == "fp32" else "double"
-        # the library's tile shape: rows per wavefront and wavefronts per workgroup
-        env_r, env_w = os.environ.get("CMCG_F2_RPW", ""), os.environ.get("CMCG_F2_WAVES", "")
-        rpw = int(env_r) if env_r in ("1", "2") else (2 if precision == "fp32" else 1)
-        wv = 16 if rpw == 1 else (int(env_w) if env_w in ("12", "16") else (12 if lam else 16))
+        # (the tile shape, rows per wavefront and wavefronts per workgroup, as the library reports)
         out["roofline"] = roofline_entry(
             f"f2_block_kernel<{tname}, {kb}, {rpw}, {wv}>", t, step_words * esz * nodes * kb,
             launch_words * esz * nodes, nl,

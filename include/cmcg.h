@@ -206,6 +206,11 @@ typedef struct {
   int32_t n_fields;            /* fields written by the filter outputs: n_shots, or 1          */
   int32_t steps_per_launch;    /* leapfrog steps fused per launch in homogeneous periods, after
                                   the library default is applied                              */
+  int32_t block_rows;          /* F2 with steps_per_launch > 1: grid rows per wavefront of the
+                                  blocked launches' tiles (a tile is 64 nodes by block_rows x
+                                  block_waves rows); 0 otherwise                              */
+  int32_t block_waves;         /* F2 with steps_per_launch > 1: wavefronts per workgroup of the
+                                  blocked launches; 0 otherwise                               */
 } cmcg_info;
 
 cmcg_status cmcg_get_info(const cmcg_handle *h, cmcg_info *info);

@@ -76,7 +76,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("steps_per_period", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("T", ctypes.c_double), ("h", ctypes.c_double), ("state_len", ctypes.c_int64),
                 ("field_len", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("n_fields", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32)]
+                ("n_fields", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32),
+                ("block_rows", ctypes.c_int32), ("block_waves", ctypes.c_int32)]
 
 
 class _ServerOptions(ctypes.Structure):

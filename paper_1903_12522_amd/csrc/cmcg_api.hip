@@ -216,6 +216,7 @@ cmcg_status cmcg_create(const cmcg_problem *P, const cmcg_options *O, cmcg_handl
 
 cmcg_status cmcg_get_info(const cmcg_handle *H, cmcg_info *info) {
   if (!H || !info) return set_error("null argument"), CMCG_EINVAL;
+  *info = cmcg_info{};
   H->solver->info(info);
   return CMCG_OK;
 }

@@ -71,6 +71,9 @@ struct F2Args {
 
 template <typename T>
 hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s);
+// rows per wavefront and wavefronts per workgroup of the blocked launches in precision T
+template <typename T>
+void f2_block_shape(int *rpw, int *wv);
 // K (2..4) homogeneous steps in one launch, temporally blocked: from u^n (cur) and u^{n-1}
 // (prev) to u^{n+K} (out_k) and u^{n+K-1} (out_km1); the outputs may alias neither input
 template <typename T>

@@ -303,23 +303,25 @@ struct F2BlockShape {
   int xcd = 0;
 };
 
-// Default tile shapes, from a sweep of FP32 K = 3 launches (us per launch, 32-plane chunks):
-//   rows x waves      64x16 (1x16)   64x32 (2x16)   64x24 (2x12)   64x20 (2x10)
-//   512^3 inclusions      894            984            875           1414
-//   1025^3 ball          6028           5509           5840           7128
-// Two rows per wavefront halve the barriers per node and re-read fewer halo rows, but take the
-// FP32 instance from 52 to 84 VGPRs: a 16-wave workgroup then runs alone on its CU.  With a
-// per-node lambda (one more load per node) 12-wave workgroups held to 80 VGPRs, two per CU, do
-// best; with a constant lambda the 64 x 32 tile does.  64-plane chunks and K = 2 or 4 were
-// slower on both.  FP64 keeps one row (two rows spill in FP64).
+// Default tile shapes, from sweeps on a 513^3 grid with a per-node lambda and a 1025^3 ball with a
+// constant lambda (us per step of the blocked launch, 16 wavefronts unless noted):
+//   FP32, K x rows per wavefront    3 x 2    3 x 2 (12 waves)    3 x 3    4 x 2    4 x 3    4 x 4
+//   513^3, 32-plane chunks            293          294             305      273      260      503
+//   1025^3, 64-plane chunks          1584           --            1753     1428     1345     2051
+//   FP64, 513^3, 32-plane chunks: 3 x 1 525-563, 3 x 2 472, 4 x 1 573
+// A 16-wave workgroup holds its CU alone once its instance needs more than 64 VGPRs, so up to
+// 128 VGPRs taller tiles cost no occupancy and re-read fewer halo rows (64 x 48 tiles write
+// 56 x 40 columns at K = 4).  The deepest blocking pays in FP32, where a step of the interior
+// path is about ten vector instructions; FP64 does best at K = 3 with two rows (the solver picks
+// K per precision).  The 4-row tile spills heavily.
 template <typename T>
-constexpr int default_rpw() { return sizeof(T) == 4 ? 2 : 1; }
-inline int default_waves(int rpw, const void *lam) {
-  return (rpw == 2 && lam != nullptr) ? 12 : kBlockWaves;
+constexpr int default_rpw() { return sizeof(T) == 4 ? 3 : 2; }
+// Planes per workgroup: 64 when the grid still has at least 8 workgroups per CU that way
+// (1025^3 ball, FP32: 1345 against 1545 us per step with 32), 32 otherwise (513^3: 260 against
+// 267 with 64, whose 9 chunks leave 4.6 workgroups per CU).
+inline int default_chunk(long tiles_xy, int nz, int cus) {
+  return tiles_xy * ((nz + 1 + 63) / 64) >= 8L * cus ? 64 : kBlockChunk;
 }
-// Planes per workgroup: 64 for the 64 x 32 tile (1025^3 ball: 4995 against 5291 us per
-// launch), 32 otherwise (64-plane chunks were slower with the other shapes).
-inline int default_chunk(int rpw, int wv) { return (rpw == 2 && wv == 16) ? 64 : kBlockChunk; }
 
 // Tile (bx, by, bz) of workgroup blockIdx: in launch order, or XCD-aware (consecutive workgroup
 // ids go round-robin over the XCDs; the remap gives each XCD a contiguous run of tiles).
@@ -332,10 +334,43 @@ __device__ __forceinline__ void block_tile(int xcd, int &bx, int &by, int &bz) {
   bz = b / (gx * gy);
 }
 
+// Raw buffer access of one plane: the resource's base is the plane's first node and its size the
+// plane's bytes (under 2^31 for every grid the library accepts), the lane's column offset is a
+// VGPR computed once, so a plane's loads and stores cost no per-lane address arithmetic.  A lane
+// offset of 2^31, or a resource of size 0, is out of range: the hardware drops such a store, so
+// halo lanes and planes outside the chunk store without branching.
+constexpr int kPlaneRsrcWord3 = 0x00020000;   // gfx9 resource word 3: raw (unswizzled) access
+constexpr unsigned kPlaneDrop = 0x80000000u;
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *base, const F2Geom &g,
+                                                             int k, bool live) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(base + (size_t)k * g.plane), (short)0,
+                                           live ? (int)(g.plane * sizeof(T)) : 0,
+                                           kPlaneRsrcWord3);
+}
+__device__ __forceinline__ void plane_ld(float &x, __amdgpu_buffer_rsrc_t r, unsigned vo) {
+  x = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, 0, 0));
+}
+__device__ __forceinline__ void plane_ld(double &x, __amdgpu_buffer_rsrc_t r, unsigned vo) {
+  x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, 0, 0));
+}
+typedef int f2_i32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void plane_st(float x, __amdgpu_buffer_rsrc_t r, unsigned vo) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(x), r, (int)vo, 0, 0);
+}
+__device__ __forceinline__ void plane_st(double x, __amdgpu_buffer_rsrc_t r, unsigned vo) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(f2_i32x2, x), r, (int)vo, 0, 0);
+}
+
+// lambda in the blocked tile: read per node if the array is present (kLamAny), or known to be
+// present (kLamArray) or absent (kLamConst, the constant (c dt / h)^2)
+enum { kLamAny = 0, kLamArray = 1, kLamConst = 2 };
+
 // INNER: the tile's columns and rows (halo included) hold no node on an x or y box face and no
 // sound-soft node, so the x/y mirror substitutions, the mask and the x/y absorbing faces drop
-// out; only the z face planes (plane-uniform) keep their mirror and absorption.
-template <typename T, int K, int RPW, int WV, bool INNER>
+// out; only the z face planes (plane-uniform) keep their mirror and absorption.  ZIN: no plane
+// the chunk computes is a z face plane either, so those drop out too.
+template <typename T, int K, int RPW, int WV, bool INNER, bool ZIN, int LAM>
 __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, const T *prev,
                                               const T *lam, T *out_k, T *out_km1,
                                               T (&lds)[K][2][WV * RPW][64], int bx, int by,
@@ -347,16 +382,17 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
   const int ic = INNER ? i : min(max(i, 0), g.nx);
   // per row t of this wavefront: tile row R = RPW w + t, box row j
   int jr[RPW], jcr[RPW], mxy[RPW];
-  size_t col[RPW];
-  bool store[RPW];
+  unsigned vo[RPW], vs[RPW];   // byte offset of the column in a plane; for stores, or the drop
+
 #pragma unroll
   for (int t = 0; t < RPW; ++t) {
     const int R = RPW * w + t;
     const int j = by * OH - K + R;
     jr[t] = j;
     jcr[t] = INNER ? j : min(max(j, 0), g.ny);
-    col[t] = (size_t)jcr[t] * g.px + ic;
-    store[t] = lane >= K && lane < 64 - K && R >= K && R < TY - K && i <= g.nx && j <= g.ny;
+    vo[t] = (unsigned)(((size_t)jcr[t] * g.px + ic) * sizeof(T));
+    const bool store = lane >= K && lane < 64 - K && R >= K && R < TY - K && i <= g.nx && j <= g.ny;
+    vs[t] = store ? vo[t] : kPlaneDrop;
     // absorbing faces at this column from the x and y faces (zero for INNER tiles)
     mxy[t] = INNER ? 0
                    : (ic == 0 ? g.abs_face[0] : 0) + (ic == g.nx ? g.abs_face[1] : 0) +
@@ -385,12 +421,15 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
   };
   auto load_plane = [&](int p, Plane &x) {
     const int pc = min(max(p, 0), g.nz);
+    const auto rc = plane_rsrc(cur, g, pc, true), rp = plane_rsrc(prev, g, pc, true);
 #pragma unroll
     for (int t = 0; t < RPW; ++t) {
-      const size_t o = (size_t)pc * g.plane + col[t];
-      x.a[t] = cur[o];
-      x.b[t] = prev[o];
-      x.l[t] = lam_at(g, lam, o);
+      plane_ld(x.a[t], rc, vo[t]);
+      plane_ld(x.b[t], rp, vo[t]);
+      if (LAM == kLamArray || (LAM == kLamAny && lam))
+        plane_ld(x.l[t], plane_rsrc(lam, g, pc, true), vo[t]);
+      else
+        x.l[t] = (T)g.lam_const;
       x.r[t] = INNER ? T(1) : (masked(g, ic, jcr[t], pc) ? T(0) : T(1));
     }
   };
@@ -422,20 +461,25 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
         const T zc = W[t][s - 1][1];
         T zp = W[t][s - 1][2];
         T xl = lane_from_left(zc), xr = lane_from_right(zc);
-        T ym = t > 0 ? W[t - 1][s - 1][1] : (RPW * w > 0 ? yl : zc);
-        T yp = t < RPW - 1 ? W[t + 1][s - 1][1] : (RPW * w + RPW < TY ? yh : zc);
+        // (at the tile's first and last rows Rlo and Rhi are the wavefront's own rows, whose
+        // LDS values are zc itself)
+        T ym = t > 0 ? W[t - 1][s - 1][1] : yl;
+        T yp = t < RPW - 1 ? W[t + 1][s - 1][1] : yh;
         if (!INNER) {
           if (i == 0) xl = xr;
           if (i == g.nx) xr = xl;
           if (jr[t] == 0) ym = yp;
           if (jr[t] == g.ny) yp = ym;
         }
-        if (q == 0) zm = zp;
-        if (q == g.nz) zp = zm;
+        if (!ZIN) {
+          if (q == 0) zm = zp;
+          if (q == g.nz) zp = zm;
+        }
         const T lap = T(6) * zc - (zm + zp + xl + xr + ym + yp);
         const T l = Ld[t][s];
         const T aux = s == 1 ? b1[t] : W[t][s >= 2 ? s - 2 : 0][0];
-        const int m = mxy[t] + (q == 0 ? g.abs_face[4] : 0) + (q == g.nz ? g.abs_face[5] : 0);
+        const int m =
+            mxy[t] + (ZIN ? 0 : (q == 0 ? g.abs_face[4] : 0) + (q == g.nz ? g.abs_face[5] : 0));
         if (m == 0) {
           un[t] = fma(-l, lap, T(2) * zc - aux);
         } else {
@@ -452,10 +496,12 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
           W[t][s][2] = un[t];
           lds[s][p & 1][RPW * w + t][lane] = un[t];
         }
-        if (store[t] && q >= k0 && q < k1) {
-          if (s == K) out_k[(size_t)q * g.plane + col[t]] = un[t];
-          if (s == K - 1) out_km1[(size_t)q * g.plane + col[t]] = un[t];
-        }
+      }
+      if (s >= K - 1) {
+        const auto ro = plane_rsrc(s == K ? out_k : out_km1, g, min(max(q, 0), g.nz),
+                                   q >= k0 && q < k1);
+#pragma unroll
+        for (int t = 0; t < RPW; ++t) plane_st(un[t], ro, vs[t]);
       }
     }
 #pragma unroll
@@ -471,6 +517,28 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
   load_plane(k0 - K, x0);
   // (the loads past the last plane read clamped planes and are not used: unconditional loads
   // need no copies of the register set they replace)
+  if constexpr (ZIN) {
+    // Unrolled by 12, a multiple of every window's period (3 planes per level, K + 1 of lambda,
+    // 2 load sets), so that the windows' shifts are register renames rather than moves.
+    Plane xs[2] = {x0, x1};
+    int p = k0 - K;
+    for (; p + 11 <= pend; p += 12) {
+#pragma unroll
+      for (int u = 0; u < 12; ++u) {
+        load_plane(p + u + 1, xs[(u + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        plane_iteration(p + u, xs[u & 1]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 11; ++u) {
+      if (p + u > pend) break;
+      load_plane(p + u + 1, xs[(u + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+      plane_iteration(p + u, xs[u & 1]);
+    }
+    return;
+  }
   for (int p = k0 - K; p <= pend; p += 2) {
     load_plane(p + 1, x1);
     __builtin_amdgcn_sched_barrier(0);   // issue the loads before this plane's work
@@ -506,12 +574,20 @@ __attribute__((amdgpu_waves_per_eu(F2BlockOccupancy<WV>::value))) void f2_block_
   const int k0 = bz * shape.chunk, k1 = min(k0 + shape.chunk, g.nz + 1);
   const bool mask = g.mask && i1 >= g.mlo[0] && i0 <= g.mhi[0] && j1 >= g.mlo[1] &&
                     j0 <= g.mhi[1] && k1 + K - 1 >= g.mlo[2] && k0 - K <= g.mhi[2];
-  if (!faces && !mask)
-    f2_block_tile<T, K, RPW, WV, true>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,
-                                       shape.chunk);
+  // level s computes planes p - s for p = k0 - K .. k1 + K - 1: planes k0 - 2K .. k1 + K - 2
+  const bool zin = k0 - 2 * K >= 1 && k1 + K - 2 <= g.nz - 1;
+  if (!faces && !mask && zin && lam)
+    f2_block_tile<T, K, RPW, WV, true, true, kLamArray>(g, cur, prev, lam, out_k, out_km1, lds,
+                                                        bx, by, bz, shape.chunk);
+  else if (!faces && !mask && zin)
+    f2_block_tile<T, K, RPW, WV, true, true, kLamConst>(g, cur, prev, lam, out_k, out_km1, lds,
+                                                        bx, by, bz, shape.chunk);
+  else if (!faces && !mask)
+    f2_block_tile<T, K, RPW, WV, true, false, kLamAny>(g, cur, prev, lam, out_k, out_km1, lds,
+                                                       bx, by, bz, shape.chunk);
   else
-    f2_block_tile<T, K, RPW, WV, false>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,
-                                        shape.chunk);
+    f2_block_tile<T, K, RPW, WV, false, false, kLamAny>(g, cur, prev, lam, out_k, out_km1, lds,
+                                                        bx, by, bz, shape.chunk);
 }
 
 // out = psi in, psi = lambda R / ((1 + beta) eta)
@@ -803,48 +879,70 @@ hipError_t f2_march(int mode, const F2Geom &g, const F2Args<T> &p, hipStream_t s
   return hipGetLastError();
 }
 
+// Tile shape of the blocked launches: rows per wavefront and wavefronts per workgroup.
+// CMCG_F2_RPW and CMCG_F2_WAVES (environment, read per call) override them for sweeps and tests:
+// rows 1 or 2 (FP32 also 3 or 4), and 12 wavefronts instead of 16 with two rows.
 template <typename T>
-hipError_t f2_march_block(const F2Geom &g, const T *cur, const T *prev, const T *lam, T *out_k,
-                          T *out_km1, int K, hipStream_t s) {
-  // CMCG_F2_CHUNK and CMCG_F2_XCD (environment, read once) override the launch shape for
-  // sweeps (chunk 0: the tile shape's default)
-  static const F2BlockShape env_shape = [] {
-    F2BlockShape sh;
-    sh.chunk = 0;
-    if (const char *e = std::getenv("CMCG_F2_CHUNK")) sh.chunk = std::max(1, std::atoi(e));
-    if (const char *e = std::getenv("CMCG_F2_XCD")) sh.xcd = std::atoi(e);
-    return sh;
-  }();
-  // CMCG_F2_RPW and CMCG_F2_WAVES (environment, read per launch): rows per wavefront (1 or 2)
-  // and wavefronts per workgroup (16, or 12 with two rows)
+void f2_block_shape(int *rpw, int *wv) {
   const char *re = std::getenv("CMCG_F2_RPW");
   const char *we = std::getenv("CMCG_F2_WAVES");
   const int want = re ? std::atoi(re) : 0;
-  const int rpw = (want == 1 || want == 2) ? want : default_rpw<T>();
-  const int wq = we ? std::atoi(we) : 0;
-  const int wv = rpw == 1 ? kBlockWaves : (wq == 12 || wq == 16) ? wq : default_waves(rpw, lam);
+  const int rmax = sizeof(T) == 4 ? 4 : 2;
+  *rpw = (want >= 1 && want <= rmax) ? want : default_rpw<T>();
+  *wv = (*rpw == 2 && we && std::atoi(we) == 12) ? 12 : kBlockWaves;
+}
+
+template <typename T>
+hipError_t f2_march_block(const F2Geom &g, const T *cur, const T *prev, const T *lam, T *out_k,
+                          T *out_km1, int K, hipStream_t s) {
+  // CMCG_F2_CHUNK and CMCG_F2_XCD (environment, read per launch) override the launch shape for
+  // sweeps and tests (chunk 0: the tile shape's default)
+  F2BlockShape env_shape;
+  env_shape.chunk = 0;
+  if (const char *e = std::getenv("CMCG_F2_CHUNK")) env_shape.chunk = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("CMCG_F2_XCD")) env_shape.xcd = std::atoi(e);
+  int rpw = 0, wv = 0;
+  f2_block_shape<T>(&rpw, &wv);
   dim3 block(64 * wv);
   F2BlockShape shape = env_shape;
-  if (shape.chunk == 0) shape.chunk = default_chunk(rpw, wv);
+  auto tiles = [&](int k, int ax) {
+    const int n = ax == 0 ? g.nx : g.ny, w = (ax == 0 ? 64 : wv * rpw) - 2 * k;
+    return (n + 1 + w - 1) / w;
+  };
+  if (shape.chunk == 0) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return hipErrorInvalidDevice;
+    shape.chunk = default_chunk((long)tiles(K, 0) * tiles(K, 1), g.nz, cus);
+  }
   auto grid = [&](int k) {
-    const int ty = wv * rpw;
-    return dim3((g.nx + 1 + 64 - 2 * k - 1) / (64 - 2 * k),
-                (g.ny + 1 + ty - 2 * k - 1) / (ty - 2 * k),
-                (g.nz + 1 + shape.chunk - 1) / shape.chunk);
+    return dim3(tiles(k, 0), tiles(k, 1), (g.nz + 1 + shape.chunk - 1) / shape.chunk);
   };
 #define CMCG_F2_BLOCK(KK, RR, WW)                                                              \
   hipLaunchKernelGGL((f2_block_kernel<T, KK, RR, WW>), grid(KK), block, 0, s, g, cur, prev,    \
                      lam, out_k, out_km1, shape)
-  switch ((K * 4 + rpw) * 32 + wv) {
-    case (2 * 4 + 1) * 32 + 16: CMCG_F2_BLOCK(2, 1, 16); break;
-    case (3 * 4 + 1) * 32 + 16: CMCG_F2_BLOCK(3, 1, 16); break;
-    case (4 * 4 + 1) * 32 + 16: CMCG_F2_BLOCK(4, 1, 16); break;
-    case (2 * 4 + 2) * 32 + 16: CMCG_F2_BLOCK(2, 2, 16); break;
-    case (3 * 4 + 2) * 32 + 16: CMCG_F2_BLOCK(3, 2, 16); break;
-    case (4 * 4 + 2) * 32 + 16: CMCG_F2_BLOCK(4, 2, 16); break;
-    case (2 * 4 + 2) * 32 + 12: CMCG_F2_BLOCK(2, 2, 12); break;
-    case (3 * 4 + 2) * 32 + 12: CMCG_F2_BLOCK(3, 2, 12); break;
-    case (4 * 4 + 2) * 32 + 12: CMCG_F2_BLOCK(4, 2, 12); break;
+  if constexpr (sizeof(T) == 4) {
+    switch ((K * 8 + rpw) * 32 + wv) {
+      case (2 * 8 + 3) * 32 + 16: CMCG_F2_BLOCK(2, 3, 16); return hipGetLastError();
+      case (3 * 8 + 3) * 32 + 16: CMCG_F2_BLOCK(3, 3, 16); return hipGetLastError();
+      case (4 * 8 + 3) * 32 + 16: CMCG_F2_BLOCK(4, 3, 16); return hipGetLastError();
+      case (2 * 8 + 4) * 32 + 16: CMCG_F2_BLOCK(2, 4, 16); return hipGetLastError();
+      case (3 * 8 + 4) * 32 + 16: CMCG_F2_BLOCK(3, 4, 16); return hipGetLastError();
+      case (4 * 8 + 4) * 32 + 16: CMCG_F2_BLOCK(4, 4, 16); return hipGetLastError();
+      default: break;
+    }
+  }
+  switch ((K * 8 + rpw) * 32 + wv) {
+    case (2 * 8 + 1) * 32 + 16: CMCG_F2_BLOCK(2, 1, 16); break;
+    case (3 * 8 + 1) * 32 + 16: CMCG_F2_BLOCK(3, 1, 16); break;
+    case (4 * 8 + 1) * 32 + 16: CMCG_F2_BLOCK(4, 1, 16); break;
+    case (2 * 8 + 2) * 32 + 16: CMCG_F2_BLOCK(2, 2, 16); break;
+    case (3 * 8 + 2) * 32 + 16: CMCG_F2_BLOCK(3, 2, 16); break;
+    case (4 * 8 + 2) * 32 + 16: CMCG_F2_BLOCK(4, 2, 16); break;
+    case (2 * 8 + 2) * 32 + 12: CMCG_F2_BLOCK(2, 2, 12); break;
+    case (3 * 8 + 2) * 32 + 12: CMCG_F2_BLOCK(3, 2, 12); break;
+    case (4 * 8 + 2) * 32 + 12: CMCG_F2_BLOCK(4, 2, 12); break;
     default: return hipErrorInvalidValue;
   }
 #undef CMCG_F2_BLOCK
@@ -947,6 +1045,7 @@ hipError_t f2_pack(const F2Geom &g, const T *dev, double *packed, int nfields, h
   template hipError_t f2_psi_scale<T>(const F2Geom &, const T *, const T *, T *, hipStream_t);   \
   template hipError_t f2_march_block<T>(const F2Geom &, const T *, const T *, const T *, T *,    \
                                         T *, int, hipStream_t);                                  \
+  template void f2_block_shape<T>(int *, int *);                                                 \
   template hipError_t f2_mass_inverse<T>(const F2Geom &, const T *, double *, const T *,         \
                                          hipStream_t);                                            \
   template hipError_t f2_setup<T>(const F2Geom &, const double *, double, const double *,        \

@@ -61,8 +61,10 @@ __global__ void f2_output_kernel(F2Geom g, const double *ure, const double *uim,
   }
 }
 
-// Homogeneous steps fused per launch by default (temporal blocking; 1 = one step per launch).
-constexpr int kF2DefaultBlock = 3;
+// Homogeneous steps fused per launch by default (temporal blocking; 1 = one step per launch):
+// 4 in FP32 and 3 in FP64, the depths at which each precision's blocked launch does a step
+// fastest (with its default tile shape).
+constexpr int kF2DefaultBlock32 = 4, kF2DefaultBlock64 = 3;
 
 // Weights of the source components at one time: (c, s)_j = amp (cos, sin)(m_j omega t).
 struct ShotPhase {
@@ -165,6 +167,7 @@ struct F2Set {
   void *lam = nullptr;
   void *Fre = nullptr, *Fim = nullptr;             // load amplitudes, one field per component
   void *Fc = nullptr;                              // several components: the load of one sweep
+  int kstep = 1;                                   // homogeneous steps per blocked launch
 };
 
 class F2Solver final : public Solver {
@@ -192,7 +195,6 @@ class F2Solver final : public Solver {
   bool multi = false;                      // several source components
   double *DA = nullptr, *DB = nullptr;     // several components: Dirichlet values of one sweep
   bool pure_neumann = false;               // no absorbing face and no sound-soft node
-  int kstep = 1;                           // homogeneous steps per blocked launch
   double *cpart = nullptr, *h_cpart = nullptr;   // compatibility sums: device partials, host copy
   double *partials = nullptr, *scalars = nullptr, *h_scalars = nullptr;
   RieszMGT<double> mg;     // FP64 hierarchy: the PCG solve, and FP64 solves' V-cycle
@@ -301,9 +303,14 @@ class F2Solver final : public Solver {
     // temporal blocking of the homogeneous steps: K steps per launch (1 = off); each set gets
     // the fourth state buffer it needs (in FP32-mixed mode the FP64 set's backward periods, in
     // the refreshes, then run blocked too)
-    kstep = cfg.steps_request > 0 ? std::min(cfg.steps_request, 4) : kF2DefaultBlock;
-    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im, J, kstep > 1));
-    if (mixed) CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, var_c, forced, has_im, J, kstep > 1));
+    const int kreq = cfg.steps_request > 0 ? std::min(cfg.steps_request, 4) : 0;
+    hi.kstep = kreq ? kreq : kF2DefaultBlock64;
+    lo.kstep = kreq ? kreq : kF2DefaultBlock32;
+    // (a blocked launch addresses each plane through a buffer resource of the plane's bytes,
+    // which must stay below 2^31 in FP64; larger planes step one step per launch)
+    if (g.plane * sizeof(double) > 0x7fffffffull) hi.kstep = lo.kstep = 1;
+    CMCG_TRY(alloc_set(hi, CMCG_FP64, var_c, forced, has_im, J, hi.kstep > 1));
+    if (mixed) CMCG_TRY(alloc_set(lo, CMCG_FP32_MIXED, var_c, forced, has_im, J, lo.kstep > 1));
     else lo = hi;
     CMCG_TRY(arena.alloc(2 * g.fs * (mixed ? sizeof(float) : sizeof(double)), &D, s));
     CMCG_TRY(arena.alloc_n(2 * g.fs, &Z, s));
@@ -412,7 +419,7 @@ class F2Solver final : public Solver {
 
   // ------------------------------------------------------------------ periods
   // `count` homogeneous steps from (cur, prev) = (u^n, u^{n-1}); on return they point to
-  // u^{n+count} and u^{n+count-1}.  With the set's fourth buffer, kstep steps per blocked launch
+  // u^{n+count} and u^{n+count-1}.  With the set's fourth buffer, b.kstep steps per blocked launch
   // (then the remainder one at a time); outputs always go to buffers that are not inputs.
   // Compulsory HBM bytes of one sweep: each array its arguments name read (or written) once,
   // the subtrahend as two fields, the filter's FP64 accumulators read and written
@@ -443,6 +450,7 @@ class F2Solver final : public Solver {
     };
     long long full = 0;   // blocked launches of full depth so far (the bulk of the period)
     while (count > 0) {
+      const int kstep = b.kstep;
       const int K = (b.D && kstep > 1 && count >= 2) ? std::min(kstep, count) : 1;
       if (K >= 2) {
         T *ok = pick(cur, prev, nullptr);
@@ -1096,7 +1104,12 @@ class F2Solver final : public Solver {
     i->field_len = nn;
     i->device_bytes = (int64_t)arena.bytes();
     i->n_fields = cfg.nshots;
-    i->steps_per_launch = kstep;
+    // the set that runs the CG iterations' periods
+    i->steps_per_launch = lo.kstep;
+    if (lo.kstep > 1) {
+      if (mixed) f2_block_shape<float>(&i->block_rows, &i->block_waves);
+      else f2_block_shape<double>(&i->block_rows, &i->block_waves);
+    }
   }
 };
 

@@ -61,7 +61,9 @@ def test_temporal_blocking_is_bitwise(cm, prec):
             assert s.info["steps_per_launch"] == k
             outs.append((s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z)))
     with cm.Solver(prob, prec) as s:
-        assert s.info["steps_per_launch"] == 3       # the nodal default
+        # the nodal defaults: 4 steps per launch in FP32 (3 rows per wavefront), 3 in FP64 (2)
+        assert s.info["steps_per_launch"] == (4 if prec == "fp32" else 3)
+        assert (s.info["block_rows"], s.info["block_waves"]) == ((3 if prec == "fp32" else 2), 16)
     for k, (a, b) in zip((2, 3, 4), outs[1:]):
         assert np.array_equal(a, outs[0][0]), (k, np.max(np.abs(a - outs[0][0])))
         assert np.array_equal(b, outs[0][1]), (k, np.max(np.abs(b - outs[0][1])))
@@ -72,28 +74,37 @@ def test_temporal_blocking_is_bitwise(cm, prec):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_blocked_tile_height_is_bitwise(cm, prec, monkeypatch):
-    """Tiles of one row per wavefront (64 x 16) and of two (64 x 32, CMCG_F2_RPW=2) give the same
-    periods bit for bit on a ragged box with a sound-soft block and mixed faces, where tile
-    edges fall at different rows."""
+    """Tiles of one row per wavefront (64 x 16) and of two (64 x 32, CMCG_F2_RPW=2; in FP32 also
+    three and four, 64 x 48 and 64 x 64) give the same periods bit for bit on a ragged box with a
+    sound-soft block and mixed faces, where tile edges fall at different rows."""
     prob = _mixed3d(n=(70, 45, 40), seed=12)
     o = F2(prob)
     z = np.random.default_rng(13).standard_normal(o.size) * np.concatenate([o.free.ravel()] * 2)
     outs = []
-    for rpw in ("1", "2"):
+    for rpw in ("1", "2", "3", "4") if prec == "fp32" else ("1", "2"):
         monkeypatch.setenv("CMCG_F2_RPW", rpw)
         with cm.Solver(prob, prec, steps_per_launch=3) as s:
             outs.append((s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z)))
-    assert np.array_equal(outs[0][0], outs[1][0])
-    assert np.array_equal(outs[0][1], outs[1][1])
+    for out in outs[1:]:
+        assert np.array_equal(outs[0][0], out[0])
+        assert np.array_equal(outs[0][1], out[1])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_blocking_bitwise_around_a_sound_soft_ball(cm, prec):
+@pytest.mark.parametrize("prec,rpw,chunk", [("fp64", None, None), ("fp32", None, None),
+                                            ("fp64", "2", "32"), ("fp32", "2", "32"),
+                                            ("fp32", "3", "32"), ("fp32", "4", "32"),
+                                            ("fp32", "3", "16")])
+def test_blocking_bitwise_around_a_sound_soft_ball(cm, prec, rpw, chunk, monkeypatch):
     """129^3 nodes, a sound-soft ball in the middle: interior tiles whose columns cross the
     ball's bounding box but whose plane chunk lies above or below it take the unmasked inner
-    path, the others the masked one; blocked periods (K = 2, 3, 4) equal one step per launch bit
-    for bit, and the ball's nodes stay zero."""
+    path, the others the masked one, and tiles whose chunk is clear of the z faces too the
+    z-interior path (with chunks of 16 or 32 planes); blocked periods (K = 2, 3, 4) equal one
+    step per launch bit for bit, in the default tile shape and in tiles of 2, 3 and 4 rows per
+    wavefront, and the ball's nodes stay zero."""
     import torch
+    if rpw:
+        monkeypatch.setenv("CMCG_F2_RPW", rpw)
+        monkeypatch.setenv("CMCG_F2_CHUNK", chunk)
     prob = ci.sound_soft_sphere_3d(n=128, freq=6.0, radius=0.15)
     mask = torch.as_tensor(np.concatenate([prob.sound_soft.ravel()] * 2) != 0).cuda()
     with cm.Solver(prob, prec, steps_per_launch=1) as s:
@@ -392,11 +403,11 @@ def c3():
 
 
 def test_full_size_blocked_period_is_bitwise(cm, c3):
-    """512^3, FP32: forward and backward homogeneous periods with 3 steps per launch (the
-    default) equal one step per launch bit for bit."""
+    """512^3, FP32: forward and backward homogeneous periods with 4 steps per launch (the
+    default) and with 3 equal one step per launch bit for bit."""
     import torch
     outs = []
-    for k in (1, 3):
+    for k in (1, 4, 3):
         with cm.Solver(c3, "fp32", steps_per_launch=k) as s:
             n = s.info["state_len"]
             g = torch.Generator(device="cuda").manual_seed(11)
@@ -404,8 +415,9 @@ def test_full_size_blocked_period_is_bitwise(cm, c3):
             outs.append((s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z)))
             del z
             torch.cuda.synchronize()
-    assert torch.equal(outs[0][0], outs[1][0])
-    assert torch.equal(outs[0][1], outs[1][1])
+    for out in outs[1:]:
+        assert torch.equal(outs[0][0], out[0])
+        assert torch.equal(outs[0][1], out[1])
 
 
 def test_full_size_adjoint_identity_fp64(cm, c3):

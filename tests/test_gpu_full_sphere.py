@@ -73,7 +73,7 @@ def test_full_size_sphere_periods_sampled(cm, c5):
     torch.cuda.empty_cache()         # the handle allocates about 240 GB outside torch's cache
     with cm.Solver(c5, "fp32") as s:
         N = s.info["steps_per_period"]
-        assert N == 21 and s.info["steps_per_launch"] == 3 and s.info["state_len"] == 2 * nn
+        assert N == 21 and s.info["steps_per_launch"] == 4 and s.info["state_len"] == 2 * nn
         o_N = int(math.ceil((2 * math.pi / c5.omega) * 1.0 / (0.5 / NSIDE)))
         assert N == o_N
         m = N + 2
