@@ -71,6 +71,21 @@ __device__ __forceinline__ T lam_at(const F2Geom &g, const T *lam, size_t o) {
   return lam ? lam[o] : (T)g.lam_const;
 }
 
+// The absorbing-face coefficient beta = m sqrt(lambda) and a step's division by 1 + beta.  FP64
+// takes the correctly rounded square root and quotient; FP32 (the FP32-mixed stencils) the
+// hardware's approximations (v_sqrt_f32, v_rcp_f32, about one ulp each), a few instructions
+// where the correctly rounded forms take about 25 on every wavefront that holds a face node.
+// Every kernel that takes a leapfrog step uses these, so blocked and single-step launches
+// still agree bit for bit.
+__device__ __forceinline__ float face_beta(int m, float l) {
+  return (float)m * __builtin_amdgcn_sqrtf(l);
+}
+__device__ __forceinline__ double face_beta(int m, double l) { return (double)m * sqrt(l); }
+__device__ __forceinline__ float face_div(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+__device__ __forceinline__ double face_div(double a, double b) { return a / b; }
+
 // Dirichlet data value at device index o (dc, ds: cos/sin weights of the time)
 template <typename T>
 __device__ __forceinline__ T dirichlet_at(const F2Args<T> &p, size_t o, double dc, double ds) {
@@ -89,7 +104,7 @@ __device__ __forceinline__ T sval(const F2Geom &g, const T *f, const T *lam, int
     // (1 + beta) g  (g vanishes on sound-soft nodes)
     const int m = abs_faces(g, i, j, k);
     if (m == 0) return a;
-    return (T(1) + (T)m * sqrt(lam_at(g, lam, o))) * a;
+    return (T(1) + face_beta(m, lam_at(g, lam, o))) * a;
   }
   return a;
 }
@@ -102,7 +117,7 @@ __device__ __forceinline__ void node_update(const F2Geom &g, const F2Args<T> &p,
   const T dt = (T)g.dt;
   const bool R = !masked(g, i, j, k);
   const int m = abs_faces(g, i, j, k);
-  const T beta = m ? (T)m * sqrt(l) : T(0);
+  const T beta = m ? face_beta(m, l) : T(0);
   if (MODE == kF2FwdStart) {
     // u^1 = R(u^0 + dt (1-beta) v^0 - (lambda L u^0 - F^0) / 2)
     if (p.ure) {
@@ -118,14 +133,14 @@ __device__ __forceinline__ void node_update(const F2Geom &g, const F2Args<T> &p,
     }
     T un;
     if (m == 0) un = fma(-l, lap, T(2) * zc - aux) + F;
-    else un = (T(2) * zc - (T(1) - beta) * aux - (l * lap - F)) / (T(1) + beta);
+    else un = face_div(T(2) * zc - (T(1) - beta) * aux - (l * lap - F), T(1) + beta);
     const T hold = (!R && p.dre) ? dirichlet_at(p, o, p.dcos1, p.dsin1) : T(0);
     p.out[o] = R ? un : hold;
   } else if (MODE == kF2FwdEnd) {
     // out = (u^N, (u^{N+1} - u^{N-1}) / (2 dt)) - sub
     T up;
     if (m == 0) up = fma(-l, lap, T(2) * zc - aux) + F;
-    else up = (T(2) * zc - (T(1) - beta) * aux - (l * lap - F)) / (T(1) + beta);
+    else up = face_div(T(2) * zc - (T(1) - beta) * aux - (l * lap - F), T(1) + beta);
     T ou = zc, ov = (up - aux) / (T(2) * dt);
     if (p.sub) {
       ou -= p.sub[o];
@@ -145,14 +160,14 @@ __device__ __forceinline__ void node_update(const F2Geom &g, const F2Args<T> &p,
     //                                 psi b_0 = (Lb - 1) g_y / (2 dt) = -g_y / ((1+beta) dt)
     const T eta = (T)eta_of(g, i, j, k);
     const T psi = R ? l / ((T(1) + beta) * eta) : T(0);
-    const T Kg = R ? (T(2) * zc - l * lap) / (T(1) + beta) : T(0);
+    const T Kg = R ? face_div(T(2) * zc - l * lap, T(1) + beta) : T(0);
     p.out[o] = psi * aux + Kg / (T(2) * dt);
     p.out2[o] = R ? -zc / ((T(1) + beta) * dt) : T(0);
   } else if (MODE == kF2AdjStepFirst) {
     // g_1 = K g_0 + psi b_0
     T gn;
     if (m == 0) gn = fma(-l, lap, T(2) * zc);
-    else gn = (T(2) * zc - l * lap) / (T(1) + beta);
+    else gn = face_div(T(2) * zc - l * lap, T(1) + beta);
     p.out[o] = R ? gn + aux : T(0);
   } else if (MODE == kF2AdjEnd) {
     // st = g_M (stencilled as (1+beta) g), aux = g_{M-1}; a = (1+beta) eta g / lambda:
@@ -483,8 +498,8 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
         if (m == 0) {
           un[t] = fma(-l, lap, T(2) * zc - aux);
         } else {
-          const T beta = (T)m * sqrt(l);
-          un[t] = (T(2) * zc - (T(1) - beta) * aux - l * lap) / (T(1) + beta);
+          const T beta = face_beta(m, l);
+          un[t] = face_div(T(2) * zc - (T(1) - beta) * aux - l * lap, T(1) + beta);
         }
         if (!INNER) un[t] = Rd[t][s] != T(0) ? un[t] : T(0);
       }
@@ -603,7 +618,7 @@ __global__ void f2_psi_scale_kernel(F2Geom g, const T *in, const T *lam, T *out)
   if (m == 0 && i > 0 && i < g.nx && j > 0 && j < g.ny && k > 0 && k < g.nz) {
     out[o] = l * in[o];
   } else {
-    const T beta = m ? (T)m * sqrt(l) : T(0);
+    const T beta = m ? face_beta(m, l) : T(0);
     out[o] = l * in[o] / ((T(1) + beta) * (T)eta_of(g, i, j, k));
   }
   F2_ROWS_END
