@@ -49,17 +49,18 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes": n * 8}))
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter record (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain-copy calibration), or None when the record was taken on
-    another version of the kernel's source file."""
+def measured_traffic(kernel: str, workload: str = ""):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter record
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration; records are keyed
+    "kernel @ workload", since one kernel instance serves several workloads), or None when the
+    record was taken on another version of the kernel's source files."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         rec = json.load(open(rec_path))
     except (OSError, ValueError):
         return None
-    e = rec.get("kernels", {}).get(kernel)
+    e = rec.get("kernels", {}).get(f"{kernel} @ {workload}" if workload else kernel)
     if not e or "source" not in e:
         return None
     names = [e["source"]] if isinstance(e["source"], str) else list(e["source"])
@@ -75,7 +76,7 @@ def measured_traffic(kernel: str):
 
 
 def roofline_entry(kernel: str, launch_s: float, alg_bytes: float, one_pass_bytes: float,
-                   launches: int, **extra):
+                   launches: int, workload: str = "", **extra):
     """The roofline of one kernel instance from its own average launch time.
 
     * achieved / frac: the scope's convention for the leapfrog sweep, single-step compulsory
@@ -87,7 +88,7 @@ def roofline_entry(kernel: str, launch_s: float, alg_bytes: float, one_pass_byte
       sits under the roof.
     * traffic / measured_GBps / frac_measured: the HBM bytes the counters saw per launch
       (null once the kernel's source has changed since they were taken)."""
-    traffic = measured_traffic(kernel)
+    traffic = measured_traffic(kernel, workload)
     achieved = alg_bytes / launch_s / 1e9
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 3),
@@ -179,6 +180,7 @@ def nodal_3d(which: str, precision: str, max_iter: int, chunk: int = 10, keep=No
         out["roofline"] = roofline_entry(
             f"f2_block_kernel<{tname}, {kb}, {rpw}, {wv}>", t, step_words * esz * nodes * kb,
             launch_words * esz * nodes, nl,
+            workload="inclusions 512^3" if which == "inclusions" else "sphere 1024^3",
             fwd_avg_launch_us=round(rep["seconds_bulk_fwd"] / max(1, rep["bulk_launches_fwd"]) * 1e6, 2),
             adj_avg_launch_us=round(rep["seconds_bulk_adj"] / max(1, rep["bulk_launches_adj"]) * 1e6, 2))
     return out
@@ -518,7 +520,7 @@ def main():
     bytes_per_update = 56 if args.fp64_step else 28
     kname = f"f1_stream_kernel<{'double' if args.fp64_step else 'float'}, {kb}, false, false, 0>"
     roofline = roofline_entry(kname, tb / nl, bytes_per_update * cells * kb,
-                              bytes_per_update * cells, nl,
+                              bytes_per_update * cells, nl, workload="random medium 4096^2",
                               fwd_avg_launch_us=round(fwd_us, 2), adj_avg_launch_us=round(adj_us, 2))
 
     out = {"metric": METRIC, "value": round(glups, 2), "unit": "GLUP/s", "n_gpus": 1,

@@ -48,13 +48,18 @@ def test_measured_traffic_needs_every_named_source_unchanged(tmp_path, monkeypat
         "k1": {"source": ["a.hip", "b.h"], "fetch_bytes_per_launch": 300,
                "write_bytes_per_launch": 100},
         "k2": {"source": "a.hip", "fetch_bytes_per_launch": 10, "write_bytes_per_launch": 5},
-        "k3": {"fetch_bytes_per_launch": 1, "write_bytes_per_launch": 1}}}
+        "k3": {"fetch_bytes_per_launch": 1, "write_bytes_per_launch": 1},
+        "k5 @ w1": {"source": "a.hip", "fetch_bytes_per_launch": 7, "write_bytes_per_launch": 1},
+        "k5 @ w2": {"source": "a.hip", "fetch_bytes_per_launch": 9, "write_bytes_per_launch": 1}}}
     (tmp_path / "profiles" / "hbm_traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic("k1") == 400
     assert bench.measured_traffic("k2") == 15
     assert bench.measured_traffic("k3") is None       # no source recorded
     assert bench.measured_traffic("k4") is None       # no record
+    assert bench.measured_traffic("k5", "w1") == 8    # one instance, two workloads
+    assert bench.measured_traffic("k5", "w2") == 10
+    assert bench.measured_traffic("k5", "w3") is None
     (csrc / "b.h").write_text("header b, edited")
     assert bench.measured_traffic("k1") is None       # one of its sources changed
     assert bench.measured_traffic("k2") == 15
