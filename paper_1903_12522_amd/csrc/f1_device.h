@@ -271,7 +271,15 @@ __device__ __forceinline__ void buf_st(double x, __amdgpu_buffer_rsrc_t r, unsig
 // row loop, whose previous and current register sets trade roles, that tie forces a copy before
 // almost every FMA.  The FP32 middle instance's loop goes from 168 vector instructions per two
 // rows (53 of them moves) to 132 (17), and the launch on a 4096^2 grid from 163.4 to 160.0 us.
-// Arithmetic only: no memory is touched.
+// Arithmetic only: no memory is touched.  A translation unit that defines CMCG_FMA_TIED before
+// including this header gets plain fma instead: the persistent serving kernel, held to 128
+// VGPRs, spills 71 registers with the untied form against 34.
+#ifdef CMCG_FMA_TIED
+template <typename T>
+__device__ __forceinline__ T fma3(T a, T b, T c) {
+  return fma(a, b, c);
+}
+#else
 __device__ __forceinline__ float fma3(float a, float b, float c) {
   float r;
   asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
@@ -282,6 +290,7 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
   asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
   return r;
 }
+#endif
 
 // Resources and offsets of one fast-variant wavefront.
 struct FastIO {

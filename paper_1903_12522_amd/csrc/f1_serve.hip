@@ -12,6 +12,8 @@
 // workgroup gives up after `spin_limit` polls, or when the host sets the abort flag (pinned
 // host memory) or another workgroup has given up; the kernel then ends at that barrier and the
 // tick reports the failure.
+// (the two-address FMA form: the untied one raises this kernel's spills at its 128-VGPR cap)
+#define CMCG_FMA_TIED
 #include "f1_device.h"
 
 namespace cmcg {
