@@ -111,8 +111,10 @@ typedef struct {
   void *hip_stream;            /* hipStream_t to run on, or NULL                                */
   int32_t steps_per_launch;    /* leapfrog steps fused per kernel launch (temporal blocking):
                                   F1 1..8 (default 7); F2 1..4 for the
-                                  homogeneous steps (default 3; 1 = one step per launch);
-                                  0 = library default.  Results do not depend on it (bitwise)  */
+                                  homogeneous steps (default 4 in FP32, 3 in FP64, the FP64
+                                  refreshes of FP32-mixed solves included; a value given here
+                                  sets both; 1 = one step per launch); 0 = library default.
+                                  Results do not depend on it (bitwise)                        */
   int32_t riesz_max_iter;      /* F2: cap on the Riesz (elliptic) PCG iterations; 0 = default  */
   double riesz_tol;            /* F2: relative tolerance of the Riesz solve; 0 = default       */
   double fp64_refresh;         /* FP32-mixed: recompute the true gradient with FP64 periods
