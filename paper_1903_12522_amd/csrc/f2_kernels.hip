@@ -381,20 +381,24 @@ __device__ __forceinline__ void plane_st(double x, __amdgpu_buffer_rsrc_t r, uns
 // present (kLamArray) or absent (kLamConst, the constant (c dt / h)^2)
 enum { kLamAny = 0, kLamArray = 1, kLamConst = 2 };
 
-// INNER: the tile's columns and rows (halo included) hold no node on an x or y box face and no
-// sound-soft node, so the x/y mirror substitutions, the mask and the x/y absorbing faces drop
-// out; only the z face planes (plane-uniform) keep their mirror and absorption.  ZIN: no plane
-// the chunk computes is a z face plane either, so those drop out too.
-template <typename T, int K, int RPW, int WV, bool INNER, bool ZIN, int LAM>
+// EDGE: which of the per-node boundary treatments the tile needs.  kEdgeX: its columns (halo
+// included) meet an x box face (per-lane mirror substitution, absorption, clamped columns);
+// kEdgeY: its rows meet a y face (row-uniform mirror and absorption, clamped rows); kEdgeM: it
+// may hold sound-soft nodes (the mask).  A tile with none (EDGE = 0) keeps only the z face
+// planes' mirror and absorption, which are plane-uniform.  ZIN: no plane the chunk computes is a
+// z face plane either, so those drop out too.
+enum { kEdgeX = 1, kEdgeY = 2, kEdgeM = 4 };
+template <typename T, int K, int RPW, int WV, int EDGE, bool ZIN, int LAM>
 __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, const T *prev,
                                               const T *lam, T *out_k, T *out_km1,
                                               T (&lds)[K][2][WV * RPW][64], int bx, int by,
                                               int bz, int chunk) {
   constexpr int TY = WV * RPW, OW = 64 - 2 * K, OH = TY - 2 * K;
+  constexpr bool EX = EDGE & kEdgeX, EY = EDGE & kEdgeY, EM = EDGE & kEdgeM;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = bx * OW - K + lane;
   const int k0 = bz * chunk, k1 = min(k0 + chunk, g.nz + 1);
-  const int ic = INNER ? i : min(max(i, 0), g.nx);
+  const int ic = EX ? min(max(i, 0), g.nx) : i;
   // per row t of this wavefront: tile row R = RPW w + t, box row j
   int jr[RPW], jcr[RPW], mxy[RPW];
   unsigned vo[RPW], vs[RPW];   // byte offset of the column in a plane; for stores, or the drop
@@ -404,14 +408,13 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
     const int R = RPW * w + t;
     const int j = by * OH - K + R;
     jr[t] = j;
-    jcr[t] = INNER ? j : min(max(j, 0), g.ny);
+    jcr[t] = EY ? min(max(j, 0), g.ny) : j;
     vo[t] = (unsigned)(((size_t)jcr[t] * g.px + ic) * sizeof(T));
     const bool store = lane >= K && lane < 64 - K && R >= K && R < TY - K && i <= g.nx && j <= g.ny;
     vs[t] = store ? vo[t] : kPlaneDrop;
-    // absorbing faces at this column from the x and y faces (zero for INNER tiles)
-    mxy[t] = INNER ? 0
-                   : (ic == 0 ? g.abs_face[0] : 0) + (ic == g.nx ? g.abs_face[1] : 0) +
-                         (jcr[t] == 0 ? g.abs_face[2] : 0) + (jcr[t] == g.ny ? g.abs_face[3] : 0);
+    // absorbing faces at this column from the x faces (per lane) and the y faces (per row)
+    mxy[t] = (EX ? (ic == 0 ? g.abs_face[0] : 0) + (ic == g.nx ? g.abs_face[1] : 0) : 0) +
+             (EY ? (jcr[t] == 0 ? g.abs_face[2] : 0) + (jcr[t] == g.ny ? g.abs_face[3] : 0) : 0);
   }
   // the rows just outside this wavefront's rows (clamped to the tile), read from LDS
   const int Rlo = RPW * w > 0 ? RPW * w - 1 : 0;
@@ -445,7 +448,7 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
         plane_ld(x.l[t], plane_rsrc(lam, g, pc, true), vo[t]);
       else
         x.l[t] = (T)g.lam_const;
-      x.r[t] = INNER ? T(1) : (masked(g, ic, jcr[t], pc) ? T(0) : T(1));
+      x.r[t] = EM ? (masked(g, ic, jcr[t], pc) ? T(0) : T(1)) : T(1);
     }
   };
   auto plane_iteration = [&](int p, const Plane &x) {
@@ -454,10 +457,10 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
 #pragma unroll
       for (int d = K; d > 0; --d) {
         Ld[t][d] = Ld[t][d - 1];
-        if (!INNER) Rd[t][d] = Rd[t][d - 1];
+        if (EM) Rd[t][d] = Rd[t][d - 1];
       }
       Ld[t][0] = x.l[t];
-      if (!INNER) Rd[t][0] = x.r[t];
+      if (EM) Rd[t][0] = x.r[t];
       W[t][0][0] = W[t][0][1];
       W[t][0][1] = W[t][0][2];
       W[t][0][2] = x.a[t];
@@ -480,9 +483,11 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
         // LDS values are zc itself)
         T ym = t > 0 ? W[t - 1][s - 1][1] : yl;
         T yp = t < RPW - 1 ? W[t + 1][s - 1][1] : yh;
-        if (!INNER) {
+        if (EX) {
           if (i == 0) xl = xr;
           if (i == g.nx) xr = xl;
+        }
+        if (EY) {
           if (jr[t] == 0) ym = yp;
           if (jr[t] == g.ny) yp = ym;
         }
@@ -501,7 +506,7 @@ __device__ __forceinline__ void f2_block_tile(const F2Geom &g, const T *cur, con
           const T beta = face_beta(m, l);
           un[t] = face_div(T(2) * zc - (T(1) - beta) * aux - l * lap, T(1) + beta);
         }
-        if (!INNER) un[t] = Rd[t][s] != T(0) ? un[t] : T(0);
+        if (EM) un[t] = Rd[t][s] != T(0) ? un[t] : T(0);
       }
 #pragma unroll
       for (int t = 0; t < RPW; ++t) {
@@ -583,7 +588,7 @@ __attribute__((amdgpu_waves_per_eu(F2BlockOccupancy<WV>::value))) void f2_block_
   block_tile(shape.xcd, bx, by, bz);
   const int i0 = bx * OW - K, j0 = by * OH - K;
   const int i1 = i0 + 63, j1 = j0 + TY - 1;
-  const bool faces = i0 < 1 || i1 > g.nx - 1 || j0 < 1 || j1 > g.ny - 1;
+  const bool fx = i0 < 1 || i1 > g.nx - 1, fy = j0 < 1 || j1 > g.ny - 1;
   // the tile reads planes k0 - K .. k1 + K - 1 of its chunk: it meets a sound-soft node only if
   // that slab meets the mask's bounding box too
   const int k0 = bz * shape.chunk, k1 = min(k0 + shape.chunk, g.nz + 1);
@@ -591,18 +596,16 @@ __attribute__((amdgpu_waves_per_eu(F2BlockOccupancy<WV>::value))) void f2_block_
                     j0 <= g.mhi[1] && k1 + K - 1 >= g.mlo[2] && k0 - K <= g.mhi[2];
   // level s computes planes p - s for p = k0 - K .. k1 + K - 1: planes k0 - 2K .. k1 + K - 2
   const bool zin = k0 - 2 * K >= 1 && k1 + K - 2 <= g.nz - 1;
-  if (!faces && !mask && zin && lam)
-    f2_block_tile<T, K, RPW, WV, true, true, kLamArray>(g, cur, prev, lam, out_k, out_km1, lds,
-                                                        bx, by, bz, shape.chunk);
-  else if (!faces && !mask && zin)
-    f2_block_tile<T, K, RPW, WV, true, true, kLamConst>(g, cur, prev, lam, out_k, out_km1, lds,
-                                                        bx, by, bz, shape.chunk);
-  else if (!faces && !mask)
-    f2_block_tile<T, K, RPW, WV, true, false, kLamAny>(g, cur, prev, lam, out_k, out_km1, lds,
-                                                       bx, by, bz, shape.chunk);
-  else
-    f2_block_tile<T, K, RPW, WV, false, false, kLamAny>(g, cur, prev, lam, out_k, out_km1, lds,
-                                                        bx, by, bz, shape.chunk);
+#define CMCG_F2_TILE(E, Z, L)                                                                  \
+  f2_block_tile<T, K, RPW, WV, E, Z, L>(g, cur, prev, lam, out_k, out_km1, lds, bx, by, bz,     \
+                                        shape.chunk)
+  if (!fx && !fy && !mask && zin && lam) CMCG_F2_TILE(0, true, kLamArray);
+  else if (!fx && !fy && !mask && zin) CMCG_F2_TILE(0, true, kLamConst);
+  else if (!fx && !fy && !mask) CMCG_F2_TILE(0, false, kLamAny);
+  else if (!fx && !mask) CMCG_F2_TILE(kEdgeY, false, kLamAny);
+  else if (!mask) CMCG_F2_TILE(kEdgeX | kEdgeY, false, kLamAny);
+  else CMCG_F2_TILE(kEdgeX | kEdgeY | kEdgeM, false, kLamAny);
+#undef CMCG_F2_TILE
 }
 
 // out = psi in, psi = lambda R / ((1 + beta) eta)
