@@ -7,11 +7,13 @@
 
 namespace cmcg {
 
+// (bound_ctrl set: a lane with no source lane reads 0 in hardware, so the shift needs no zeroed
+// old value, which the compiler otherwise materialises with an extra move per 32-bit shift)
 __device__ __forceinline__ int dpp_shr1(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int dpp_shl1(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true);
 }
 __device__ __forceinline__ float lane_from_left(float x) {
   return __int_as_float(dpp_shr1(__float_as_int(x)));
