@@ -121,6 +121,26 @@ def test_blocking_bitwise_around_a_sound_soft_ball(cm, prec, rpw, chunk, monkeyp
             assert torch.equal(a, b), (k, (a - b).abs().max().item())
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_blocking_bitwise_on_a_wide_box_without_mask(cm, prec):
+    """201 x 151 x 81 nodes, absorbing and Neumann faces, random c, no sound-soft node: four x
+    tiles and several y tiles, so the blocked launch takes every unmasked tile path (interior
+    and z-interior tiles, tiles on a y face only, tiles on an x face); blocked periods (K = 2, 3,
+    4) equal one step per launch bit for bit."""
+    import torch
+    prob = _mixed3d(n=(200, 150, 80), seed=21, masked=False)
+    with cm.Solver(prob, prec, steps_per_launch=1) as s:
+        n = s.info["state_len"]
+        g = torch.Generator(device="cuda").manual_seed(22)
+        z = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        ref = (s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z))
+    for k in (2, 3, 4):
+        with cm.Solver(prob, prec, steps_per_launch=k) as s:
+            out = (s.apply(cm.OP_FORWARD, z), s.apply(cm.OP_ADJOINT, z))
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), (k, (a - b).abs().max().item())
+
+
 def test_report_counts_compulsory_traffic(cm):
     """cmcg_report.dram_bytes of a nodal solve: blocked interior steps (5 words per 3 steps)
     and single-step start, end, metric and scaling sweeps, all in FP64: between the blocked rate
