@@ -94,19 +94,21 @@ __device__ __forceinline__ T dirichlet_at(const F2Args<T> &p, size_t o, double d
   return (T)v;
 }
 
-// value of the stencilled field at a node, per sweep
+// value of the stencilled field at a node, per sweep, from the stored value a there
 template <typename T, int MODE>
-__device__ __forceinline__ T sval(const F2Geom &g, const T *f, const T *lam, int i, int j, int k) {
-  const size_t o = g.idx(i, j, k);
-  const T a = f[o];
+__device__ __forceinline__ T sfix(const F2Geom &g, const T *lam, int i, int j, int k, T a) {
   if (MODE == kF2Metric) return masked(g, i, j, k) ? T(0) : a;
   if (MODE == kF2AdjEnd) {
     // (1 + beta) g  (g vanishes on sound-soft nodes)
     const int m = abs_faces(g, i, j, k);
     if (m == 0) return a;
-    return (T(1) + face_beta(m, lam_at(g, lam, o))) * a;
+    return (T(1) + face_beta(m, lam_at(g, lam, g.idx(i, j, k)))) * a;
   }
   return a;
+}
+template <typename T, int MODE>
+__device__ __forceinline__ T sval(const F2Geom &g, const T *f, const T *lam, int i, int j, int k) {
+  return sfix<T, MODE>(g, lam, i, j, k, f[g.idx(i, j, k)]);
 }
 
 // Output of one node of one sweep, given the stencilled centre value zc, the 7-point operator
@@ -214,12 +216,15 @@ __device__ __forceinline__ void plane_loads(const F2Geom &g, const F2Args<T> &p,
 // The grid is (x tiles of 64 nodes, y tiles of 4 rows, z chunks); each wavefront owns one row.
 // Lanes past the last node shadow it so that every lane takes part in the DPP shifts; they
 // never store.  The two end lanes of a wavefront load their outer x neighbour in the same load
-// instruction in which the other lanes reload their own node (a cache hit).  Sweeps that
-// stencil the field as stored issue the loads of plane k+1 before computing plane k (register
-// double buffering), which doubles the bytes each wavefront keeps in flight.
+// instruction in which the other lanes reload their own node (a cache hit).  The sweeps issue
+// the loads of plane k+1 before computing plane k (register double buffering), which doubles
+// the bytes each wavefront keeps in flight; the metric and the transposed start map stencil a
+// transform of the stored values (sfix), applied to each loaded value.  Only the start map of a
+// forced period or one with Dirichlet data (whose stencil reads the data on sound-soft nodes)
+// loads plane by plane.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
-  constexpr bool kPlain = MODE != kF2Metric && MODE != kF2AdjEnd && MODE != kF2FwdStart;
+  const bool prefetch = MODE != kF2FwdStart || (!p.forced && p.dre == nullptr);
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 64 + lane;
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -234,12 +239,18 @@ __global__ __launch_bounds__(256) void f2_march_kernel(F2Geom g, F2Args<T> p) {
   const int k1 = min(k0 + g.kchunk, g.nz + 1);
   T zm = sval<T, MODE>(g, p.st, p.lam, ic, j, mirror(k0 - 1, g.nz));
   T zc = sval<T, MODE>(g, p.st, p.lam, ic, j, k0);
-  if (kPlain) {
+  if (prefetch) {
     PlaneLoads<T> nxt;
     plane_loads<T, MODE>(g, p, ic, xend, j, jm, jp, k0, nxt);
     for (int k = k0; k < k1; ++k) {
-      const PlaneLoads<T> q = nxt;
+      PlaneLoads<T> q = nxt;
       if (k + 1 < k1) plane_loads<T, MODE>(g, p, ic, xend, j, jm, jp, k + 1, nxt);
+      if (MODE == kF2Metric || MODE == kF2AdjEnd) {
+        q.zp = sfix<T, MODE>(g, p.lam, ic, j, mirror(k + 1, g.nz), q.zp);
+        q.xe = sfix<T, MODE>(g, p.lam, xend, j, k, q.xe);
+        q.ym = sfix<T, MODE>(g, p.lam, ic, jm, k, q.ym);
+        q.yp = sfix<T, MODE>(g, p.lam, ic, jp, k, q.yp);
+      }
       T xl = lane_from_left(zc);
       T xr = lane_from_right(zc);
       if (lane == 0) xl = q.xe;
